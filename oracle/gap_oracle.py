@@ -1,0 +1,228 @@
+"""Plain, slow, obviously correct FP64 CPU oracle for sparse-GPR GAP fitting.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this module.
+It shares no code, tables or helpers with the GPU library; the two meet only
+through arrays produced by the seeded generator in ``synth``.
+
+Everything is computed in float64 with NumPy/SciPy: a library GEMM, Cholesky or
+LAPACK QR is used as a single step where the paper's definition calls for that
+operation, and nothing is blocked, fused or reordered beyond the definitions
+cited on each function (section / equation names of Klawohn et al., "Gaussian
+Approximation Potentials: theory, software implementation and application
+examples", arXiv:2310.03921).
+
+Notation: descriptors d_i (rows of ``desc``), sparse points x_m (rows of ``X``),
+p_im = d_i . x_m, polynomial dot-product kernel k = delta^2 p^zeta,
+configuration c with atoms cfg_ptr[c]:cfg_ptr[c+1], neighbour pair (i, k) with
+target atom j(i, k) = pair_j[pair_ptr[i] + k] and Jacobian slot
+J[pair, alpha, :] = d(d_i)/d(r_{j(i,k), alpha}).
+Observation rows: n_cfg total energies first, then 3 force components per atom
+in atom-major order (row n_cfg + 3 j + alpha).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+from scipy.linalg import lapack
+
+
+def _check_zeta(zeta):
+    # The dot product of two descriptors may be negative; only an integer
+    # exponent >= 1 gives a real kernel there (reading of the dot-product kernel).
+    if int(zeta) != zeta or zeta < 1:
+        raise ValueError("zeta must be an integer >= 1")
+    return int(zeta)
+
+
+def poly_kernel(p, zeta, delta):
+    """k(x, x') = delta^2 (x . x')^zeta.
+
+    Sec. "Regression" (polynomial / dot-product kernel); delta is the
+    energy_scale of the GAP string (the GP standard deviation), entering as
+    delta^2 on every covariance.
+    """
+    zeta = _check_zeta(zeta)
+    return delta * delta * np.asarray(p, dtype=np.float64) ** zeta
+
+
+def poly_kernel_grad_scale(p, zeta, delta):
+    """d k / d p = delta^2 zeta p^(zeta - 1)  (gradient of the dot-product kernel)."""
+    zeta = _check_zeta(zeta)
+    return delta * delta * zeta * np.asarray(p, dtype=np.float64) ** (zeta - 1)
+
+
+def build_kmm(X, zeta, delta):
+    """K_MM[m, m'] = k(x_m, x_m')  (Sec. "Theory", definition after eq. GP_L)."""
+    X = np.asarray(X, dtype=np.float64)
+    return poly_kernel(X @ X.T, zeta, delta)
+
+
+def pair_transpose(pair_ptr, pair_j, n_atoms):
+    """Target-major view of the pair list.
+
+    The operator L-hat (Sec. "Theory") accumulates, for a force observation on
+    atom j, every (i, k) pair whose neighbour slot points at j.  Returns
+    tgt_ptr [n_atoms+1] and tgt_pair [n_pairs]: pairs pointing at j are
+    tgt_pair[tgt_ptr[j]:tgt_ptr[j+1]] in increasing pair order.
+    """
+    pair_j = np.asarray(pair_j, dtype=np.int64)
+    counts = np.bincount(pair_j, minlength=n_atoms)
+    tgt_ptr = np.zeros(n_atoms + 1, dtype=np.int64)
+    np.cumsum(counts, out=tgt_ptr[1:])
+    tgt_pair = np.argsort(pair_j, kind="stable").astype(np.int32)
+    return tgt_ptr, tgt_pair
+
+
+def pair_sources(pair_ptr):
+    """Source atom i of every pair (i, k) from the source-major CSR."""
+    pair_ptr = np.asarray(pair_ptr, dtype=np.int64)
+    return np.repeat(np.arange(len(pair_ptr) - 1), np.diff(pair_ptr))
+
+
+def build_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
+    """L-hat K_NM: energy rows then force rows, (n_cfg + 3 N_at) x M, FP64.
+
+    Energy row of configuration c (eq. 1 and eq. epsilon summed by L-hat):
+        K_E[c, m] = sum_{i in c} k(d_i, x_m).
+    Force row of atom j, component alpha (Sec. "Theory": the derivative rows of
+    K_NM are -grad_x k(x_n, x_m) . dx_n/dr_{j alpha}, accumulated by L-hat):
+        K_F[(j, alpha), m] = - sum_{(i,k): j(i,k)=j} dk/dp(p_im) (J[(i,k), alpha] . x_m).
+    Pairs never leave their configuration, so the sum runs per configuration:
+    a GEMM J_c X^T, the elementwise kernel-gradient scale of the source atom,
+    and a dense 0/1 incidence matrix (target x pair) for the accumulation.
+    """
+    cfg_ptr = np.asarray(cfg_ptr, dtype=np.int64)
+    pair_ptr = np.asarray(pair_ptr, dtype=np.int64)
+    pair_j = np.asarray(pair_j, dtype=np.int64)
+    X = np.asarray(X, dtype=np.float64)
+    n_cfg, n_at, M = len(cfg_ptr) - 1, int(cfg_ptr[-1]), X.shape[0]
+    D = X.shape[1]
+    K = np.zeros((n_cfg + 3 * n_at, M))
+    for c in range(n_cfg):
+        a0, a1 = int(cfg_ptr[c]), int(cfg_ptr[c + 1])
+        if a1 == a0:
+            continue
+        d = np.asarray(desc[a0:a1], dtype=np.float64)
+        P = d @ X.T                                          # p_im
+        K[c] = poly_kernel(P, zeta, delta).sum(axis=0)
+        p0, p1 = int(pair_ptr[a0]), int(pair_ptr[a1])
+        if p1 == p0:
+            continue
+        src = pair_sources(pair_ptr[a0:a1 + 1] - p0)         # local source atom
+        tgt = pair_j[p0:p1] - a0                             # local target atom
+        if tgt.min() < 0 or tgt.max() >= a1 - a0:
+            raise ValueError("a neighbour pair leaves its configuration")
+        Jc = np.asarray(jac[p0:p1], dtype=np.float64).reshape(-1, D)
+        G = (Jc @ X.T).reshape(p1 - p0, 3, M)                # J[(i,k),alpha] . x_m
+        H = poly_kernel_grad_scale(P, zeta, delta)[src][:, None, :] * G
+        inc = np.zeros((a1 - a0, p1 - p0))
+        inc[tgt, np.arange(p1 - p0)] = 1.0
+        KF = -(inc @ H.reshape(p1 - p0, 3 * M)).reshape(a1 - a0, 3, M)
+        K[n_cfg + 3 * a0:n_cfg + 3 * a1] = KF.reshape(3 * (a1 - a0), M)
+    return K
+
+
+def design_matrix(Knm, Kmm, y, sigma, jitter):
+    """A = [Sigma^-1/2 L-hat K_NM ; U_MM], b = [Sigma^-1/2 y ; 0].
+
+    Sec. "Theory": U_MM is the upper Cholesky factor of K_MM after the jitter
+    is added to its diagonal (K_MM + jitter I = U^T U).  The padded target is
+    scaled by Sigma^-1/2 like the rows of A so that the least-squares problem
+    reproduces eq. GP_L (the paper writes b = [y; 0]; this reading is needed
+    for the equivalence it states).
+    """
+    Kmm = np.asarray(Kmm, dtype=np.float64)
+    M = Kmm.shape[0]
+    U = sla.cholesky(Kmm + jitter * np.eye(M), lower=False)
+    w = 1.0 / np.asarray(sigma, dtype=np.float64)
+    A = np.vstack([w[:, None] * np.asarray(Knm, dtype=np.float64), U])
+    b = np.concatenate([w * np.asarray(y, dtype=np.float64), np.zeros(M)])
+    return A, b
+
+
+def solve_qr(A, b):
+    """c = R^-1 Q^T b with A = QR (Householder, LAPACK dgeqrf/dormqr/dtrtrs).
+
+    Sec. "Theory", least-squares form of eq. GP_L solved by QR.
+    """
+    A = np.asarray(A, dtype=np.float64, order="F")
+    n = A.shape[1]
+    qr, tau, _, info = lapack.dgeqrf(A)
+    if info != 0:
+        raise RuntimeError("dgeqrf failed")
+    qtb, _, info = lapack.dormqr("L", "T", qr, tau, np.asarray(b, dtype=np.float64)[:, None],
+                                 lwork=max(1, 64 * n))
+    if info != 0:
+        raise RuntimeError("dormqr failed")
+    c, info = lapack.dtrtrs(np.triu(qr[:n, :n]), qtb[:n, 0])
+    if info != 0:
+        raise RuntimeError("R is singular")
+    return c
+
+
+def fit(Knm, Kmm, y, sigma, jitter):
+    """Sparse-GPR coefficients by the stable least-squares route (Sec. "Theory")."""
+    A, b = design_matrix(Knm, Kmm, y, sigma, jitter)
+    return solve_qr(A, b)
+
+
+def solve_normal_equations(Knm, Kmm, y, sigma, jitter):
+    """c = [K_MM + K_MN Sigma^-1 K_NM]^-1 K_MN Sigma^-1 y  (eq. GP_L, jitter on K_MM)."""
+    Knm = np.asarray(Knm, dtype=np.float64)
+    w2 = 1.0 / np.asarray(sigma, dtype=np.float64) ** 2
+    M = Knm.shape[1]
+    lhs = np.asarray(Kmm) + jitter * np.eye(M) + Knm.T @ (w2[:, None] * Knm)
+    rhs = Knm.T @ (w2 * np.asarray(y, dtype=np.float64))
+    return np.linalg.solve(lhs, rhs)
+
+
+def predict(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta):
+    """Local energies, configuration energies, descriptor gradients and forces.
+
+    eq. epsilon: eps_i = sum_m c_m k(d_i, x_m).
+    gp_predict gradient: g_i = d eps_i / d d_i = sum_m c_m dk/dp(p_im) x_m.
+    Forces by the chain rule (Sec. "Theory"): F_{j alpha} = -dE/dr_{j alpha}
+        = - sum_{(i,k): j(i,k)=j} J[(i,k), alpha] . g_i.
+    ``jac`` may be None (no forces).
+    """
+    desc = np.asarray(desc, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    P = desc @ X.T
+    e_atom = poly_kernel(P, zeta, delta) @ c
+    g = (poly_kernel_grad_scale(P, zeta, delta) * c[None, :]) @ X
+    cfg_ptr = np.asarray(cfg_ptr, dtype=np.int64)
+    e_cfg = np.array([e_atom[cfg_ptr[k]:cfg_ptr[k + 1]].sum() for k in range(len(cfg_ptr) - 1)])
+    forces = None
+    if jac is not None:
+        n_at = desc.shape[0]
+        src = pair_sources(pair_ptr)
+        pj = np.asarray(pair_j, dtype=np.int64)
+        forces = np.zeros((n_at, 3))
+        step = 1 << 16
+        for p0 in range(0, len(src), step):
+            p1 = min(len(src), p0 + step)
+            Jp = np.asarray(jac[p0:p1], dtype=np.float64)
+            contrib = np.einsum("pad,pd->pa", Jp, g[src[p0:p1]])
+            np.add.at(forces, pj[p0:p1], -contrib)
+    return e_atom, e_cfg, g, forces
+
+
+def predict_backward(desc, X, c, g_e, zeta, delta):
+    """Gradients of L = sum_i g_e[i] eps_i with respect to d_i, c and x_m.
+
+    From eq. epsilon with k = delta^2 p^zeta:
+      dL/dd_i = g_e[i] sum_m c_m dk/dp(p_im) x_m
+      dL/dc_m = sum_i g_e[i] k(p_im)
+      dL/dx_m = c_m sum_i g_e[i] dk/dp(p_im) d_i
+    """
+    desc = np.asarray(desc, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    g_e = np.asarray(g_e, dtype=np.float64)
+    P = desc @ X.T
+    Sg = poly_kernel_grad_scale(P, zeta, delta)
+    d_desc = g_e[:, None] * ((Sg * c[None, :]) @ X)
+    d_c = poly_kernel(P, zeta, delta).T @ g_e
+    d_X = c[:, None] * ((Sg * g_e[:, None]).T @ desc)
+    return d_desc, d_c, d_X

@@ -1,0 +1,314 @@
+"""Checks that pin the FP64 oracle to facts fixed by the paper and by mathematics.
+
+Each check takes the oracle module (or a planted mutant of it) and raises
+AssertionError when the fact does not hold.  They are independent of the
+oracle's own arithmetic: complex-step and central finite differences of the
+energy of a linearised descriptor, Euler's theorem for homogeneous functions,
+ζ=1 / ζ=2 special cases computed through linearity and Kronecker products,
+brute-force loops on tiny inputs, the normal-equation closed form (eq. GP_L),
+an SVD least-squares solver, the full-GPR push-through identity, and the
+delta / sigma scaling law.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import synth
+
+TINY = synth.Workload("tiny", seed=11, n_cfg=4, atoms_lo=1, atoms_hi=5, D=6, nb=3, M=5,
+                      zeta=4, delta=1.3)
+
+
+def tiny_batch(w=TINY, seed=None):
+    if seed is not None:
+        w = w.with_(seed=seed)
+    b = synth.generate(w, threads=1)
+    X = synth.sparse_points(w, b)
+    return w, b, X
+
+
+def linearised_energy(w, b, X, cfg, m, dr):
+    """E_c^m(r0 + dr) = delta^2 sum_{i in c} ((d_i + sum_k J_ik . dr_{j(i,k)}) . x_m)^zeta.
+
+    dr is a complex array [N_at, 3]; the descriptor is linear in positions
+    with slope given by the Jacobian slots (eq. for d eps / d r in Sec. Theory).
+    Plain loops: independent of the oracle's GEMM/incidence structure.
+    """
+    a0, a1 = int(b.cfg_ptr[cfg]), int(b.cfg_ptr[cfg + 1])
+    E = 0j
+    for i in range(a0, a1):
+        d = b.desc[i].astype(np.complex128)
+        for p in range(int(b.pair_ptr[i]), int(b.pair_ptr[i + 1])):
+            j = int(b.pair_j[p])
+            for a in range(3):
+                d = d + b.jac[p, a].astype(np.float64) * dr[j, a]
+        s = 0j
+        for k in range(w.D):
+            s += d[k] * X[m, k]
+        E += s ** w.zeta
+    return w.delta ** 2 * E
+
+
+def check_kmm(orc):
+    w, b, X = tiny_batch()
+    K = orc.build_kmm(X, w.zeta, w.delta)
+    assert np.array_equal(K, K.T), "K_MM not exactly symmetric"
+    assert np.linalg.eigvalsh(K).min() > 0, "K_MM not positive definite"
+    # unit-norm descriptors: k(x, x) = delta^2 (normalised kernel)
+    assert np.allclose(np.diag(K), w.delta ** 2, rtol=1e-13, atol=0)
+    # brute force entries
+    for a in range(w.M):
+        for c in range(w.M):
+            s = sum(X[a, k] * X[c, k] for k in range(w.D))
+            assert abs(K[a, c] - w.delta ** 2 * s ** w.zeta) <= 1e-14 * abs(w.delta ** 2)
+
+
+def check_energy_rows_zeta1(orc):
+    w, b, X = tiny_batch()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, 1, w.delta)
+    # zeta = 1: the energy row is linear, (sum_i d_i) . x_m
+    for c in range(b.n_cfg):
+        s = b.desc[b.cfg_ptr[c]:b.cfg_ptr[c + 1]].sum(axis=0)
+        assert np.allclose(K[c], w.delta ** 2 * (X @ s), rtol=1e-13, atol=1e-15)
+
+
+def check_energy_rows_zeta2(orc):
+    w, b, X = tiny_batch()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, 2, w.delta)
+    # zeta = 2: (d . x)^2 = (d (x) d) . (x (x) x)
+    for c in range(b.n_cfg):
+        s = sum(np.kron(d, d) for d in b.desc[b.cfg_ptr[c]:b.cfg_ptr[c + 1]])
+        ref = np.array([np.dot(s, np.kron(x, x)) for x in X]) * w.delta ** 2
+        assert np.allclose(K[c], ref, rtol=1e-12, atol=1e-15)
+
+
+def check_energy_rows_bruteforce(orc):
+    w, b, X = tiny_batch()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    zero = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+    for c in range(b.n_cfg):
+        for m in range(w.M):
+            ref = linearised_energy(w, b, X, c, m, zero).real
+            assert abs(K[c, m] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def check_sparse_self_entry(orc):
+    w, b, X = tiny_batch()
+    idx = synth.sparse_indices(w)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    # a one-atom configuration made of a sparse atom has energy row entry delta^2 there
+    one = np.array([0, 1], dtype=np.int64)
+    for m, i in enumerate(idx):
+        d = b.desc[i:i + 1]
+        K1 = orc.build_knm(one, d, np.array([0, 0]), np.zeros(0, np.int32),
+                           np.zeros((0, 3, w.D)), X, w.zeta, w.delta)
+        assert abs(K1[0, m] - w.delta ** 2) <= 1e-13
+        assert K1.shape == (4, w.M) and np.all(K1[1:] == 0)
+    assert K.shape == (b.n_rows, w.M)
+
+
+def check_force_rows_complex_step(orc, h=1e-30):
+    w, b, X = tiny_batch()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    for c in range(b.n_cfg):
+        for j in range(int(b.cfg_ptr[c]), int(b.cfg_ptr[c + 1])):
+            for a in range(3):
+                dr = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+                dr[j, a] = 1j * h
+                for m in range(w.M):
+                    ref = -linearised_energy(w, b, X, c, m, dr).imag / h
+                    got = K[b.n_cfg + 3 * j + a, m]
+                    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (c, j, a, m, got, ref)
+
+
+def check_force_rows_central_fd(orc, h=1e-4):
+    w, b, X = tiny_batch()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    scale = np.abs(K[b.n_cfg:]).max()
+    for c in range(b.n_cfg):
+        for j in range(int(b.cfg_ptr[c]), int(b.cfg_ptr[c + 1])):
+            for a in range(3):
+                dp = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+                dp[j, a] = h
+                for m in range(w.M):
+                    ref = -(linearised_energy(w, b, X, c, m, dp).real
+                            - linearised_energy(w, b, X, c, m, -dp).real) / (2 * h)
+                    assert abs(K[b.n_cfg + 3 * j + a, m] - ref) <= 1e-7 * scale
+
+
+def permuted_batch(b, rng):
+    """Relabel atoms inside each configuration; pairs follow their source."""
+    perm = np.empty(b.n_atoms, dtype=np.int64)          # new index of old atom
+    for c in range(b.n_cfg):
+        a0, a1 = int(b.cfg_ptr[c]), int(b.cfg_ptr[c + 1])
+        perm[a0:a1] = a0 + rng.permutation(a1 - a0)
+    inv = np.argsort(perm)                              # old atom at new index
+    cnt = np.diff(b.pair_ptr)[inv]
+    pair_ptr = np.zeros(b.n_atoms + 1, dtype=np.int64)
+    np.cumsum(cnt, out=pair_ptr[1:])
+    order = np.concatenate([np.arange(b.pair_ptr[o], b.pair_ptr[o + 1]) for o in inv])
+    return (b.desc[inv], pair_ptr, perm[b.pair_j[order]].astype(np.int32), b.jac[order], perm)
+
+
+def check_permutation(orc):
+    w, b, X = tiny_batch()
+    rng = np.random.default_rng(5)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    desc, pptr, pj, jac, perm = permuted_batch(b, rng)
+    K2 = orc.build_knm(b.cfg_ptr, desc, pptr, pj, jac, X, w.zeta, w.delta)
+    assert np.allclose(K2[:b.n_cfg], K[:b.n_cfg], rtol=1e-13, atol=1e-16)
+    rows = b.n_cfg + 3 * np.repeat(perm, 3) + np.tile(np.arange(3), b.n_atoms)
+    assert np.allclose(K2[rows], K[b.n_cfg:], rtol=1e-12, atol=1e-15)
+
+
+def check_pair_transpose(orc):
+    w, b, X = tiny_batch()
+    tptr, tpair = orc.pair_transpose(b.pair_ptr, b.pair_j, b.n_atoms)
+    for j in range(b.n_atoms):
+        brute = [p for p in range(b.n_pairs) if b.pair_j[p] == j]
+        assert list(tpair[tptr[j]:tptr[j + 1]]) == brute
+
+
+def small_fit_problem(seed=3, jitter=1e-8):
+    w, b, X = tiny_batch(TINY.with_(n_cfg=6, atoms_lo=3, atoms_hi=7, D=8, M=6), seed=seed)
+    return w, b, X, jitter
+
+
+def check_qr_vs_closed_forms(orc):
+    w, b, X, jit = small_fit_problem()
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal(b.n_rows)
+    sig = synth.sigma_rows(w, b.counts)
+    c = orc.fit(K, Kmm, y, sig, jit)
+    # eq. GP_L with jitter on K_MM, solved here by an SVD-based route
+    w2 = 1.0 / sig ** 2
+    lhs = Kmm + jit * np.eye(w.M) + K.T @ (w2[:, None] * K)
+    ref = np.linalg.pinv(lhs) @ (K.T @ (w2 * y))
+    assert np.linalg.norm(c - ref) <= 1e-8 * np.linalg.norm(ref)
+    # least squares of the stacked system by SVD (gelsd), not by QR
+    L = np.linalg.cholesky(Kmm + jit * np.eye(w.M))
+    A = np.vstack([K / sig[:, None], L.T])
+    bb = np.concatenate([y / sig, np.zeros(w.M)])
+    ref2 = np.linalg.lstsq(A, bb, rcond=None)[0]
+    assert np.linalg.norm(c - ref2) <= 1e-10 * np.linalg.norm(ref2)
+
+
+def check_full_gpr_identity(orc):
+    # energy-only observations, sparse set = every atom, no jitter:
+    # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
+    w = TINY.with_(n_cfg=5, atoms_lo=2, atoms_hi=4, D=12, zeta=2, delta=0.7)
+    b = synth.generate(w, threads=1)
+    X = b.desc.astype(np.float64)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    KE = K[:b.n_cfg]
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    sig = np.full(b.n_cfg, 0.05)
+    y = np.random.default_rng(2).standard_normal(b.n_cfg)
+    c = orc.fit(KE, Kmm, y, sig, 0.0)
+    Lhat = np.zeros((b.n_cfg, b.n_atoms))
+    for k in range(b.n_cfg):
+        Lhat[k, b.cfg_ptr[k]:b.cfg_ptr[k + 1]] = 1.0
+    Kfull = np.array([[w.delta ** 2 * np.dot(p, q) ** w.zeta for q in X] for p in X])
+    alpha = np.linalg.solve(Lhat @ Kfull @ Lhat.T + np.diag(sig ** 2), y)
+    ref = Lhat.T @ alpha
+    assert np.linalg.norm(c - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
+def check_delta_scaling(orc):
+    # K scales with delta^2; scaling Sigma and the jitter by delta^2 as well
+    # leaves the posterior mean unchanged and divides c by delta^2.
+    w, b, X, jit = small_fit_problem(seed=4)
+    y = np.random.default_rng(9).standard_normal(b.n_rows)
+    sig = synth.sigma_rows(w, b.counts)
+    out = []
+    for dl in (1.0, 2.5):
+        K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, dl)
+        Kmm = orc.build_kmm(X, w.zeta, dl)
+        out.append(orc.fit(K, Kmm, y, sig * dl, jit * dl * dl))
+    assert np.allclose(out[1] * 2.5 ** 2, out[0], rtol=1e-8, atol=1e-10)
+
+
+def check_predict_energy_and_gradient(orc, h=1e-30):
+    w, b, X = tiny_batch()
+    c = np.random.default_rng(3).standard_normal(w.M)
+    e, ecfg, g, F = orc.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, c, w.zeta, w.delta)
+    for i in range(b.n_atoms):
+        ref = sum(c[m] * w.delta ** 2 * np.dot(b.desc[i], X[m]) ** w.zeta for m in range(w.M))
+        assert abs(e[i] - ref) <= 1e-13 * max(1, abs(ref))
+        # Euler: eps is homogeneous of degree zeta in d_i
+        assert abs(np.dot(b.desc[i], g[i]) - w.zeta * e[i]) <= 1e-12 * max(1, abs(e[i]))
+        for k in range(w.D):
+            d = b.desc[i].astype(np.complex128)
+            d[k] += 1j * h
+            ref = sum(c[m] * w.delta ** 2 * np.dot(d, X[m]) ** w.zeta for m in range(w.M)).imag / h
+            assert abs(g[i, k] - ref) <= 1e-12 * max(1, abs(ref))
+    for k in range(b.n_cfg):
+        assert abs(ecfg[k] - e[b.cfg_ptr[k]:b.cfg_ptr[k + 1]].sum()) <= 1e-13 * max(1, abs(ecfg[k]))
+
+
+def check_predict_forces(orc, h=1e-30):
+    w, b, X = tiny_batch()
+    c = np.random.default_rng(4).standard_normal(w.M)
+    _, _, _, F = orc.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, c, w.zeta, w.delta)
+    for cfg in range(b.n_cfg):
+        for j in range(int(b.cfg_ptr[cfg]), int(b.cfg_ptr[cfg + 1])):
+            for a in range(3):
+                dr = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+                dr[j, a] = 1j * h
+                E = sum(c[m] * linearised_energy(w, b, X, cfg, m, dr) for m in range(w.M))
+                ref = -E.imag / h
+                assert abs(F[j, a] - ref) <= 1e-12 * max(1, abs(ref)), (j, a, F[j, a], ref)
+
+
+def check_predict_matches_knm(orc):
+    # two routes to the same observables: K_NM c and predict
+    w, b, X = tiny_batch()
+    c = np.random.default_rng(6).standard_normal(w.M)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    _, ecfg, _, F = orc.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, c, w.zeta, w.delta)
+    y = K @ c
+    assert np.allclose(y[:b.n_cfg], ecfg, rtol=1e-12, atol=1e-14)
+    assert np.allclose(y[b.n_cfg:], F.reshape(-1), rtol=1e-11, atol=1e-14)
+
+
+def check_backward(orc, h=1e-30):
+    w, b, X = tiny_batch()
+    rng = np.random.default_rng(8)
+    c = rng.standard_normal(w.M)
+    ge = rng.standard_normal(b.n_atoms)
+    dD, dc, dX = orc.predict_backward(b.desc, X, c, ge, w.zeta, w.delta)
+
+    def L(desc, X_, c_):
+        tot = 0j
+        for i in range(desc.shape[0]):
+            for m in range(X_.shape[0]):
+                tot += ge[i] * c_[m] * w.delta ** 2 * np.dot(desc[i], X_[m]) ** w.zeta
+        return tot
+
+    L0 = L(b.desc, X, c).real
+    # homogeneity: degree 1 in c, degree zeta in X and in desc
+    assert abs(np.dot(c, dc) - L0) <= 1e-12 * max(1, abs(L0))
+    assert abs(np.sum(X * dX) - w.zeta * L0) <= 1e-11 * max(1, abs(L0))
+    assert abs(np.sum(b.desc * dD) - w.zeta * L0) <= 1e-11 * max(1, abs(L0))
+    for (arr, grad) in ((b.desc, dD), (X, dX)):
+        for idx in [(0, 0), (1, 2), (arr.shape[0] - 1, arr.shape[1] - 1)]:
+            A = arr.astype(np.complex128)
+            A[idx] += 1j * h
+            ref = (L(A, X, c) if arr is b.desc else L(b.desc, A, c)).imag / h
+            assert abs(grad[idx] - ref) <= 1e-12 * max(1, abs(ref))
+    for m in range(w.M):
+        cc = c.astype(np.complex128)
+        cc[m] += 1j * h
+        ref = L(b.desc, X, cc).imag / h
+        assert abs(dc[m] - ref) <= 1e-12 * max(1, abs(ref))
+
+
+ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
+              check_energy_rows_bruteforce, check_sparse_self_entry,
+              check_force_rows_complex_step, check_force_rows_central_fd,
+              check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
+              check_full_gpr_identity, check_delta_scaling,
+              check_predict_energy_and_gradient, check_predict_forces,
+              check_predict_matches_knm, check_backward]

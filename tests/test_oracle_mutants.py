@@ -1,0 +1,123 @@
+"""Plant plausible mistakes in the oracle (CPU only) and check that a pin catches each.
+
+A pin that no mutant can trip proves nothing; these keep the pins honest.
+"""
+import numpy as np
+import pytest
+
+import pins
+from oracle import gap_oracle as G
+
+_orig_knm = G.build_knm
+_orig_grad = G.poly_kernel_grad_scale
+_orig_kernel = G.poly_kernel
+_orig_design = G.design_matrix
+_orig_predict = G.predict
+_orig_backward = G.predict_backward
+_orig_pt = G.pair_transpose
+
+
+def knm_sign_flip(*a):
+    K = _orig_knm(*a)
+    n_cfg = len(a[0]) - 1
+    K[n_cfg:] *= -1
+    return K
+
+
+def knm_drop_last_atom(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
+    K = _orig_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta)
+    for c in range(len(cfg_ptr) - 1):
+        if cfg_ptr[c + 1] - cfg_ptr[c] > 1:
+            i = cfg_ptr[c + 1] - 1
+            K[c] -= _orig_kernel(np.asarray(desc[i], float) @ np.asarray(X, float).T, zeta, delta)
+    return K
+
+
+def knm_scale_by_target(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
+    # scale pairs by the kernel gradient of the target atom instead of the source
+    swapped = G.pair_sources(pair_ptr)
+    return _orig_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta) if len(swapped) == 0 else \
+        _scale_target(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta)
+
+
+def _scale_target(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
+    n_cfg = len(cfg_ptr) - 1
+    K = _orig_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta)
+    X = np.asarray(X, float)
+    P = np.asarray(desc, float) @ X.T
+    S = _orig_grad(P, zeta, delta)
+    src = G.pair_sources(pair_ptr)
+    KF = np.zeros((int(cfg_ptr[-1]), 3, X.shape[0]))
+    for p in range(len(pair_j)):
+        KF[pair_j[p]] -= S[pair_j[p]][None, :] * (np.asarray(jac[p], float) @ X.T)
+    K[n_cfg:] = KF.reshape(-1, X.shape[0])
+    return K
+
+
+def grad_wrong_power(p, zeta, delta):
+    return delta * delta * zeta * np.asarray(p, float) ** zeta
+
+
+def kernel_delta_not_squared(p, zeta, delta):
+    return delta * np.asarray(p, float) ** zeta
+
+
+def design_b_unscaled(Knm, Kmm, y, sigma, jitter):
+    A, b = _orig_design(Knm, Kmm, y, sigma, jitter)
+    b[:len(y)] = y
+    return A, b
+
+
+def design_no_jitter(Knm, Kmm, y, sigma, jitter):
+    return _orig_design(Knm, Kmm, y, sigma, 0.0 if jitter > 0 else 1e-3)
+
+
+def predict_forces_transposed(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta):
+    e, ec, g, F = _orig_predict(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta)
+    if F is not None:
+        # accumulate on the source atom instead of the target atom
+        src = G.pair_sources(pair_ptr)
+        F2 = np.zeros_like(F)
+        for p in range(len(src)):
+            F2[src[p]] -= np.asarray(jac[p], float) @ g[src[p]]
+        F = F2
+    return e, ec, g, F
+
+
+def backward_dx_missing_c(desc, X, c, g_e, zeta, delta):
+    dD, dc, dX = _orig_backward(desc, X, c, g_e, zeta, delta)
+    return dD, dc, dX / np.asarray(c, float)[:, None]
+
+
+def pair_transpose_unstable(pair_ptr, pair_j, n_atoms):
+    tptr, tpair = _orig_pt(pair_ptr, pair_j, n_atoms)
+    for j in range(n_atoms):
+        s = slice(tptr[j], tptr[j + 1])
+        tpair[s] = tpair[s][::-1].copy()
+    return tptr, tpair
+
+
+MUTANTS = [
+    ("build_knm", knm_sign_flip),
+    ("build_knm", knm_drop_last_atom),
+    ("build_knm", knm_scale_by_target),
+    ("poly_kernel_grad_scale", grad_wrong_power),
+    ("poly_kernel", kernel_delta_not_squared),
+    ("design_matrix", design_b_unscaled),
+    ("design_matrix", design_no_jitter),
+    ("predict", predict_forces_transposed),
+    ("predict_backward", backward_dx_missing_c),
+    ("pair_transpose", pair_transpose_unstable),
+]
+
+
+@pytest.mark.parametrize("name,mutant", MUTANTS, ids=[m[1].__name__ for m in MUTANTS])
+def test_some_pin_catches_mutant(monkeypatch, name, mutant):
+    monkeypatch.setattr(G, name, mutant)
+    caught = []
+    for check in pins.ALL_CHECKS:
+        try:
+            check(G)
+        except (AssertionError, np.linalg.LinAlgError, ValueError, RuntimeError):
+            caught.append(check.__name__)
+    assert caught, f"no pin catches mutant {mutant.__name__}"
