@@ -1,0 +1,205 @@
+/*
+ * gap.h -- C ABI of the MI355X (gfx950) GAP regression hot path.
+ *
+ * Sparse Gaussian-process regression for Gaussian Approximation Potentials
+ * with the polynomial dot-product kernel k(x, x') = delta^2 (x . x')^zeta
+ * (Klawohn et al., arXiv:2310.03921, Sec. "Theory" and Sec. "Regression").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All array arguments are DEVICE pointers on the handle's device, owned by
+ *   the caller, unless a comment says "host".  The library owns only the
+ *   workspace attached to the handle (grown on demand, freed by gap_destroy).
+ * - Work is enqueued on the handle's HIP stream.  Every call is asynchronous
+ *   except gap_fit, gap_lstsq and gap_sync, which wait for the stream because
+ *   they report conditions found on the device (NOT_PD, RANK, bad indices).
+ * - Argument errors are returned before anything is enqueued; the message is
+ *   kept in the handle (gap_last_error).  Device-side index errors (a pair
+ *   target outside [0, n_atoms)) drop the offending pair and are reported as
+ *   GAP_E_INVALID by the next synchronising call.
+ * - Row-major arrays have a leading dimension ld >= the row length; every
+ *   leading dimension of a floating-point row-major array must be a multiple
+ *   of 4 elements and the base pointer 32-byte aligned (vector loads).
+ *   Elements between the row length and ld are never read.
+ * - Column-major matrices (K_MM, K_NM, the least-squares matrix) have ld >=
+ *   the number of rows.
+ * - Observation rows of K_NM: row c < n_cfg is the total energy of
+ *   configuration c; row n_cfg + 3 j + alpha is force component alpha on atom
+ *   j.  Force rows carry the minus sign of F = -dE/dr.
+ * - Only integer zeta >= 1 is supported (descriptor dot products can be
+ *   negative); anything else returns GAP_E_UNSUPPORTED.
+ */
+#ifndef GAP_H
+#define GAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GAP_OK = 0,
+  GAP_E_INVALID = -1,     /* bad argument or bad index data                 */
+  GAP_E_NOT_PD = -2,      /* K_MM + jitter I is not positive definite        */
+  GAP_E_RANK = -3,        /* R of the least-squares QR has a zero pivot      */
+  GAP_E_NOMEM = -4,       /* workspace allocation failed                     */
+  GAP_E_HIP = -5,         /* HIP runtime error                               */
+  GAP_E_UNSUPPORTED = -6  /* valid request this build does not implement     */
+} gap_status;
+
+/* Arithmetic of the descriptor / Jacobian contractions.
+ * GAP_FP64:   FP64 MFMA throughout.
+ * GAP_BF16X3: each FP32 operand x is split into hi = bf16(x), lo = bf16(x - hi);
+ *             products hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+ *             accumulation (lo*lo dropped).  Scales, reductions and outputs
+ *             stay FP64. */
+typedef enum { GAP_FP64 = 0, GAP_BF16X3 = 1 } gap_precision;
+
+typedef enum { GAP_DT_F32 = 0, GAP_DT_F64 = 1 } gap_dtype;
+
+typedef struct gap_handle gap_handle;
+
+/* A batch of atomic configurations: the descriptors x_i of every atom and the
+ * descriptor derivatives with "pointers" to the atoms they belong to
+ * (Sec. "Regression", last paragraph; Sec. "Program structure").
+ *   cfg_ptr  [n_cfg+1]   int64  atoms of configuration c: cfg_ptr[c] .. cfg_ptr[c+1]-1
+ *                               (cfg_ptr[0] = 0, cfg_ptr[n_cfg] = n_atoms, non-decreasing)
+ *   desc     [n_atoms][ld_desc]  descriptor rows, f32 or f64
+ *   pair_ptr [n_atoms+1] int64  source-major CSR of neighbour pairs (i, k):
+ *                               pairs of atom i are pair_ptr[i] .. pair_ptr[i+1]-1,
+ *                               pair_ptr[n_atoms] = n_pairs
+ *   pair_j   [n_pairs]   int32  global atom index j(i, k) the pair points at
+ *   jac      [n_pairs][3][ld_jac]  d desc_i / d r_{j(i,k), alpha}, f32 or f64
+ *                               (may be NULL when no force rows / forces are asked) */
+typedef struct {
+  int64_t n_cfg, n_atoms, n_pairs, D;
+  const int64_t *cfg_ptr;
+  const void *desc;
+  gap_dtype desc_dt;
+  int64_t ld_desc;
+  const int64_t *pair_ptr;
+  const int32_t *pair_j;
+  const void *jac;
+  gap_dtype jac_dt;
+  int64_t ld_jac;
+} gap_atoms;
+
+/* Sparse (representative) points x_m, m < M, row-major FP64 [M][ld_x],
+ * and the kernel hyperparameters: zeta (soap_exponent) and delta
+ * (energy_scale, the GP standard deviation). */
+typedef struct {
+  int64_t M, D, ld_x;
+  const double *X;
+  int zeta;
+  double delta;
+} gap_sparse;
+
+/* Host-side report of gap_fit. */
+typedef struct {
+  double resid_norm[8];  /* ||A^T (b - A c)|| after the solve and after each refinement step */
+  double min_abs_rdiag;  /* min_k |R_kk| of the QR factor */
+  double max_abs_rdiag;  /* max_k |R_kk| */
+  int refine_done;       /* refinement steps carried out */
+} gap_fit_info;
+
+/* Create a handle bound to HIP device `device` and HIP stream `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  Fails with GAP_E_HIP if
+ * the device is missing or is not gfx950. */
+gap_status gap_create(gap_handle **h, int device, void *hip_stream);
+gap_status gap_destroy(gap_handle *h);
+/* Message of the last error on this handle ("" if none).  Valid until the
+ * next call on the handle. */
+const char *gap_last_error(const gap_handle *h);
+/* Wait for the handle's stream and report deferred device-side errors. */
+gap_status gap_sync(gap_handle *h);
+
+/* Workspace bytes the handle will hold for a fit of `atoms` with `sp`
+ * (K_NM and the least-squares matrix excluded: those are caller buffers);
+ * the equivalent of a dry run (cf. the gap_fit `dryrun` argument). */
+gap_status gap_workspace_query(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                               size_t *bytes);
+
+/* Target-major view of the pair list that the operator L-hat needs to
+ * accumulate force observations (Sec. "Theory", definition of L-hat):
+ *   tgt_ptr  [n_atoms+1] int64, tgt_pair [n_pairs] int32 -- the pairs pointing
+ *   at atom j are tgt_pair[tgt_ptr[j] .. tgt_ptr[j+1]-1] in increasing pair order.
+ * Pairs whose target is out of range are left out (and reported). */
+gap_status gap_pair_transpose(gap_handle *h, const gap_atoms *atoms, int64_t *tgt_ptr,
+                              int32_t *tgt_pair);
+
+/* K_MM[m][m'] = delta^2 (x_m . x_m')^zeta, column-major M x M with leading
+ * dimension ld >= M (no jitter).  Exactly symmetric: each off-diagonal value
+ * is computed once and stored at both positions.
+ * (Sec. "Theory", definition of K_MM after eq. GP_L.) */
+gap_status gap_build_kmm(gap_handle *h, const gap_sparse *sp, double *Kmm, int64_t ld);
+
+/* L-hat K_NM, column-major, (n_cfg + 3 n_atoms) rows x M columns, ld >= rows:
+ *   energy row c:        sum_{i in c} delta^2 (d_i . x_m)^zeta
+ *   force row (j,alpha): - sum_{(i,k): j(i,k)=j} delta^2 zeta (d_i . x_m)^(zeta-1) J[(i,k),alpha] . x_m
+ * (Sec. "Theory": eq. 1, eq. epsilon, the derivative rows of K_NM.)
+ * Pairs may point at any atom of the batch.  `prec` selects the contraction
+ * arithmetic (GAP_BF16X3 requires jac_dt / desc_dt in {F32, F64}; values are
+ * rounded to FP32 before the split). */
+gap_status gap_build_knm(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                         gap_precision prec, double *Knm, int64_t ld);
+
+/* Least-squares solve of min ||A x - b|| by blocked Householder QR and back
+ * substitution, x = R^-1 (Q^T b)[0:n] (Sec. "Theory", QR route).
+ * A is column-major m x (n+1) with ld >= m, m >= n; column n holds b.
+ * A is overwritten by the Householder vectors, R and Q^T b.  x: [n].
+ * Returns GAP_E_RANK if some R_kk is zero or not finite.
+ * `rdiag_minmax` (host, may be NULL) receives min and max |R_kk|.  Synchronous. */
+gap_status gap_lstsq(gap_handle *h, double *A, int64_t ld, int64_t m, int64_t n, double *x,
+                     double *rdiag_minmax);
+
+/* Fit the sparse-GPR coefficients c (Sec. "Theory"):
+ *   A = [Sigma^-1/2 L-hat K_NM ; U_MM],  b = [Sigma^-1/2 y ; 0],
+ *   K_MM + jitter I = U^T U (upper Cholesky),  c = R^-1 Q^T b.
+ * A: column-major buffer with ld >= n_rows + M and M + 1 columns; on entry
+ *    rows [0, n_rows) of columns [0, M) hold L-hat K_NM (as written by
+ *    gap_build_knm with the same ld); the whole buffer is overwritten.
+ * Kmm [M x M] col-major (ld = M), y [n_rows], sigma [n_rows] > 0, jitter >= 0.
+ * refine_steps > 0 (requires `train`): after the solve, that many steps of
+ *    r = b - A_exact c,  R^T R dc = A_exact^T r,  c += dc
+ *    with A_exact applied matrix-free in FP64 from `train` and `sp`
+ *    (iterative refinement of the mixed-precision form; the residual is exact
+ *    FP64 so it removes the assembly error of a BF16X3 K_NM).
+ * c: [M] output.  info: host, may be NULL.  Synchronous.
+ * Returns GAP_E_NOT_PD if the Cholesky of K_MM + jitter I fails. */
+gap_status gap_fit(gap_handle *h, double *A, int64_t ld, int64_t n_rows, const double *Kmm,
+                   const double *y, const double *sigma, double jitter, const gap_atoms *train,
+                   const gap_sparse *sp, int refine_steps, double *c, gap_fit_info *info);
+
+/* Predict with coefficients c [M] (eq. epsilon and the chain rule for forces):
+ *   e_atom [n_atoms]      eps_i = sum_m c_m delta^2 (d_i . x_m)^zeta
+ *   e_cfg  [n_cfg]        sum of eps_i over the configuration
+ *   dEdd   [n_atoms][D]   g_i = d eps_i / d d_i (row-major, ld = D)
+ *   forces [n_atoms][3]   F_j = - sum_{(i,k): j(i,k)=j} J[(i,k)]^T g_i   (needs jac)
+ * All outputs FP64; any may be NULL. */
+gap_status gap_predict(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                       const double *c, gap_precision prec, double *e_atom, double *e_cfg,
+                       double *dEdd, double *forces);
+
+/* Backward of e_atom = predict(desc, X, c) for an upstream gradient g_e [n_atoms]
+ * (differentiation of eq. epsilon; (d_i . x_m)^(zeta-1) is recomputed):
+ *   d_desc [n_atoms][D] = g_e[i] g_i
+ *   d_c    [M]          = sum_i g_e[i] delta^2 (d_i . x_m)^zeta
+ *   d_X    [M][D]       = c_m sum_i g_e[i] delta^2 zeta (d_i . x_m)^(zeta-1) d_i
+ * All FP64 row-major (ld = D); any may be NULL. */
+gap_status gap_predict_backward(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                                const double *c, gap_precision prec, const double *g_e,
+                                double *d_desc, double *d_c, double *d_X);
+
+/* Forces from descriptor gradients by the chain rule (Sec. "Theory"):
+ *   forces[j][alpha] = - sum_{(i,k): j(i,k)=j} J[(i,k)][alpha] . dEdd[i]
+ * dEdd [n_atoms][D] FP64 row-major (ld = D); forces [n_atoms][3] FP64.
+ * Deterministic: per-pair contributions are summed per target in pair order. */
+gap_status gap_forces(gap_handle *h, const gap_atoms *atoms, const double *dEdd, double *forces);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAP_H */

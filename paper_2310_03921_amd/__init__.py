@@ -1,0 +1,378 @@
+"""MI355X (gfx950) GAP regression hot path: thin Python binding of libgap.
+
+Argument marshalling only: every step runs in the HIP kernels of libgap.so
+(built in-tree by ``paper_2310_03921_amd.build``).  PyTorch provides device
+memory and the stream.  There is no CPU fallback: without the library or a
+gfx950 device every call raises.
+
+Column-major matrices (K_MM, K_NM, the least-squares matrix A) are held in
+torch tensors of shape (columns, ld): element (row r, column c) is t[c, r].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgap.so")
+
+GAP_OK, GAP_E_INVALID, GAP_E_NOT_PD, GAP_E_RANK = 0, -1, -2, -3
+GAP_E_NOMEM, GAP_E_HIP, GAP_E_UNSUPPORTED = -4, -5, -6
+_STATUS = {0: "GAP_OK", -1: "GAP_E_INVALID", -2: "GAP_E_NOT_PD", -3: "GAP_E_RANK",
+           -4: "GAP_E_NOMEM", -5: "GAP_E_HIP", -6: "GAP_E_UNSUPPORTED"}
+PRECISION = {"fp64": 0, "bf16x3": 1}
+_DT = {torch.float32: 0, torch.float64: 1}
+
+
+class GapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gap_atoms(ctypes.Structure):
+    _fields_ = [("n_cfg", ctypes.c_int64), ("n_atoms", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("D", ctypes.c_int64),
+                ("cfg_ptr", ctypes.c_void_p), ("desc", ctypes.c_void_p),
+                ("desc_dt", ctypes.c_int), ("ld_desc", ctypes.c_int64),
+                ("pair_ptr", ctypes.c_void_p), ("pair_j", ctypes.c_void_p),
+                ("jac", ctypes.c_void_p), ("jac_dt", ctypes.c_int), ("ld_jac", ctypes.c_int64)]
+
+
+class gap_sparse(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("D", ctypes.c_int64), ("ld_x", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("zeta", ctypes.c_int), ("delta", ctypes.c_double)]
+
+
+class gap_fit_info(ctypes.Structure):
+    _fields_ = [("resid_norm", ctypes.c_double * 8), ("min_abs_rdiag", ctypes.c_double),
+                ("max_abs_rdiag", ctypes.c_double), ("refine_done", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgap.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2310_03921_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        S = ctypes.c_int
+        sigs = {
+            "gap_create": ([ctypes.POINTER(P), I32, P], S),
+            "gap_destroy": ([P], S),
+            "gap_last_error": ([P], ctypes.c_char_p),
+            "gap_sync": ([P], S),
+            "gap_workspace_query": ([P, P, P, ctypes.POINTER(ctypes.c_size_t)], S),
+            "gap_pair_transpose": ([P, P, P, P], S),
+            "gap_build_kmm": ([P, P, P, I64], S),
+            "gap_build_knm": ([P, P, P, I32, P, I64], S),
+            "gap_lstsq": ([P, P, I64, I64, I64, P, P], S),
+            "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
+            "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
+            "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
+            "gap_forces": ([P, P, P, P], S),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _round4(n: int) -> int:
+    return (n + 3) // 4 * 4
+
+
+def padded_rows(x: torch.Tensor, D: int, dtype=None, device=None) -> torch.Tensor:
+    """Copy a (..., D) array into a zero-padded (..., round4(D)) contiguous device tensor."""
+    x = torch.as_tensor(x)
+    dtype = dtype or x.dtype
+    out = torch.zeros(*x.shape[:-1], _round4(D), dtype=dtype, device=device)
+    out[..., :D] = x.to(device=device, dtype=dtype)
+    return out
+
+
+@dataclass
+class Atoms:
+    """Device arrays of a batch of configurations (see gap_atoms in gap.h)."""
+    cfg_ptr: torch.Tensor      # int64 [n_cfg+1]
+    desc: torch.Tensor         # f32/f64 [n_atoms, ld]
+    pair_ptr: torch.Tensor     # int64 [n_atoms+1]
+    pair_j: torch.Tensor       # int32 [n_pairs]
+    jac: torch.Tensor | None   # f32/f64 [n_pairs, 3, ld]
+    D: int
+
+    @classmethod
+    def from_host(cls, cfg_ptr, desc, pair_ptr, pair_j, jac, device="cuda", desc_dtype=None,
+                  jac_dtype=None):
+        desc = torch.as_tensor(desc)
+        D = int(desc.shape[1])
+        j = None
+        if jac is not None:
+            jt = torch.as_tensor(jac)
+            j = padded_rows(jt, D, dtype=jac_dtype or jt.dtype, device=device)
+        return cls(torch.as_tensor(cfg_ptr, dtype=torch.int64).to(device),
+                   padded_rows(desc, D, dtype=desc_dtype or desc.dtype, device=device),
+                   torch.as_tensor(pair_ptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(pair_j, dtype=torch.int32).to(device), j, D)
+
+    @property
+    def n_cfg(self):
+        return self.cfg_ptr.numel() - 1
+
+    @property
+    def n_atoms(self):
+        return self.desc.shape[0]
+
+    @property
+    def n_pairs(self):
+        return self.pair_j.numel()
+
+    @property
+    def n_rows(self):
+        return self.n_cfg + 3 * self.n_atoms
+
+    def struct(self) -> gap_atoms:
+        s = gap_atoms()
+        s.n_cfg, s.n_atoms, s.n_pairs, s.D = self.n_cfg, self.n_atoms, self.n_pairs, self.D
+        s.cfg_ptr = self.cfg_ptr.data_ptr()
+        s.desc = self.desc.data_ptr()
+        s.desc_dt = _DT[self.desc.dtype]
+        s.ld_desc = self.desc.shape[1]
+        s.pair_ptr = self.pair_ptr.data_ptr()
+        s.pair_j = self.pair_j.data_ptr() if self.n_pairs else 0
+        if self.jac is not None:
+            s.jac = self.jac.data_ptr()
+            s.jac_dt = _DT[self.jac.dtype]
+            s.ld_jac = self.jac.shape[-1]
+        else:
+            s.jac, s.jac_dt, s.ld_jac = 0, 1, _round4(self.D)
+        return s
+
+
+@dataclass
+class Sparse:
+    """Sparse points X (FP64 [M, ld]) and the kernel hyperparameters zeta, delta."""
+    X: torch.Tensor
+    D: int
+    zeta: int = 4
+    delta: float = 1.0
+
+    @classmethod
+    def from_host(cls, X, zeta=4, delta=1.0, device="cuda"):
+        X = torch.as_tensor(X, dtype=torch.float64)
+        return cls(padded_rows(X, X.shape[1], dtype=torch.float64, device=device),
+                   int(X.shape[1]), int(zeta), float(delta))
+
+    @property
+    def M(self):
+        return self.X.shape[0]
+
+    def struct(self) -> gap_sparse:
+        s = gap_sparse()
+        s.M, s.D, s.ld_x = self.M, self.D, self.X.shape[1]
+        s.X = self.X.data_ptr()
+        s.zeta, s.delta = self.zeta, self.delta
+        return s
+
+
+def colmajor(rows: int, cols: int, ld: int | None = None, device="cuda") -> torch.Tensor:
+    """A zeroed column-major FP64 buffer: tensor (cols, ld), element (r, c) at t[c, r]."""
+    ld = _round4(rows) if ld is None else ld
+    return torch.zeros(cols, ld, dtype=torch.float64, device=device)
+
+
+class Gap:
+    """A libgap handle bound to one device and the current torch stream."""
+
+    def __init__(self, device: int | None = None, stream: torch.cuda.Stream | None = None):
+        L = lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgap needs a gfx950 GPU; none is visible")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        st = L.gap_create(ctypes.byref(self._h), self.device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != GAP_OK:
+            raise GapError(st, f"gap_create failed on device {self.device}")
+
+    def close(self):
+        if self._h:
+            lib().gap_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != GAP_OK:
+            raise GapError(st, lib().gap_last_error(self._h).decode())
+
+    def sync(self):
+        self._check(lib().gap_sync(self._h))
+
+    def workspace_bytes(self, atoms: Atoms, sparse: Sparse) -> int:
+        a, s, n = atoms.struct(), sparse.struct(), ctypes.c_size_t()
+        self._check(lib().gap_workspace_query(self._h, ctypes.byref(a), ctypes.byref(s),
+                                              ctypes.byref(n)))
+        return n.value
+
+    def pair_transpose(self, atoms: Atoms):
+        a = atoms.struct()
+        dev = atoms.desc.device
+        tptr = torch.empty(atoms.n_atoms + 1, dtype=torch.int64, device=dev)
+        tpair = torch.empty(max(atoms.n_pairs, 1), dtype=torch.int32, device=dev)
+        self._check(lib().gap_pair_transpose(self._h, ctypes.byref(a), _ptr(tptr), _ptr(tpair)))
+        return tptr, tpair[:atoms.n_pairs]
+
+    def build_kmm(self, sparse: Sparse, out: torch.Tensor | None = None) -> torch.Tensor:
+        M = sparse.M
+        out = colmajor(M, M, M, sparse.X.device) if out is None else out
+        s = sparse.struct()
+        self._check(lib().gap_build_kmm(self._h, ctypes.byref(s), _ptr(out), out.shape[1]))
+        return out
+
+    def design_buffer(self, atoms: Atoms, sparse: Sparse) -> torch.Tensor:
+        """Column-major buffer sized for gap_fit: ld = round4(n_rows + M), M + 1 columns."""
+        return colmajor(atoms.n_rows + sparse.M, sparse.M + 1, device=sparse.X.device)
+
+    def build_knm(self, atoms: Atoms, sparse: Sparse, precision: str = "fp64",
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.design_buffer(atoms, sparse) if out is None else out
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_build_knm(self._h, ctypes.byref(a), ctypes.byref(s),
+                                        PRECISION[precision], _ptr(out), out.shape[1]))
+        return out
+
+    def lstsq(self, A: torch.Tensor, m: int, n: int):
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+        rd = (ctypes.c_double * 2)()
+        self._check(lib().gap_lstsq(self._h, _ptr(A), A.shape[1], m, n, _ptr(x), rd))
+        return x, (rd[0], rd[1])
+
+    def fit(self, A: torch.Tensor, n_rows: int, Kmm: torch.Tensor, y: torch.Tensor,
+            sigma: torch.Tensor, jitter: float, sparse: Sparse, train: Atoms | None = None,
+            refine_steps: int = 0):
+        c = torch.empty(sparse.M, dtype=torch.float64, device=A.device)
+        s = sparse.struct()
+        info = gap_fit_info()
+        tr = ctypes.byref(train.struct()) if train is not None else None
+        self._check(lib().gap_fit(self._h, _ptr(A), A.shape[1], n_rows, _ptr(Kmm),
+                                  _ptr(y.contiguous()), _ptr(sigma.contiguous()), float(jitter),
+                                  tr, ctypes.byref(s), int(refine_steps), _ptr(c),
+                                  ctypes.byref(info)))
+        return c, {"resid_norm": list(info.resid_norm)[:info.refine_done + 1],
+                   "min_abs_rdiag": info.min_abs_rdiag, "max_abs_rdiag": info.max_abs_rdiag,
+                   "refine_done": info.refine_done}
+
+    def predict(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, precision: str = "fp64",
+                e_atom=True, e_cfg=True, dEdd=False, forces=False):
+        dev = sparse.X.device
+        N, D = atoms.n_atoms, atoms.D
+        out = {
+            "e_atom": torch.empty(N, dtype=torch.float64, device=dev) if e_atom else None,
+            "e_cfg": torch.empty(atoms.n_cfg, dtype=torch.float64, device=dev) if e_cfg else None,
+            "dEdd": torch.empty(N, D, dtype=torch.float64, device=dev) if dEdd else None,
+            "forces": torch.empty(N, 3, dtype=torch.float64, device=dev) if forces else None,
+        }
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_predict(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
+                                      PRECISION[precision], _ptr(out["e_atom"]),
+                                      _ptr(out["e_cfg"]), _ptr(out["dEdd"]), _ptr(out["forces"])))
+        return out
+
+    def predict_backward(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, g_e: torch.Tensor,
+                         precision: str = "fp64", d_desc=True, d_c=True, d_X=True):
+        dev = sparse.X.device
+        N, M, D = atoms.n_atoms, sparse.M, atoms.D
+        dd = torch.empty(N, D, dtype=torch.float64, device=dev) if d_desc else None
+        dc = torch.empty(M, dtype=torch.float64, device=dev) if d_c else None
+        dX = torch.empty(M, D, dtype=torch.float64, device=dev) if d_X else None
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_predict_backward(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
+                                               PRECISION[precision], _ptr(g_e.contiguous()),
+                                               _ptr(dd), _ptr(dc), _ptr(dX)))
+        return dd, dc, dX
+
+    def forces(self, atoms: Atoms, dEdd: torch.Tensor) -> torch.Tensor:
+        F = torch.empty(atoms.n_atoms, 3, dtype=torch.float64, device=dEdd.device)
+        a = atoms.struct()
+        self._check(lib().gap_forces(self._h, ctypes.byref(a), _ptr(dEdd.contiguous()), _ptr(F)))
+        return F
+
+
+_default = {}
+
+
+def default_handle() -> Gap:
+    dev = torch.cuda.current_device()
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream)
+    if key not in _default:
+        _default[key] = Gap(dev)
+    return _default[key]
+
+
+class GapPredict(torch.autograd.Function):
+    """Per-atom energies eps_i = sum_m c_m delta^2 (d_i . x_m)^zeta with a hand-written backward.
+
+    forward(desc [N, D], X [M, D], c [M], cfg_ptr, zeta, delta, precision) -> e_atom [N] (FP64).
+    backward gives dE/d desc, dE/d X and dE/d c from gap_predict_backward, which
+    recomputes (d . x)^(zeta-1) instead of keeping it from the forward pass.
+    """
+
+    @staticmethod
+    def forward(ctx, desc, X, c, zeta=4, delta=1.0, precision="fp64"):
+        gap = default_handle()
+        D = desc.shape[1]
+        dev = desc.device
+        desc_p = desc if (D % 4 == 0 and desc.is_contiguous()) else padded_rows(desc.detach(), D, device=dev)
+        atoms = Atoms(torch.tensor([0, desc.shape[0]], dtype=torch.int64, device=dev), desc_p.detach(),
+                      torch.zeros(desc.shape[0] + 1, dtype=torch.int64, device=dev),
+                      torch.zeros(0, dtype=torch.int32, device=dev), None, D)
+        sp = Sparse(padded_rows(X.detach(), D, dtype=torch.float64, device=dev), D, int(zeta),
+                    float(delta))
+        c64 = c.detach().to(torch.float64).contiguous()
+        out = gap.predict(atoms, sp, c64, precision, e_atom=True, e_cfg=False)["e_atom"]
+        ctx.save_for_backward(desc, X, c)
+        ctx.meta = (int(zeta), float(delta), precision)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_e):
+        desc, X, c = ctx.saved_tensors
+        zeta, delta, precision = ctx.meta
+        gap = default_handle()
+        D = desc.shape[1]
+        dev = desc.device
+        desc_p = desc if (D % 4 == 0 and desc.is_contiguous()) else padded_rows(desc.detach(), D, device=dev)
+        atoms = Atoms(torch.tensor([0, desc.shape[0]], dtype=torch.int64, device=dev), desc_p.detach(),
+                      torch.zeros(desc.shape[0] + 1, dtype=torch.int64, device=dev),
+                      torch.zeros(0, dtype=torch.int32, device=dev), None, D)
+        sp = Sparse(padded_rows(X.detach(), D, dtype=torch.float64, device=dev), D, zeta, delta)
+        dd, dc, dX = gap.predict_backward(atoms, sp, c.detach().to(torch.float64).contiguous(),
+                                          g_e.detach().to(torch.float64).contiguous(), precision,
+                                          ctx.needs_input_grad[0], ctx.needs_input_grad[2],
+                                          ctx.needs_input_grad[1])
+        return (dd.to(desc.dtype) if dd is not None else None,
+                dX.to(X.dtype) if dX is not None else None,
+                dc.to(c.dtype) if dc is not None else None, None, None, None)
+
+
+def gap_energy(desc, X, c, zeta=4, delta=1.0, precision="fp64"):
+    """Differentiable per-atom GAP energies (see GapPredict)."""
+    return GapPredict.apply(desc, X, c, zeta, delta, precision)

@@ -1,0 +1,581 @@
+// C ABI of libgap: argument checks, workspace, and the order of kernel launches
+// for each verb.  Every numerical step runs in the gfx950 kernels; this file
+// only validates, lays out device workspace and enqueues.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/gap.h"
+#include "launch.h"
+
+struct gap_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* dev_err = nullptr;     // device status word
+  double* dev_small = nullptr; // 64 doubles of small device scratch
+};
+
+namespace {
+
+gap_status fail(gap_handle* h, gap_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  return s;
+}
+
+#define HIP_TRY(h, expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((h), GAP_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+bool aligned32(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 31u) == 0; }
+
+// Bump layout of the handle's device workspace (256-byte aligned slices).
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+gap_status ensure_ws(gap_handle* h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return GAP_OK;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (h->ws) HIP_TRY(h, hipFree(h->ws));
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+  const size_t want = bytes + bytes / 8;
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    h->ws = nullptr;
+    return fail(h, GAP_E_NOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  h->ws_bytes = want;
+  return GAP_OK;
+}
+
+template <typename T>
+T* at(gap_handle* h, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(h->ws) + off);
+}
+
+gap_status set_device(gap_handle* h) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  return GAP_OK;
+}
+
+gap_status check_sparse(gap_handle* h, const gap_sparse* sp) {
+  if (!sp) return fail(h, GAP_E_INVALID, "sparse points are NULL");
+  if (sp->M < 1 || sp->D < 1) return fail(h, GAP_E_INVALID, "M and D must be >= 1");
+  if (!sp->X) return fail(h, GAP_E_INVALID, "X is NULL");
+  if (sp->ld_x < sp->D || sp->ld_x % 4 != 0)
+    return fail(h, GAP_E_INVALID, "ld_x must be >= D and a multiple of 4");
+  if (!aligned32(sp->X)) return fail(h, GAP_E_INVALID, "X must be 32-byte aligned");
+  if (sp->zeta < 1 || sp->zeta > 64)
+    return fail(h, GAP_E_UNSUPPORTED, "zeta must be an integer in [1, 64]");
+  if (!std::isfinite(sp->delta)) return fail(h, GAP_E_INVALID, "delta must be finite");
+  return GAP_OK;
+}
+
+gap_status check_atoms(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, bool need_jac) {
+  if (!a) return fail(h, GAP_E_INVALID, "atoms are NULL");
+  if (a->n_cfg < 0 || a->n_atoms < 0 || a->n_pairs < 0)
+    return fail(h, GAP_E_INVALID, "negative sizes");
+  if (a->n_pairs > INT32_MAX || a->n_atoms > INT32_MAX)
+    return fail(h, GAP_E_INVALID, "n_atoms and n_pairs must fit in int32");
+  if (sp && a->D != sp->D) return fail(h, GAP_E_INVALID, "atoms.D != sparse.D");
+  if (a->n_atoms > 0) {
+    if (!a->desc) return fail(h, GAP_E_INVALID, "desc is NULL");
+    if (a->desc_dt != GAP_DT_F32 && a->desc_dt != GAP_DT_F64)
+      return fail(h, GAP_E_INVALID, "bad desc dtype");
+    if (a->ld_desc < a->D || a->ld_desc % 4 != 0)
+      return fail(h, GAP_E_INVALID, "ld_desc must be >= D and a multiple of 4");
+    if (!aligned32(a->desc)) return fail(h, GAP_E_INVALID, "desc must be 32-byte aligned");
+  }
+  if (!a->cfg_ptr && a->n_cfg > 0) return fail(h, GAP_E_INVALID, "cfg_ptr is NULL");
+  if (need_jac) {
+    if (!a->pair_ptr || (a->n_pairs > 0 && !a->pair_j))
+      return fail(h, GAP_E_INVALID, "pair_ptr / pair_j are NULL");
+    if (a->n_pairs > 0) {
+      if (!a->jac) return fail(h, GAP_E_INVALID, "jac is NULL");
+      if (a->jac_dt != GAP_DT_F32 && a->jac_dt != GAP_DT_F64)
+        return fail(h, GAP_E_INVALID, "bad jac dtype");
+      if (a->ld_jac < a->D || a->ld_jac % 4 != 0)
+        return fail(h, GAP_E_INVALID, "ld_jac must be >= D and a multiple of 4");
+      if (!aligned32(a->jac)) return fail(h, GAP_E_INVALID, "jac must be 32-byte aligned");
+    }
+  }
+  return GAP_OK;
+}
+
+gap_status drain_dev_err(gap_handle* h) {
+  int v = 0;
+  HIP_TRY(h, hipMemcpyAsync(&v, h->dev_err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (v != 0) {
+    int zero = 0;
+    HIP_TRY(h, hipMemcpy(h->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
+  if (v & GAP_DEVERR_NOT_PD)
+    return fail(h, GAP_E_NOT_PD, "K_MM + jitter I is not positive definite (Cholesky pivot <= 0)");
+  if (v & GAP_DEVERR_RANK)
+    return fail(h, GAP_E_RANK, "least-squares matrix is rank deficient (zero pivot in R)");
+  if (v & GAP_DEVERR_INDEX)
+    return fail(h, GAP_E_INVALID, "index data out of range (pair target or pair_ptr)");
+  return GAP_OK;
+}
+
+// Workspace slices of the pair transposition.
+struct PairWs {
+  size_t tgt_ptr, tgt_pair, src, order, scratch;
+};
+void layout_pairs(Layout& L, int64_t n_atoms, int64_t n_pairs, PairWs& p) {
+  p.tgt_ptr = L.take(sizeof(int64_t) * (n_atoms + 1));
+  p.tgt_pair = L.take(sizeof(int32_t) * std::max<int64_t>(n_pairs, 1));
+  p.src = L.take(sizeof(int32_t) * std::max<int64_t>(n_pairs, 1));
+  p.order = L.take(sizeof(int32_t) * std::max<int64_t>(n_atoms, 1));
+  p.scratch = L.take(sizeof(int32_t) * (n_atoms + 2048));
+}
+
+void run_pairs(gap_handle* h, const gap_atoms* a, const PairWs& p, bool want_order) {
+  gapk::pair_transpose(a->pair_ptr, a->pair_j, a->n_atoms, a->n_pairs, at<int64_t>(h, p.tgt_ptr),
+                       at<int32_t>(h, p.tgt_pair), at<int32_t>(h, p.src),
+                       want_order ? at<int32_t>(h, p.order) : nullptr, at<int32_t>(h, p.scratch),
+                       h->dev_err, h->stream);
+}
+
+bool f32(gap_dtype d) { return d == GAP_DT_F32; }
+
+// Row strides of internal FP64 row-major buffers: a multiple of 4 doubles so
+// that every row starts 32-byte aligned (vector loads).
+int64_t ld4(int64_t n) { return (n + 3) & ~int64_t(3); }
+
+// Predict internals shared by gap_predict and the refinement residual.
+struct PredictWs {
+  size_t W, e_atom, g, f_pair;
+  PairWs pairs;
+};
+void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool need_g,
+                    bool need_eatom, bool need_gbuf, bool need_forces, PredictWs& w) {
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  w.W = need_g ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1)) : 0;
+  w.e_atom = need_eatom ? L.take(sizeof(double) * std::max<int64_t>(N, 1)) : 0;
+  w.g = need_gbuf ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1)) : 0;
+  w.f_pair = need_forces ? L.take(sizeof(double) * std::max<int64_t>(3 * a->n_pairs, 1)) : 0;
+  if (need_forces) layout_pairs(L, N, a->n_pairs, w.pairs);
+}
+
+void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
+                 const PredictWs& w, double* e_atom, double* e_cfg, double* dEdd,
+                 double* forces) {
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  const bool need_g = dEdd || forces;
+  double* ea = e_atom ? e_atom : (e_cfg ? at<double>(h, w.e_atom) : nullptr);
+  double* W = need_g ? at<double>(h, w.W) : nullptr;
+  const int64_t ldw = ld4(M);
+  gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                   sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream);
+  if (e_cfg) gapk::segment_sum_f64(ea, a->cfg_ptr, a->n_cfg, N, e_cfg, h->stream);
+  if (forces) {
+    double* g = at<double>(h, w.g);
+    const int64_t ldg = ld4(D);
+    gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, g, ldg, h->stream);
+    if (dEdd) gapk::copy_rows_f64(g, ldg, dEdd, D, N, D, h->stream);
+    run_pairs(h, a, w.pairs, false);
+    gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg, at<int32_t>(h, w.pairs.src), N,
+                     a->n_pairs, at<int64_t>(h, w.pairs.tgt_ptr),
+                     at<int32_t>(h, w.pairs.tgt_pair), at<double>(h, w.f_pair), forces,
+                     h->stream);
+  } else if (dEdd) {
+    gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, dEdd, D, h->stream);
+  }
+}
+
+gap_status check_gfx950(gap_handle* h) {
+  hipDeviceProp_t prop;
+  HIP_TRY(h, hipGetDeviceProperties(&prop, h->device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(h, GAP_E_HIP, "device %d is %s, this library is built for gfx950", h->device,
+                prop.gcnArchName);
+  return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status gap_create(gap_handle** out, int device, void* hip_stream) {
+  if (!out) return GAP_E_INVALID;
+  *out = nullptr;
+  gap_handle* h = new gap_handle();
+  h->device = device;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    delete h;
+    return GAP_E_HIP;
+  }
+  if (hipSetDevice(device) != hipSuccess || check_gfx950(h) != GAP_OK) {
+    delete h;
+    return GAP_E_HIP;
+  }
+  if (hipMalloc(&h->dev_err, 256) != hipSuccess) {
+    delete h;
+    return GAP_E_NOMEM;
+  }
+  if (hipMalloc(&h->dev_small, 64 * sizeof(double)) != hipSuccess) {
+    (void)hipFree(h->dev_err);
+    delete h;
+    return GAP_E_NOMEM;
+  }
+  int zero = 0;
+  if (hipMemcpy(h->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(h->dev_err);
+    (void)hipFree(h->dev_small);
+    delete h;
+    return GAP_E_HIP;
+  }
+  *out = h;
+  return GAP_OK;
+}
+
+gap_status gap_destroy(gap_handle* h) {
+  if (!h) return GAP_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->dev_err) (void)hipFree(h->dev_err);
+  if (h->dev_small) (void)hipFree(h->dev_small);
+  delete h;
+  return GAP_OK;
+}
+
+const char* gap_last_error(const gap_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+gap_status gap_sync(gap_handle* h) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  return drain_dev_err(h);
+}
+
+gap_status gap_workspace_query(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                               size_t* bytes) {
+  if (!h || !bytes) return GAP_E_INVALID;
+  gap_status s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, false);
+  if (s != GAP_OK) return s;
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  const int64_t n_rows = a->n_cfg + 3 * N;
+  Layout L;
+  PairWs p;
+  layout_pairs(L, N, a->n_pairs, p);
+  L.take(sizeof(double) * N * M);  // S
+  size_t knm = L.off;
+  Layout F;
+  F.take(sizeof(double) * M * M);
+  F.take(gapk::qr_workspace_bytes(n_rows + M, M));
+  PredictWs pw;
+  layout_predict(F, a, sp, true, true, true, true, pw);
+  F.take(sizeof(double) * (3 * n_rows + 4 * M + 2 * N + N * D));
+  *bytes = std::max(knm, F.off);
+  return GAP_OK;
+}
+
+gap_status gap_pair_transpose(gap_handle* h, const gap_atoms* a, int64_t* tgt_ptr,
+                              int32_t* tgt_pair) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  if (!a || !a->pair_ptr || (a->n_pairs > 0 && !a->pair_j) || !tgt_ptr ||
+      (a->n_pairs > 0 && !tgt_pair))
+    return fail(h, GAP_E_INVALID, "NULL argument");
+  if (a->n_atoms < 0 || a->n_pairs < 0 || a->n_pairs > INT32_MAX || a->n_atoms > INT32_MAX)
+    return fail(h, GAP_E_INVALID, "bad sizes");
+  Layout L;
+  const size_t src = L.take(sizeof(int32_t) * std::max<int64_t>(a->n_pairs, 1));
+  const size_t scr = L.take(sizeof(int32_t) * (a->n_atoms + 2048));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::pair_transpose(a->pair_ptr, a->pair_j, a->n_atoms, a->n_pairs, tgt_ptr, tgt_pair,
+                       at<int32_t>(h, src), nullptr, at<int32_t>(h, scr), h->dev_err, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_build_kmm(gap_handle* h, const gap_sparse* sp, double* Kmm, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  if (!Kmm || ld < sp->M) return fail(h, GAP_E_INVALID, "Kmm NULL or ld < M");
+  gapk::kmm_f64(sp->X, sp->ld_x, sp->M, sp->D, sp->zeta, sp->delta, Kmm, ld, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                         gap_precision prec, double* Knm, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, true);
+  if (s != GAP_OK) return s;
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  const int64_t n_rows = a->n_cfg + 3 * N;
+  if (!Knm || ld < n_rows) return fail(h, GAP_E_INVALID, "Knm NULL or ld < n_cfg + 3 n_atoms");
+  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  Layout L;
+  PairWs p;
+  layout_pairs(L, N, a->n_pairs, p);
+  const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * M, 1));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  run_pairs(h, a, p, true);
+  gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N, sp->X,
+                        sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), M,
+                        h->stream);
+  gapk::force_rows_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, sp->X, sp->ld_x, M,
+                       at<double>(h, S), M, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+                       at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
+                       h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n, double* x,
+                     double* rdiag_minmax) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  if (!A || !x || n < 1 || m < n || ld < m || ld % 4 != 0 || !aligned32(A))
+    return fail(h, GAP_E_INVALID, "need A, x, 1 <= n <= m <= ld, ld % 4 == 0, A 32-byte aligned");
+  if (n > 8000) return fail(h, GAP_E_UNSUPPORTED, "n > 8000");
+  Layout L;
+  const size_t q = L.take(gapk::qr_workspace_bytes(m, n));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::QrWork qw;
+  gapk::qr_bind_workspace(at<char>(h, q), m, n, &qw);
+  gapk::qr_factor(A, ld, m, n + 1, n, &qw, h->stream);
+  gapk::back_substitute(A, ld, n, A + n * ld, x, h->dev_small, h->dev_err, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  double rd[2] = {0, 0};
+  HIP_TRY(h, hipMemcpyAsync(rd, h->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  s = drain_dev_err(h);
+  if (rdiag_minmax) {
+    rdiag_minmax[0] = rd[0];
+    rdiag_minmax[1] = rd[1];
+  }
+  return s;
+}
+
+gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const double* Kmm,
+                   const double* y, const double* sigma, double jitter, const gap_atoms* train,
+                   const gap_sparse* sp, int refine_steps, double* c, gap_fit_info* info) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  const int64_t M = sp->M, D = sp->D;
+  const int64_t m = n_rows + M;
+  if (!A || !Kmm || !y || !sigma || !c) return fail(h, GAP_E_INVALID, "NULL argument");
+  if (n_rows < 0 || ld < m || ld % 4 != 0 || !aligned32(A))
+    return fail(h, GAP_E_INVALID, "A needs ld >= n_rows + M, ld % 4 == 0, 32-byte alignment");
+  if (!(jitter >= 0.0) || !std::isfinite(jitter)) return fail(h, GAP_E_INVALID, "bad jitter");
+  if (M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
+  if (refine_steps < 0 || refine_steps > 7) return fail(h, GAP_E_INVALID, "refine_steps in [0,7]");
+  if (refine_steps > 0) {
+    s = check_atoms(h, train, sp, true);
+    if (s != GAP_OK) return s;
+    if (train->n_cfg + 3 * train->n_atoms != n_rows)
+      return fail(h, GAP_E_INVALID, "train does not match n_rows");
+    if (D > 2048) return fail(h, GAP_E_UNSUPPORTED, "refinement needs D <= 2048");
+  }
+  Layout L;
+  const size_t Lw = L.take(sizeof(double) * M * M);
+  const size_t q = L.take(gapk::qr_workspace_bytes(m, M));
+  size_t kc = 0, rtop = 0, rbot = 0, v = 0, hbuf = 0, ge = 0, gvec = 0, dcp = 0, acfg = 0;
+  PredictWs pw{};
+  if (refine_steps > 0) {
+    const int64_t N = train->n_atoms;
+    kc = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+    rtop = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+    rbot = L.take(sizeof(double) * M);
+    v = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+    hbuf = L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1));
+    ge = L.take(sizeof(double) * std::max<int64_t>(N, 1));
+    gvec = L.take(sizeof(double) * M);
+    dcp = L.take(sizeof(double) * gapk::pstage_row_blocks(N) * M + 8);
+    acfg = L.take(sizeof(int32_t) * std::max<int64_t>(N, 1));
+    layout_predict(L, train, sp, true, true, true, true, pw);
+  }
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::QrWork qw;
+  gapk::qr_bind_workspace(at<char>(h, q), m, M, &qw);
+  double* Lm = at<double>(h, Lw);
+  gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->stream);
+  gapk::scale_stack(A, ld, n_rows, M, y, sigma, Lm, M, h->stream);
+  gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream);
+  gapk::back_substitute(A, ld, M, A + M * ld, c, h->dev_small, h->dev_err, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  gap_fit_info inf;
+  std::memset(&inf, 0, sizeof inf);
+  for (double& r : inf.resid_norm) r = NAN;
+  double rd[2];
+  HIP_TRY(h, hipMemcpyAsync(rd, h->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  s = drain_dev_err(h);
+  inf.min_abs_rdiag = rd[0];
+  inf.max_abs_rdiag = rd[1];
+  if (s != GAP_OK) {
+    if (info) *info = inf;
+    return s;
+  }
+  if (refine_steps > 0) {
+    const gap_atoms* a = train;
+    const int64_t N = a->n_atoms;
+    gapk::atom_config(a->cfg_ptr, a->n_cfg, N, at<int32_t>(h, acfg), h->stream);
+    for (int step = 0; step <= refine_steps; ++step) {
+      // r = b - A_exact c, matrix-free in FP64: K c = [E_cfg ; F] from predict.
+      double* kcp = at<double>(h, kc);
+      run_predict(h, a, sp, c, pw, nullptr, kcp, nullptr, kcp + a->n_cfg);
+      gapk::refine_residual(y, sigma, kcp, n_rows, Lm, M, M, c, at<double>(h, rtop),
+                            at<double>(h, rbot), h->stream);
+      // A^T r = K^T (r_top / sigma) + U^T r_bot
+      gapk::div_sigma(at<double>(h, rtop), sigma, n_rows, at<double>(h, v), h->stream);
+      gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
+                                    N, a->n_pairs, at<double>(h, v) + a->n_cfg,
+                                    at<double>(h, hbuf), ld4(D), h->stream);
+      gapk::expand_cfg(at<double>(h, v), at<int32_t>(h, acfg), N, at<double>(h, ge), h->stream);
+      gapk::pstage_f64(2, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D,
+                       sp->zeta, sp->delta, nullptr, at<double>(h, ge), at<double>(h, hbuf),
+                       ld4(D), nullptr, 0, nullptr, at<double>(h, dcp), h->stream);
+      gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M,
+                            at<double>(h, gvec), h->stream);
+      gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), at<double>(h, gvec), h->stream);
+      gapk::norm2_f64(at<double>(h, gvec), M, h->dev_small + 8 + step, h->stream);
+      if (step == refine_steps) break;
+      // R^T R dc = A^T r ; c += dc
+      gapk::seminormal_solve(A, ld, M, at<double>(h, gvec), h->stream);
+      gapk::axpy_f64(M, 1.0, at<double>(h, gvec), c, h->stream);
+    }
+    HIP_TRY(h, hipGetLastError());
+    double rn[8];
+    HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, (refine_steps + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    s = drain_dev_err(h);
+    for (int i = 0; i <= refine_steps && i < 8; ++i) inf.resid_norm[i] = rn[i];
+    inf.refine_done = refine_steps;
+  }
+  if (info) *info = inf;
+  return s;
+}
+
+gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
+                       gap_precision prec, double* e_atom, double* e_cfg, double* dEdd,
+                       double* forces) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, forces != nullptr);
+  if (s != GAP_OK) return s;
+  if (!c) return fail(h, GAP_E_INVALID, "c is NULL");
+  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  Layout L;
+  PredictWs pw;
+  layout_predict(L, a, sp, dEdd || forces, e_cfg && !e_atom, forces != nullptr, forces != nullptr,
+                 pw);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                                const double* c, gap_precision prec, const double* g_e,
+                                double* d_desc, double* d_c, double* d_X) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, false);
+  if (s != GAP_OK) return s;
+  if (!c || !g_e) return fail(h, GAP_E_INVALID, "c or g_e is NULL");
+  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  Layout L;
+  const bool needW = d_desc || d_X;
+  const int64_t ldw = ld4(M);
+  const size_t W = needW ? L.take(sizeof(double) * std::max<int64_t>(N * ldw, 1)) : 0;
+  const size_t dcp = L.take(sizeof(double) * (gapk::pstage_row_blocks(N) * M + 8));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  double* Wp = needW ? at<double>(h, W) : nullptr;
+  gapk::pstage_f64(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                   sp->delta, c, g_e, nullptr, 0, Wp, ldw, nullptr, at<double>(h, dcp), h->stream);
+  if (d_c) gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, d_c, h->stream);
+  if (d_desc) gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
+  if (d_X)
+    gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_forces(gap_handle* h, const gap_atoms* a, const double* dEdd, double* forces) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, nullptr, true);
+  if (s != GAP_OK) return s;
+  if (!dEdd || !forces) return fail(h, GAP_E_INVALID, "dEdd or forces is NULL");
+  const bool direct = aligned32(dEdd) && a->D % 4 == 0;
+  Layout L;
+  PairWs p;
+  layout_pairs(L, a->n_atoms, a->n_pairs, p);
+  const size_t fp = L.take(sizeof(double) * std::max<int64_t>(3 * a->n_pairs, 1));
+  const size_t gp = direct ? 0 : L.take(sizeof(double) * std::max<int64_t>(a->n_atoms * ld4(a->D), 1));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  const double* g = dEdd;
+  int64_t ldg = a->D;
+  if (!direct) {
+    ldg = ld4(a->D);
+    gapk::copy_rows_f64(dEdd, a->D, at<double>(h, gp), ldg, a->n_atoms, a->D, h->stream);
+    g = at<double>(h, gp);
+  }
+  run_pairs(h, a, p, false);
+  gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, a->D, g, ldg, at<int32_t>(h, p.src),
+                   a->n_atoms, a->n_pairs, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+                   at<double>(h, fp), forces, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+}  // extern "C"

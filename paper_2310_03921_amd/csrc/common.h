@@ -1,0 +1,96 @@
+// Device-side building blocks shared by the gfx950 kernels of libgap.
+//
+// FP64 matrix cores: v_mfma_f64_16x16x4_f64 computes D = A(16x4) B(4x16) + C.
+// Operand layout of one 64-lane wavefront (lane l, group g = l / 16, idx = l % 16):
+//   A: lane holds A[idx][g]        B: lane holds B[g][idx]
+//   C/D: lane holds D[4 g + r][idx] for r = 0..3 (four doubles)
+// Contraction order is free, so over a block of 16 k values the kernels let
+// lane group g own k = k0 + 4 g + s for MFMA step s = 0..3.  A lane then
+// reads four consecutive k of one row (one 32-byte load) when the operand is
+// contiguous along k, or one element per step, coalesced across the 16 lanes
+// of its group, when the operand is contiguous along the other index.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+#define GAP_DEV __device__ __forceinline__
+
+GAP_DEV d4v mfma_f64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+GAP_DEV d4v zero4() { d4v z = {0.0, 0.0, 0.0, 0.0}; return z; }
+
+// x^n for a small integer n >= 0 by repeated squaring (the dot-product kernel
+// exponent is an integer; p may be negative).
+GAP_DEV double ipow(double x, int n) {
+  double r = 1.0;
+  double b = x;
+  while (n > 0) {
+    if (n & 1) r *= b;
+    b *= b;
+    n >>= 1;
+  }
+  return r;
+}
+
+// Four consecutive elements row[k .. k+3] (k % 4 == 0) as doubles, elements
+// at or beyond kmax set to zero.  The row's storage must extend to k + 3
+// whenever k < kmax (leading dimensions are multiples of 4).
+GAP_DEV void load4(const double* __restrict__ row, int64_t k, int64_t kmax, double out[4]) {
+  if (k + 3 < kmax) {
+    d4v v = *reinterpret_cast<const d4v*>(row + k);
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+  } else if (k < kmax) {
+    d4v v = *reinterpret_cast<const d4v*>(row + k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] = (k + s < kmax) ? v[s] : 0.0;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] = 0.0;
+  }
+}
+
+GAP_DEV void load4(const float* __restrict__ row, int64_t k, int64_t kmax, double out[4]) {
+  if (k < kmax) {
+    f4v v = *reinterpret_cast<const f4v*>(row + k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] = (k + s < kmax) ? (double)v[s] : 0.0;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] = 0.0;
+  }
+}
+
+GAP_DEV void zero_frag(double out[4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) out[s] = 0.0;
+}
+
+// Block-to-tile mapping that keeps consecutive logical tiles on one XCD.
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
+// logical = (b % 8) * per_xcd + b / 8 makes the blocks an XCD runs back to
+// back consecutive logical tiles, so tiles that share operands share that
+// XCD's L2.  The grid must be 8 * per_xcd; logical >= total exits.
+GAP_DEV int64_t xcd_logical_block(int64_t per_xcd) {
+  const int64_t b = blockIdx.x;
+  return (b & 7) * per_xcd + (b >> 3);
+}
+
+GAP_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+GAP_DEV int wave_max16(int v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+

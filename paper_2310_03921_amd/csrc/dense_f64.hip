@@ -1,0 +1,398 @@
+// Dense FP64 contractions of the polynomial dot-product kernel on gfx950 MFMA:
+//   K_MM = delta^2 (X X^T)^zeta                         (covariance of sparse points)
+//   energy rows of L-hat K_NM and the kernel-gradient scale S used by force rows
+//   predict / backward P-stage (P = D X^T recomputed, never stored)
+//   the two follow-up GEMMs W X and W^T D.
+// Polynomial dot-product kernel: Sec. "Regression"; energy rows: eq. 1 summed
+// by L-hat over a configuration (Sec. "Theory"); predict: eq. epsilon.
+#include <algorithm>
+
+#include "launch.h"
+#include "mma_f64.h"
+
+namespace gapk {
+
+namespace {
+
+constexpr int kNC = 4;  // 16-column tiles per wave
+
+template <typename T>
+inline const T* tptr(const void* p) {
+  return reinterpret_cast<const T*>(p);
+}
+
+// ---------------------------------------------------------------- K_MM ----
+// Block (bi, bj) with bi <= bj computes the 64 x 64 tile of X X^T; every value
+// with row <= col is written to (row, col) and (col, row), so K_MM is exactly
+// symmetric whatever the summation order inside the matrix core.
+__global__ __launch_bounds__(256) void k_kmm(const double* __restrict__ X, int64_t ldx, int64_t M,
+                                             int64_t D, int zeta, double delta,
+                                             double* __restrict__ K, int64_t ldk) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t row = (int64_t)bi * 64 + wave * 16 + idx;
+  FragRowK<double> fa{X + (row < M ? row : 0) * ldx, D, row < M};
+  FragRowK<double> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = (int64_t)bj * 64 + u * 16 + idx;
+    fb[u] = FragRowK<double>{X + (col < M ? col : 0) * ldx, D, col < M};
+  }
+  d4v acc[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+  wave_mma<kNC>(fa, fb, D, g, acc);
+  const double d2 = delta * delta;
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = (int64_t)bj * 64 + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = (int64_t)bi * 64 + wave * 16 + 4 * g + r;
+      if (rr < M && col < M && rr <= col) {
+        const double v = d2 * ipow(acc[u][r], zeta);
+        K[rr + col * ldk] = v;
+        K[col + rr * ldk] = v;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- energy rows ----
+// Block (column tile ct, configuration c): the four waves own disjoint 64-column
+// ranges and walk the configuration's atoms 16 at a time.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc, int64_t ldd,
+                                                     const int64_t* __restrict__ cfg_ptr,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     int64_t M, int64_t D, int zeta, double delta,
+                                                     double* __restrict__ K, int64_t ldk,
+                                                     double* __restrict__ S, int64_t ldS,
+                                                     int64_t n_atoms) {
+  const int64_t c = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = (int64_t)blockIdx.x * 256 + wave * 64;
+  if (colbase >= M) return;
+  // clamp to [0, n_atoms] so malformed cfg_ptr data cannot address outside desc / S
+  const int64_t a0 = max((int64_t)0, min(cfg_ptr[c], n_atoms));
+  const int64_t a1 = max(a0, min(cfg_ptr[c + 1], n_atoms));
+  FragRowK<double> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = FragRowK<double>{X + (col < M ? col : 0) * ldx, D, col < M};
+  }
+  const double d2 = delta * delta, d2z = d2 * zeta;
+  double e[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) e[u] = 0.0;
+  for (int64_t a = a0; a < a1; a += 16) {
+    const int64_t row = a + idx;
+    FragRowK<TD> fa{desc + (row < a1 ? row : a0) * ldd, D, row < a1};
+    d4v acc[kNC];
+#pragma unroll
+    for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+    wave_mma<kNC>(fa, fb, D, g, acc);
+#pragma unroll
+    for (int u = 0; u < kNC; ++u) {
+      const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = a + 4 * g + r;
+        if (rr < a1) {
+          const double p = acc[u][r];
+          const double pz1 = ipow(p, zeta - 1);
+          e[u] += d2 * pz1 * p;
+          if (col < M) S[rr * ldS + col] = d2z * pz1;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    double v = e[u];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    const int64_t col = colbase + u * 16 + idx;
+    if (g == 0 && col < M) K[c + col * ldk] = v;
+  }
+}
+
+// ------------------------------------------------------------- P-stage ----
+// Block = 64 rows (16 per wave); loops over all columns 64 at a time.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__ desc, int64_t ldd,
+                                                int64_t n, const double* __restrict__ X,
+                                                int64_t ldx, int64_t M, int64_t D, int zeta,
+                                                double delta, const double* __restrict__ cc,
+                                                const double* __restrict__ g_e,
+                                                const double* __restrict__ H, int64_t ldh,
+                                                double* __restrict__ W, int64_t ldw,
+                                                double* __restrict__ e_atom,
+                                                double* __restrict__ dc_part) {
+  __shared__ double colsum[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const bool rvalid = row < n;
+  FragRowK<TD> fa{desc + (rvalid ? row : 0) * ldd, D, rvalid};
+  FragRowK<double> fh{H ? H + (rvalid ? row : 0) * ldh : nullptr, D, rvalid && H != nullptr};
+  const double d2 = delta * delta, d2z = d2 * zeta;
+  double ge[4];
+  bool rv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t rr = rowbase + 4 * g + r;
+    rv[r] = rr < n;
+    ge[r] = (mode != 0 && rv[r]) ? g_e[rr] : 0.0;
+  }
+  double esum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t col0 = 0; col0 < M; col0 += 16 * kNC) {
+    FragRowK<double> fb[kNC];
+#pragma unroll
+    for (int u = 0; u < kNC; ++u) {
+      const int64_t col = col0 + u * 16 + idx;
+      fb[u] = FragRowK<double>{X + (col < M ? col : 0) * ldx, D, col < M};
+    }
+    d4v acc[kNC], accq[kNC];
+#pragma unroll
+    for (int u = 0; u < kNC; ++u) {
+      acc[u] = zero4();
+      accq[u] = zero4();
+    }
+    if (mode == 2)
+      wave_mma2<kNC>(fa, fh, fb, D, g, acc, accq);
+    else
+      wave_mma<kNC>(fa, fb, D, g, acc);
+#pragma unroll
+    for (int u = 0; u < kNC; ++u) {
+      const int64_t col = col0 + u * 16 + idx;
+      const bool cvalid = col < M;
+      const double cm = (cvalid && cc) ? cc[col] : 0.0;
+      double csum = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = rowbase + 4 * g + r;
+        if (!rv[r] || !cvalid) continue;
+        const double p = acc[u][r];
+        const double pz1 = ipow(p, zeta - 1);
+        const double kval = d2 * pz1 * p;
+        if (mode == 0) {
+          esum[r] += cm * kval;
+          if (W) W[rr * ldw + col] = d2z * cm * pz1;
+        } else if (mode == 1) {
+          csum += ge[r] * kval;
+          if (W) W[rr * ldw + col] = ge[r] * d2z * cm * pz1;
+        } else {
+          csum += ge[r] * kval - d2z * pz1 * accq[u][r];
+        }
+      }
+      if (mode != 0) {
+        csum += __shfl_xor(csum, 16);
+        csum += __shfl_xor(csum, 32);
+        if (g == 0) colsum[wave][u * 16 + idx] = csum;
+      }
+    }
+    if (mode != 0) {
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        const int64_t col = col0 + threadIdx.x;
+        if (col < M)
+          dc_part[(int64_t)blockIdx.x * M + col] =
+              ((colsum[0][threadIdx.x] + colsum[1][threadIdx.x]) + colsum[2][threadIdx.x]) +
+              colsum[3][threadIdx.x];
+      }
+      __syncthreads();
+    }
+  }
+  if (mode == 0 && e_atom) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = esum[r];
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+      const int64_t rr = rowbase + 4 * g + r;
+      if (idx == 0 && rr < n) e_atom[rr] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------- out = W X (row-major)
+__global__ __launch_bounds__(256) void k_gemm_wx(const double* __restrict__ W, int64_t ldw,
+                                                 int64_t n, int64_t M,
+                                                 const double* __restrict__ X, int64_t ldx,
+                                                 int64_t D, double* __restrict__ out,
+                                                 int64_t ldo) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const int64_t colbase = (int64_t)blockIdx.y * 64;
+  FragRowK<double> fa{W + (row < n ? row : 0) * ldw, M, row < n};
+  FragColK<double> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = FragColK<double>{X + (col < D ? col : 0), ldx, M, col < D};
+  }
+  d4v acc[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+  wave_mma<kNC>(fa, fb, M, g, acc);
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + 4 * g + r;
+      if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+
+// ------------------------------------------------------ out = W^T desc ----
+template <typename TD>
+__global__ __launch_bounds__(256) void k_gemm_wtd(const double* __restrict__ W, int64_t ldw,
+                                                  int64_t n, int64_t M,
+                                                  const TD* __restrict__ desc, int64_t ldd,
+                                                  int64_t D, double* __restrict__ out,
+                                                  int64_t ldo) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;  // sparse point m
+  const int64_t row = rowbase + idx;
+  const int64_t colbase = (int64_t)blockIdx.y * 64;                 // descriptor component
+  FragColK<double> fa{W + (row < M ? row : 0), ldw, n, row < M};
+  FragColK<TD> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = FragColK<TD>{desc + (col < D ? col : 0), ldd, n, col < D};
+  }
+  d4v acc[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+  wave_mma<kNC>(fa, fb, n, g, acc);
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + 4 * g + r;
+      if (rr < M && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+
+__global__ void k_reduce_rows(const double* __restrict__ part, int64_t nparts, int64_t M,
+                              double* __restrict__ out) {
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t p = 0; p < nparts; ++p) s += part[p * M + m];
+    out[m] = s;
+  }
+}
+
+__global__ void k_segment_sum(const double* __restrict__ v, const int64_t* __restrict__ ptr,
+                              int64_t nseg, int64_t n, double* __restrict__ out) {
+  const int64_t c = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nseg) return;
+  const int64_t lo = max((int64_t)0, min(ptr[c], n)), hi = max(lo, min(ptr[c + 1], n));
+  double s = 0.0;
+  for (int64_t i = lo + lane; i < hi; i += 64) s += v[i];
+  s = wave_sum(s);
+  if (lane == 0) out[c] = s;
+}
+
+__global__ void k_copy_rows(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                            int64_t ldd, int64_t n, int64_t D) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * D;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / D, j = e - i * D;
+    dst[i * ldd + j] = src[i * lds + j];
+  }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+void copy_rows_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int64_t D,
+                   hipStream_t st) {
+  if (n <= 0 || D <= 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>((n * D + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_copy_rows, dim3(g), dim3(256), 0, st, src, lds, dst, ldd, n, D);
+}
+
+void kmm_f64(const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+             double* K, int64_t ldk, hipStream_t st) {
+  if (M <= 0) return;
+  const unsigned nt = cdiv(M, 64);
+  hipLaunchKernelGGL(k_kmm, dim3(nt, nt), dim3(256), 0, st, X, ldx, M, D, zeta, delta, K, ldk);
+}
+
+void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
+                     int64_t n_cfg, int64_t n_atoms, const double* X, int64_t ldx, int64_t M,
+                     int64_t D, int zeta, double delta, double* K, int64_t ldk, double* S,
+                     int64_t ldS, hipStream_t st) {
+  if (n_cfg <= 0 || M <= 0) return;
+  dim3 grid(cdiv(M, 256), (unsigned)n_cfg);
+  if (desc_f32)
+    hipLaunchKernelGGL(k_energy_rows<float>, grid, dim3(256), 0, st, tptr<float>(desc), ldd,
+                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+  else
+    hipLaunchKernelGGL(k_energy_rows<double>, grid, dim3(256), 0, st, tptr<double>(desc), ldd,
+                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+}
+
+int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }
+
+void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+                const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
+                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st) {
+  if (n <= 0 || M <= 0) return;
+  dim3 grid((unsigned)pstage_row_blocks(n));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_pstage<float>, grid, dim3(256), 0, st, mode, tptr<float>(desc), ldd, n,
+                       X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part);
+  else
+    hipLaunchKernelGGL(k_pstage<double>, grid, dim3(256), 0, st, mode, tptr<double>(desc), ldd,
+                       n, X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part);
+}
+
+void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
+                 int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st) {
+  if (n <= 0 || D <= 0) return;
+  hipLaunchKernelGGL(k_gemm_wx, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
+                     X, ldx, D, out, ldo);
+}
+
+void gemm_wtd_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
+                  bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
+                  hipStream_t st) {
+  if (M <= 0 || D <= 0) return;
+  dim3 grid(cdiv(M, 64), cdiv(D, 64));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_gemm_wtd<float>, grid, dim3(256), 0, st, W, ldw, n, M,
+                       tptr<float>(desc), ldd, D, out, ldo);
+  else
+    hipLaunchKernelGGL(k_gemm_wtd<double>, grid, dim3(256), 0, st, W, ldw, n, M,
+                       tptr<double>(desc), ldd, D, out, ldo);
+}
+
+void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out,
+                     hipStream_t st) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(cdiv(M, 256)), dim3(256), 0, st, part, nparts, M, out);
+}
+
+void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,
+                     double* e_cfg, hipStream_t st) {
+  if (n_cfg <= 0) return;
+  hipLaunchKernelGGL(k_segment_sum, dim3(cdiv(n_cfg, 4)), dim3(256), 0, st, e_atom, cfg_ptr,
+                     n_cfg, n, e_cfg);
+}
+
+}  // namespace gapk

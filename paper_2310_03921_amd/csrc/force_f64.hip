@@ -1,0 +1,289 @@
+// Force observations of L-hat K_NM, and force prediction, in FP64.
+//
+// Force row (j, alpha), column m (Sec. "Theory": derivative rows of K_NM,
+// accumulated over every pair pointing at atom j):
+//   K_F[(j,alpha), m] = - sum_{(i,k): j(i,k)=j} S[i][m] * (J[(i,k)][alpha] . x_m),
+//   S[i][m] = delta^2 zeta (d_i . x_m)^(zeta-1)   (written by the energy-row kernel).
+//
+// Work decomposition: a wavefront owns 16 target atoms (a "slot group" of the
+// degree-sorted target list) and 16*NC sparse-point columns.  Step t multiplies
+// the t-th incoming pair of each of the 16 targets (one matrix row per target,
+// three alpha components as three accumulators) with X^T on the FP64 matrix
+// core, scales the 16 x 16 results by S of each pair's source atom, and adds
+// them into per-target accumulators that stay in registers for the whole
+// kernel.  Each output row is written once, no atomics, so results do not
+// depend on scheduling.  The four waves of a block share the slot group (their
+// Jacobian rows hit L1) and cover consecutive column ranges.
+#include "launch.h"
+#include "mma_f64.h"
+
+namespace gapk {
+
+namespace {
+
+constexpr int kFNC = 2;  // 16-column tiles per wave in the force-row kernel
+
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_force_rows(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
+    int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
+    const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
+    int64_t per_xcd) {
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, grp = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = (ct * 4 + wave) * (16 * kFNC);
+  if (colbase >= M) return;
+
+  // Row metadata: lane idx describes slot row idx (same in every lane group).
+  const int64_t slot = grp * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+
+  FragRowK<double> fb[kFNC];
+#pragma unroll
+  for (int u = 0; u < kFNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = FragRowK<double>{X + (col < M ? col : 0) * ldx, D, col < M};
+  }
+  int64_t colr[kFNC];
+#pragma unroll
+  for (int u = 0; u < kFNC; ++u) colr[u] = colbase + u * 16 + idx;
+
+  d4v acc[3][kFNC];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int u = 0; u < kFNC; ++u) acc[a][u] = zero4();
+
+  for (int t = 0; t < maxdeg; ++t) {
+    int pair = t < deg ? tgt_pair[seg0 + t] : -1;
+    const int src = pair >= 0 ? pair_src[pair] : -1;
+    if (src < 0) pair = -1;
+    const TJ* jr = jac + (int64_t)(pair >= 0 ? pair : 0) * 3 * ldj;
+    FragRowK<TJ> fa[3] = {FragRowK<TJ>{jr, D, pair >= 0}, FragRowK<TJ>{jr + ldj, D, pair >= 0},
+                          FragRowK<TJ>{jr + 2 * ldj, D, pair >= 0}};
+    d4v G[3][kFNC];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < kFNC; ++u) G[a][u] = zero4();
+
+    double a0[3][4], a1[3][4], b0[kFNC][4], b1[kFNC][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fa[a].frag(0, g, a0[a]);
+#pragma unroll
+    for (int u = 0; u < kFNC; ++u) fb[u].frag(0, g, b0[u]);
+    int64_t k0 = 0;
+    for (; k0 + 16 < D; k0 += 32) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) fa[a].frag(k0 + 16, g, a1[a]);
+#pragma unroll
+      for (int u = 0; u < kFNC; ++u) fb[u].frag(k0 + 16, g, b1[u]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mma_block<kFNC>(a0[a], b0, G[a]);
+      if (k0 + 32 < D) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fa[a].frag(k0 + 32, g, a0[a]);
+#pragma unroll
+        for (int u = 0; u < kFNC; ++u) fb[u].frag(k0 + 32, g, b0[u]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mma_block<kFNC>(a1[a], b1, G[a]);
+    }
+    if (k0 < D) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mma_block<kFNC>(a0[a], b0, G[a]);
+    }
+
+    // acc += S[src(row)][col] * G   (C layout: lane holds rows 4g + r)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int src_r = __shfl(src, 4 * g + r);
+#pragma unroll
+      for (int u = 0; u < kFNC; ++u) {
+        const double sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, 4 * g + r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kFNC; ++u) {
+      if (colr[u] >= M) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -acc[a][u][r];
+    }
+  }
+}
+
+// f_pair[p][alpha] = J[p][alpha] . g[src(p)]; one wavefront per pair.
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_pair_dots(const TJ* __restrict__ jac, int64_t ldj,
+                                                   int64_t D, const double* __restrict__ gm,
+                                                   int64_t ldg, const int32_t* __restrict__ src,
+                                                   int64_t n_pairs, double* __restrict__ f_pair) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t p = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); p < n_pairs;
+       p += nw) {
+    const int i = src[p];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (i >= 0) {
+      const TJ* jr = jac + p * 3 * ldj;
+      const double* gr = gm + (int64_t)i * ldg;
+      for (int64_t k = 4 * lane; k < D; k += 256) {
+        double gv[4], j0[4], j1[4], j2[4];
+        load4(gr, k, D, gv);
+        load4(jr, k, D, j0);
+        load4(jr + ldj, k, D, j1);
+        load4(jr + 2 * ldj, k, D, j2);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s0 += j0[q] * gv[q];
+          s1 += j1[q] * gv[q];
+          s2 += j2[q] * gv[q];
+        }
+      }
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      f_pair[p * 3 + 0] = s0;
+      f_pair[p * 3 + 1] = s1;
+      f_pair[p * 3 + 2] = s2;
+    }
+  }
+}
+
+__global__ void k_gather_forces(const double* __restrict__ f_pair,
+                                const int64_t* __restrict__ tgt_ptr,
+                                const int32_t* __restrict__ tgt_pair, int64_t n_atoms,
+                                double* __restrict__ F) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 3 * n_atoms;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = q / 3;
+    const int a = (int)(q - 3 * j);
+    double s = 0.0;
+    for (int64_t e = tgt_ptr[j]; e < tgt_ptr[j + 1]; ++e) s += f_pair[(int64_t)tgt_pair[e] * 3 + a];
+    F[q] = -s;
+  }
+}
+
+// h[i] = sum over the pairs (i, k) of sum_alpha v[j(i,k)][alpha] J[(i,k)][alpha]; one wave per atom.
+constexpr int kHMaxIt = 8;  // D <= 2048
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_jac_t_apply(const TJ* __restrict__ jac, int64_t ldj,
+                                                     int64_t D, const int64_t* __restrict__ pair_ptr,
+                                                     const int32_t* __restrict__ pair_j,
+                                                     int64_t n_atoms, int64_t n_pairs,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ h, int64_t ldh) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n_atoms) return;
+  double acc[kHMaxIt][4];
+#pragma unroll
+  for (int it = 0; it < kHMaxIt; ++it)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[it][q] = 0.0;
+  const int64_t lo = max((int64_t)0, pair_ptr[i]), hi = min(n_pairs, pair_ptr[i + 1]);
+  for (int64_t p = lo; p < hi; ++p) {
+    const int32_t j = pair_j[p];
+    if (j < 0 || j >= n_atoms) continue;
+    const double v0 = v[3 * (int64_t)j], v1 = v[3 * (int64_t)j + 1], v2 = v[3 * (int64_t)j + 2];
+    const TJ* jr = jac + p * 3 * ldj;
+#pragma unroll
+    for (int it = 0; it < kHMaxIt; ++it) {
+      const int64_t k = 4 * lane + 256 * it;
+      if (k >= D) break;
+      double j0[4], j1[4], j2[4];
+      load4(jr, k, D, j0);
+      load4(jr + ldj, k, D, j1);
+      load4(jr + 2 * ldj, k, D, j2);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[it][q] += v0 * j0[q] + v1 * j1[q] + v2 * j2[q];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kHMaxIt; ++it) {
+    const int64_t k = 4 * lane + 256 * it;
+    if (k >= D) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k + q < D) h[i * ldh + k + q] = acc[it][q];
+  }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
+                    int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* tgt_ptr,
+                    const int32_t* tgt_pair, const int32_t* pair_src, const int32_t* order,
+                    int64_t n_atoms, int64_t row0, double* K, int64_t ldk, hipStream_t st) {
+  if (n_atoms <= 0 || M <= 0) return;
+  const int64_t n_ct = (M + 4 * 16 * kFNC - 1) / (4 * 16 * kFNC);
+  const int64_t n_grp = (n_atoms + 15) / 16;
+  const int64_t total = n_ct * n_grp;
+  const int64_t per_xcd = (total + 7) / 8;
+  dim3 grid((unsigned)(8 * per_xcd));
+  if (jac_f32)
+    hipLaunchKernelGGL(k_force_rows<float>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+  else
+    hipLaunchKernelGGL(k_force_rows<double>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+}
+
+void forces_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* g,
+                int64_t ldg, const int32_t* pair_src, int64_t n_atoms, int64_t n_pairs,
+                const int64_t* tgt_ptr, const int32_t* tgt_pair, double* f_pair, double* forces,
+                hipStream_t st) {
+  if (n_atoms <= 0) return;
+  if (n_pairs > 0) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((n_pairs + 3) / 4, 65536);
+    if (jac_f32)
+      hipLaunchKernelGGL(k_pair_dots<float>, dim3(blocks), dim3(256), 0, st,
+                         reinterpret_cast<const float*>(jac), ldj, D, g, ldg, pair_src, n_pairs,
+                         f_pair);
+    else
+      hipLaunchKernelGGL(k_pair_dots<double>, dim3(blocks), dim3(256), 0, st,
+                         reinterpret_cast<const double*>(jac), ldj, D, g, ldg, pair_src, n_pairs,
+                         f_pair);
+  }
+  hipLaunchKernelGGL(k_gather_forces, dim3(std::min<unsigned>(cdiv(3 * n_atoms, 256), 65536u)),
+                     dim3(256), 0, st, f_pair, tgt_ptr, tgt_pair, n_atoms, forces);
+}
+
+void jac_transpose_apply_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D,
+                             const int64_t* pair_ptr, const int32_t* pair_j, int64_t n_atoms,
+                             int64_t n_pairs, const double* v, double* h, int64_t ldh,
+                             hipStream_t st) {
+  if (n_atoms <= 0) return;
+  dim3 grid(cdiv(n_atoms, 4));
+  if (jac_f32)
+    hipLaunchKernelGGL(k_jac_t_apply<float>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const float*>(jac), ldj, D, pair_ptr, pair_j, n_atoms,
+                       n_pairs, v, h, ldh);
+  else
+    hipLaunchKernelGGL(k_jac_t_apply<double>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const double*>(jac), ldj, D, pair_ptr, pair_j, n_atoms,
+                       n_pairs, v, h, ldh);
+}
+
+}  // namespace gapk

@@ -1,0 +1,125 @@
+// Host-side launchers of the gfx950 kernels (implemented in the .hip files).
+// Every launcher only enqueues work on `st`; argument validation is done by
+// the C ABI layer before these are called.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+// Device status word bits (accumulated with atomicOr, read by synchronising calls).
+#define GAP_DEVERR_INDEX 1   // a pair target or pointer outside its range
+#define GAP_DEVERR_NOT_PD 2  // non-positive or non-finite Cholesky pivot
+#define GAP_DEVERR_RANK 4    // zero or non-finite diagonal of R
+
+namespace gapk {
+
+// ---- pairs.hip ------------------------------------------------------------
+// tgt_ptr/tgt_pair (target-major pair view), pair_src, and the targets sorted
+// by decreasing in-degree (order).  scratch_i32 needs n_atoms + 2048 ints.
+void pair_transpose(const int64_t* pair_ptr, const int32_t* pair_j, int64_t n_atoms,
+                    int64_t n_pairs, int64_t* tgt_ptr, int32_t* tgt_pair, int32_t* pair_src,
+                    int32_t* order, int32_t* scratch_i32, int* dev_err, hipStream_t st);
+// Configuration index of each atom (atom_cfg[i] = c for cfg_ptr[c] <= i < cfg_ptr[c+1]).
+void atom_config(const int64_t* cfg_ptr, int64_t n_cfg, int64_t n_atoms, int32_t* atom_cfg,
+                 hipStream_t st);
+
+// ---- dense_f64.hip --------------------------------------------------------
+void kmm_f64(const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+             double* K, int64_t ldk, hipStream_t st);
+// Energy rows K[c][m] (col-major, ldk) and S[i][m] = delta^2 zeta p^(zeta-1) (row-major, ldS).
+void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
+                     int64_t n_cfg, int64_t n_atoms, const double* X, int64_t ldx, int64_t M,
+                     int64_t D, int zeta, double delta, double* K, int64_t ldk, double* S,
+                     int64_t ldS, hipStream_t st);
+// P-stage of predict / backward.  For rows i of desc:
+//   mode 0 (forward):  W[i][m] = delta^2 zeta c_m p^(zeta-1)       (if W)
+//                      e_atom[i] = sum_m c_m delta^2 p^zeta         (if e_atom)
+//   mode 1 (backward): W[i][m] = g_e[i] delta^2 zeta c_m p^(zeta-1) (if W)
+//                      dc_part[rb][m] = sum_{i in row block rb} g_e[i] delta^2 p^zeta
+//   mode 2 (residual): W[i][m] = g_e[i] delta^2 p^zeta + delta^2 zeta p^(zeta-1) q_im
+//                      where q = H X^T with H [n][ldh] (rows of h_i); only dc_part is written
+//                      (column partial sums of W over the row block)
+void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+                const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
+                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st);
+int64_t pstage_row_blocks(int64_t n);
+// out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
+void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
+                 int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st);
+// out[m][j] = sum_i W[i][m] desc[i][j]        (M x D, row-major ldo)
+void gemm_wtd_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
+                  bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
+                  hipStream_t st);
+// dst[i][0:D] = src[i][0:D]
+void copy_rows_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int64_t D,
+                   hipStream_t st);
+// out[m] = sum_rb part[rb][m]
+void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out, hipStream_t st);
+// e_cfg[c] = sum_{i in c} e_atom[i]
+void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,
+                     double* e_cfg, hipStream_t st);
+
+// ---- force_f64.hip --------------------------------------------------------
+void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
+                    int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* tgt_ptr,
+                    const int32_t* tgt_pair, const int32_t* pair_src, const int32_t* order,
+                    int64_t n_atoms, int64_t row0, double* K, int64_t ldk, hipStream_t st);
+// f_pair[p][alpha] = J[p][alpha] . g[src(p)], then forces[j][alpha] = -sum_{p -> j} f_pair[p][alpha]
+void forces_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* g,
+                int64_t ldg, const int32_t* pair_src, int64_t n_atoms, int64_t n_pairs,
+                const int64_t* tgt_ptr, const int32_t* tgt_pair, double* f_pair, double* forces,
+                hipStream_t st);
+// h[i][:] = sum_k sum_alpha v[j(i,k)][alpha] J[(i,k)][alpha][:]  (n_atoms x D, ld = ldh)
+void jac_transpose_apply_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D,
+                             const int64_t* pair_ptr, const int32_t* pair_j, int64_t n_atoms,
+                             int64_t n_pairs, const double* v, double* h, int64_t ldh,
+                             hipStream_t st);
+
+// ---- linalg.hip -----------------------------------------------------------
+// A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows;
+// rows n_rows .. n_rows+M-1: U = L^T from the lower factor L (col-major ldl), b = 0.
+void scale_stack(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
+                 const double* sigma, const double* L, int64_t ldl, hipStream_t st);
+// In-place lower Cholesky of the M x M col-major matrix Lw (ld = ldl) after adding
+// jitter to its diagonal; the strict upper part is left untouched.
+void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const double* Kmm,
+                    int64_t ldk, int* dev_err, hipStream_t st);
+struct QrWork {
+  double* part;       // split-K partials
+  int64_t part_elems;
+  double* W;          // nb x (n+1) reduced V^T C
+  double* Wt;         // T^T W
+  double* T;          // nb x nb
+  double* colstate;   // per column: tau, beta, scale, then tw[nb]
+  double* red;        // panel reduction partials
+  unsigned int* counter;
+};
+size_t qr_workspace_bytes(int64_t m, int64_t n);
+void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w);
+// Householder QR of the m x ncols col-major A (ncols = n + 1 with b last); R in the
+// upper triangle of the first n columns, Q^T b in column n.
+void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
+               hipStream_t st);
+// x = R^-1 z (R upper n x n col-major in A, z = A[0:n][n]); records min/max |R_kk|
+// into rd[0..1] (device) and flags zero/non-finite pivots.
+void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
+                     double* rd, int* dev_err, hipStream_t st);
+// Solve R^T y = z (forward) then R x = y (backward), in place on x.
+void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st);
+// r_top[r] = (y_r - kc_r) / sigma_r ; r_bot = -U c ;  also returns sum of squares pieces
+void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
+                     const double* L, int64_t ldl, int64_t M, const double* c, double* r_top,
+                     double* r_bot, hipStream_t st);
+// g[m] += (U^T r_bot)[m]  (U = L^T)
+void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, double* g,
+              hipStream_t st);
+// v[r] = r_top[r] / sigma_r (weights for K^T)
+void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st);
+void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st);
+void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st);
+// Expand per-configuration weights to atoms: out[i] = v[cfg(i)]
+void expand_cfg(const double* v, const int32_t* atom_cfg, int64_t n_atoms, double* out,
+                hipStream_t st);
+
+}  // namespace gapk

@@ -1,0 +1,731 @@
+// FP64 linear algebra of the stable least-squares route (Sec. "Theory"):
+//   A = [Sigma^-1/2 L-hat K_NM ; U_MM],  b = [Sigma^-1/2 y ; 0],
+//   K_MM + jitter I = U^T U (Cholesky), A = QR (Householder), c = R^-1 Q^T b,
+// plus the pieces of FP64 iterative refinement (semi-normal equations).
+//
+// Householder QR, right-looking and blocked (compact WY, Q = I - V T V^T):
+//   panel: one launch per column; every launch applies the previous reflector
+//          to the rest of the panel and, in the same pass over the rows,
+//          accumulates the norm and dot products that define the next
+//          reflector; the last block to finish reduces the per-block partial
+//          sums in a fixed order (no atomics on data, deterministic).
+//   trailing update: W = V^T C (split over row slabs on FP64 MFMA, then a
+//          fixed-order reduction), T from the Gram V^T V and tau, and
+//          C -= V (T^T W) on FP64 MFMA.  b rides along as the last column.
+#include <algorithm>
+
+#include "launch.h"
+#include "mma_f64.h"
+
+namespace gapk {
+
+namespace {
+
+constexpr int kQrNB = 64;      // panel width
+constexpr int kCholNB = 64;    // Cholesky block
+constexpr int kPanelMaxGrid = 256;
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+GAP_DEV double vload(const double* p) { return *reinterpret_cast<const volatile double*>(p); }
+
+// ----------------------------------------------------------- scale/stack ----
+__global__ void k_scale_stack(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
+                              const double* __restrict__ y, const double* __restrict__ sigma,
+                              const double* __restrict__ L, int64_t ldl) {
+  const int64_t col = blockIdx.y;
+  const int64_t rtot = n_rows + M;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rtot;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double v;
+    if (r < n_rows) {
+      const double w = 1.0 / sigma[r];
+      v = (col < M) ? A[r + col * ld] * w : y[r] * w;
+    } else {
+      const int64_t i = r - n_rows;  // row i of U = column i of L
+      v = (col < M && col >= i) ? L[col + i * ldl] : 0.0;
+    }
+    A[r + col * ld] = v;
+  }
+}
+
+// -------------------------------------------------------------- Cholesky ----
+__global__ void k_chol_init(double* __restrict__ Lw, int64_t ldl, int64_t M, double jitter,
+                            const double* __restrict__ Kmm, int64_t ldk) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Lw[i + j * ldl] = Kmm[i + j * ldk] + (i == j ? jitter : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Lw, int64_t ldl, int64_t j0,
+                                                   int nbj, int* dev_err) {
+  __shared__ double s[kCholNB][kCholNB + 1];
+  for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
+    const int r = e % nbj, c = e / nbj;
+    s[r][c] = Lw[(j0 + r) + (j0 + c) * ldl];
+  }
+  __syncthreads();
+  for (int c = 0; c < nbj; ++c) {
+    if (threadIdx.x == 0) {
+      double p = s[c][c];
+      if (!(p > 0.0) || !isfinite(p)) {
+        atomicOr(dev_err, GAP_DEVERR_NOT_PD);
+        p = 1.0;
+      }
+      s[c][c] = sqrt(p);
+    }
+    __syncthreads();
+    const double d = s[c][c];
+    for (int r = c + 1 + threadIdx.x; r < nbj; r += 256) s[r][c] /= d;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
+      const int r = e % nbj, q = e / nbj;
+      if (q > c && r >= q) s[r][q] -= s[r][c] * s[q][c];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
+    const int r = e % nbj, c = e / nbj;
+    if (r >= c) Lw[(j0 + r) + (j0 + c) * ldl] = s[r][c];
+  }
+}
+
+// Rows below the diagonal block: L[r, j0:j0+nbj] = A[r, j0:j0+nbj] L_dd^-T.
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ Lw, int64_t ldl, int64_t M,
+                                                    int64_t j0, int nbj) {
+  __shared__ double s[kCholNB][kCholNB + 1];
+  for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
+    const int r = e % nbj, c = e / nbj;
+    s[r][c] = (r >= c) ? Lw[(j0 + r) + (j0 + c) * ldl] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r = j0 + nbj + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= M) return;
+  double x[kCholNB];
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c) {
+    if (c < nbj) {
+      double v = Lw[r + (j0 + c) * ldl];
+#pragma unroll
+      for (int q = 0; q < c; ++q) v -= x[q] * s[c][q];
+      x[c] = v / s[c][c];
+      Lw[r + (j0 + c) * ldl] = x[c];
+    } else {
+      x[c] = 0.0;
+    }
+  }
+}
+
+// C[r][c] -= sum_k P[r][k] P[c][k] on the lower trailing block (r >= c).
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lw, int64_t ldl,
+                                                     int64_t M, int64_t j0, int nbj) {
+  const int64_t t0 = j0 + nbj;
+  const int64_t cbase = t0 + (int64_t)blockIdx.x * 64;  // columns (MFMA rows)
+  const int64_t rbase = t0 + (int64_t)blockIdx.y * 64;  // rows (MFMA columns)
+  if (rbase + 63 < cbase) return;                        // tile strictly above the diagonal
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t c = cbase + wave * 16 + idx;
+  FragColK<double> fa{Lw + (c < M ? c : 0) + j0 * ldl, ldl, nbj, c < M};
+  FragColK<double> fb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = rbase + u * 16 + idx;
+    fb[u] = FragColK<double>{Lw + (r < M ? r : 0) + j0 * ldl, ldl, nbj, r < M};
+  }
+  d4v acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = zero4();
+  wave_mma<4>(fa, fb, nbj, g, acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = rbase + u * 16 + idx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t cc = cbase + wave * 16 + 4 * g + q;
+      if (r < M && cc < M && r >= cc) Lw[r + cc * ldl] -= acc[u][q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------- QR ----
+// Column state of the current panel, per column: tau, beta, scale, tw[kQrNB]
+// where tw[j] = tau * (v^T a_j) for the panel columns j to its right.
+constexpr int kCS = kQrNB + 3;
+
+__global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t ld, int64_t m,
+                                                int64_t j0, int pw, int64_t k,
+                                                double* __restrict__ colstate,
+                                                double* __restrict__ red,
+                                                unsigned int* __restrict__ counter) {
+  __shared__ double s_tw[kQrNB];
+  __shared__ double s_red[4][kQrNB];
+  __shared__ double s_tot[kQrNB];
+  __shared__ int s_last;
+  __shared__ double s_par[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t pend = j0 + pw;
+  const bool has_prev = k > j0;
+  const bool has_next = k < pend;
+  const int64_t prev = k - 1;
+  double beta_p = 0.0, scale_p = 0.0;
+  if (has_prev) {
+    const double* cs = colstate + (prev - j0) * kCS;
+    beta_p = cs[1];
+    scale_p = cs[2];
+    for (int j = threadIdx.x; j < kQrNB; j += 256) s_tw[j] = cs[3 + j];
+  }
+  __syncthreads();
+  const int ncnt = has_next ? (int)(pend - k) : 0;  // sigma, then d_{k+1} .. d_{pend-1}
+  double part[kQrNB];
+#pragma unroll
+  for (int jj = 0; jj < kQrNB; ++jj) part[jj] = 0.0;
+
+  const int64_t r_lo = has_prev ? prev : k;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = r_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += stride) {
+    const bool acc_row = has_next && r > k;
+    if (has_prev) {
+      double v;
+      if (r == prev) {
+        v = 1.0;
+        A[prev + prev * ld] = beta_p;
+      } else {
+        v = A[r + prev * ld] * scale_p;
+        A[r + prev * ld] = v;
+      }
+      double ak = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kQrNB; ++jj) {
+        const int64_t j = k + jj;
+        if (j < pend) {
+          const double a = A[r + j * ld] - s_tw[j - j0] * v;
+          A[r + j * ld] = a;
+          if (acc_row) {
+            if (jj == 0) {
+              ak = a;
+              part[0] += a * a;
+            } else {
+              part[jj] += ak * a;
+            }
+          }
+        }
+      }
+    } else if (acc_row) {
+      const double ak = A[r + k * ld];
+      part[0] += ak * ak;
+#pragma unroll
+      for (int jj = 1; jj < kQrNB; ++jj) {
+        const int64_t j = k + jj;
+        if (j < pend) part[jj] += ak * A[r + j * ld];
+      }
+    }
+  }
+  if (!has_next) return;
+
+  // block partial sums -> red[v * gridDim.x + block]
+#pragma unroll
+  for (int v = 0; v < kQrNB; ++v) {
+    if (v < ncnt) {
+      const double s = wave_sum(part[v]);
+      if (lane == 0) s_red[wave][v] = s;
+    }
+  }
+  __syncthreads();
+  const int G = gridDim.x;
+  for (int v = threadIdx.x; v < ncnt; v += 256)
+    red[(int64_t)v * G + blockIdx.x] = ((s_red[0][v] + s_red[1][v]) + s_red[2][v]) + s_red[3][v];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = atomicAdd(counter, 1u);
+    s_last = (t == (unsigned)G - 1u);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int v = 0; v < ncnt; ++v) {
+    double s = (threadIdx.x < G) ? vload(red + (int64_t)v * G + threadIdx.x) : 0.0;
+    s = wave_sum(s);
+    if (lane == 0) s_red[wave][0] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) s_tot[v] = ((s_red[0][0] + s_red[1][0]) + s_red[2][0]) + s_red[3][0];
+    __syncthreads();
+  }
+  double* cs = colstate + (k - j0) * kCS;
+  if (threadIdx.x == 0) {
+    const double alpha = vload(A + k + k * ld);
+    const double xnorm = sqrt(s_tot[0]);
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (xnorm > 0.0) {
+      beta = -copysign(hypot(alpha, xnorm), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    cs[0] = tau;
+    cs[1] = beta;
+    cs[2] = scale;
+    s_par[0] = tau;
+    s_par[1] = scale;
+    *counter = 0u;
+  }
+  __syncthreads();
+  for (int jj = 1 + threadIdx.x; jj < ncnt; jj += 256) {
+    const int64_t j = k + jj;
+    const double w = vload(A + k + j * ld) + s_par[1] * s_tot[jj];
+    cs[3 + (j - j0)] = s_par[0] * w;
+  }
+}
+
+// Panel column c of V (unit lower trapezoidal) or a plain column of A.
+struct FragPanel {
+  const double* col;   // A + column * ld
+  int64_t r0;          // first row of the slab
+  int64_t r1;          // end row (exclusive)
+  int64_t diag;        // global row of the unit diagonal, or -1 for a plain column
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, double out[4]) const {
+    const int64_t r = r0 + k0 + 4 * g;
+    if (!valid) {
+      zero_frag(out);
+      return;
+    }
+    load4(col, r, r1, out);
+    if (diag >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t rr = r + q;
+        out[q] = (rr == diag) ? 1.0 : (rr > diag ? out[q] : 0.0);
+      }
+    }
+  }
+};
+
+// part[s][i][c'] = sum over rows of slab s of V[r][i] * A[r][j0 + c'],   i < pw, c' < nct
+__global__ __launch_bounds__(256) void k_qr_vtc(const double* __restrict__ A, int64_t ld, int64_t m,
+                                                int64_t j0, int pw, int64_t nct, int64_t slab,
+                                                double* __restrict__ part) {
+  const int64_t s = blockIdx.x;
+  const int64_t r0 = j0 + s * slab, r1 = std::min(m, r0 + slab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int i = wave * 16 + idx;
+  FragPanel fa{A + (j0 + (i < pw ? i : 0)) * ld, r0, r1, j0 + i, i < pw};
+  FragPanel fb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t cp = (int64_t)blockIdx.y * 64 + u * 16 + idx;
+    const bool ok = cp < nct;
+    fb[u] = FragPanel{A + (j0 + (ok ? cp : 0)) * ld, r0, r1, (ok && cp < pw) ? j0 + cp : -1, ok};
+  }
+  d4v acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = zero4();
+  wave_mma<4>(fa, fb, r1 - r0, g, acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t cp = (int64_t)blockIdx.y * 64 + u * 16 + idx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ii = wave * 16 + 4 * g + q;
+      if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[u][q];
+    }
+  }
+}
+
+__global__ void k_sum_slabs(const double* __restrict__ part, int64_t nslab, int64_t n,
+                            double* __restrict__ W) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t q = 0; q < nslab; ++q) s += part[q * n + e];
+    W[e] = s;
+  }
+}
+
+// T (pw x pw upper, row-major ld kQrNB): T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+__global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, int64_t nct, int pw,
+                                                  const double* __restrict__ colstate,
+                                                  double* __restrict__ T) {
+  __shared__ double sT[kQrNB][kQrNB + 1];
+  __shared__ double sG[kQrNB][kQrNB + 1];
+  for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
+    const int l = e / kQrNB, i = e % kQrNB;
+    sG[l][i] = (l < pw && i < pw) ? W[(int64_t)l * nct + i] : 0.0;
+    sT[l][i] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < pw; ++i) {
+    const double tau = colstate[i * kCS];
+    double z = 0.0;
+    const int l = threadIdx.x;
+    if (l < i)
+      for (int q = l; q < i; ++q) z += sT[l][q] * sG[q][i];
+    __syncthreads();
+    if (l < i) sT[l][i] = -tau * z;
+    if (l == i) sT[i][i] = tau;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) T[e] = sT[e / kQrNB][e % kQrNB];
+}
+
+// Wt[kk][c'] = sum_{l <= kk} T[l][kk] W[l][c']  for c' in [pw, nct)
+__global__ void k_qr_tw(const double* __restrict__ W, int64_t nct, int pw,
+                        const double* __restrict__ T, double* __restrict__ Wt) {
+  const int64_t ntr = nct - pw;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)pw * ntr;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int kk = (int)(e / ntr);
+    const int64_t cp = pw + (e - (int64_t)kk * ntr);
+    double s = 0.0;
+    for (int l = 0; l <= kk; ++l) s += T[l * kQrNB + kk] * W[(int64_t)l * nct + cp];
+    Wt[(int64_t)kk * nct + cp] = s;
+  }
+}
+
+// Rows of V for the update: element (r, kk) = V[r][kk] read along kk for fixed r.
+struct FragVRow {
+  const double* A;
+  int64_t ld;
+  int64_t r;     // global row
+  int64_t j0;    // panel start
+  int pw;
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, double out[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kk = k0 + 4 * g + q;
+      double v = 0.0;
+      if (valid && kk < pw) {
+        const int64_t rr = r - j0;
+        v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
+      }
+      out[q] = v;
+    }
+  }
+};
+
+// C[r][c] -= sum_kk V[r][kk] Wt[kk][c - j0]  for r in [j0, m), c in [j0 + pw, ncols)
+__global__ __launch_bounds__(256) void k_qr_update(double* __restrict__ A, int64_t ld, int64_t m,
+                                                   int64_t j0, int pw, int64_t ncols, int64_t nct,
+                                                   const double* __restrict__ Wt) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t cbase = j0 + pw + (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t rbase = j0 + (int64_t)blockIdx.y * 64;
+  const int64_t c = cbase + idx;
+  FragColK<double> fa{Wt + (c < ncols ? c - j0 : 0), nct, pw, c < ncols};
+  FragVRow fb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = rbase + u * 16 + idx;
+    fb[u] = FragVRow{A, ld, r, j0, pw, r < m};
+  }
+  d4v acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = zero4();
+  wave_mma<4>(fa, fb, pw, g, acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = rbase + u * 16 + idx;
+    if (r >= m) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t cc = cbase + 4 * g + q;
+      if (cc < ncols) A[r + cc * ld] -= acc[u][q];
+    }
+  }
+}
+
+// ------------------------------------------------------- triangular solves ----
+// x = R^-1 z, R upper (col-major, ld), one block; x kept in LDS (n <= 16384).
+__global__ __launch_bounds__(1024) void k_trsv_upper(const double* __restrict__ R, int64_t ld,
+                                                     int64_t n, const double* __restrict__ z,
+                                                     double* __restrict__ x, int* dev_err) {
+  extern __shared__ double xs[];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = z[i];
+  __syncthreads();
+  for (int64_t c = n - 1; c >= 0; --c) {
+    if (threadIdx.x == 0) {
+      const double d = R[c + c * ld];
+      if (d == 0.0 || !isfinite(d)) atomicOr(dev_err, GAP_DEVERR_RANK);
+      xs[c] = xs[c] / d;
+    }
+    __syncthreads();
+    const double xc = xs[c];
+    for (int64_t l = threadIdx.x; l < c; l += blockDim.x) xs[l] -= R[l + c * ld] * xc;
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
+}
+
+// y = R^-T z in place on x (forward substitution with the transpose).
+__global__ __launch_bounds__(1024) void k_trsv_upper_t(const double* __restrict__ R, int64_t ld,
+                                                       int64_t n, double* __restrict__ x) {
+  extern __shared__ double xs[];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[i];
+  __syncthreads();
+  for (int64_t c = 0; c < n; ++c) {
+    if (threadIdx.x == 0) xs[c] = xs[c] / R[c + c * ld];
+    __syncthreads();
+    const double xc = xs[c];
+    for (int64_t l = c + 1 + threadIdx.x; l < n; l += blockDim.x) xs[l] -= R[c + l * ld] * xc;
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
+}
+
+__global__ __launch_bounds__(1024) void k_trsv_upper_inplace(const double* __restrict__ R,
+                                                             int64_t ld, int64_t n,
+                                                             double* __restrict__ x) {
+  extern __shared__ double xs[];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[i];
+  __syncthreads();
+  for (int64_t c = n - 1; c >= 0; --c) {
+    if (threadIdx.x == 0) xs[c] = xs[c] / R[c + c * ld];
+    __syncthreads();
+    const double xc = xs[c];
+    for (int64_t l = threadIdx.x; l < c; l += blockDim.x) xs[l] -= R[l + c * ld] * xc;
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
+}
+
+__global__ __launch_bounds__(1024) void k_rdiag_minmax(const double* __restrict__ R, int64_t ld,
+                                                       int64_t n, double* __restrict__ rd) {
+  __shared__ double smin[16], smax[16];
+  double lo = INFINITY, hi = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = fabs(R[i + i * ld]);
+    lo = fmin(lo, a);
+    hi = fmax(hi, a);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smin[threadIdx.x >> 6] = lo;
+    smax[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      lo = fmin(lo, smin[w]);
+      hi = fmax(hi, smax[w]);
+    }
+    lo = fmin(lo, smin[0]);
+    hi = fmax(hi, smax[0]);
+    rd[0] = lo;
+    rd[1] = hi;
+  }
+}
+
+// ------------------------------------------------------------ refinement ----
+// r_top[r] = (y_r - kc_r) / sigma_r;  r_bot[i] = -(U c)_i = -sum_{j >= i} L[j][i] c_j
+__global__ void k_residual_top(const double* __restrict__ y, const double* __restrict__ sigma,
+                               const double* __restrict__ kc, int64_t n, double* __restrict__ r) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = (y[i] - kc[i]) / sigma[i];
+}
+
+__global__ __launch_bounds__(256) void k_residual_bot(const double* __restrict__ L, int64_t ldl,
+                                                      int64_t M, const double* __restrict__ c,
+                                                      double* __restrict__ rb) {
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= M) return;
+  double s = 0.0;
+  for (int64_t j = i + lane; j < M; j += 64) s += L[j + i * ldl] * c[j];
+  s = wave_sum(s);
+  if (lane == 0) rb[i] = -s;
+}
+
+// g[m] += sum_{i <= m} U[i][m] r_bot[i] = sum_{i <= m} L[m][i] r_bot[i]
+__global__ void k_add_ut_r(const double* __restrict__ L, int64_t ldl, int64_t M,
+                           const double* __restrict__ rb, double* __restrict__ g) {
+  for (int64_t mm = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; mm < M;
+       mm += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = 0; i <= mm; ++i) s += L[mm + i * ldl] * rb[i];
+    g[mm] += s;
+  }
+}
+
+__global__ void k_div(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                      double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = a[i] / b[i];
+}
+
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+__global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ x, int64_t n,
+                                                double* __restrict__ out) {
+  __shared__ double sp[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * x[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sp[w];
+    *out = sqrt(t);
+  }
+}
+
+__global__ void k_expand_cfg(const double* __restrict__ v, const int32_t* __restrict__ atom_cfg,
+                             int64_t n, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = atom_cfg[i];
+    out[i] = c >= 0 ? v[c] : 0.0;
+  }
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+inline unsigned g256(int64_t n) { return std::max(1u, std::min(cdiv(n, 256), 65536u)); }
+
+}  // namespace
+
+void scale_stack(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
+                 const double* sigma, const double* L, int64_t ldl, hipStream_t st) {
+  dim3 grid(std::min(cdiv(n_rows + M, 256), 4096u), (unsigned)(M + 1));
+  hipLaunchKernelGGL(k_scale_stack, grid, dim3(256), 0, st, A, ld, n_rows, M, y, sigma, L, ldl);
+}
+
+void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const double* Kmm,
+                    int64_t ldk, int* dev_err, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_init, dim3(cdiv(M, 256), (unsigned)M), dim3(256), 0, st, Lw, ldl, M,
+                     jitter, Kmm, ldk);
+  for (int64_t j0 = 0; j0 < M; j0 += kCholNB) {
+    const int nbj = (int)std::min<int64_t>(kCholNB, M - j0);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, Lw, ldl, j0, nbj, dev_err);
+    const int64_t rest = M - j0 - nbj;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rest, 256)), dim3(256), 0, st, Lw, ldl, M, j0, nbj);
+    hipLaunchKernelGGL(k_chol_update, dim3(cdiv(rest, 64), cdiv(rest, 64)), dim3(256), 0, st, Lw,
+                       ldl, M, j0, nbj);
+  }
+}
+
+static int64_t qr_slab_rows(int64_t m) {
+  // at most 64 slabs, each a multiple of 16 rows and at least 1024 rows
+  int64_t s = (m + 63) / 64;
+  s = std::max<int64_t>(s, 1024);
+  return (s + 15) / 16 * 16;
+}
+
+size_t qr_workspace_bytes(int64_t m, int64_t n) {
+  const int64_t ncols = n + 1;
+  const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
+  size_t d = 0;
+  d += (size_t)nslab * kQrNB * ncols;        // part
+  d += (size_t)kQrNB * ncols * 2;            // W, Wt
+  d += (size_t)kQrNB * kQrNB;                // T
+  d += (size_t)kQrNB * kCS;                  // colstate
+  d += (size_t)kQrNB * kPanelMaxGrid;        // red
+  return d * sizeof(double) + 256;
+}
+
+void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
+  const int64_t ncols = n + 1;
+  const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
+  double* p = reinterpret_cast<double*>(base);
+  w->part = p;
+  w->part_elems = nslab * kQrNB * ncols;
+  p += w->part_elems;
+  w->W = p;
+  p += kQrNB * ncols;
+  w->Wt = p;
+  p += kQrNB * ncols;
+  w->T = p;
+  p += kQrNB * kQrNB;
+  w->colstate = p;
+  p += kQrNB * kCS;
+  w->red = p;
+  p += kQrNB * kPanelMaxGrid;
+  w->counter = reinterpret_cast<unsigned int*>(p);
+}
+
+void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter);
+  const int64_t slab = qr_slab_rows(m);
+  for (int64_t j0 = 0; j0 < n; j0 += kQrNB) {
+    const int pw = (int)std::min<int64_t>(kQrNB, n - j0);
+    for (int64_t k = j0; k <= j0 + pw; ++k) {
+      const int64_t r_lo = (k > j0) ? k - 1 : k;
+      const int64_t rows = m - r_lo;
+      const unsigned G = std::max(1u, std::min(cdiv(rows, 1024), (unsigned)kPanelMaxGrid));
+      hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, j0, pw, k, w->colstate,
+                         w->red, w->counter);
+    }
+    const int64_t nct = ncols - j0;  // columns from the panel start (V columns first)
+    if (nct <= pw) continue;
+    const int64_t nslab = (m - j0 + slab - 1) / slab;
+    hipLaunchKernelGGL(k_qr_vtc, dim3((unsigned)nslab, cdiv(nct, 64)), dim3(256), 0, st, A, ld, m,
+                       j0, pw, nct, slab, w->part);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
+                       (int64_t)pw * nct, w->W);
+    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->colstate, w->T);
+    hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw,
+                       w->T, w->Wt);
+    hipLaunchKernelGGL(k_qr_update, dim3(cdiv(nct - pw, 64), cdiv(m - j0, 64)), dim3(256), 0, st,
+                       A, ld, m, j0, pw, ncols, nct, w->Wt);
+  }
+}
+
+void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
+                     double* rd, int* dev_err, hipStream_t st) {
+  hipLaunchKernelGGL(k_rdiag_minmax, dim3(1), dim3(1024), 0, st, A, ld, n, rd);
+  hipLaunchKernelGGL(k_trsv_upper, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld, n,
+                     z, x, dev_err);
+}
+
+void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_trsv_upper_t, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld,
+                     n, x);
+  hipLaunchKernelGGL(k_trsv_upper_inplace, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
+                     ld, n, x);
+}
+
+void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
+                     const double* L, int64_t ldl, int64_t M, const double* c, double* r_top,
+                     double* r_bot, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_top, dim3(g256(n_rows)), dim3(256), 0, st, y, sigma, kc, n_rows,
+                     r_top);
+  hipLaunchKernelGGL(k_residual_bot, dim3(cdiv(M, 4)), dim3(256), 0, st, L, ldl, M, c, r_bot);
+}
+
+void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, double* g,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_add_ut_r, dim3(g256(M)), dim3(256), 0, st, L, ldl, M, r_bot, g);
+}
+
+void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_div, dim3(g256(n)), dim3(256), 0, st, r_top, sigma, n, v);
+}
+
+void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(g256(n)), dim3(256), 0, st, n, a, x, y);
+}
+
+void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, x, n, out);
+}
+
+void expand_cfg(const double* v, const int32_t* atom_cfg, int64_t n_atoms, double* out,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_expand_cfg, dim3(g256(n_atoms)), dim3(256), 0, st, v, atom_cfg, n_atoms,
+                     out);
+}
+
+}  // namespace gapk
