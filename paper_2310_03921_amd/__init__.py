@@ -91,6 +91,11 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _f64(t: torch.Tensor) -> torch.Tensor:
+    """FP64 contiguous view or copy of a device tensor (the ABI takes double*)."""
+    return t.to(torch.float64).contiguous()
+
+
 def _round4(n: int) -> int:
     return (n + 3) // 4 * 4
 
@@ -272,8 +277,9 @@ class Gap:
         s = sparse.struct()
         info = gap_fit_info()
         tr = ctypes.byref(train.struct()) if train is not None else None
+        y, sigma, Kmm = _f64(y), _f64(sigma), _f64(Kmm)
         self._check(lib().gap_fit(self._h, _ptr(A), A.shape[1], n_rows, _ptr(Kmm),
-                                  _ptr(y.contiguous()), _ptr(sigma.contiguous()), float(jitter),
+                                  _ptr(y), _ptr(sigma), float(jitter),
                                   tr, ctypes.byref(s), int(refine_steps), _ptr(c),
                                   ctypes.byref(info)))
         return c, {"resid_norm": list(info.resid_norm)[:info.refine_done + 1],
@@ -291,6 +297,7 @@ class Gap:
             "forces": torch.empty(N, 3, dtype=torch.float64, device=dev) if forces else None,
         }
         a, s = atoms.struct(), sparse.struct()
+        c = _f64(c)
         self._check(lib().gap_predict(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
                                       PRECISION[precision], _ptr(out["e_atom"]),
                                       _ptr(out["e_cfg"]), _ptr(out["dEdd"]), _ptr(out["forces"])))
@@ -304,15 +311,17 @@ class Gap:
         dc = torch.empty(M, dtype=torch.float64, device=dev) if d_c else None
         dX = torch.empty(M, D, dtype=torch.float64, device=dev) if d_X else None
         a, s = atoms.struct(), sparse.struct()
+        c, g_e = _f64(c), _f64(g_e)
         self._check(lib().gap_predict_backward(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
-                                               PRECISION[precision], _ptr(g_e.contiguous()),
+                                               PRECISION[precision], _ptr(g_e),
                                                _ptr(dd), _ptr(dc), _ptr(dX)))
         return dd, dc, dX
 
     def forces(self, atoms: Atoms, dEdd: torch.Tensor) -> torch.Tensor:
         F = torch.empty(atoms.n_atoms, 3, dtype=torch.float64, device=dEdd.device)
         a = atoms.struct()
-        self._check(lib().gap_forces(self._h, ctypes.byref(a), _ptr(dEdd.contiguous()), _ptr(F)))
+        dEdd = _f64(dEdd)
+        self._check(lib().gap_forces(self._h, ctypes.byref(a), _ptr(dEdd), _ptr(F)))
         return F
 
 

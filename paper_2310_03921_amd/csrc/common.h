@@ -3,7 +3,8 @@
 // FP64 matrix cores: v_mfma_f64_16x16x4_f64 computes D = A(16x4) B(4x16) + C.
 // Operand layout of one 64-lane wavefront (lane l, group g = l / 16, idx = l % 16):
 //   A: lane holds A[idx][g]        B: lane holds B[g][idx]
-//   C/D: lane holds D[4 g + r][idx] for r = 0..3 (four doubles)
+//   C/D: lane holds D[g + 4 r][idx] for r = 0..3 (four doubles, rows interleaved
+//        across the lane groups; checked on gfx950 with an in-bounds probe)
 // Contraction order is free, so over a block of 16 k values the kernels let
 // lane group g own k = k0 + 4 g + s for MFMA step s = 0..3.  A lane then
 // reads four consecutive k of one row (one 32-byte load) when the operand is

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_kmm(const double* __restrict__ X, int64
     const int64_t col = (int64_t)bj * 64 + u * 16 + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t rr = (int64_t)bi * 64 + wave * 16 + 4 * g + r;
+      const int64_t rr = (int64_t)bi * 64 + wave * 16 + g + 4 * r;
       if (rr < M && col < M && rr <= col) {
         const double v = d2 * ipow(acc[u][r], zeta);
         K[rr + col * ldk] = v;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc
       const int64_t col = colbase + u * 16 + idx;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t rr = a + 4 * g + r;
+        const int64_t rr = a + g + 4 * r;
         if (rr < a1) {
           const double p = acc[u][r];
           const double pz1 = ipow(p, zeta - 1);
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
   bool rv[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int64_t rr = rowbase + 4 * g + r;
+    const int64_t rr = rowbase + g + 4 * r;
     rv[r] = rr < n;
     ge[r] = (mode != 0 && rv[r]) ? g_e[rr] : 0.0;
   }
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
       double csum = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t rr = rowbase + 4 * g + r;
+        const int64_t rr = rowbase + g + 4 * r;
         if (!rv[r] || !cvalid) continue;
         const double p = acc[u][r];
         const double pz1 = ipow(p, zeta - 1);
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
       double v = esum[r];
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
-      const int64_t rr = rowbase + 4 * g + r;
+      const int64_t rr = rowbase + g + 4 * r;
       if (idx == 0 && rr < n) e_atom[rr] = v;
     }
   }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_gemm_wx(const double* __restrict__ W, i
     const int64_t col = colbase + u * 16 + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t rr = rowbase + 4 * g + r;
+      const int64_t rr = rowbase + g + 4 * r;
       if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
     }
   }
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_gemm_wtd(const double* __restrict__ W, 
     const int64_t col = colbase + u * 16 + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t rr = rowbase + 4 * g + r;
+      const int64_t rr = rowbase + g + 4 * r;
       if (rr < M && col < D) out[rr * ldo + col] = acc[u][r];
     }
   }

@@ -101,10 +101,10 @@ __global__ __launch_bounds__(256) void k_force_rows(
       for (int a = 0; a < 3; ++a) mma_block<kFNC>(a0[a], b0, G[a]);
     }
 
-    // acc += S[src(row)][col] * G   (C layout: lane holds rows 4g + r)
+    // acc += S[src(row)][col] * G   (C layout: lane holds rows g + 4 r)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int src_r = __shfl(src, 4 * g + r);
+      const int src_r = __shfl(src, g + 4 * r);
 #pragma unroll
       for (int u = 0; u < kFNC; ++u) {
         const double sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.0;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_force_rows(
 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int tr = __shfl(target, 4 * g + r);
+    const int tr = __shfl(target, g + 4 * r);
     if (tr < 0) continue;
 #pragma unroll
     for (int u = 0; u < kFNC; ++u) {

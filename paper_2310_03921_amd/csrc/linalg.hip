@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lw, in
     const int64_t r = rbase + u * 16 + idx;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t cc = cbase + wave * 16 + 4 * g + q;
+      const int64_t cc = cbase + wave * 16 + g + 4 * q;
       if (r < M && cc < M && r >= cc) Lw[r + cc * ldl] -= acc[u][q];
     }
   }
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_qr_vtc(const double* __restrict__ A, in
     const int64_t cp = (int64_t)blockIdx.y * 64 + u * 16 + idx;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ii = wave * 16 + 4 * g + q;
+      const int ii = wave * 16 + g + 4 * q;
       if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[u][q];
     }
   }
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_qr_update(double* __restrict__ A, int64
     if (r >= m) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t cc = cbase + 4 * g + q;
+      const int64_t cc = cbase + g + 4 * q;
       if (cc < ncols) A[r + cc * ld] -= acc[u][q];
     }
   }

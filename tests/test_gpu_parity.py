@@ -70,7 +70,8 @@ def test_hand_example(gapx, gap):
     close(Kmm, g["Kmm"], 1e-14, "Kmm")
     A = gap.build_knm(atoms, sp)
     close(knm_host(A, atoms.n_rows, sp.M), g["Knm"], 1e-14, "Knm")
-    out = gap.predict(atoms, sp, torch.tensor(g["c"], device="cuda"), dEdd=True, forces=True)
+    out = gap.predict(atoms, sp, torch.tensor(g["c"], dtype=torch.float64, device="cuda"),
+                      dEdd=True, forces=True)
     close(out["e_atom"].cpu(), g["e_atom"], 1e-14, "e_atom")
     close(out["e_cfg"].cpu(), g["e_cfg"], 1e-14, "e_cfg")
     close(out["dEdd"].cpu(), g["dEdd"], 1e-14, "dEdd")
@@ -219,7 +220,7 @@ def test_fit_refinement_keeps_fp64_solution(gapx, gap):
 
 
 def test_fit_not_pd_reported(gapx, gap):
-    w = synth.WORKLOADS["fit_small"].with_(n_cfg=4)
+    w = synth.WORKLOADS["fit_small"].with_(n_cfg=12)
     b, X = batch_and_sparse(w)
     atoms, sp = to_device(gapx, b, X, w)
     A = gap.build_knm(atoms, sp)
