@@ -198,6 +198,16 @@ gap_status gap_predict_backward(gap_handle *h, const gap_atoms *atoms, const gap
  * Deterministic: per-pair contributions are summed per target in pair order. */
 gap_status gap_forces(gap_handle *h, const gap_atoms *atoms, const double *dEdd, double *forces);
 
+/* Stage timing (profiling aid, off by default).  When enabled, the library
+ * records HIP events on the handle's stream around each stage it enqueues;
+ * gap_timing_read waits for them and returns the accumulated milliseconds and
+ * the number of intervals per stage (arrays of gap_timing_count() entries, host),
+ * optionally resetting the accumulators.  Stage names: gap_timing_name(i). */
+gap_status gap_timing(gap_handle *h, int enable);
+gap_status gap_timing_read(gap_handle *h, double *ms, int64_t *count, int reset);
+const char *gap_timing_name(int i);
+int gap_timing_count(void);
+
 #ifdef __cplusplus
 }
 #endif

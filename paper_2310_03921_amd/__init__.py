@@ -78,6 +78,10 @@ def lib():
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_forces": ([P, P, P, P], S),
+            "gap_timing": ([P, I32], S),
+            "gap_timing_read": ([P, P, P, I32], S),
+            "gap_timing_name": ([I32], ctypes.c_char_p),
+            "gap_timing_count": ([], I32),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(L, name)
@@ -230,6 +234,19 @@ class Gap:
 
     def sync(self):
         self._check(lib().gap_sync(self._h))
+
+    def timing(self, enable: bool = True):
+        """Record HIP events around each library stage on this handle's stream."""
+        self._check(lib().gap_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self, reset: bool = True) -> dict:
+        """{stage: (total_ms, intervals)} accumulated since the last reset (waits for the events)."""
+        L = lib()
+        n = L.gap_timing_count()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._check(L.gap_timing_read(self._h, ms, cnt, 1 if reset else 0))
+        return {L.gap_timing_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
 
     def workspace_bytes(self, atoms: Atoms, sparse: Sparse) -> int:
         a, s, n = atoms.struct(), sparse.struct(), ctypes.c_size_t()

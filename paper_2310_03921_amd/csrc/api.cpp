@@ -21,6 +21,9 @@ struct gap_handle {
   size_t ws_bytes = 0;
   int* dev_err = nullptr;     // device status word
   double* dev_small = nullptr; // 64 doubles of small device scratch
+  gapk::Timer timer;
+  double tm_ms[gapk::TM_COUNT] = {};
+  int64_t tm_n[gapk::TM_COUNT] = {};
 };
 
 namespace {
@@ -153,10 +156,12 @@ void layout_pairs(Layout& L, int64_t n_atoms, int64_t n_pairs, PairWs& p) {
 }
 
 void run_pairs(gap_handle* h, const gap_atoms* a, const PairWs& p, bool want_order) {
+  h->timer.begin(gapk::TM_PAIRS);
   gapk::pair_transpose(a->pair_ptr, a->pair_j, a->n_atoms, a->n_pairs, at<int64_t>(h, p.tgt_ptr),
                        at<int32_t>(h, p.tgt_pair), at<int32_t>(h, p.src),
                        want_order ? at<int32_t>(h, p.order) : nullptr, at<int32_t>(h, p.scratch),
                        h->dev_err, h->stream);
+  h->timer.end(gapk::TM_PAIRS);
 }
 
 bool f32(gap_dtype d) { return d == GAP_DT_F32; }
@@ -225,6 +230,7 @@ gap_status gap_create(gap_handle** out, int device, void* hip_stream) {
   gap_handle* h = new gap_handle();
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->timer.st = h->stream;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
     delete h;
@@ -258,6 +264,9 @@ gap_status gap_destroy(gap_handle* h) {
   if (!h) return GAP_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  double ms[gapk::TM_COUNT];
+  int64_t n[gapk::TM_COUNT];
+  h->timer.collect(ms, n);
   if (h->ws) (void)hipFree(h->ws);
   if (h->dev_err) (void)hipFree(h->dev_err);
   if (h->dev_small) (void)hipFree(h->dev_small);
@@ -273,6 +282,36 @@ gap_status gap_sync(gap_handle* h) {
   if (s != GAP_OK) return s;
   return drain_dev_err(h);
 }
+
+static const char* kTimerNames[gapk::TM_COUNT] = {
+    "pair_transpose", "kmm", "energy_rows", "force_rows", "cholesky_stack", "qr_panel",
+    "qr_update", "back_substitution", "predict", "predict_backward", "refinement", "split_bf16"};
+
+gap_status gap_timing(gap_handle* h, int enable) {
+  if (!h) return GAP_E_INVALID;
+  h->timer.on = enable != 0;
+  return GAP_OK;
+}
+
+gap_status gap_timing_read(gap_handle* h, double* ms, int64_t* count, int reset) {
+  if (!h || !ms || !count) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  h->timer.collect(h->tm_ms, h->tm_n);
+  for (int i = 0; i < gapk::TM_COUNT; ++i) {
+    ms[i] = h->tm_ms[i];
+    count[i] = h->tm_n[i];
+    if (reset) {
+      h->tm_ms[i] = 0.0;
+      h->tm_n[i] = 0;
+    }
+  }
+  return GAP_OK;
+}
+
+const char* gap_timing_name(int i) { return (i >= 0 && i < gapk::TM_COUNT) ? kTimerNames[i] : ""; }
+
+int gap_timing_count(void) { return gapk::TM_COUNT; }
 
 gap_status gap_workspace_query(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
                                size_t* bytes) {
@@ -326,7 +365,9 @@ gap_status gap_build_kmm(gap_handle* h, const gap_sparse* sp, double* Kmm, int64
   s = check_sparse(h, sp);
   if (s != GAP_OK) return s;
   if (!Kmm || ld < sp->M) return fail(h, GAP_E_INVALID, "Kmm NULL or ld < M");
+  h->timer.begin(gapk::TM_KMM);
   gapk::kmm_f64(sp->X, sp->ld_x, sp->M, sp->D, sp->zeta, sp->delta, Kmm, ld, h->stream);
+  h->timer.end(gapk::TM_KMM);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }
@@ -351,13 +392,17 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   run_pairs(h, a, p, true);
+  h->timer.begin(gapk::TM_ENERGY);
   gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N, sp->X,
                         sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), M,
                         h->stream);
+  h->timer.end(gapk::TM_ENERGY);
+  h->timer.begin(gapk::TM_FORCE);
   gapk::force_rows_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, sp->X, sp->ld_x, M,
                        at<double>(h, S), M, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
                        at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
                        h->stream);
+  h->timer.end(gapk::TM_FORCE);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }
@@ -436,10 +481,14 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   gapk::QrWork qw;
   gapk::qr_bind_workspace(at<char>(h, q), m, M, &qw);
   double* Lm = at<double>(h, Lw);
+  h->timer.begin(gapk::TM_CHOL);
   gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->stream);
   gapk::scale_stack(A, ld, n_rows, M, y, sigma, Lm, M, h->stream);
-  gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream);
+  h->timer.end(gapk::TM_CHOL);
+  gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream, &h->timer);
+  h->timer.begin(gapk::TM_TRSV);
   gapk::back_substitute(A, ld, M, A + M * ld, c, h->dev_small, h->dev_err, h->stream);
+  h->timer.end(gapk::TM_TRSV);
   HIP_TRY(h, hipGetLastError());
   gap_fit_info inf;
   std::memset(&inf, 0, sizeof inf);
@@ -457,6 +506,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   if (refine_steps > 0) {
     const gap_atoms* a = train;
     const int64_t N = a->n_atoms;
+    h->timer.begin(gapk::TM_REFINE);
     gapk::atom_config(a->cfg_ptr, a->n_cfg, N, at<int32_t>(h, acfg), h->stream);
     for (int step = 0; step <= refine_steps; ++step) {
       // r = b - A_exact c, matrix-free in FP64: K c = [E_cfg ; F] from predict.
@@ -482,6 +532,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
       gapk::seminormal_solve(A, ld, M, at<double>(h, gvec), h->stream);
       gapk::axpy_f64(M, 1.0, at<double>(h, gvec), c, h->stream);
     }
+    h->timer.end(gapk::TM_REFINE);
     HIP_TRY(h, hipGetLastError());
     double rn[8];
     HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, (refine_steps + 1) * sizeof(double),
@@ -512,7 +563,9 @@ gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, 
                  pw);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
+  h->timer.begin(gapk::TM_PREDICT);
   run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces);
+  h->timer.end(gapk::TM_PREDICT);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }
@@ -538,12 +591,14 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   double* Wp = needW ? at<double>(h, W) : nullptr;
+  h->timer.begin(gapk::TM_BACKWARD);
   gapk::pstage_f64(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
                    sp->delta, c, g_e, nullptr, 0, Wp, ldw, nullptr, at<double>(h, dcp), h->stream);
   if (d_c) gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, d_c, h->stream);
   if (d_desc) gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
   if (d_X)
     gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D, h->stream);
+  h->timer.end(gapk::TM_BACKWARD);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }

@@ -6,12 +6,55 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <tuple>
+#include <vector>
+
 // Device status word bits (accumulated with atomicOr, read by synchronising calls).
 #define GAP_DEVERR_INDEX 1   // a pair target or pointer outside its range
 #define GAP_DEVERR_NOT_PD 2  // non-positive or non-finite Cholesky pivot
 #define GAP_DEVERR_RANK 4    // zero or non-finite diagonal of R
 
 namespace gapk {
+
+// Optional per-stage timing with HIP events recorded on the launch stream
+// (a profiling aid: off unless the caller enables it on the handle).
+enum TimerCat {
+  TM_PAIRS = 0, TM_KMM, TM_ENERGY, TM_FORCE, TM_CHOL, TM_QR_PANEL, TM_QR_UPDATE, TM_TRSV,
+  TM_PREDICT, TM_BACKWARD, TM_REFINE, TM_SPLIT, TM_COUNT
+};
+struct Timer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  hipEvent_t open[TM_COUNT] = {};
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
+  void begin(int c) {
+    if (!on) return;
+    if (hipEventCreate(&open[c]) != hipSuccess) return;
+    (void)hipEventRecord(open[c], st);
+  }
+  void end(int c) {
+    if (!on || !open[c]) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    pending.emplace_back(c, open[c], e);
+    open[c] = nullptr;
+  }
+  // Accumulate finished intervals into ms[c], count[c] (waits for the events).
+  void collect(double* ms, int64_t* count) {
+    for (auto& p : pending) {
+      float t = 0.f;
+      (void)hipEventSynchronize(std::get<2>(p));
+      if (hipEventElapsedTime(&t, std::get<1>(p), std::get<2>(p)) == hipSuccess) {
+        ms[std::get<0>(p)] += t;
+        count[std::get<0>(p)] += 1;
+      }
+      (void)hipEventDestroy(std::get<1>(p));
+      (void)hipEventDestroy(std::get<2>(p));
+    }
+    pending.clear();
+  }
+};
 
 // ---- pairs.hip ------------------------------------------------------------
 // tgt_ptr/tgt_pair (target-major pair view), pair_src, and the targets sorted
@@ -100,7 +143,7 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w);
 // Householder QR of the m x ncols col-major A (ncols = n + 1 with b last); R in the
 // upper triangle of the first n columns, Q^T b in column n.
 void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
-               hipStream_t st);
+               hipStream_t st, Timer* tm = nullptr);
 // x = R^-1 z (R upper n x n col-major in A, z = A[0:n][n]); records min/max |R_kk|
 // into rd[0..1] (device) and flags zero/non-finite pivots.
 void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,

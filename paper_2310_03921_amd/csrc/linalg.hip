@@ -656,11 +656,14 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
 }
 
 void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
-               hipStream_t st) {
+               hipStream_t st, Timer* tm) {
+  Timer dummy;
+  if (!tm) tm = &dummy;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter);
   const int64_t slab = qr_slab_rows(m);
   for (int64_t j0 = 0; j0 < n; j0 += kQrNB) {
     const int pw = (int)std::min<int64_t>(kQrNB, n - j0);
+    tm->begin(TM_QR_PANEL);
     for (int64_t k = j0; k <= j0 + pw; ++k) {
       const int64_t r_lo = (k > j0) ? k - 1 : k;
       const int64_t rows = m - r_lo;
@@ -668,8 +671,10 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
       hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, j0, pw, k, w->colstate,
                          w->red, w->counter);
     }
+    tm->end(TM_QR_PANEL);
     const int64_t nct = ncols - j0;  // columns from the panel start (V columns first)
     if (nct <= pw) continue;
+    tm->begin(TM_QR_UPDATE);
     const int64_t nslab = (m - j0 + slab - 1) / slab;
     hipLaunchKernelGGL(k_qr_vtc, dim3((unsigned)nslab, cdiv(nct, 64)), dim3(256), 0, st, A, ld, m,
                        j0, pw, nct, slab, w->part);
@@ -680,6 +685,7 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
                        w->T, w->Wt);
     hipLaunchKernelGGL(k_qr_update, dim3(cdiv(nct - pw, 64), cdiv(m - j0, 64)), dim3(256), 0, st,
                        A, ld, m, j0, pw, ncols, nct, w->Wt);
+    tm->end(TM_QR_UPDATE);
   }
 }
 

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2310_03921_amd", "libgap.so")
 
 def declared_symbols():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:gap_status|const char \*)\s*(gap_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:gap_status|const char \*|int)\s*(gap_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_verbs():
