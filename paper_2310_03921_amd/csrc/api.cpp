@@ -170,14 +170,39 @@ bool f32(gap_dtype d) { return d == GAP_DT_F32; }
 // that every row starts 32-byte aligned (vector loads).
 int64_t ld4(int64_t n) { return (n + 3) & ~int64_t(3); }
 
+// Split halves of X for the BF16x3 form.
+struct SplitWs {
+  size_t xh = 0, xl = 0, xth = 0, xtl = 0;
+};
+void layout_split(Layout& L, int64_t M, int64_t D, bool transposed, SplitWs& w) {
+  const int64_t n = M * gapk::split_ld(D);
+  w.xh = L.take(2 * n);
+  w.xl = L.take(2 * n);
+  if (transposed) {
+    const int64_t nt = D * gapk::split_ld(M);
+    w.xth = L.take(2 * nt);
+    w.xtl = L.take(2 * nt);
+  }
+}
+void run_split(gap_handle* h, const gap_sparse* sp, const SplitWs& w, bool transposed) {
+  h->timer.begin(gapk::TM_SPLIT);
+  gapk::split_x_bf16(sp->X, sp->ld_x, sp->M, sp->D, at<__bf16>(h, w.xh), at<__bf16>(h, w.xl),
+                     transposed ? at<__bf16>(h, w.xth) : nullptr,
+                     transposed ? at<__bf16>(h, w.xtl) : nullptr, h->stream);
+  h->timer.end(gapk::TM_SPLIT);
+}
+
 // Predict internals shared by gap_predict and the refinement residual.
 struct PredictWs {
   size_t W, e_atom, g, f_pair;
   PairWs pairs;
+  SplitWs split;
 };
 void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool need_g,
-                    bool need_eatom, bool need_gbuf, bool need_forces, PredictWs& w) {
+                    bool need_eatom, bool need_gbuf, bool need_forces, PredictWs& w,
+                    bool bf16 = false) {
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  if (bf16) layout_split(L, M, D, true, w.split);
   w.W = need_g ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1)) : 0;
   w.e_atom = need_eatom ? L.take(sizeof(double) * std::max<int64_t>(N, 1)) : 0;
   w.g = need_gbuf ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1)) : 0;
@@ -187,19 +212,33 @@ void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool ne
 
 void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
                  const PredictWs& w, double* e_atom, double* e_cfg, double* dEdd,
-                 double* forces) {
+                 double* forces, bool bf16 = false) {
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   const bool need_g = dEdd || forces;
   double* ea = e_atom ? e_atom : (e_cfg ? at<double>(h, w.e_atom) : nullptr);
   double* W = need_g ? at<double>(h, w.W) : nullptr;
   const int64_t ldw = ld4(M);
-  gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
-                   sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream);
+  auto wx = [&](double* out, int64_t ldo) {
+    if (bf16)
+      gapk::gemm_wx_bf16x3(W, ldw, N, M, at<__bf16>(h, w.split.xth), at<__bf16>(h, w.split.xtl), D,
+                           out, ldo, h->stream);
+    else
+      gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, out, ldo, h->stream);
+  };
+  if (bf16) {
+    run_split(h, sp, w.split, true);
+    gapk::pstage_bf16x3(0, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, w.split.xh),
+                        at<__bf16>(h, w.split.xl), M, D, sp->zeta, sp->delta, c, nullptr, W, ldw,
+                        ea, nullptr, h->stream);
+  } else {
+    gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                     sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream);
+  }
   if (e_cfg) gapk::segment_sum_f64(ea, a->cfg_ptr, a->n_cfg, N, e_cfg, h->stream);
   if (forces) {
     double* g = at<double>(h, w.g);
     const int64_t ldg = ld4(D);
-    gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, g, ldg, h->stream);
+    wx(g, ldg);
     if (dEdd) gapk::copy_rows_f64(g, ldg, dEdd, D, N, D, h->stream);
     run_pairs(h, a, w.pairs, false);
     gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg, at<int32_t>(h, w.pairs.src), N,
@@ -207,7 +246,7 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
                      at<int32_t>(h, w.pairs.tgt_pair), at<double>(h, w.f_pair), forces,
                      h->stream);
   } else if (dEdd) {
-    gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, dEdd, D, h->stream);
+    wx(dEdd, D);
   }
 }
 
@@ -384,14 +423,33 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   const int64_t n_rows = a->n_cfg + 3 * N;
   if (!Knm || ld < n_rows) return fail(h, GAP_E_INVALID, "Knm NULL or ld < n_cfg + 3 n_atoms");
-  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  if (prec != GAP_FP64 && prec != GAP_BF16X3) return fail(h, GAP_E_INVALID, "bad precision");
   Layout L;
   PairWs p;
   layout_pairs(L, N, a->n_pairs, p);
   const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * M, 1));
+  SplitWs sw;
+  if (prec == GAP_BF16X3) layout_split(L, M, D, false, sw);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   run_pairs(h, a, p, true);
+  if (prec == GAP_BF16X3) {
+    run_split(h, sp, sw, false);
+    h->timer.begin(gapk::TM_ENERGY);
+    gapk::energy_rows_bf16x3(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N,
+                             at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M, D, sp->zeta,
+                             sp->delta, Knm, ld, at<double>(h, S), M, h->stream);
+    h->timer.end(gapk::TM_ENERGY);
+    h->timer.begin(gapk::TM_FORCE);
+    gapk::force_rows_bf16x3(a->jac, f32(a->jac_dt), a->ld_jac, D, at<__bf16>(h, sw.xh),
+                            at<__bf16>(h, sw.xl), M, at<double>(h, S), M,
+                            at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+                            at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
+                            h->stream);
+    h->timer.end(gapk::TM_FORCE);
+    HIP_TRY(h, hipGetLastError());
+    return GAP_OK;
+  }
   h->timer.begin(gapk::TM_ENERGY);
   gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N, sp->X,
                         sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), M,
@@ -556,15 +614,16 @@ gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, 
   s = check_atoms(h, a, sp, forces != nullptr);
   if (s != GAP_OK) return s;
   if (!c) return fail(h, GAP_E_INVALID, "c is NULL");
-  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  if (prec != GAP_FP64 && prec != GAP_BF16X3) return fail(h, GAP_E_INVALID, "bad precision");
+  const bool bf = prec == GAP_BF16X3;
   Layout L;
   PredictWs pw;
   layout_predict(L, a, sp, dEdd || forces, e_cfg && !e_atom, forces != nullptr, forces != nullptr,
-                 pw);
+                 pw, bf);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   h->timer.begin(gapk::TM_PREDICT);
-  run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces);
+  run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces, bf);
   h->timer.end(gapk::TM_PREDICT);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
@@ -581,23 +640,46 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
   s = check_atoms(h, a, sp, false);
   if (s != GAP_OK) return s;
   if (!c || !g_e) return fail(h, GAP_E_INVALID, "c or g_e is NULL");
-  if (prec != GAP_FP64) return fail(h, GAP_E_UNSUPPORTED, "precision not available in this build");
+  if (prec != GAP_FP64 && prec != GAP_BF16X3) return fail(h, GAP_E_INVALID, "bad precision");
+  const bool bf = prec == GAP_BF16X3;
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   Layout L;
   const bool needW = d_desc || d_X;
   const int64_t ldw = ld4(M);
   const size_t W = needW ? L.take(sizeof(double) * std::max<int64_t>(N * ldw, 1)) : 0;
   const size_t dcp = L.take(sizeof(double) * (gapk::pstage_row_blocks(N) * M + 8));
+  SplitWs sw;
+  if (bf) layout_split(L, M, D, true, sw);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   double* Wp = needW ? at<double>(h, W) : nullptr;
   h->timer.begin(gapk::TM_BACKWARD);
-  gapk::pstage_f64(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
-                   sp->delta, c, g_e, nullptr, 0, Wp, ldw, nullptr, at<double>(h, dcp), h->stream);
+  if (bf) {
+    run_split(h, sp, sw, true);
+    gapk::pstage_bf16x3(1, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, sw.xh),
+                        at<__bf16>(h, sw.xl), M, D, sp->zeta, sp->delta, c, g_e, Wp, ldw, nullptr,
+                        at<double>(h, dcp), h->stream);
+  } else {
+    gapk::pstage_f64(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                     sp->delta, c, g_e, nullptr, 0, Wp, ldw, nullptr, at<double>(h, dcp),
+                     h->stream);
+  }
   if (d_c) gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, d_c, h->stream);
-  if (d_desc) gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
-  if (d_X)
-    gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D, h->stream);
+  if (d_desc) {
+    if (bf)
+      gapk::gemm_wx_bf16x3(Wp, ldw, N, M, at<__bf16>(h, sw.xth), at<__bf16>(h, sw.xtl), D, d_desc,
+                           D, h->stream);
+    else
+      gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
+  }
+  if (d_X) {
+    if (bf)
+      gapk::gemm_wtd_bf16x3(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D,
+                            h->stream);
+    else
+      gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D,
+                         h->stream);
+  }
   h->timer.end(gapk::TM_BACKWARD);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;

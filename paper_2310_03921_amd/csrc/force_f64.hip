@@ -127,6 +127,151 @@ __global__ __launch_bounds__(256) void k_force_rows(
   }
 }
 
+// LDS-resident variant for D <= 256: the block's 64 sparse-point columns of X
+// stay in LDS for its whole lifetime, stored in the order the matrix core
+// consumes them (per 16-k block, per 16-column tile, per lane: 4 doubles), so
+// every B fragment is one conflict-free 32-byte LDS read.  Each of the four
+// waves owns its own 16-target slot group; a block covers 64 targets x 64
+// columns.  Consecutive logical blocks on one XCD walk the column tiles of
+// the same 64 targets, so their Jacobian rows are fetched from HBM once and
+// then served from that XCD's L2.
+constexpr int kLdsNC = 4;
+constexpr int kLdsMaxKb = 16;  // D <= 256
+
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_force_rows_lds(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
+    int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
+    const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
+    int64_t per_xcd, int nkb) {
+  extern __shared__ double xs[];  // [nkb][kLdsNC][64 lanes][4]
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = ct * (16 * kLdsNC);
+
+  for (int e = threadIdx.x; e < nkb * kLdsNC * 64; e += 256) {
+    const int kb = e / (kLdsNC * 64), rem = e % (kLdsNC * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + u * 16 + (ln & 15);
+    double v[4];
+    if (col < M)
+      load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
+    else
+      zero_frag(v);
+    d4v w = {v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<d4v*>(xs + (size_t)e * 4) = w;
+  }
+  __syncthreads();
+
+  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  int64_t colr[kLdsNC];
+#pragma unroll
+  for (int u = 0; u < kLdsNC; ++u) colr[u] = colbase + u * 16 + idx;
+
+  d4v acc[3][kLdsNC];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int u = 0; u < kLdsNC; ++u) acc[a][u] = zero4();
+
+  const d4v* xb = reinterpret_cast<const d4v*>(xs) + lane;
+  for (int t = 0; t < maxdeg; ++t) {
+    int pair = t < deg ? tgt_pair[seg0 + t] : -1;
+    const int src = pair >= 0 ? pair_src[pair] : -1;
+    if (src < 0) pair = -1;
+    const bool pv = pair >= 0;
+    const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
+    d4v G[3][kLdsNC];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < kLdsNC; ++u) G[a][u] = zero4();
+
+    double a0[3][4], a1[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (pv) load4(jr + a * ldj, 4 * g, D, a0[a]); else zero_frag(a0[a]);
+    }
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (pv) load4(jr + a * ldj, (int64_t)(kb + 1) * 16 + 4 * g, D, a1[a]); else zero_frag(a1[a]);
+      }
+      {
+        d4v b[kLdsNC];
+#pragma unroll
+        for (int u = 0; u < kLdsNC; ++u) b[u] = xb[(kb * kLdsNC + u) * 64];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int u = 0; u < kLdsNC; ++u) G[a][u] = mfma_f64(a0[a][s4], b[u][s4], G[a][u]);
+      }
+      if (kb + 2 < nkb) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (pv) load4(jr + a * ldj, (int64_t)(kb + 2) * 16 + 4 * g, D, a0[a]); else zero_frag(a0[a]);
+        }
+      }
+      {
+        d4v b[kLdsNC];
+#pragma unroll
+        for (int u = 0; u < kLdsNC; ++u) b[u] = xb[((kb + 1) * kLdsNC + u) * 64];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int u = 0; u < kLdsNC; ++u) G[a][u] = mfma_f64(a1[a][s4], b[u][s4], G[a][u]);
+      }
+    }
+    if (kb < nkb) {
+      d4v b[kLdsNC];
+#pragma unroll
+      for (int u = 0; u < kLdsNC; ++u) b[u] = xb[(kb * kLdsNC + u) * 64];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int u = 0; u < kLdsNC; ++u) G[a][u] = mfma_f64(a0[a][s4], b[u][s4], G[a][u]);
+    }
+
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int src_r = __shfl(src, g + 4 * r);
+#pragma unroll
+      for (int u = 0; u < kLdsNC; ++u) {
+        const double sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, g + 4 * r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kLdsNC; ++u) {
+      if (colr[u] >= M) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -acc[a][u][r];
+    }
+  }
+}
+
 // f_pair[p][alpha] = J[p][alpha] . g[src(p)]; one wavefront per pair.
 template <typename TJ>
 __global__ __launch_bounds__(256) void k_pair_dots(const TJ* __restrict__ jac, int64_t ldj,
@@ -235,6 +380,37 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
                     const int32_t* tgt_pair, const int32_t* pair_src, const int32_t* order,
                     int64_t n_atoms, int64_t row0, double* K, int64_t ldk, hipStream_t st) {
   if (n_atoms <= 0 || M <= 0) return;
+  if (D <= 16 * kLdsMaxKb) {
+    const int nkb = (int)((D + 15) / 16);
+    const int64_t n_ct = (M + 16 * kLdsNC - 1) / (16 * kLdsNC);
+    const int64_t n_tgb = (n_atoms + 63) / 64;
+    const int64_t total = n_ct * n_tgb;
+    const int64_t per_xcd = (total + 7) / 8;
+    const size_t lds = (size_t)nkb * kLdsNC * 64 * 4 * sizeof(double);
+    dim3 grid((unsigned)(8 * per_xcd));
+    if (jac_f32) {
+      static bool attr_f = false;
+      if (!attr_f) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_lds<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 16 * kLdsNC * 64 * 4 * 8);
+        attr_f = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_lds<float>, grid, dim3(256), lds, st,
+                         reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+    } else {
+      static bool attr_d = false;
+      if (!attr_d) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_lds<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 16 * kLdsNC * 64 * 4 * 8);
+        attr_d = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_lds<double>, grid, dim3(256), lds, st,
+                         reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+    }
+    return;
+  }
   const int64_t n_ct = (M + 4 * 16 * kFNC - 1) / (4 * 16 * kFNC);
   const int64_t n_grp = (n_atoms + 15) / 16;
   const int64_t total = n_ct * n_grp;

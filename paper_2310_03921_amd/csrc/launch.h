@@ -119,6 +119,32 @@ void jac_transpose_apply_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t
                              int64_t n_pairs, const double* v, double* h, int64_t ldh,
                              hipStream_t st);
 
+// ---- mixed.hip (split-BF16, BF16x3) ---------------------------------------
+// Row length of split arrays: n rounded up to a multiple of 32 (zero padded).
+int64_t split_ld(int64_t n);
+// X -> hi/lo halves [M][split_ld(D)]; optionally also the transposed halves
+// [D][split_ld(M)] (Xth/Xtl may be null).
+void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh, __bf16* Xl,
+                  __bf16* Xth, __bf16* Xtl, hipStream_t st);
+void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
+                        int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
+                        int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
+                        double* S, int64_t ldS, hipStream_t st);
+void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
+                       const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                       const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
+                       const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
+                       int64_t ldk, hipStream_t st);
+void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                   const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
+                   double delta, const double* c, const double* g_e, double* W, int64_t ldw,
+                   double* e_atom, double* dc_part, hipStream_t st);
+void gemm_wx_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
+                    const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st);
+void gemm_wtd_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
+                     bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
+                     hipStream_t st);
+
 // ---- linalg.hip -----------------------------------------------------------
 // A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows;
 // rows n_rows .. n_rows+M-1: U = L^T from the lower factor L (col-major ldl), b = 0.

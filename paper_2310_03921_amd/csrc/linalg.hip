@@ -27,7 +27,13 @@ constexpr int kPanelMaxGrid = 256;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-GAP_DEV double vload(const double* p) { return *reinterpret_cast<const volatile double*>(p); }
+// Device-coherent load that the compiler may still pipeline (relaxed, agent scope):
+// used for values other blocks of the same launch wrote before a fence.
+GAP_DEV double vload(const double* p) {
+  const uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(double, bits);
+}
 
 // ----------------------------------------------------------- scale/stack ----
 __global__ void k_scale_stack(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
@@ -244,14 +250,27 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  for (int v = 0; v < ncnt; ++v) {
-    double s = (threadIdx.x < G) ? vload(red + (int64_t)v * G + threadIdx.x) : 0.0;
-    s = wave_sum(s);
-    if (lane == 0) s_red[wave][0] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) s_tot[v] = ((s_red[0][0] + s_red[1][0]) + s_red[2][0]) + s_red[3][0];
-    __syncthreads();
+  // Fixed-order reduction of the per-block partials: thread t sums blocks
+  // t, t + 256, ... (loads issued together), then a wave and block tree.
+  double tot[kQrNB];
+#pragma unroll
+  for (int v = 0; v < kQrNB; ++v) tot[v] = 0.0;
+  for (int b = threadIdx.x; b < G; b += 256) {
+#pragma unroll
+    for (int v = 0; v < kQrNB; ++v)
+      if (v < ncnt) tot[v] += vload(red + (int64_t)v * G + b);
   }
+#pragma unroll
+  for (int v = 0; v < kQrNB; ++v) {
+    if (v < ncnt) {
+      const double s = wave_sum(tot[v]);
+      if (lane == 0) s_red[wave][v] = s;
+    }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < ncnt; v += 256)
+    s_tot[v] = ((s_red[0][v] + s_red[1][v]) + s_red[2][v]) + s_red[3][v];
+  __syncthreads();
   double* cs = colstate + (k - j0) * kCS;
   if (threadIdx.x == 0) {
     const double alpha = vload(A + k + k * ld);
@@ -667,7 +686,7 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
     for (int64_t k = j0; k <= j0 + pw; ++k) {
       const int64_t r_lo = (k > j0) ? k - 1 : k;
       const int64_t rows = m - r_lo;
-      const unsigned G = std::max(1u, std::min(cdiv(rows, 1024), (unsigned)kPanelMaxGrid));
+      const unsigned G = std::max(1u, std::min(cdiv(rows, 512), (unsigned)kPanelMaxGrid));
       hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, j0, pw, k, w->colstate,
                          w->red, w->counter);
     }

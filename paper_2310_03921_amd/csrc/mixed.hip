@@ -1,0 +1,596 @@
+// Split-BF16 (BF16x3) forms of the descriptor and Jacobian contractions:
+// the same outputs as the FP64 kernels (energy rows + kernel-gradient scale,
+// force rows, predict P-stage, W X and W^T D), with every D . x and J . x
+// product formed on the BF16 matrix cores from hi/lo halves (see mma_bf16.h).
+// Kernel scales, pair accumulation and outputs stay in FP64 except the
+// per-target accumulation of force rows, which is FP32 (relative 1e-7,
+// below the split error).
+#include <algorithm>
+
+#include "launch.h"
+#include "mma_bf16.h"
+
+namespace gapk {
+
+namespace {
+
+constexpr int kNCb = 4;  // 16-column tiles per wave in the dense BF16x3 kernels
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ split ----
+// X [M][ldx] FP64 -> Xh/Xl [M][ldp] (ldp = D rounded up to 32, zero padded)
+// and, when Xth is given, the transposed halves Xth/Xtl [D][ldm] (ldm = M rounded to 32).
+__global__ void k_split_x(const double* __restrict__ X, int64_t ldx, int64_t M, int64_t D,
+                          __bf16* __restrict__ Xh, __bf16* __restrict__ Xl, int64_t ldp,
+                          __bf16* __restrict__ Xth, __bf16* __restrict__ Xtl, int64_t ldm) {
+  const int64_t rows = std::max(M, (int64_t)0);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * ldp;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / ldp, k = e - m * ldp;
+    const float x = (k < D) ? (float)X[m * ldx + k] : 0.f;
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    Xh[e] = h;
+    Xl[e] = l;
+    if (Xth && k < D) {
+      Xth[k * ldm + m] = h;
+      Xtl[k * ldm + m] = l;
+    }
+  }
+}
+
+__global__ void k_zero_bf16(__bf16* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (__bf16)0.0f;
+}
+
+// --------------------------------------------------------- energy rows ----
+template <typename TD>
+__global__ __launch_bounds__(256) void k_energy_rows_b3(
+    const TD* __restrict__ desc, int64_t ldd, const int64_t* __restrict__ cfg_ptr,
+    const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t ldp, int64_t M,
+    int64_t D, int zeta, double delta, double* __restrict__ K, int64_t ldk,
+    double* __restrict__ S, int64_t ldS, int64_t n_atoms) {
+  const int64_t c = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = (int64_t)blockIdx.x * 256 + wave * 64;
+  if (colbase >= M) return;
+  const int64_t a0 = max((int64_t)0, min(cfg_ptr[c], n_atoms));
+  const int64_t a1 = max(a0, min(cfg_ptr[c + 1], n_atoms));
+  Frag32Split fb[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    const int64_t cc = col < M ? col : 0;
+    fb[u] = Frag32Split{Xh + cc * ldp, Xl + cc * ldp, col < M};
+  }
+  const double d2 = delta * delta, d2z = d2 * zeta;
+  double e[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) e[u] = 0.0;
+  for (int64_t a = a0; a < a1; a += 16) {
+    const int64_t row = a + idx;
+    Frag32Row<TD> fa{desc + (row < a1 ? row : a0) * ldd, D, row < a1};
+    f4v acc[kNCb];
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
+    wave_mma_bf16x3<kNCb>(fa, fb, D, g, acc);
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) {
+      const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = a + 4 * g + r;
+        if (rr < a1) {
+          const double p = acc[u][r];
+          const double pz1 = ipow(p, zeta - 1);
+          e[u] += d2 * pz1 * p;
+          if (col < M) S[rr * ldS + col] = d2z * pz1;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    double v = e[u];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    const int64_t col = colbase + u * 16 + idx;
+    if (g == 0 && col < M) K[c + col * ldk] = v;
+  }
+}
+
+// ------------------------------------------------------------ force rows ----
+// As the FP64 LDS kernel: a block covers 64 targets (four slot groups of 16,
+// one per wave) x 16*NCF columns; the split halves of its X columns sit in
+// LDS in matrix-core order (per 32-k block, per column tile, per lane: 8 hi
+// then 8 lo), so each B fragment pair is one 32-byte LDS read.  Jacobian rows
+// are split in registers.
+constexpr int kNCF = 8;       // 128 columns per block
+constexpr int kMaxKb32 = 8;   // D <= 256
+
+struct SplitPair {
+  bf8v h, l;
+};
+
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_force_rows_b3(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
+    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const double* __restrict__ S,
+    int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
+    int64_t per_xcd, int nkb) {
+  extern __shared__ SplitPair xs2[];  // [nkb][kNCF][64]
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = ct * (16 * kNCF);
+
+  for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 256) {
+    const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + u * 16 + (ln & 15);
+    SplitPair sp;
+    if (col < M) {
+      const int64_t k = (int64_t)kb * 32 + 8 * (ln >> 4);
+      sp.h = *reinterpret_cast<const bf8v*>(Xh + col * ldp + k);
+      sp.l = *reinterpret_cast<const bf8v*>(Xl + col * ldp + k);
+    } else {
+      zero_split(sp.h, sp.l);
+    }
+    xs2[e] = sp;
+  }
+  __syncthreads();
+
+  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  int64_t colr[kNCF];
+#pragma unroll
+  for (int u = 0; u < kNCF; ++u) colr[u] = colbase + u * 16 + idx;
+
+  f4v acc[3][kNCF];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int u = 0; u < kNCF; ++u) acc[a][u] = zero4f();
+
+  const SplitPair* xb = xs2 + lane;
+  for (int t = 0; t < maxdeg; ++t) {
+    int pair = t < deg ? tgt_pair[seg0 + t] : -1;
+    const int src = pair >= 0 ? pair_src[pair] : -1;
+    if (src < 0) pair = -1;
+    const bool pv = pair >= 0;
+    const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
+    f4v G[3][kNCF];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u) G[a][u] = zero4f();
+    float nx[3][8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (pv) load8f(jr + a * ldj, 8 * g, D, nx[a]);
+      else
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nx[a][e] = 0.f;
+    }
+    for (int kb = 0; kb < nkb; ++kb) {
+      bf8v ah[3], al[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) split8(nx[a], ah[a], al[a]);
+      if (kb + 1 < nkb) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (pv) load8f(jr + a * ldj, (int64_t)(kb + 1) * 32 + 8 * g, D, nx[a]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u) {
+        const SplitPair b = xb[(kb * kNCF + u) * 64];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          G[a][u] = mfma_bf16(ah[a], b.h, G[a][u]);
+          G[a][u] = mfma_bf16(ah[a], b.l, G[a][u]);
+          G[a][u] = mfma_bf16(al[a], b.h, G[a][u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int src_r = __shfl(src, 4 * g + r);
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u) {
+        const float sv = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, 4 * g + r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kNCF; ++u) {
+      if (colr[u] >= M) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -(double)acc[a][u][r];
+    }
+  }
+}
+
+// General-D force rows: X halves streamed from global (L2) per wave.
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_force_rows_b3_global(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
+    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const double* __restrict__ S,
+    int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
+    int64_t per_xcd) {
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = ct * (16 * kNCb);
+  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  Frag32Split fb[kNCb];
+  int64_t colr[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    colr[u] = colbase + u * 16 + idx;
+    const int64_t cc = colr[u] < M ? colr[u] : 0;
+    fb[u] = Frag32Split{Xh + cc * ldp, Xl + cc * ldp, colr[u] < M};
+  }
+  f4v acc[3][kNCb];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) acc[a][u] = zero4f();
+  for (int t = 0; t < maxdeg; ++t) {
+    int pair = t < deg ? tgt_pair[seg0 + t] : -1;
+    const int src = pair >= 0 ? pair_src[pair] : -1;
+    if (src < 0) pair = -1;
+    const bool pv = pair >= 0;
+    const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
+    f4v G[3][kNCb];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) G[a][u] = zero4f();
+    for (int64_t k0 = 0; k0 < D; k0 += 32) {
+      bf8v bh[kNCb], bl[kNCb];
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Frag32Row<TJ> fa{jr + a * ldj, D, pv};
+        bf8v ah, al;
+        fa.frag(k0, g, ah, al);
+        f4v tmp[kNCb];
+#pragma unroll
+        for (int u = 0; u < kNCb; ++u) tmp[u] = G[a][u];
+        mma3_block<kNCb>(ah, al, bh, bl, tmp);
+#pragma unroll
+        for (int u = 0; u < kNCb; ++u) G[a][u] = tmp[u];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int src_r = __shfl(src, 4 * g + r);
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) {
+        const float sv = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, 4 * g + r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) {
+      if (colr[u] >= M) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -(double)acc[a][u][r];
+    }
+  }
+}
+
+// ------------------------------------------------------------- P-stage ----
+template <typename TD>
+__global__ __launch_bounds__(256) void k_pstage_b3(int mode, const TD* __restrict__ desc,
+                                                   int64_t ldd, int64_t n,
+                                                   const __bf16* __restrict__ Xh,
+                                                   const __bf16* __restrict__ Xl, int64_t ldp,
+                                                   int64_t M, int64_t D, int zeta, double delta,
+                                                   const double* __restrict__ cc,
+                                                   const double* __restrict__ g_e,
+                                                   double* __restrict__ W, int64_t ldw,
+                                                   double* __restrict__ e_atom,
+                                                   double* __restrict__ dc_part) {
+  __shared__ double colsum[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const bool rvalid = row < n;
+  Frag32Row<TD> fa{desc + (rvalid ? row : 0) * ldd, D, rvalid};
+  const double d2 = delta * delta, d2z = d2 * zeta;
+  double ge[4];
+  bool rv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t rr = rowbase + 4 * g + r;
+    rv[r] = rr < n;
+    ge[r] = (mode != 0 && rv[r]) ? g_e[rr] : 0.0;
+  }
+  double esum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t col0 = 0; col0 < M; col0 += 16 * kNCb) {
+    Frag32Split fb[kNCb];
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) {
+      const int64_t col = col0 + u * 16 + idx;
+      const int64_t c2 = col < M ? col : 0;
+      fb[u] = Frag32Split{Xh + c2 * ldp, Xl + c2 * ldp, col < M};
+    }
+    f4v acc[kNCb];
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
+    wave_mma_bf16x3<kNCb>(fa, fb, D, g, acc);
+#pragma unroll
+    for (int u = 0; u < kNCb; ++u) {
+      const int64_t col = col0 + u * 16 + idx;
+      const bool cvalid = col < M;
+      const double cm = (cvalid && cc) ? cc[col] : 0.0;
+      double csum = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = rowbase + 4 * g + r;
+        if (!rv[r] || !cvalid) continue;
+        const double p = acc[u][r];
+        const double pz1 = ipow(p, zeta - 1);
+        const double kval = d2 * pz1 * p;
+        if (mode == 0) {
+          esum[r] += cm * kval;
+          if (W) W[rr * ldw + col] = d2z * cm * pz1;
+        } else {
+          csum += ge[r] * kval;
+          if (W) W[rr * ldw + col] = ge[r] * d2z * cm * pz1;
+        }
+      }
+      if (mode != 0) {
+        csum += __shfl_xor(csum, 16);
+        csum += __shfl_xor(csum, 32);
+        if (g == 0) colsum[wave][u * 16 + idx] = csum;
+      }
+    }
+    if (mode != 0) {
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        const int64_t col = col0 + threadIdx.x;
+        if (col < M)
+          dc_part[(int64_t)blockIdx.x * M + col] =
+              ((colsum[0][threadIdx.x] + colsum[1][threadIdx.x]) + colsum[2][threadIdx.x]) +
+              colsum[3][threadIdx.x];
+      }
+      __syncthreads();
+    }
+  }
+  if (mode == 0 && e_atom) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = esum[r];
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+      const int64_t rr = rowbase + 4 * g + r;
+      if (idx == 0 && rr < n) e_atom[rr] = v;
+    }
+  }
+}
+
+// out[i][d] = sum_m W[i][m] X[m][d]  with X^T halves [D][ldm]
+__global__ __launch_bounds__(256) void k_gemm_wx_b3(const double* __restrict__ W, int64_t ldw,
+                                                    int64_t n, int64_t M,
+                                                    const __bf16* __restrict__ Xth,
+                                                    const __bf16* __restrict__ Xtl, int64_t ldm,
+                                                    int64_t D, double* __restrict__ out,
+                                                    int64_t ldo) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const int64_t colbase = (int64_t)blockIdx.y * 64;
+  Frag32Row<double> fa{W + (row < n ? row : 0) * ldw, M, row < n};
+  Frag32Split fb[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    const int64_t c2 = col < D ? col : 0;
+    fb[u] = Frag32Split{Xth + c2 * ldm, Xtl + c2 * ldm, col < D};
+  }
+  f4v acc[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
+  wave_mma_bf16x3<kNCb>(fa, fb, M, g, acc);
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + 4 * g + r;
+      if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+
+// out[m][d] = sum_i W[i][m] desc[i][d]
+template <typename TD>
+__global__ __launch_bounds__(256) void k_gemm_wtd_b3(const double* __restrict__ W, int64_t ldw,
+                                                     int64_t n, int64_t M,
+                                                     const TD* __restrict__ desc, int64_t ldd,
+                                                     int64_t D, double* __restrict__ out,
+                                                     int64_t ldo) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const int64_t colbase = (int64_t)blockIdx.y * 64;
+  Frag32Col<double> fa{W + (row < M ? row : 0), ldw, n, row < M};
+  Frag32Col<TD> fb[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = Frag32Col<TD>{desc + (col < D ? col : 0), ldd, n, col < D};
+  }
+  f4v acc[kNCb];
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
+  wave_mma_bf16x3<kNCb>(fa, fb, n, g, acc);
+#pragma unroll
+  for (int u = 0; u < kNCb; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + 4 * g + r;
+      if (rr < M && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+
+template <typename T>
+inline const T* tp(const void* p) {
+  return reinterpret_cast<const T*>(p);
+}
+
+}  // namespace
+
+int64_t split_ld(int64_t n) { return (n + 31) / 32 * 32; }
+
+void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh, __bf16* Xl,
+                  __bf16* Xth, __bf16* Xtl, hipStream_t st) {
+  const int64_t ldp = split_ld(D), ldm = split_ld(M);
+  if (Xth) {
+    const int64_t nt = D * ldm;
+    const unsigned gz = std::max(1u, std::min(cdiv(nt, 256), 65536u));
+    hipLaunchKernelGGL(k_zero_bf16, dim3(gz), dim3(256), 0, st, Xth, nt);
+    hipLaunchKernelGGL(k_zero_bf16, dim3(gz), dim3(256), 0, st, Xtl, nt);
+  }
+  const unsigned g = std::max(1u, std::min(cdiv(M * ldp, 256), 65536u));
+  hipLaunchKernelGGL(k_split_x, dim3(g), dim3(256), 0, st, X, ldx, M, D, Xh, Xl, ldp, Xth, Xtl,
+                     ldm);
+}
+
+void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
+                        int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
+                        int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
+                        double* S, int64_t ldS, hipStream_t st) {
+  if (n_cfg <= 0 || M <= 0) return;
+  const int64_t ldp = split_ld(D);
+  dim3 grid(cdiv(M, 256), (unsigned)n_cfg);
+  if (desc_f32)
+    hipLaunchKernelGGL(k_energy_rows_b3<float>, grid, dim3(256), 0, st, tp<float>(desc), ldd,
+                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+  else
+    hipLaunchKernelGGL(k_energy_rows_b3<double>, grid, dim3(256), 0, st, tp<double>(desc), ldd,
+                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+}
+
+void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
+                       const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                       const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
+                       const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
+                       int64_t ldk, hipStream_t st) {
+  if (n_atoms <= 0 || M <= 0) return;
+  const int64_t ldp = split_ld(D);
+  const int64_t n_tgb = (n_atoms + 63) / 64;
+  if (D <= 32 * kMaxKb32) {
+    const int nkb = (int)(ldp / 32);
+    const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
+    const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+    const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
+    const size_t lds_max = (size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair);
+    if (jac_f32) {
+      static bool a = false;
+      if (!a) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+        a = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_b3<float>, dim3((unsigned)(8 * per_xcd)), dim3(256), lds, st,
+                         tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                         pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+    } else {
+      static bool a = false;
+      if (!a) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+        a = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_b3<double>, dim3((unsigned)(8 * per_xcd)), dim3(256), lds,
+                         st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                         pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+    }
+    return;
+  }
+  const int64_t n_ct = (M + 16 * kNCb - 1) / (16 * kNCb);
+  const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+  if (jac_f32)
+    hipLaunchKernelGGL(k_force_rows_b3_global<float>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0,
+                       st, tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+  else
+    hipLaunchKernelGGL(k_force_rows_b3_global<double>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0,
+                       st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+}
+
+void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                   const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
+                   double delta, const double* c, const double* g_e, double* W, int64_t ldw,
+                   double* e_atom, double* dc_part, hipStream_t st) {
+  if (n <= 0 || M <= 0) return;
+  const int64_t ldp = split_ld(D);
+  dim3 grid((unsigned)((n + 63) / 64));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_pstage_b3<float>, grid, dim3(256), 0, st, mode, tp<float>(desc), ldd, n,
+                       Xh, Xl, ldp, M, D, zeta, delta, c, g_e, W, ldw, e_atom, dc_part);
+  else
+    hipLaunchKernelGGL(k_pstage_b3<double>, grid, dim3(256), 0, st, mode, tp<double>(desc), ldd,
+                       n, Xh, Xl, ldp, M, D, zeta, delta, c, g_e, W, ldw, e_atom, dc_part);
+}
+
+void gemm_wx_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
+                    const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st) {
+  if (n <= 0 || D <= 0) return;
+  hipLaunchKernelGGL(k_gemm_wx_b3, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
+                     Xth, Xtl, split_ld(M), D, out, ldo);
+}
+
+void gemm_wtd_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
+                     bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
+                     hipStream_t st) {
+  if (M <= 0 || D <= 0) return;
+  dim3 grid(cdiv(M, 64), cdiv(D, 64));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_gemm_wtd_b3<float>, grid, dim3(256), 0, st, W, ldw, n, M,
+                       tp<float>(desc), ldd, D, out, ldo);
+  else
+    hipLaunchKernelGGL(k_gemm_wtd_b3<double>, grid, dim3(256), 0, st, W, ldw, n, M,
+                       tp<double>(desc), ldd, D, out, ldo);
+}
+
+}  // namespace gapk

@@ -1,0 +1,163 @@
+// Split-BF16 ("BF16x3") contractions on the gfx950 BF16 matrix cores.
+//
+// A value x is rounded to FP32 (round to nearest even), then split into
+//   hi = bf16(x),  lo = bf16(x - hi)
+// (both round to nearest even).  A product x*y is formed as
+//   hi_x*hi_y + hi_x*lo_y + lo_x*hi_y
+// with FP32 accumulation in the matrix core; lo*lo (relative size ~2^-16) is
+// dropped.  This keeps ~16 significant bits per operand and FP32 accumulation.
+//
+// v_mfma_f32_16x16x32_bf16: D(16x16, f32) = A(16x32) B(32x16) + C.
+// Lane l (group g = l / 16, idx = l % 16) feeds A[idx][8 g + e] and
+// B[8 g + e][idx] for e = 0..7, and holds D[4 g + r][idx] for r = 0..3
+// (layout checked on gfx950 with an in-bounds probe).
+#pragma once
+
+#include "common.h"
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f8v __attribute__((ext_vector_type(8)));
+
+GAP_DEV f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+GAP_DEV f4v zero4f() { f4v z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+GAP_DEV void split8(const float x[8], bf8v& hi, bf8v& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+GAP_DEV void zero_split(bf8v& hi, bf8v& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    hi[e] = (__bf16)0.0f;
+    lo[e] = (__bf16)0.0f;
+  }
+}
+
+// Eight consecutive elements row[k .. k+7] as FP32 (zero at or beyond kmax);
+// k % 8 == 0 and the row storage extends to k + 3 whenever k < kmax
+// (leading dimensions are multiples of 4), so reads use 4-wide vectors.
+GAP_DEV void load8f(const double* __restrict__ row, int64_t k, int64_t kmax, float out[8]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t kk = k + 4 * h;
+    if (kk < kmax) {
+      d4v v = *reinterpret_cast<const d4v*>(row + kk);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[4 * h + s] = (kk + s < kmax) ? (float)v[s] : 0.f;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[4 * h + s] = 0.f;
+    }
+  }
+}
+
+GAP_DEV void load8f(const float* __restrict__ row, int64_t k, int64_t kmax, float out[8]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t kk = k + 4 * h;
+    if (kk < kmax) {
+      f4v v = *reinterpret_cast<const f4v*>(row + kk);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[4 * h + s] = (kk + s < kmax) ? v[s] : 0.f;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[4 * h + s] = 0.f;
+    }
+  }
+}
+
+// Element (idx, k) at row[k]: contiguous along k, split on the fly.
+template <typename T>
+struct Frag32Row {
+  const T* row;
+  int64_t kmax;
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, bf8v& hi, bf8v& lo) const {
+    if (!valid) {
+      zero_split(hi, lo);
+      return;
+    }
+    float x[8];
+    load8f(row, k0 + 8 * g, kmax, x);
+    split8(x, hi, lo);
+  }
+};
+
+// Element (idx, k) at col[k * ld]: contiguous along idx, split on the fly.
+template <typename T>
+struct Frag32Col {
+  const T* col;
+  int64_t ld;
+  int64_t kmax;
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, bf8v& hi, bf8v& lo) const {
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + 8 * g + e;
+      x[e] = (valid && k < kmax) ? (float)col[k * ld] : 0.f;
+    }
+    split8(x, hi, lo);
+  }
+};
+
+// Pre-split rows: hi/lo arrays padded with zeros to a multiple of 32 along k.
+struct Frag32Split {
+  const __bf16* hi;
+  const __bf16* lo;
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, bf8v& h, bf8v& l) const {
+    if (!valid) {
+      zero_split(h, l);
+      return;
+    }
+    h = *reinterpret_cast<const bf8v*>(hi + k0 + 8 * g);
+    l = *reinterpret_cast<const bf8v*>(lo + k0 + 8 * g);
+  }
+};
+
+template <int NC>
+GAP_DEV void mma3_block(const bf8v& ah, const bf8v& al, const bf8v (&bh)[NC], const bf8v (&bl)[NC],
+                        f4v (&acc)[NC]) {
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    acc[u] = mfma_bf16(ah, bh[u], acc[u]);
+    acc[u] = mfma_bf16(ah, bl[u], acc[u]);
+    acc[u] = mfma_bf16(al, bh[u], acc[u]);
+  }
+}
+
+// acc[u] += A(16 x K) B_u(K x 16) in BF16x3 over k in [0, K) (K padded to 32 by zeros).
+template <int NC, class FA, class FB>
+GAP_DEV void wave_mma_bf16x3(const FA& fa, const FB (&fb)[NC], int64_t K, int g, f4v (&acc)[NC]) {
+  for (int64_t k0 = 0; k0 < K; k0 += 32) {
+    bf8v ah, al, bh[NC], bl[NC];
+    fa.frag(k0, g, ah, al);
+#pragma unroll
+    for (int u = 0; u < NC; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
+    mma3_block<NC>(ah, al, bh, bl, acc);
+  }
+}
+
+// Two A operands against the same B tiles.
+template <int NC, class FA0, class FA1, class FB>
+GAP_DEV void wave_mma2_bf16x3(const FA0& fa0, const FA1& fa1, const FB (&fb)[NC], int64_t K, int g,
+                              f4v (&acc0)[NC], f4v (&acc1)[NC]) {
+  for (int64_t k0 = 0; k0 < K; k0 += 32) {
+    bf8v a0h, a0l, a1h, a1l, bh[NC], bl[NC];
+    fa0.frag(k0, g, a0h, a0l);
+    fa1.frag(k0, g, a1h, a1l);
+#pragma unroll
+    for (int u = 0; u < NC; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
+    mma3_block<NC>(a0h, a0l, bh, bl, acc0);
+    mma3_block<NC>(a1h, a1l, bh, bl, acc1);
+  }
+}

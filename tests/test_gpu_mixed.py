@@ -1,0 +1,125 @@
+"""Split-BF16 (BF16x3) form against the FP64 oracle, and FP64 iterative refinement.
+
+Bounds (relative to max|oracle| of each output block) follow from the split:
+hi + lo keeps ~16 significant bits of each FP32-rounded operand, products
+are accumulated in FP32 over D <= 256 terms, so K_NM, energies and gradients
+carry relative errors of order 1e-5; the bounds below leave a factor ~10.
+After refinement with an exact FP64 residual, c must match the FP64 solution
+to the FP64 bound (1e-10).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def gapx():
+    import paper_2310_03921_amd as g
+    assert torch.cuda.is_available(), "GPU tests need a gfx950 device"
+    return g
+
+
+@pytest.fixture(scope="module")
+def gap(gapx):
+    return gapx.Gap(0)
+
+
+def relmax(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def setup(gapx, w):
+    b = synth.generate(w)
+    X = synth.sparse_points(w, b)
+    atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
+    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+    return b, X, atoms, sp
+
+
+@pytest.mark.parametrize("wname,jdt", [("fit_small_mixed", "f64"), ("fit_small_mixed", "f32"),
+                                       ("ragged", "f64")])
+def test_knm_bf16x3(gapx, gap, wname, jdt):
+    if wname == "ragged":
+        w = synth.Workload("ragged", 31, n_cfg=9, atoms_lo=1, atoms_hi=23, D=37, nb=3, M=23,
+                           zeta=3, delta=1.7, precision="bf16x3")
+    else:
+        w = synth.WORKLOADS[wname].with_(jac_dtype=jdt, desc_dtype=jdt)
+    b, X, atoms, sp = setup(gapx, w)
+    A = gap.build_knm(atoms, sp, precision="bf16x3")
+    got = A[:w.M, :b.n_rows].T.cpu().numpy()
+    ref = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    e_e = relmax(got[:b.n_cfg], ref[:b.n_cfg])
+    e_f = relmax(got[b.n_cfg:], ref[b.n_cfg:])
+    print(f"\n{wname}/{jdt}: K_E rel {e_e:.2e}, K_F rel {e_f:.2e}")
+    assert e_e <= MIXED_TOL and e_f <= MIXED_TOL
+    assert e_f > 0  # the split path really ran (not the FP64 kernels)
+
+
+def test_fit_mixed_with_refinement(gapx, gap):
+    """Precision form of the small fit: c, energy RMSE, force RMSE vs the FP64 oracle."""
+    w = synth.WORKLOADS["fit_small_mixed"]
+    b, X, atoms, sp = setup(gapx, w)
+    K = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = oracle.build_kmm(X, w.zeta, w.delta)
+    y = K @ synth.hidden_coefficients(w) + synth.noise(w, b.cfg_ids, b.counts)
+    sig = synth.sigma_rows(w, b.counts)
+    c_ref = oracle.fit(K, Kmm, y, sig, w.jitter)
+    yd, sd = torch.tensor(y, device="cuda"), torch.tensor(sig, device="cuda")
+    Kmm_d = gap.build_kmm(sp)
+    out = {}
+    for steps in (0, 3):
+        A = gap.build_knm(atoms, sp, precision="bf16x3")
+        c, info = gap.fit(A, b.n_rows, Kmm_d, yd, sd, w.jitter, sp, train=atoms,
+                          refine_steps=steps)
+        c = c.cpu().numpy()
+        rel = np.linalg.norm(c - c_ref) / np.linalg.norm(c_ref)
+        e_ref = K[:b.n_cfg] @ c_ref
+        f_ref = K[b.n_cfg:] @ c_ref
+        n_c = b.counts.astype(float)
+        e_rmse = np.sqrt(np.mean(((K[:b.n_cfg] @ c - e_ref) / n_c) ** 2))
+        f_rmse = np.sqrt(np.mean((K[b.n_cfg:] @ c - f_ref) ** 2))
+        out[steps] = (rel, e_rmse, f_rmse, info["resid_norm"])
+        print(f"\nrefine={steps}: c rel {rel:.2e}, energy RMSE {e_rmse:.2e}/atom, "
+              f"force RMSE {f_rmse:.2e}, |A^T r| {info['resid_norm']}")
+    assert out[0][0] <= 1e-4 and out[0][1] <= 1e-6 and out[0][2] <= 1e-5
+    assert out[3][0] <= 1e-10
+    rn = out[3][3]
+    assert rn[-1] < rn[0]
+
+
+def test_predict_bf16x3(gapx, gap):
+    w = synth.WORKLOADS["fit_small"]
+    b, X, atoms, sp = setup(gapx, w)
+    c = np.random.default_rng(2).standard_normal(w.M)
+    out = gap.predict(atoms, sp, torch.tensor(c, device="cuda"), precision="bf16x3", dEdd=True,
+                      forces=True)
+    e, ec, g, F = oracle.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, c, w.zeta,
+                                 w.delta)
+    for name, ref in (("e_atom", e), ("e_cfg", ec), ("dEdd", g), ("forces", F)):
+        r = relmax(out[name].cpu().numpy(), ref)
+        print(f"\npredict bf16x3 {name}: rel {r:.2e}")
+        assert r <= MIXED_TOL, name
+
+
+def test_backward_bf16x3(gapx, gap):
+    w = synth.WORKLOADS["fit_small"]
+    b, X, atoms, sp = setup(gapx, w)
+    rng = np.random.default_rng(3)
+    c = rng.standard_normal(w.M)
+    ge = rng.standard_normal(b.n_atoms)
+    dd, dc, dX = gap.predict_backward(atoms, sp, torch.tensor(c, device="cuda"),
+                                      torch.tensor(ge, device="cuda"), precision="bf16x3")
+    r_dd, r_dc, r_dX = oracle.predict_backward(b.desc, X, c, ge, w.zeta, w.delta)
+    for name, got, ref in (("d_desc", dd, r_dd), ("d_c", dc, r_dc), ("d_X", dX, r_dX)):
+        r = relmax(got.cpu().numpy(), ref)
+        print(f"\nbackward bf16x3 {name}: rel {r:.2e}")
+        assert r <= MIXED_TOL, name
