@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--workload", default="fit_fp64")
     ap.add_argument("--cpu-sample-cfgs", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--refine-steps", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,9 +158,60 @@ def main():
     qr_flops = 2.0 * (n_rows + M) * (M + 1) ** 2 - 2.0 / 3.0 * (M + 1) ** 3
     qr_ms = per.get("qr_panel", 0) + per.get("qr_update", 0)
 
-    # sanity of the solution: normal-equation residual is reported by a separate test;
-    # here only that c is finite
     assert torch.isfinite(c).all().item(), "non-finite coefficients"
+    c64 = c.clone()
+
+    mixed = None
+    if not args.no_mixed:
+        def mixed_step():
+            gap.build_kmm(sp, out=Kmm)
+            gap.build_knm(atoms, sp, precision="bf16x3", out=A)
+            return gap.fit(A, n_rows, Kmm, y, sigma, w.jitter, sp, train=atoms,
+                           refine_steps=args.refine_steps)
+        mixed_step()
+        torch.cuda.synchronize()
+        log("mixed warmup done")
+        gap.timing(True)
+        gap.timing_read(reset=True)
+        tm = []
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            cmx, minfo = mixed_step()
+            torch.cuda.synchronize()
+            tm.append(time.perf_counter() - ts)
+            log(f"mixed step {i + 1}/{args.steps}: {tm[-1] * 1e3:.1f} ms")
+        mst = gap.timing_read(reset=True)
+        gap.timing(False)
+        mper = {k: (v[0] / args.steps) for k, v in mst.items() if v[1] > 0}
+        # accuracy against the FP64 fit and against the noise-free truth (forces from c*)
+        ref = gap.predict(atoms, sp, cstar, e_atom=False, e_cfg=True, forces=True)
+        p64 = gap.predict(atoms, sp, c64, e_atom=False, e_cfg=True, forces=True)
+        pmx = gap.predict(atoms, sp, cmx, e_atom=False, e_cfg=True, forces=True)
+        nat = torch.tensor(b.counts, dtype=torch.float64, device="cuda")
+
+        def rmse(a, b_):
+            return float(torch.sqrt(torch.mean((a - b_) ** 2)))
+        mknm = mper.get("split_bf16", 0) + mper.get("pair_transpose", 0) + \
+            mper.get("energy_rows", 0) + mper.get("force_rows", 0)
+        mforce_flops_exec = 3.0 * 2.0 * 3.0 * b.n_pairs * M * (((D + 31) // 32) * 32)
+        mixed = {
+            "fit_s": float(np.mean(tm)),
+            "refine_steps": args.refine_steps,
+            "stage_ms": {k: round(v, 3) for k, v in mper.items()},
+            "knm_ms": mknm,
+            "knm_gflops_algorithmic": knm_flops / (mknm * 1e-3) / 1e9 if mknm > 0 else None,
+            "force_rows_bf16_tflops_executed": mforce_flops_exec / (mper.get("force_rows", float("nan")) * 1e-3) / 1e12,
+            "force_rows_bf16_frac_of_2500": mforce_flops_exec / (mper.get("force_rows", float("nan")) * 1e-3) / 1e12 / 2500.0,
+            "c_rel_vs_fp64": float(torch.linalg.norm(cmx - c64) / torch.linalg.norm(c64)),
+            "resid_norm": minfo["resid_norm"],
+            "force_rmse_vs_truth": {"fp64": rmse(p64["forces"], ref["forces"]),
+                                    "mixed": rmse(pmx["forces"], ref["forces"])},
+            "force_rmse_mixed_vs_fp64": rmse(pmx["forces"], p64["forces"]),
+            "energy_rmse_per_atom_vs_truth": {
+                "fp64": rmse(p64["e_cfg"] / nat, ref["e_cfg"] / nat),
+                "mixed": rmse(pmx["e_cfg"] / nat, ref["e_cfg"] / nat)},
+        }
+        log(f"mixed fit {mixed['fit_s'] * 1e3:.1f} ms, c rel vs fp64 {mixed['c_rel_vs_fp64']:.2e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +243,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "flops_per_launch": force_flops},
         "cpu_baseline": cpu,
+        "mixed_bf16x3": mixed,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
     }
     print(json.dumps(out), flush=True)
