@@ -162,6 +162,7 @@ struct QrWork {
   double* T;          // nb x nb
   double* colstate;   // per column: tau, beta, scale, then tw[nb]
   double* red;        // panel reduction partials
+  double* tau;        // tau of every reflector [n]
   unsigned int* counter;
 };
 size_t qr_workspace_bytes(int64_t m, int64_t n);

@@ -21,7 +21,8 @@ namespace gapk {
 
 namespace {
 
-constexpr int kQrNB = 64;      // panel width
+constexpr int kQrNB = 64;      // outer block width (compact-WY trailing update)
+constexpr int kPanelW = 32;    // inner panel width (column-by-column factorisation)
 constexpr int kCholNB = 64;    // Cholesky block
 constexpr int kPanelMaxGrid = 256;
 
@@ -155,18 +156,19 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ Lw, in
 }
 
 // ------------------------------------------------------------------- QR ----
-// Column state of the current panel, per column: tau, beta, scale, tw[kQrNB]
-// where tw[j] = tau * (v^T a_j) for the panel columns j to its right.
-constexpr int kCS = kQrNB + 3;
+// Column state of the current inner panel, per column: tau, beta, scale,
+// tw[kPanelW] where tw[j] = tau * (v^T a_j) for the panel columns j to its right.
+constexpr int kCS = kPanelW + 3;
 
 __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t ld, int64_t m,
                                                 int64_t j0, int pw, int64_t k,
                                                 double* __restrict__ colstate,
                                                 double* __restrict__ red,
-                                                unsigned int* __restrict__ counter) {
-  __shared__ double s_tw[kQrNB];
-  __shared__ double s_red[4][kQrNB];
-  __shared__ double s_tot[kQrNB];
+                                                unsigned int* __restrict__ counter,
+                                                double* __restrict__ tau_all) {
+  __shared__ double s_tw[kPanelW];
+  __shared__ double s_red[4][kPanelW];
+  __shared__ double s_tot[kPanelW];
   __shared__ int s_last;
   __shared__ double s_par[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -179,59 +181,60 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
     const double* cs = colstate + (prev - j0) * kCS;
     beta_p = cs[1];
     scale_p = cs[2];
-    for (int j = threadIdx.x; j < kQrNB; j += 256) s_tw[j] = cs[3 + j];
+    for (int j = threadIdx.x; j < kPanelW; j += 256) s_tw[j] = cs[3 + j];
   }
   __syncthreads();
   const int ncnt = has_next ? (int)(pend - k) : 0;  // sigma, then d_{k+1} .. d_{pend-1}
-  double part[kQrNB];
+  double part[kPanelW];
 #pragma unroll
-  for (int jj = 0; jj < kQrNB; ++jj) part[jj] = 0.0;
+  for (int jj = 0; jj < kPanelW; ++jj) part[jj] = 0.0;
 
   const int64_t r_lo = has_prev ? prev : k;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // Columns touched this pass: jb .. pend-1 (jb = prev when a reflector is applied).
+  const int64_t jb = has_prev ? prev : k;
+  const int nc = (int)(pend - jb);
   for (int64_t r = r_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += stride) {
+    // all loads of the row first (independent, issued together), then compute, then store
+    double a[kPanelW + 1];
+    double* rp = A + jb * ld + r;  // column offsets jj * ld are uniform across the wave
+#pragma unroll
+    for (int jj = 0; jj <= kPanelW; ++jj) a[jj] = (jj < nc) ? rp[jj * ld] : 0.0;
     const bool acc_row = has_next && r > k;
+    int o = 0;  // offset of column k in a[]
     if (has_prev) {
       double v;
       if (r == prev) {
         v = 1.0;
-        A[prev + prev * ld] = beta_p;
+        a[0] = beta_p;
       } else {
-        v = A[r + prev * ld] * scale_p;
-        A[r + prev * ld] = v;
+        v = a[0] * scale_p;
+        a[0] = v;
       }
-      double ak = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < kQrNB; ++jj) {
-        const int64_t j = k + jj;
-        if (j < pend) {
-          const double a = A[r + j * ld] - s_tw[j - j0] * v;
-          A[r + j * ld] = a;
-          if (acc_row) {
-            if (jj == 0) {
-              ak = a;
-              part[0] += a * a;
-            } else {
-              part[jj] += ak * a;
-            }
-          }
-        }
-      }
-    } else if (acc_row) {
-      const double ak = A[r + k * ld];
+      for (int jj = 1; jj <= kPanelW; ++jj)
+        if (jj < nc) a[jj] -= s_tw[jb + jj - j0] * v;
+      o = 1;
+    }
+    if (acc_row) {
+      const double ak = has_prev ? a[1] : a[0];
       part[0] += ak * ak;
 #pragma unroll
-      for (int jj = 1; jj < kQrNB; ++jj) {
-        const int64_t j = k + jj;
-        if (j < pend) part[jj] += ak * A[r + j * ld];
-      }
+      for (int jj = 1; jj < kPanelW; ++jj)
+        if (jj < ncnt) part[jj] += ak * (has_prev ? a[jj + 1] : a[jj]);
     }
+    if (has_prev) {
+#pragma unroll
+      for (int jj = 0; jj <= kPanelW; ++jj)
+        if (jj < nc) rp[jj * ld] = a[jj];
+    }
+    (void)o;
   }
   if (!has_next) return;
 
   // block partial sums -> red[v * gridDim.x + block]
 #pragma unroll
-  for (int v = 0; v < kQrNB; ++v) {
+  for (int v = 0; v < kPanelW; ++v) {
     if (v < ncnt) {
       const double s = wave_sum(part[v]);
       if (lane == 0) s_red[wave][v] = s;
@@ -252,16 +255,16 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
   __threadfence();
   // Fixed-order reduction of the per-block partials: thread t sums blocks
   // t, t + 256, ... (loads issued together), then a wave and block tree.
-  double tot[kQrNB];
+  double tot[kPanelW];
 #pragma unroll
-  for (int v = 0; v < kQrNB; ++v) tot[v] = 0.0;
+  for (int v = 0; v < kPanelW; ++v) tot[v] = 0.0;
   for (int b = threadIdx.x; b < G; b += 256) {
 #pragma unroll
-    for (int v = 0; v < kQrNB; ++v)
+    for (int v = 0; v < kPanelW; ++v)
       if (v < ncnt) tot[v] += vload(red + (int64_t)v * G + b);
   }
 #pragma unroll
-  for (int v = 0; v < kQrNB; ++v) {
+  for (int v = 0; v < kPanelW; ++v) {
     if (v < ncnt) {
       const double s = wave_sum(tot[v]);
       if (lane == 0) s_red[wave][v] = s;
@@ -284,6 +287,7 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
     cs[0] = tau;
     cs[1] = beta;
     cs[2] = scale;
+    tau_all[k] = tau;
     s_par[0] = tau;
     s_par[1] = scale;
     *counter = 0u;
@@ -363,7 +367,7 @@ __global__ void k_sum_slabs(const double* __restrict__ part, int64_t nslab, int6
 
 // T (pw x pw upper, row-major ld kQrNB): T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
 __global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, int64_t nct, int pw,
-                                                  const double* __restrict__ colstate,
+                                                  const double* __restrict__ tau,
                                                   double* __restrict__ T) {
   __shared__ double sT[kQrNB][kQrNB + 1];
   __shared__ double sG[kQrNB][kQrNB + 1];
@@ -374,14 +378,14 @@ __global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, 
   }
   __syncthreads();
   for (int i = 0; i < pw; ++i) {
-    const double tau = colstate[i * kCS];
+    const double ti = tau[i];
     double z = 0.0;
     const int l = threadIdx.x;
     if (l < i)
       for (int q = l; q < i; ++q) z += sT[l][q] * sG[q][i];
     __syncthreads();
-    if (l < i) sT[l][i] = -tau * z;
-    if (l == i) sT[i][i] = tau;
+    if (l < i) sT[l][i] = -ti * z;
+    if (l == i) sT[i][i] = ti;
     __syncthreads();
   }
   for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) T[e] = sT[e / kQrNB][e % kQrNB];
@@ -651,6 +655,7 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
   d += (size_t)kQrNB * kQrNB;                // T
   d += (size_t)kQrNB * kCS;                  // colstate
   d += (size_t)kQrNB * kPanelMaxGrid;        // red
+  d += (size_t)n + 8;                        // tau
   return d * sizeof(double) + 256;
 }
 
@@ -671,7 +676,28 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   p += kQrNB * kCS;
   w->red = p;
   p += kQrNB * kPanelMaxGrid;
+  w->tau = p;
+  p += n + 8;
   w->counter = reinterpret_cast<unsigned int*>(p);
+}
+
+// Compact-WY update of columns [c0, c_end) with the pw reflectors stored in
+// columns [j0, j0 + pw): W = V^T A[j0:m, j0:c_end) (Gram V^T V included),
+// T from the Gram and tau, then A[j0:m, c0:c_end) -= V (T^T W).
+static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, int64_t c_end,
+                         int64_t slab, QrWork* w, hipStream_t st) {
+  const int64_t nct = c_end - j0;
+  if (nct <= pw) return;
+  const int64_t nslab = (m - j0 + slab - 1) / slab;
+  hipLaunchKernelGGL(k_qr_vtc, dim3((unsigned)nslab, cdiv(nct, 64)), dim3(256), 0, st, A, ld, m, j0,
+                     pw, nct, slab, w->part);
+  hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
+                     (int64_t)pw * nct, w->W);
+  hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
+  hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw, w->T,
+                     w->Wt);
+  hipLaunchKernelGGL(k_qr_update, dim3(cdiv(nct - pw, 64), cdiv(m - j0, 64)), dim3(256), 0, st, A,
+                     ld, m, j0, pw, c_end, nct, w->Wt);
 }
 
 void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
@@ -681,29 +707,24 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter);
   const int64_t slab = qr_slab_rows(m);
   for (int64_t j0 = 0; j0 < n; j0 += kQrNB) {
-    const int pw = (int)std::min<int64_t>(kQrNB, n - j0);
-    tm->begin(TM_QR_PANEL);
-    for (int64_t k = j0; k <= j0 + pw; ++k) {
-      const int64_t r_lo = (k > j0) ? k - 1 : k;
-      const int64_t rows = m - r_lo;
-      const unsigned G = std::max(1u, std::min(cdiv(rows, 512), (unsigned)kPanelMaxGrid));
-      hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, j0, pw, k, w->colstate,
-                         w->red, w->counter);
+    const int bw = (int)std::min<int64_t>(kQrNB, n - j0);
+    for (int64_t i0 = j0; i0 < j0 + bw; i0 += kPanelW) {
+      const int pw = (int)std::min<int64_t>(kPanelW, j0 + bw - i0);
+      tm->begin(TM_QR_PANEL);
+      for (int64_t k = i0; k <= i0 + pw; ++k) {
+        const int64_t r_lo = (k > i0) ? k - 1 : k;
+        const int64_t rows = m - r_lo;
+        const unsigned G = std::max(1u, std::min(cdiv(rows, 512), (unsigned)kPanelMaxGrid));
+        hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, i0, pw, k, w->colstate,
+                           w->red, w->counter, w->tau);
+      }
+      // rest of the outer block with this inner panel's reflectors
+      qr_wy_update(A, ld, m, i0, pw, j0 + bw, slab, w, st);
+      tm->end(TM_QR_PANEL);
     }
-    tm->end(TM_QR_PANEL);
-    const int64_t nct = ncols - j0;  // columns from the panel start (V columns first)
-    if (nct <= pw) continue;
+    if (j0 + bw >= ncols) continue;
     tm->begin(TM_QR_UPDATE);
-    const int64_t nslab = (m - j0 + slab - 1) / slab;
-    hipLaunchKernelGGL(k_qr_vtc, dim3((unsigned)nslab, cdiv(nct, 64)), dim3(256), 0, st, A, ld, m,
-                       j0, pw, nct, slab, w->part);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
-                       (int64_t)pw * nct, w->W);
-    hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->colstate, w->T);
-    hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw,
-                       w->T, w->Wt);
-    hipLaunchKernelGGL(k_qr_update, dim3(cdiv(nct - pw, 64), cdiv(m - j0, 64)), dim3(256), 0, st,
-                       A, ld, m, j0, pw, ncols, nct, w->Wt);
+    qr_wy_update(A, ld, m, j0, bw, ncols, slab, w, st);
     tm->end(TM_QR_UPDATE);
   }
 }
