@@ -140,6 +140,8 @@ gap_status drain_dev_err(gap_handle* h) {
     return fail(h, GAP_E_RANK, "least-squares matrix is rank deficient (zero pivot in R)");
   if (v & GAP_DEVERR_INDEX)
     return fail(h, GAP_E_INVALID, "index data out of range (pair target or pair_ptr)");
+  if (v & GAP_DEVERR_SYNC)
+    return fail(h, GAP_E_HIP, "a grid barrier of the cooperative QR panel kernel timed out");
   return GAP_OK;
 }
 
@@ -479,7 +481,7 @@ gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n,
   if (s != GAP_OK) return s;
   gapk::QrWork qw;
   gapk::qr_bind_workspace(at<char>(h, q), m, n, &qw);
-  gapk::qr_factor(A, ld, m, n + 1, n, &qw, h->stream);
+  gapk::qr_factor(A, ld, m, n + 1, n, &qw, h->stream, h->dev_err, &h->timer);
   gapk::back_substitute(A, ld, n, A + n * ld, x, h->dev_small, h->dev_err, h->stream);
   HIP_TRY(h, hipGetLastError());
   double rd[2] = {0, 0};
@@ -543,7 +545,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->stream);
   gapk::scale_stack(A, ld, n_rows, M, y, sigma, Lm, M, h->stream);
   h->timer.end(gapk::TM_CHOL);
-  gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream, &h->timer);
+  gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream, h->dev_err, &h->timer);
   h->timer.begin(gapk::TM_TRSV);
   gapk::back_substitute(A, ld, M, A + M * ld, c, h->dev_small, h->dev_err, h->stream);
   h->timer.end(gapk::TM_TRSV);

@@ -13,6 +13,7 @@
 #define GAP_DEVERR_INDEX 1   // a pair target or pointer outside its range
 #define GAP_DEVERR_NOT_PD 2  // non-positive or non-finite Cholesky pivot
 #define GAP_DEVERR_RANK 4    // zero or non-finite diagonal of R
+#define GAP_DEVERR_SYNC 8    // a grid barrier timed out (cooperative launch not co-resident)
 
 namespace gapk {
 
@@ -170,7 +171,7 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w);
 // Householder QR of the m x ncols col-major A (ncols = n + 1 with b last); R in the
 // upper triangle of the first n columns, Q^T b in column n.
 void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
-               hipStream_t st, Timer* tm = nullptr);
+               hipStream_t st, int* dev_err, Timer* tm = nullptr);
 // x = R^-1 z (R upper n x n col-major in A, z = A[0:n][n]); records min/max |R_kk|
 // into rd[0..1] (device) and flags zero/non-finite pivots.
 void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,

@@ -28,13 +28,22 @@ constexpr int kPanelMaxGrid = 256;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-// Device-coherent load that the compiler may still pipeline (relaxed, agent scope):
-// used for values other blocks of the same launch wrote before a fence.
+// Values exchanged between blocks of one launch (which may run on different
+// XCDs with separate L2 caches) are written and read with relaxed device-scope
+// atomics, which bypass the non-coherent caches, and ordered with s_waitcnt.
+// No device-scope fence is used: on this part such a fence writes back and
+// invalidates a whole L2.
 GAP_DEV double vload(const double* p) {
   const uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
   return __builtin_bit_cast(double, bits);
 }
+GAP_DEV void xstore(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory operation this wave issued has completed.
+GAP_DEV void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ----------------------------------------------------------- scale/stack ----
 __global__ void k_scale_stack(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
@@ -224,9 +233,15 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
         if (jj < ncnt) part[jj] += ak * (has_prev ? a[jj + 1] : a[jj]);
     }
     if (has_prev) {
+      if (r == k) {  // the next pivot row is read by the last block of this launch
 #pragma unroll
-      for (int jj = 0; jj <= kPanelW; ++jj)
-        if (jj < nc) rp[jj * ld] = a[jj];
+        for (int jj = 0; jj <= kPanelW; ++jj)
+          if (jj < nc) xstore(rp + jj * ld, a[jj]);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj <= kPanelW; ++jj)
+          if (jj < nc) rp[jj * ld] = a[jj];
+      }
     }
     (void)o;
   }
@@ -243,16 +258,17 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
   __syncthreads();
   const int G = gridDim.x;
   for (int v = threadIdx.x; v < ncnt; v += 256)
-    red[(int64_t)v * G + blockIdx.x] = ((s_red[0][v] + s_red[1][v]) + s_red[2][v]) + s_red[3][v];
-  __threadfence();
+    xstore(red + (int64_t)v * G + blockIdx.x,
+           ((s_red[0][v] + s_red[1][v]) + s_red[2][v]) + s_red[3][v]);
+  wait_mem();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned t = atomicAdd(counter, 1u);
+    const unsigned t =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_last = (t == (unsigned)G - 1u);
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   // Fixed-order reduction of the per-block partials: thread t sums blocks
   // t, t + 256, ... (loads issued together), then a wave and block tree.
   double tot[kPanelW];
@@ -290,13 +306,185 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
     tau_all[k] = tau;
     s_par[0] = tau;
     s_par[1] = scale;
-    *counter = 0u;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   for (int jj = 1 + threadIdx.x; jj < ncnt; jj += 256) {
     const int64_t j = k + jj;
     const double w = vload(A + k + j * ld) + s_par[1] * s_tot[jj];
     cs[3 + (j - j0)] = s_par[0] * w;
+  }
+}
+
+// ------------------------------------------------ register-resident panel ----
+// Householder factorisation of an inner panel of width <= kRRW with the whole
+// panel held in registers across a cooperative grid: thread t of block b owns
+// the panel rows i0 + (b * 512 + t) + q * (grid * 512), q < kRRQ.  Every column
+// step applies the previous reflector to the thread's rows, forms per-block
+// partial sums of the next column's norm and dot products, publishes them, and
+// waits at a grid barrier; every block then reduces all partials in the same
+// fixed order, so all blocks derive identical reflector parameters without a
+// second barrier.  Partials alternate between two buffers so a block that is
+// one step ahead never overwrites values a slower block is still reading.
+constexpr int kRRW = 16;    // panel width
+constexpr int kRRQ = 3;     // rows per thread
+constexpr int kRRT = 512;   // threads per block
+
+GAP_DEV void grid_barrier(unsigned int* arrive, unsigned int target, int* dev_err) {
+  wait_mem();  // this wave's cross-block stores (device-scope atomics) have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t spins = 0;
+    // Bounded wait: a barrier that does not complete within ~0.2 s sets the
+    // error bit, and every later barrier returns at once once the bit is set,
+    // so a failed co-residency assumption costs one timeout, never a hang.
+    while (__hip_atomic_load(arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(dev_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & GAP_DEVERR_SYNC)
+        break;
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1ull << 22)) {
+        atomicOr(dev_err, GAP_DEVERR_SYNC);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, int64_t ld,
+                                                      int64_t m, int64_t i0, int pw,
+                                                      double* __restrict__ red,
+                                                      double* __restrict__ piv,
+                                                      unsigned int* __restrict__ arrive,
+                                                      double* __restrict__ tau_all,
+                                                      int* __restrict__ dev_err) {
+  __shared__ double s_wred[kRRT / 64][kRRW];
+  __shared__ double s_tot[kRRW];
+  __shared__ double s_tw[kRRW];
+  __shared__ double s_par[3];  // tau, beta, scale of the reflector just formed
+  const int G = gridDim.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)G * kRRT;
+  int64_t lrow[kRRQ];  // local row index (row - i0), or -1
+  double a[kRRQ][kRRW];
+#pragma unroll
+  for (int q = 0; q < kRRQ; ++q) {
+    const int64_t lr = (int64_t)blockIdx.x * kRRT + threadIdx.x + q * stride;
+    lrow[q] = (i0 + lr < m) ? lr : -1;
+#pragma unroll
+    for (int j = 0; j < kRRW; ++j)
+      a[q][j] = (lrow[q] >= 0 && j < pw) ? A[(i0 + lr) + (i0 + j) * ld] : 0.0;
+  }
+  double beta_p = 0.0, scale_p = 0.0;
+  for (int k = 0; k <= pw; ++k) {
+    // 1. apply reflector k-1 to rows >= k-1
+    if (k > 0) {
+#pragma unroll
+      for (int q = 0; q < kRRQ; ++q) {
+        if (lrow[q] < k - 1) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j) {
+          if (j == k - 1) {
+            if (lrow[q] == k - 1) {
+              v = 1.0;
+              a[q][j] = beta_p;
+            } else {
+              v = a[q][j] * scale_p;
+              a[q][j] = v;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j)
+          if (j >= k && j < pw) a[q][j] -= s_tw[j] * v;
+      }
+    }
+    if (k == pw) break;
+    // 2. partial sums for column k over rows > k; pivot row published
+    double part[kRRW];
+#pragma unroll
+    for (int j = 0; j < kRRW; ++j) part[j] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRRQ; ++q) {
+      if (lrow[q] > k) {
+        double ak = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j)
+          if (j == k) ak = a[q][j];
+        part[0] += ak * ak;
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j)
+          if (j > k && j < pw) part[j - k] += ak * a[q][j];
+      } else if (lrow[q] == k) {
+        double* pv = piv + (k & 1) * kRRW;
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j) xstore(pv + j, a[q][j]);
+      }
+    }
+    const int ncnt = pw - k;
+#pragma unroll
+    for (int v = 0; v < kRRW; ++v) {
+      if (v < ncnt) {
+        const double s = wave_sum(part[v]);
+        if (lane == 0) s_wred[wave][v] = s;
+      }
+    }
+    __syncthreads();
+    double* rb = red + (size_t)(k & 1) * kRRW * G;
+    if (threadIdx.x < ncnt) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kRRT / 64; ++w) s += s_wred[w][threadIdx.x];
+      xstore(rb + (int64_t)threadIdx.x * G + blockIdx.x, s);
+    }
+    grid_barrier(arrive, (unsigned)(k + 1) * (unsigned)G, dev_err);
+    // 3. every block reduces all partials in the same order
+    if (wave < ncnt) {
+      double s = 0.0;
+      for (int b = lane; b < G; b += 64) s += vload(rb + (int64_t)wave * G + b);
+      s = wave_sum(s);
+      if (lane == 0) s_tot[wave] = s;
+    }
+    if (wave + (kRRT / 64) < ncnt) {
+      const int vv = wave + kRRT / 64;
+      double s = 0.0;
+      for (int b = lane; b < G; b += 64) s += vload(rb + (int64_t)vv * G + b);
+      s = wave_sum(s);
+      if (lane == 0) s_tot[vv] = s;
+    }
+    __syncthreads();
+    const double* pv = piv + (k & 1) * kRRW;
+    if (threadIdx.x == 0) {
+      const double alpha = vload(pv + k);
+      const double xnorm = sqrt(s_tot[0]);
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (xnorm > 0.0) {
+        beta = -copysign(hypot(alpha, xnorm), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      s_par[0] = tau;
+      s_par[1] = beta;
+      s_par[2] = scale;
+      if (blockIdx.x == 0) tau_all[i0 + k] = tau;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRRW) {
+      const int j = threadIdx.x;
+      s_tw[j] = (j > k && j < pw) ? s_par[0] * (vload(pv + j) + s_par[2] * s_tot[j - k]) : 0.0;
+    }
+    beta_p = s_par[1];
+    scale_p = s_par[2];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kRRQ; ++q) {
+    if (lrow[q] < 0) continue;
+#pragma unroll
+    for (int j = 0; j < kRRW; ++j)
+      if (j < pw) A[(i0 + lrow[q]) + (i0 + j) * ld] = a[q][j];
   }
 }
 
@@ -700,27 +888,67 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
                      ld, m, j0, pw, c_end, nct, w->Wt);
 }
 
+// Number of k_qr_panel_rr blocks that are co-resident on the current device (0 if unknown).
+static int rr_capacity() {
+  static int cap = -1;
+  if (cap < 0) {
+    cap = 0;
+    int dev = 0, nb = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_qr_panel_rr, kRRT, 0) == hipSuccess &&
+        nb > 0)
+      cap = std::min(nb * p.multiProcessorCount, kPanelMaxGrid);
+  }
+  return cap;
+}
+
 void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWork* w,
-               hipStream_t st, Timer* tm) {
+               hipStream_t st, int* dev_err, Timer* tm) {
   Timer dummy;
   if (!tm) tm = &dummy;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter);
   const int64_t slab = qr_slab_rows(m);
+  const int cap = rr_capacity();
   for (int64_t j0 = 0; j0 < n; j0 += kQrNB) {
     const int bw = (int)std::min<int64_t>(kQrNB, n - j0);
-    for (int64_t i0 = j0; i0 < j0 + bw; i0 += kPanelW) {
-      const int pw = (int)std::min<int64_t>(kPanelW, j0 + bw - i0);
+    int64_t i0 = j0;
+    while (i0 < j0 + bw) {
+      const int64_t rows = m - i0;
+      const int64_t G_rr = std::min<int64_t>(cap, (rows + kRRT - 1) / kRRT);
+      const bool rr = cap > 0 && rows <= G_rr * kRRT * kRRQ;
+      const int pw = (int)std::min<int64_t>(rr ? kRRW : kPanelW, j0 + bw - i0);
       tm->begin(TM_QR_PANEL);
-      for (int64_t k = i0; k <= i0 + pw; ++k) {
-        const int64_t r_lo = (k > i0) ? k - 1 : k;
-        const int64_t rows = m - r_lo;
-        const unsigned G = std::max(1u, std::min(cdiv(rows, 512), (unsigned)kPanelMaxGrid));
-        hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, i0, pw, k, w->colstate,
-                           w->red, w->counter, w->tau);
+      bool done = false;
+      if (rr) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter + 1);
+        int64_t ld_ = ld, m_ = m, i0_ = i0;
+        int pw_ = pw;
+        double* A_ = A;
+        double* red_ = w->red;
+        double* piv_ = w->T;  // the T scratch is free while a panel is factored
+        unsigned int* arr_ = w->counter + 1;
+        double* tau_ = w->tau;
+        int* err_ = dev_err;
+        void* args[] = {&A_, &ld_, &m_, &i0_, &pw_, &red_, &piv_, &arr_, &tau_, &err_};
+        done = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_qr_panel_rr),
+                                          dim3((unsigned)G_rr), dim3(kRRT), args, 0,
+                                          st) == hipSuccess;
+        if (!done) (void)hipGetLastError();
+      }
+      if (!done) {
+        for (int64_t k = i0; k <= i0 + pw; ++k) {
+          const int64_t r_lo = (k > i0) ? k - 1 : k;
+          const int64_t rr_rows = m - r_lo;
+          const unsigned G = std::max(1u, std::min(cdiv(rr_rows, 512), (unsigned)kPanelMaxGrid));
+          hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, i0, pw, k, w->colstate,
+                             w->red, w->counter, w->tau);
+        }
       }
       // rest of the outer block with this inner panel's reflectors
       qr_wy_update(A, ld, m, i0, pw, j0 + bw, slab, w, st);
       tm->end(TM_QR_PANEL);
+      i0 += pw;
     }
     if (j0 + bw >= ncols) continue;
     tm->begin(TM_QR_UPDATE);
