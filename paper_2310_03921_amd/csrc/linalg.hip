@@ -646,6 +646,236 @@ __global__ __launch_bounds__(256) void k_qr_update(double* __restrict__ A, int64
   }
 }
 
+// Trailing update, persistent over a 128-row block of C: the block stages
+// V^T for its rows once in LDS (with the unit lower trapezoid applied), then
+// walks the 64-wide column tiles of C.  W' = -(T^T W) tiles are double-buffered
+// in LDS and the next C tile is prefetched into registers while the current
+// one runs on the matrix cores; accumulators start as the C tile, so each C
+// element is read and written once.  Eight waves: 2 (column halves) x 4 (row
+// quarters), each a 32 x 32 block of (C column, C row) = (matrix-core row, col).
+constexpr int kUR = 128;  // rows of C per block
+constexpr int kUC = 64;   // columns per tile
+__global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t ld, int64_t m,
+                                                int64_t j0, int pw, int64_t c_end, int64_t nct,
+                                                const double* __restrict__ Wt) {
+  // padded row strides: the four lane groups of a fragment read (rows kk .. kk+3)
+  // fall on different banks
+  __shared__ double sV[kQrNB][kUR + 8];
+  __shared__ double sW[2][kQrNB][kUC + 8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wc = wave & 1, wr = wave >> 1;
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * kUR;
+  const int64_t cbeg = j0 + pw;
+  const int ntile = (int)((c_end - cbeg + kUC - 1) / kUC);
+  for (int e = threadIdx.x; e < kQrNB * kUR; e += 512) {
+    const int kk = e / kUR, x = e % kUR;
+    const int64_t r = r0 + x;
+    double v = 0.0;
+    if (kk < pw && r < m) {
+      const int64_t rr = r - j0;
+      v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
+    }
+    sV[kk][x] = v;
+  }
+  // W' tile in registers first (8 values per thread), written to LDS later
+  double wreg[kQrNB * kUC / 512];
+  auto load_w = [&](int tile) {
+#pragma unroll
+    for (int t = 0; t < kQrNB * kUC / 512; ++t) {
+      const int e = threadIdx.x + t * 512;
+      const int kk = e / kUC, x = e % kUC;
+      const int64_t c = cbeg + (int64_t)tile * kUC + x;
+      wreg[t] = (kk < pw && c < c_end) ? -Wt[(int64_t)kk * nct + (c - j0)] : 0.0;
+    }
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kQrNB * kUC / 512; ++t) {
+      const int e = threadIdx.x + t * 512;
+      sW[buf][e / kUC][e % kUC] = wreg[t];
+    }
+  };
+  auto load_c = [&](int tile, d4v (&dst)[2][2]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t r = r0 + wr * 32 + j * 16 + idx;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t c = cbeg + (int64_t)tile * kUC + wc * 32 + i * 16 + g + 4 * q;
+          dst[i][j][q] = (r < m && c < c_end) ? A[r + c * ld] : 0.0;
+        }
+      }
+  };
+  d4v acc[2][2], nxt[2][2];
+  load_w(0);
+  load_c(0, acc);
+  store_w(0);
+  __syncthreads();
+  int buf = 0;
+  for (int tile = 0; tile < ntile; ++tile) {
+    const bool more = tile + 1 < ntile;
+    if (more) {
+      load_w(tile + 1);
+      load_c(tile + 1, nxt);
+    }
+    for (int k0 = 0; k0 < pw; k0 += 4) {
+      const int kk = k0 + g;
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sW[buf][kk][wc * 32 + i * 16 + idx];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sV[kk][wr * 32 + j * 16 + idx];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t r = r0 + wr * 32 + j * 16 + idx;
+        if (r >= m) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t c = cbeg + (int64_t)tile * kUC + wc * 32 + i * 16 + g + 4 * q;
+          if (c < c_end) A[r + c * ld] = acc[i][j][q];
+        }
+      }
+    if (more) store_w(buf ^ 1);
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = nxt[i][j];
+    buf ^= 1;
+  }
+}
+
+// W = V^T C over row slabs, staged through LDS: a block owns one slab and a
+// 128-wide column tile (relative to the panel start; columns < pw are the
+// panel's own V columns, giving the Gram V^T V).  32-row chunks of V and C are
+// double-buffered in LDS (register prefetch of the next chunk while the
+// current one runs on the matrix cores).  Consecutive logical blocks on an XCD
+// share the slab, so its V rows come from that XCD's L2.  Eight waves:
+// 2 (V-column halves) x 4 (C-column quarters), 32 x 32 outputs each.
+constexpr int kVC = 128;  // C columns per block
+constexpr int kVK = 32;   // rows per chunk
+__global__ __launch_bounds__(512) void k_qr_vtc2(const double* __restrict__ A, int64_t ld,
+                                                 int64_t m, int64_t j0, int pw, int64_t nct,
+                                                 int64_t slab, int64_t n_ct, int64_t total,
+                                                 int64_t per_xcd, double* __restrict__ part) {
+  // row strides padded (73 and 137 doubles) so that neither the row-wise stash
+  // (consecutive threads -> consecutive rows) nor the fragment reads conflict
+  __shared__ double sV[2][kVK][kQrNB + 9];
+  __shared__ double sC[2][kVK][kVC + 9];
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t s = logical / n_ct, ct = logical % n_ct;
+  const int64_t r0 = j0 + s * slab, r1 = std::min(m, r0 + slab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wv = wave & 1, wq = wave >> 1;
+  const int64_t c0 = ct * kVC;  // first column (relative to j0) of the tile
+  // per-thread slice of a chunk: V 4 elements, C 8 elements (rows fastest);
+  // two register sets so chunk k+2 is in flight while chunk k+1 lands in LDS
+  double rv[2][4], rc[2][8];
+  auto fetch = [&](int64_t rk, int set) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = threadIdx.x + t * 512;
+      const int x = e / kVK, kk = e % kVK;
+      const int64_t r = rk + kk;
+      double v = 0.0;
+      if (x < pw && r < r1) {
+        const int64_t rr = r - j0;
+        v = (rr == x) ? 1.0 : (rr > x ? A[r + (j0 + x) * ld] : 0.0);
+      }
+      rv[set][t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = threadIdx.x + t * 512;
+      const int x = e / kVK, kk = e % kVK;
+      const int64_t r = rk + kk;
+      const int64_t cp = c0 + x;
+      double v = 0.0;
+      if (cp < nct && r < r1) {
+        if (cp < pw) {
+          const int64_t rr = r - j0;
+          v = (rr == cp) ? 1.0 : (rr > cp ? A[r + (j0 + cp) * ld] : 0.0);
+        } else {
+          v = A[r + (j0 + cp) * ld];
+        }
+      }
+      rc[set][t] = v;
+    }
+  };
+  auto stash = [&](int buf, int set) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = threadIdx.x + t * 512;
+      sV[buf][e % kVK][e / kVK] = rv[set][t];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = threadIdx.x + t * 512;
+      sC[buf][e % kVK][e / kVK] = rc[set][t];
+    }
+  };
+  d4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = zero4();
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int k0 = 0; k0 < kVK; k0 += 4) {
+      const int kk = k0 + g;
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sV[buf][kk][wv * 32 + i * 16 + idx];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sC[buf][kk][wq * 32 + j * 16 + idx];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+    }
+  };
+  // chunk c covers rows r0 + c * kVK; chunk c lives in LDS buffer c & 1 and,
+  // before that, in register set c & 1
+  const int64_t nch = (r1 - r0 + kVK - 1) / kVK;
+  fetch(r0, 0);
+  if (nch > 1) fetch(r0 + kVK, 1);
+  stash(0, 0);
+  __syncthreads();
+  for (int64_t c = 0; c < nch; c += 2) {
+    // even chunk c in LDS buffer 0; chunk c+1 in register set 1
+    if (c + 2 < nch) fetch(r0 + (c + 2) * kVK, 0);
+    compute(0);
+    if (c + 1 < nch) stash(1, 1);
+    lds_barrier();
+    if (c + 1 >= nch) break;
+    if (c + 3 < nch) fetch(r0 + (c + 3) * kVK, 1);
+    compute(1);
+    if (c + 2 < nch) stash(0, 0);
+    lds_barrier();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t cp = c0 + wq * 32 + j * 16 + idx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ii = wv * 32 + i * 16 + g + 4 * q;
+        if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[i][j][q];
+      }
+    }
+}
+
 // ------------------------------------------------------- triangular solves ----
 // x = R^-1 z, R upper (col-major, ld), one block; x kept in LDS (n <= 16384).
 __global__ __launch_bounds__(1024) void k_trsv_upper(const double* __restrict__ R, int64_t ld,
@@ -828,10 +1058,10 @@ void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const dou
 }
 
 static int64_t qr_slab_rows(int64_t m) {
-  // at most 64 slabs, each a multiple of 16 rows and at least 1024 rows
-  int64_t s = (m + 63) / 64;
-  s = std::max<int64_t>(s, 1024);
-  return (s + 15) / 16 * 16;
+  // slabs of >= 2048 rows (a multiple of 32), at most 256 of them
+  int64_t s = (m + 255) / 256;
+  s = std::max<int64_t>(s, 2048);
+  return (s + 31) / 32 * 32;
 }
 
 size_t qr_workspace_bytes(int64_t m, int64_t n) {
@@ -877,15 +1107,17 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
   const int64_t nct = c_end - j0;
   if (nct <= pw) return;
   const int64_t nslab = (m - j0 + slab - 1) / slab;
-  hipLaunchKernelGGL(k_qr_vtc, dim3((unsigned)nslab, cdiv(nct, 64)), dim3(256), 0, st, A, ld, m, j0,
-                     pw, nct, slab, w->part);
+  const int64_t n_ct = (nct + kVC - 1) / kVC;
+  const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
+  hipLaunchKernelGGL(k_qr_vtc2, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0, pw,
+                     nct, slab, n_ct, total, per_xcd, w->part);
   hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
                      (int64_t)pw * nct, w->W);
   hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
   hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw, w->T,
                      w->Wt);
-  hipLaunchKernelGGL(k_qr_update, dim3(cdiv(nct - pw, 64), cdiv(m - j0, 64)), dim3(256), 0, st, A,
-                     ld, m, j0, pw, c_end, nct, w->Wt);
+  hipLaunchKernelGGL(k_qr_upd, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0, pw, c_end,
+                     nct, w->Wt);
 }
 
 // Number of k_qr_panel_rr blocks that are co-resident on the current device (0 if unknown).
