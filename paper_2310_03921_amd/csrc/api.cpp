@@ -431,23 +431,47 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   layout_pairs(L, N, a->n_pairs, p);
   const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * M, 1));
   SplitWs sw;
-  if (prec == GAP_BF16X3) layout_split(L, M, D, false, sw);
+  size_t jh = 0, jl = 0;
+  bool presplit = false;
+  if (prec == GAP_BF16X3) {
+    layout_split(L, M, D, false, sw);
+    const size_t jbytes = (size_t)3 * a->n_pairs * gapk::split_ld(D) * 2;
+    // pre-split Jacobians when the halves fit comfortably in the workspace
+    presplit = a->n_pairs > 0 && D <= 256 && jbytes <= (size_t)16 << 30;
+    if (presplit) {
+      jh = L.take(jbytes);
+      jl = L.take(jbytes);
+    }
+  }
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   run_pairs(h, a, p, true);
   if (prec == GAP_BF16X3) {
     run_split(h, sp, sw, false);
+    if (presplit) {
+      h->timer.begin(gapk::TM_SPLIT);
+      gapk::split_j_bf16(a->jac, f32(a->jac_dt), a->ld_jac, a->n_pairs, D, at<__bf16>(h, jh),
+                         at<__bf16>(h, jl), h->stream);
+      h->timer.end(gapk::TM_SPLIT);
+    }
     h->timer.begin(gapk::TM_ENERGY);
     gapk::energy_rows_bf16x3(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N,
                              at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M, D, sp->zeta,
                              sp->delta, Knm, ld, at<double>(h, S), M, h->stream);
     h->timer.end(gapk::TM_ENERGY);
     h->timer.begin(gapk::TM_FORCE);
-    gapk::force_rows_bf16x3(a->jac, f32(a->jac_dt), a->ld_jac, D, at<__bf16>(h, sw.xh),
-                            at<__bf16>(h, sw.xl), M, at<double>(h, S), M,
-                            at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
-                            at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
-                            h->stream);
+    bool done = false;
+    if (presplit)
+      done = gapk::force_rows_bf16x3_split(
+          at<__bf16>(h, jh), at<__bf16>(h, jl), D, at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M,
+          at<double>(h, S), M, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+          at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld, h->stream);
+    if (!done)
+      gapk::force_rows_bf16x3(a->jac, f32(a->jac_dt), a->ld_jac, D, at<__bf16>(h, sw.xh),
+                              at<__bf16>(h, sw.xl), M, at<double>(h, S), M,
+                              at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+                              at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
+                              h->stream);
     h->timer.end(gapk::TM_FORCE);
     HIP_TRY(h, hipGetLastError());
     return GAP_OK;

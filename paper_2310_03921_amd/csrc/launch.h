@@ -136,6 +136,15 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
                        const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
                        int64_t ldk, hipStream_t st);
+// J -> hi/lo halves [3 n_pairs][split_ld(D)] each.
+void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
+                  __bf16* Jh, __bf16* Jl, hipStream_t st);
+// Force rows from pre-split Jacobians (returns false when D is too large for it).
+bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, const __bf16* Xh,
+                             const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                             const int64_t* tgt_ptr, const int32_t* tgt_pair,
+                             const int32_t* pair_src, const int32_t* order, int64_t n_atoms,
+                             int64_t row0, double* K, int64_t ldk, hipStream_t st);
 void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                    const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
                    double delta, const double* c, const double* g_e, double* W, int64_t ldw,

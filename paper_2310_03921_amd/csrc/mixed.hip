@@ -313,6 +313,146 @@ __global__ __launch_bounds__(256) void k_force_rows_b3_global(
   }
 }
 
+// Jacobian rows split once into hi/lo halves, [n_pairs][3][ldp] each (ldp = D
+// rounded up to 32, zero padded), so the force-row kernel streams 4 bytes per
+// element and does no splitting in its inner loop.
+template <typename TJ>
+__global__ void k_split_j(const TJ* __restrict__ J, int64_t ldj, int64_t rows, int64_t D,
+                          __bf16* __restrict__ Jh, __bf16* __restrict__ Jl, int64_t ldp) {
+  const int64_t per_row = ldp / 8;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * per_row;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / per_row, k = (e - r * per_row) * 8;
+    float x[8];
+    load8f(J + r * ldj, k, D, x);
+    bf8v h, l;
+    split8(x, h, l);
+    *reinterpret_cast<bf8v*>(Jh + r * ldp + k) = h;
+    *reinterpret_cast<bf8v*>(Jl + r * ldp + k) = l;
+  }
+}
+
+// Twelve-wave BF16x3 force rows on pre-split Jacobians: wave w handles
+// component alpha = w % 3 of slot group w / 3 (16 targets), 128 columns whose
+// split X halves sit in LDS in matrix-core order.  Pair metadata, the next
+// pair's first Jacobian block and the S values of the current step are
+// fetched ahead, as in the FP64 form.
+template <bool kUnused>
+__global__ __launch_bounds__(768) void k_force_rows_b3s(
+    const __bf16* __restrict__ Jh, const __bf16* __restrict__ Jl, int64_t ldp, int64_t D,
+    const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t M,
+    const double* __restrict__ S, int64_t ldS, const int64_t* __restrict__ tgt_ptr,
+    const int32_t* __restrict__ tgt_pair, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ order, int64_t n_atoms, int64_t row0, double* __restrict__ K,
+    int64_t ldk, int64_t n_ct, int64_t total, int64_t per_xcd, int nkb) {
+  extern __shared__ SplitPair xs3[];  // [nkb][kNCF][64]
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int alpha = wave % 3, grp = wave / 3;
+  const int64_t colbase = ct * (16 * kNCF);
+  for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 768) {
+    const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + u * 16 + (ln & 15);
+    SplitPair sp;
+    if (col < M) {
+      const int64_t k = (int64_t)kb * 32 + 8 * (ln >> 4);
+      sp.h = *reinterpret_cast<const bf8v*>(Xh + col * ldp + k);
+      sp.l = *reinterpret_cast<const bf8v*>(Xl + col * ldp + k);
+    } else {
+      zero_split(sp.h, sp.l);
+    }
+    xs3[e] = sp;
+  }
+  __syncthreads();
+  const int64_t slot = (tgb * 4 + grp) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  int64_t colr[kNCF];
+#pragma unroll
+  for (int u = 0; u < kNCF; ++u) colr[u] = colbase + u * 16 + idx;
+  f4v acc[kNCF];
+#pragma unroll
+  for (int u = 0; u < kNCF; ++u) acc[u] = zero4f();
+  const SplitPair* xb = xs3 + lane;
+  auto pair_at = [&](int t) -> int { return t < deg ? tgt_pair[seg0 + t] : -1; };
+  auto rowoff = [&](int p) -> int64_t { return ((int64_t)p * 3 + alpha) * ldp + 8 * g; };
+  int pair = maxdeg > 0 ? pair_at(0) : -1;
+  int src = pair >= 0 ? pair_src[pair] : -1;
+  if (src < 0) pair = -1;
+  bf8v ah, al;
+  if (pair >= 0) {
+    ah = *reinterpret_cast<const bf8v*>(Jh + rowoff(pair));
+    al = *reinterpret_cast<const bf8v*>(Jl + rowoff(pair));
+  } else {
+    zero_split(ah, al);
+  }
+  for (int t = 0; t < maxdeg; ++t) {
+    const bool pv = pair >= 0;
+    const int64_t ro = pv ? rowoff(pair) : 0;
+    int pair_n = pair_at(t + 1);
+    int src_n = -1;
+    float sv[4][kNCF];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int src_r = __shfl(src, 4 * g + r);
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u)
+        sv[r][u] = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
+    }
+    f4v G[kNCF];
+#pragma unroll
+    for (int u = 0; u < kNCF; ++u) G[u] = zero4f();
+    for (int kb = 0; kb < nkb; ++kb) {
+      bf8v nh, nl;
+      if (kb == 0) src_n = pair_n >= 0 ? pair_src[pair_n] : -1;
+      if (kb + 1 < nkb) {
+        if (pv) {
+          nh = *reinterpret_cast<const bf8v*>(Jh + ro + (int64_t)(kb + 1) * 32);
+          nl = *reinterpret_cast<const bf8v*>(Jl + ro + (int64_t)(kb + 1) * 32);
+        } else {
+          zero_split(nh, nl);
+        }
+      } else {
+        if (src_n < 0) pair_n = -1;
+        if (pair_n >= 0) {
+          nh = *reinterpret_cast<const bf8v*>(Jh + rowoff(pair_n));
+          nl = *reinterpret_cast<const bf8v*>(Jl + rowoff(pair_n));
+        } else {
+          zero_split(nh, nl);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u) {
+        const SplitPair b = xb[(kb * kNCF + u) * 64];
+        G[u] = mfma_bf16(ah, b.h, G[u]);
+        G[u] = mfma_bf16(ah, b.l, G[u]);
+        G[u] = mfma_bf16(al, b.h, G[u]);
+      }
+      ah = nh;
+      al = nl;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int u = 0; u < kNCF; ++u) acc[u][r] += sv[r][u] * G[u][r];
+    pair = pair_n;
+    src = src_n;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, 4 * g + r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kNCF; ++u)
+      if (colr[u] < M) K[(row0 + 3 * (int64_t)tr + alpha) + colr[u] * ldk] = -(double)acc[u][r];
+  }
+}
+
 // ------------------------------------------------------------- P-stage ----
 template <typename TD>
 __global__ __launch_bounds__(256) void k_pstage_b3(int mode, const TD* __restrict__ desc,
@@ -556,6 +696,45 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
     hipLaunchKernelGGL(k_force_rows_b3_global<double>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0,
                        st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
                        pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+}
+
+void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
+                  __bf16* Jh, __bf16* Jl, hipStream_t st) {
+  if (n_pairs <= 0) return;
+  const int64_t ldp = split_ld(D), rows = 3 * n_pairs;
+  const unsigned g = std::max(1u, std::min(cdiv(rows * (ldp / 8), 256), 65536u));
+  if (jac_f32)
+    hipLaunchKernelGGL(k_split_j<float>, dim3(g), dim3(256), 0, st, tp<float>(jac), ldj, rows, D,
+                       Jh, Jl, ldp);
+  else
+    hipLaunchKernelGGL(k_split_j<double>, dim3(g), dim3(256), 0, st, tp<double>(jac), ldj, rows, D,
+                       Jh, Jl, ldp);
+}
+
+bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, const __bf16* Xh,
+                             const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                             const int64_t* tgt_ptr, const int32_t* tgt_pair,
+                             const int32_t* pair_src, const int32_t* order, int64_t n_atoms,
+                             int64_t row0, double* K, int64_t ldk, hipStream_t st) {
+  if (n_atoms <= 0 || M <= 0) return true;
+  if (D > 32 * kMaxKb32) return false;
+  const int64_t ldp = split_ld(D);
+  const int nkb = (int)(ldp / 32);
+  const int64_t n_tgb = (n_atoms + 63) / 64;
+  const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
+  const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+  const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
+  static bool a = false;
+  if (!a) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3s<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair)));
+    a = true;
+  }
+  hipLaunchKernelGGL(k_force_rows_b3s<true>, dim3((unsigned)(8 * per_xcd)), dim3(768), lds, st, Jh,
+                     Jl, ldp, D, Xh, Xl, M, S, ldS, tgt_ptr, tgt_pair, pair_src, order, n_atoms,
+                     row0, K, ldk, n_ct, total, per_xcd, nkb);
+  return true;
 }
 
 void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
