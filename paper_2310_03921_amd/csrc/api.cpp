@@ -545,7 +545,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   Layout L;
   const size_t Lw = L.take(sizeof(double) * M * M);
   const size_t q = L.take(gapk::qr_workspace_bytes(m, M));
-  size_t kc = 0, rtop = 0, rbot = 0, v = 0, hbuf = 0, ge = 0, gvec = 0, dcp = 0, acfg = 0;
+  size_t kc = 0, rtop = 0, rbot = 0, v = 0, hbuf = 0, gvec = 0, dcp = 0, ke = 0;
   PredictWs pw{};
   if (refine_steps > 0) {
     const int64_t N = train->n_atoms;
@@ -554,11 +554,11 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
     rbot = L.take(sizeof(double) * M);
     v = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
     hbuf = L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1));
-    ge = L.take(sizeof(double) * std::max<int64_t>(N, 1));
     gvec = L.take(sizeof(double) * M);
     dcp = L.take(sizeof(double) * gapk::pstage_row_blocks(N) * M + 8);
-    acfg = L.take(sizeof(int32_t) * std::max<int64_t>(N, 1));
-    layout_predict(L, train, sp, true, true, true, true, pw);
+    ke = L.take(sizeof(double) * std::max<int64_t>(train->n_cfg, 1) * M);
+    // pw.W holds S = delta^2 zeta p^(zeta-1) for the whole refinement.
+    layout_predict(L, train, sp, true, false, true, true, pw);
   }
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
@@ -589,32 +589,45 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   }
   if (refine_steps > 0) {
     const gap_atoms* a = train;
-    const int64_t N = a->n_atoms;
+    const int64_t N = a->n_atoms, nc = a->n_cfg;
+    const int64_t ldS = ld4(M), ldg = ld4(D), ldke = std::max<int64_t>(nc, 1);
+    double* S = at<double>(h, pw.W);
+    double* g = at<double>(h, pw.g);
+    double* kE = at<double>(h, ke);
+    double* kcp = at<double>(h, kc);
+    double* vv = at<double>(h, v);
+    double* gv = at<double>(h, gvec);
     h->timer.begin(gapk::TM_REFINE);
-    gapk::atom_config(a->cfg_ptr, a->n_cfg, N, at<int32_t>(h, acfg), h->stream);
+    // Exact FP64 energy rows K_E and force-row weights S, once: every residual
+    // below is then K_E c, J^T-contracted (S diag(c)) X, and their transposes.
+    gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, nc, N, sp->X,
+                          sp->ld_x, M, D, sp->zeta, sp->delta, kE, ldke, S, ldS, h->stream);
+    run_pairs(h, a, pw.pairs, false);
     for (int step = 0; step <= refine_steps; ++step) {
-      // r = b - A_exact c, matrix-free in FP64: K c = [E_cfg ; F] from predict.
-      double* kcp = at<double>(h, kc);
-      run_predict(h, a, sp, c, pw, nullptr, kcp, nullptr, kcp + a->n_cfg);
+      // r = b - A_exact c, matrix-free in FP64: K c = [K_E c ; F(c)].
+      gapk::gemv_cm_f64(kE, ldke, nc, M, c, kcp, h->stream);
+      gapk::gemm_wx_scaled_f64(S, ldS, N, M, c, sp->X, sp->ld_x, D, g, ldg, h->stream);
+      gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg,
+                       at<int32_t>(h, pw.pairs.src), N, a->n_pairs,
+                       at<int64_t>(h, pw.pairs.tgt_ptr), at<int32_t>(h, pw.pairs.tgt_pair),
+                       at<double>(h, pw.f_pair), kcp + nc, h->stream);
       gapk::refine_residual(y, sigma, kcp, n_rows, Lm, M, M, c, at<double>(h, rtop),
                             at<double>(h, rbot), h->stream);
-      // A^T r = K^T (r_top / sigma) + U^T r_bot
-      gapk::div_sigma(at<double>(h, rtop), sigma, n_rows, at<double>(h, v), h->stream);
+      // A^T r = K_E^T v_E + K_F^T v_F + U^T r_bot,  v = r_top / sigma
+      gapk::div_sigma(at<double>(h, rtop), sigma, n_rows, vv, h->stream);
       gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
-                                    N, a->n_pairs, at<double>(h, v) + a->n_cfg,
-                                    at<double>(h, hbuf), ld4(D), h->stream);
-      gapk::expand_cfg(at<double>(h, v), at<int32_t>(h, acfg), N, at<double>(h, ge), h->stream);
-      gapk::pstage_f64(2, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D,
-                       sp->zeta, sp->delta, nullptr, at<double>(h, ge), at<double>(h, hbuf),
-                       ld4(D), nullptr, 0, nullptr, at<double>(h, dcp), h->stream);
-      gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M,
-                            at<double>(h, gvec), h->stream);
-      gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), at<double>(h, gvec), h->stream);
-      gapk::norm2_f64(at<double>(h, gvec), M, h->dev_small + 8 + step, h->stream);
+                                    N, a->n_pairs, vv + nc, at<double>(h, hbuf), ldg, h->stream);
+      gapk::pstage_f64(3, nullptr, false, 0, N, sp->X, sp->ld_x, M, D, sp->zeta, sp->delta,
+                       nullptr, nullptr, at<double>(h, hbuf), ldg, nullptr, 0, nullptr,
+                       at<double>(h, dcp), h->stream, S, ldS);
+      gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, gv, h->stream);
+      gapk::gemvt_cm_add_f64(kE, ldke, nc, M, vv, gv, h->stream);
+      gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), gv, h->stream);
+      gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);
       if (step == refine_steps) break;
       // R^T R dc = A^T r ; c += dc
-      gapk::seminormal_solve(A, ld, M, at<double>(h, gvec), h->stream);
-      gapk::axpy_f64(M, 1.0, at<double>(h, gvec), c, h->stream);
+      gapk::seminormal_solve(A, ld, M, gv, h->stream);
+      gapk::axpy_f64(M, 1.0, gv, c, h->stream);
     }
     h->timer.end(gapk::TM_REFINE);
     HIP_TRY(h, hipGetLastError());

@@ -130,13 +130,14 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
                                                 const double* __restrict__ H, int64_t ldh,
                                                 double* __restrict__ W, int64_t ldw,
                                                 double* __restrict__ e_atom,
-                                                double* __restrict__ dc_part) {
+                                                double* __restrict__ dc_part,
+                                                const double* __restrict__ Sx, int64_t ldsx) {
   __shared__ double colsum[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
   const int64_t row = rowbase + idx;
   const bool rvalid = row < n;
-  FragRowK<TD> fa{desc + (rvalid ? row : 0) * ldd, D, rvalid};
+  FragRowK<TD> fa{desc + (rvalid ? row : 0) * ldd, D, rvalid && mode != 3};
   FragRowK<double> fh{H ? H + (rvalid ? row : 0) * ldh : nullptr, D, rvalid && H != nullptr};
   const double d2 = delta * delta, d2z = d2 * zeta;
   double ge[4];
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
   for (int r = 0; r < 4; ++r) {
     const int64_t rr = rowbase + g + 4 * r;
     rv[r] = rr < n;
-    ge[r] = (mode != 0 && rv[r]) ? g_e[rr] : 0.0;
+    ge[r] = ((mode == 1 || mode == 2) && rv[r]) ? g_e[rr] : 0.0;
   }
   double esum[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t col0 = 0; col0 < M; col0 += 16 * kNC) {
@@ -163,6 +164,8 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
     }
     if (mode == 2)
       wave_mma2<kNC>(fa, fh, fb, D, g, acc, accq);
+    else if (mode == 3)
+      wave_mma<kNC>(fh, fb, D, g, accq);
     else
       wave_mma<kNC>(fa, fb, D, g, acc);
 #pragma unroll
@@ -175,6 +178,10 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = rowbase + g + 4 * r;
         if (!rv[r] || !cvalid) continue;
+        if (mode == 3) {
+          csum -= Sx[rr * ldsx + col] * accq[u][r];
+          continue;
+        }
         const double p = acc[u][r];
         const double pz1 = ipow(p, zeta - 1);
         const double kval = d2 * pz1 * p;
@@ -216,6 +223,92 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
       if (idx == 0 && rr < n) e_atom[rr] = v;
     }
   }
+}
+
+// A row of W with every element k scaled by cs[k] (cs: any alignment, length kmax).
+struct FragRowKScaled {
+  const double* row;
+  const double* cs;
+  int64_t kmax;
+  bool valid;
+  GAP_DEV void frag(int64_t k0, int g, double out[4]) const {
+    if (!valid) {
+      zero_frag(out);
+      return;
+    }
+    const int64_t k = k0 + 4 * g;
+    load4(row, k, kmax, out);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] *= (k + s < kmax) ? cs[k + s] : 0.0;
+  }
+};
+
+// ------------------------------------------------------- out = W X (row-major)
+// With cs non-null, W is used with its columns scaled: out = (W diag(cs)) X.
+__global__ __launch_bounds__(256) void k_gemm_wx_cs(const double* __restrict__ W, int64_t ldw,
+                                                    int64_t n, int64_t M,
+                                                    const double* __restrict__ cs,
+                                                    const double* __restrict__ X, int64_t ldx,
+                                                    int64_t D, double* __restrict__ out,
+                                                    int64_t ldo) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const int64_t colbase = (int64_t)blockIdx.y * 64;
+  FragRowKScaled fa{W + (row < n ? row : 0) * ldw, cs, M, row < n};
+  FragColK<double> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+    fb[u] = FragColK<double>{X + (col < D ? col : 0), ldx, M, col < D};
+  }
+  d4v acc[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+  wave_mma<kNC>(fa, fb, M, g, acc);
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + g + 4 * r;
+      if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+
+// y[i] = sum_k A[i + k * lda] x[k]  (column-major GEMV): 64 rows per block, 16 waves
+// splitting k, partial sums combined in LDS in a fixed order.
+__global__ __launch_bounds__(1024) void k_gemv_cm(const double* __restrict__ A, int64_t lda,
+                                                  int64_t rows, int64_t cols,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+  __shared__ double part[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (i < rows)
+    for (int64_t k = wave; k < cols; k += 16) s += A[i + k * lda] * x[k];
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && i < rows) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += part[w][lane];
+    y[i] = t;
+  }
+}
+
+// y[k] += sum_i A[i + k * lda] x[i]  (transposed GEMV, one wave per column)
+__global__ void k_gemvt_cm_add(const double* __restrict__ A, int64_t lda, int64_t rows,
+                               int64_t cols, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t k = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= cols) return;
+  double s = 0.0;
+  for (int64_t i = lane; i < rows; i += 64) s += A[i + k * lda] * x[i];
+  s = wave_sum(s);
+  if (lane == 0) y[k] += s;
 }
 
 // ------------------------------------------------------- out = W X (row-major)
@@ -283,13 +376,24 @@ __global__ __launch_bounds__(256) void k_gemm_wtd(const double* __restrict__ W, 
   }
 }
 
-__global__ void k_reduce_rows(const double* __restrict__ part, int64_t nparts, int64_t M,
-                              double* __restrict__ out) {
-  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M;
-       m += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t p = 0; p < nparts; ++p) s += part[p * M + m];
-    out[m] = s;
+// out[m] = sum_p part[p * M + m]: 64 columns per block, 16 waves splitting p, partial
+// sums combined in LDS in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_rows(const double* __restrict__ part,
+                                                      int64_t nparts, int64_t M,
+                                                      double* __restrict__ out) {
+  __shared__ double ps[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t m = (int64_t)blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (m < M)
+    for (int64_t p = wave; p < nparts; p += 16) s += part[p * M + m];
+  ps[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && m < M) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += ps[w][lane];
+    out[m] = t;
   }
 }
 
@@ -351,15 +455,18 @@ int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }
 void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
                 const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
-                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st) {
+                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st,
+                const double* Sx, int64_t ldsx) {
   if (n <= 0 || M <= 0) return;
   dim3 grid((unsigned)pstage_row_blocks(n));
   if (desc_f32)
     hipLaunchKernelGGL(k_pstage<float>, grid, dim3(256), 0, st, mode, tptr<float>(desc), ldd, n,
-                       X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part);
+                       X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part, Sx,
+                       ldsx);
   else
     hipLaunchKernelGGL(k_pstage<double>, grid, dim3(256), 0, st, mode, tptr<double>(desc), ldd,
-                       n, X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part);
+                       n, X, ldx, M, D, zeta, delta, c, g_e, H, ldh, W, ldw, e_atom, dc_part, Sx,
+                       ldsx);
 }
 
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
@@ -367,6 +474,28 @@ void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const doubl
   if (n <= 0 || D <= 0) return;
   hipLaunchKernelGGL(k_gemm_wx, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
                      X, ldx, D, out, ldo);
+}
+
+void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* cs,
+                        const double* X, int64_t ldx, int64_t D, double* out, int64_t ldo,
+                        hipStream_t st) {
+  if (n <= 0 || D <= 0) return;
+  hipLaunchKernelGGL(k_gemm_wx_cs, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
+                     cs, X, ldx, D, out, ldo);
+}
+
+void gemv_cm_f64(const double* A, int64_t lda, int64_t rows, int64_t cols, const double* x,
+                 double* y, hipStream_t st) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_gemv_cm, dim3(cdiv(rows, 64)), dim3(1024), 0, st, A, lda, rows, cols, x,
+                     y);
+}
+
+void gemvt_cm_add_f64(const double* A, int64_t lda, int64_t rows, int64_t cols, const double* x,
+                      double* y, hipStream_t st) {
+  if (cols <= 0) return;
+  hipLaunchKernelGGL(k_gemvt_cm_add, dim3(cdiv(cols, 4)), dim3(256), 0, st, A, lda, rows, cols, x,
+                     y);
 }
 
 void gemm_wtd_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
@@ -385,7 +514,7 @@ void gemm_wtd_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const void
 void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out,
                      hipStream_t st) {
   if (M <= 0) return;
-  hipLaunchKernelGGL(k_reduce_rows, dim3(cdiv(M, 256)), dim3(256), 0, st, part, nparts, M, out);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(cdiv(M, 64)), dim3(1024), 0, st, part, nparts, M, out);
 }
 
 void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,

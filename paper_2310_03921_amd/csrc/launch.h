@@ -83,14 +83,26 @@ void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t
 //   mode 2 (residual): W[i][m] = g_e[i] delta^2 p^zeta + delta^2 zeta p^(zeta-1) q_im
 //                      where q = H X^T with H [n][ldh] (rows of h_i); only dc_part is written
 //                      (column partial sums of W over the row block)
+//   mode 3 (residual, force part with a stored S): dc_part = column partial sums of
+//                      -S[i][m] q_im, q = H X^T (desc unused)
 void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
                 const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
-                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st);
+                int64_t ldw, double* e_atom, double* dc_part, hipStream_t st,
+                const double* Sx = nullptr, int64_t ldsx = 0);
 int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st);
+// out = (W diag(cs)) X   (cs: [M], any alignment)
+void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* cs,
+                        const double* X, int64_t ldx, int64_t D, double* out, int64_t ldo,
+                        hipStream_t st);
+// y = A x (column-major rows x cols);  y += A^T x
+void gemv_cm_f64(const double* A, int64_t lda, int64_t rows, int64_t cols, const double* x,
+                 double* y, hipStream_t st);
+void gemvt_cm_add_f64(const double* A, int64_t lda, int64_t rows, int64_t cols, const double* x,
+                      double* y, hipStream_t st);
 // out[m][j] = sum_i W[i][m] desc[i][j]        (M x D, row-major ldo)
 void gemm_wtd_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
                   bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,

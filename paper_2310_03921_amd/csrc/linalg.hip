@@ -877,57 +877,81 @@ __global__ __launch_bounds__(512) void k_qr_vtc2(const double* __restrict__ A, i
 }
 
 // ------------------------------------------------------- triangular solves ----
-// x = R^-1 z, R upper (col-major, ld), one block; x kept in LDS (n <= 16384).
-__global__ __launch_bounds__(1024) void k_trsv_upper(const double* __restrict__ R, int64_t ld,
-                                                     int64_t n, const double* __restrict__ z,
-                                                     double* __restrict__ x, int* dev_err) {
+// One workgroup of 16 waves solves R x = z (TRANS = false, back substitution) or
+// R^T x = z (TRANS = true, forward substitution), R upper triangular, col-major (ld).
+// Blocks of 64 unknowns: the 64 x 64 diagonal block is staged in LDS and solved by
+// wave 0 (one unknown per lane, the solved value broadcast by a lane shuffle); the
+// off-diagonal part is a GEMV over all 16 waves.  x lives in LDS (n doubles).
+// A zero or non-finite diagonal entry sets GAP_DEVERR_RANK (if dev_err).
+template <bool TRANS>
+__global__ __launch_bounds__(1024) void k_trsv_blk(const double* __restrict__ R, int64_t ld,
+                                                   int64_t n, const double* z, double* x,
+                                                   int* dev_err) {
   extern __shared__ double xs[];
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = z[i];
-  __syncthreads();
-  for (int64_t c = n - 1; c >= 0; --c) {
-    if (threadIdx.x == 0) {
-      const double d = R[c + c * ld];
-      if (d == 0.0 || !isfinite(d)) atomicOr(dev_err, GAP_DEVERR_RANK);
-      xs[c] = xs[c] / d;
+  __shared__ double T[64][65];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int64_t i = tid; i < n; i += 1024) xs[i] = z[i];
+  const int64_t nb = (n + 63) / 64;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t blk = TRANS ? b : nb - 1 - b;
+    const int64_t j0 = blk * 64;
+    const int w = (int)min((int64_t)64, n - j0);
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 1024) {
+      const int r = e & 63, c = e >> 6;
+      T[r][c] = (r < w && c < w && r <= c) ? R[(j0 + r) + (j0 + c) * ld] : 0.0;
+    }
+    if (TRANS) {
+      // x_j -= sum_{i < j0} R[i][j] x_i for the block's columns (left-looking)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cj = wave * 4 + q;
+        if (cj < w) {
+          const double* col = R + (j0 + cj) * ld;
+          double s = 0.0;
+          for (int64_t i = lane; i < j0; i += 64) s += col[i] * xs[i];
+          s = wave_sum(s);
+          if (lane == 0) xs[j0 + cj] -= s;
+        }
+      }
     }
     __syncthreads();
-    const double xc = xs[c];
-    for (int64_t l = threadIdx.x; l < c; l += blockDim.x) xs[l] -= R[l + c * ld] * xc;
+    if (wave == 0) {
+      double t = lane < w ? xs[j0 + lane] : 0.0;
+      bool bad = false;
+      if (TRANS) {
+        for (int c = 0; c < w; ++c) {
+          const double d = T[c][c];
+          bad |= (d == 0.0 || !isfinite(d));
+          const double xc = __shfl(t, c) / d;
+          if (lane == c) t = xc;
+          else if (lane > c) t -= T[c][lane] * xc;
+        }
+      } else {
+        for (int c = w - 1; c >= 0; --c) {
+          const double d = T[c][c];
+          bad |= (d == 0.0 || !isfinite(d));
+          const double xc = __shfl(t, c) / d;
+          if (lane == c) t = xc;
+          else if (lane < c) t -= T[lane][c] * xc;
+        }
+      }
+      if (lane < w) xs[j0 + lane] = t;
+      if (bad && lane == 0 && dev_err) atomicOr(dev_err, GAP_DEVERR_RANK);
+    }
     __syncthreads();
+    if (!TRANS) {
+      // x_i -= sum_{c in block} R[i][c] x_c for i < j0 (right-looking)
+      for (int64_t i = tid; i < j0; i += 1024) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < w; ++c) s += R[i + (j0 + c) * ld] * xs[j0 + c];
+        xs[i] -= s;
+      }
+    }
   }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
-}
-
-// y = R^-T z in place on x (forward substitution with the transpose).
-__global__ __launch_bounds__(1024) void k_trsv_upper_t(const double* __restrict__ R, int64_t ld,
-                                                       int64_t n, double* __restrict__ x) {
-  extern __shared__ double xs[];
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[i];
   __syncthreads();
-  for (int64_t c = 0; c < n; ++c) {
-    if (threadIdx.x == 0) xs[c] = xs[c] / R[c + c * ld];
-    __syncthreads();
-    const double xc = xs[c];
-    for (int64_t l = c + 1 + threadIdx.x; l < n; l += blockDim.x) xs[l] -= R[c + l * ld] * xc;
-    __syncthreads();
-  }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
-}
-
-__global__ __launch_bounds__(1024) void k_trsv_upper_inplace(const double* __restrict__ R,
-                                                             int64_t ld, int64_t n,
-                                                             double* __restrict__ x) {
-  extern __shared__ double xs[];
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[i];
-  __syncthreads();
-  for (int64_t c = n - 1; c >= 0; --c) {
-    if (threadIdx.x == 0) xs[c] = xs[c] / R[c + c * ld];
-    __syncthreads();
-    const double xc = xs[c];
-    for (int64_t l = threadIdx.x; l < c; l += blockDim.x) xs[l] -= R[l + c * ld] * xc;
-    __syncthreads();
-  }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
+  for (int64_t i = tid; i < n; i += 1024) x[i] = xs[i];
 }
 
 __global__ __launch_bounds__(1024) void k_rdiag_minmax(const double* __restrict__ R, int64_t ld,
@@ -983,13 +1007,23 @@ __global__ __launch_bounds__(256) void k_residual_bot(const double* __restrict__
 }
 
 // g[m] += sum_{i <= m} U[i][m] r_bot[i] = sum_{i <= m} L[m][i] r_bot[i]
-__global__ void k_add_ut_r(const double* __restrict__ L, int64_t ldl, int64_t M,
-                           const double* __restrict__ rb, double* __restrict__ g) {
-  for (int64_t mm = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; mm < M;
-       mm += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t i = 0; i <= mm; ++i) s += L[mm + i * ldl] * rb[i];
-    g[mm] += s;
+// 64 rows per block, 16 waves splitting i; partial sums combined in LDS in a fixed order.
+__global__ __launch_bounds__(1024) void k_add_ut_r(const double* __restrict__ L, int64_t ldl,
+                                                   int64_t M, const double* __restrict__ rb,
+                                                   double* __restrict__ g) {
+  __shared__ double part[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t mm = (int64_t)blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (mm < M)
+    for (int64_t i = wave; i <= mm; i += 16) s += L[mm + i * ldl] * rb[i];
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && mm < M) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += part[w][lane];
+    g[mm] += t;
   }
 }
 
@@ -1192,15 +1226,15 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
 void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
                      double* rd, int* dev_err, hipStream_t st) {
   hipLaunchKernelGGL(k_rdiag_minmax, dim3(1), dim3(1024), 0, st, A, ld, n, rd);
-  hipLaunchKernelGGL(k_trsv_upper, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld, n,
-                     z, x, dev_err);
+  hipLaunchKernelGGL(k_trsv_blk<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
+                     ld, n, z, x, dev_err);
 }
 
 void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_trsv_upper_t, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld,
-                     n, x);
-  hipLaunchKernelGGL(k_trsv_upper_inplace, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
-                     ld, n, x);
+  hipLaunchKernelGGL(k_trsv_blk<true>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld,
+                     n, x, x, nullptr);
+  hipLaunchKernelGGL(k_trsv_blk<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
+                     ld, n, x, x, nullptr);
 }
 
 void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
@@ -1213,7 +1247,8 @@ void refine_residual(const double* y, const double* sigma, const double* kc, int
 
 void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, double* g,
               hipStream_t st) {
-  hipLaunchKernelGGL(k_add_ut_r, dim3(g256(M)), dim3(256), 0, st, L, ldl, M, r_bot, g);
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_add_ut_r, dim3(cdiv(M, 64)), dim3(1024), 0, st, L, ldl, M, r_bot, g);
 }
 
 void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st) {
