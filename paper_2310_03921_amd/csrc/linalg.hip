@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, 
 }
 
 // Wt[kk][c'] = sum_{l <= kk} T[l][kk] W[l][c']  for c' in [pw, nct)
+// Wt[kk][cp] = -(T^T W)[kk][cp] for cp in [pw, nct) (negated: the update adds V Wt)
 __global__ void k_qr_tw(const double* __restrict__ W, int64_t nct, int pw,
                         const double* __restrict__ T, double* __restrict__ Wt) {
   const int64_t ntr = nct - pw;
@@ -589,7 +590,7 @@ __global__ void k_qr_tw(const double* __restrict__ W, int64_t nct, int pw,
     const int64_t cp = pw + (e - (int64_t)kk * ntr);
     double s = 0.0;
     for (int l = 0; l <= kk; ++l) s += T[l * kQrNB + kk] * W[(int64_t)l * nct + cp];
-    Wt[(int64_t)kk * nct + cp] = s;
+    Wt[(int64_t)kk * nct + cp] = -s;
   }
 }
 
@@ -682,10 +683,12 @@ __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t 
   auto load_w = [&](int tile) {
 #pragma unroll
     for (int t = 0; t < kQrNB * kUC / 512; ++t) {
+      // clamped, unconditional: rows kk >= pw meet zero rows of sV, columns
+      // beyond c_end only feed outputs that are never stored
       const int e = threadIdx.x + t * 512;
-      const int kk = e / kUC, x = e % kUC;
-      const int64_t c = cbeg + (int64_t)tile * kUC + x;
-      wreg[t] = (kk < pw && c < c_end) ? -Wt[(int64_t)kk * nct + (c - j0)] : 0.0;
+      const int kk = min(e / kUC, pw - 1), x = e % kUC;
+      const int64_t c = min(cbeg + (int64_t)min(tile, ntile - 1) * kUC + x, c_end - 1);
+      wreg[t] = Wt[(int64_t)kk * nct + (c - j0)];
     }
   };
   auto store_w = [&](int buf) {
@@ -700,11 +703,11 @@ __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int64_t r = r0 + wr * 32 + j * 16 + idx;
+        const int64_t rc = min(r0 + wr * 32 + j * 16 + idx, m - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t c = cbeg + (int64_t)tile * kUC + wc * 32 + i * 16 + g + 4 * q;
-          dst[i][j][q] = (r < m && c < c_end) ? A[r + c * ld] : 0.0;
+          dst[i][j][q] = A[rc + min(c, c_end - 1) * ld];
         }
       }
   };
@@ -874,6 +877,305 @@ __global__ __launch_bounds__(512) void k_qr_vtc2(const double* __restrict__ A, i
         if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[i][j][q];
       }
     }
+}
+
+// ---------------------------------------------- outer (128-wide) WY update ----
+// The same two products as above for a reflector block up to kQrOB = 128 wide:
+// one pass over the trailing columns per 128 reflectors halves the HBM traffic
+// of the 64-wide update, and each C element then carries 256 flops per 16 bytes
+// moved, enough to keep the FP64 matrix cores ahead of memory.
+constexpr int kQrOB = 128;
+
+// W = V^T C over row slabs with V up to 128 wide.  Eight waves: 2 (64-column
+// halves of V) x 4 (32-column quarters of the 128-column C tile).
+__global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, int64_t ld,
+                                                 int64_t m, int64_t j0, int pw, int64_t nct,
+                                                 int64_t slab, int64_t n_ct, int64_t total,
+                                                 int64_t per_xcd, double* __restrict__ part) {
+  __shared__ double sV[2][kVK][kQrOB + 9];
+  __shared__ double sC[2][kVK][kVC + 9];
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t s = logical / n_ct, ct = logical % n_ct;
+  const int64_t r0 = j0 + s * slab, r1 = std::min(m, r0 + slab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wv = wave & 1, wq = wave >> 1;
+  const int64_t c0 = ct * kVC;
+  // each thread stages one row (kk) of a chunk and the columns x0 + 16 t
+  const int kk_t = threadIdx.x & (kVK - 1), x0 = threadIdx.x / kVK;
+  double rv[8], rc[8];
+  // Two fetch forms.  Interior chunks (every row inside the slab and below the
+  // V triangle) load from clamped addresses with no condition at all: V
+  // columns >= pw only feed W rows >= pw and C columns >= nct only feed W
+  // columns >= nct, none of which are stored.  A guarded load compiles to a
+  // branch that waits for the load on the spot, so guards are kept to the few
+  // edge chunks (the V triangle at the top of the first slab, a partial last
+  // chunk), which use the masked form.
+  auto fetch_fast = [&](int64_t rk) {
+    const double* rowp = A + (rk + kk_t);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      rv[t] = rowp[(j0 + min(x0 + 16 * t, pw - 1)) * ld];
+      rc[t] = rowp[(j0 + min(c0 + x0 + 16 * t, nct - 1)) * ld];
+    }
+  };
+  auto fetch_masked = [&](int64_t rk) {
+    const int64_t r = rk + kk_t;
+    const bool rin = r < r1;
+    const int64_t rr = r - j0;
+    const double* rowp = A + (rin ? r : 0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int x = x0 + 16 * t;
+      double v = 0.0;
+      if (rin && x < pw) v = (rr == x) ? 1.0 : (rr > x ? rowp[(j0 + x) * ld] : 0.0);
+      rv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t cp = c0 + x0 + 16 * t;
+      double v = 0.0;
+      if (rin && cp < nct) {
+        if (cp >= pw)
+          v = rowp[(j0 + cp) * ld];
+        else
+          v = (rr == cp) ? 1.0 : (rr > cp ? rowp[(j0 + cp) * ld] : 0.0);
+      }
+      rc[t] = v;
+    }
+  };
+  auto fetch = [&](int64_t rk) {
+    if (rk - j0 >= pw && rk + kVK <= r1)
+      fetch_fast(rk);
+    else
+      fetch_masked(rk);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      sV[buf][kk_t][x0 + 16 * t] = rv[t];
+      sC[buf][kk_t][x0 + 16 * t] = rc[t];
+    }
+  };
+  d4v acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = zero4();
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int k0 = 0; k0 < kVK; k0 += 4) {
+      const int kk = k0 + g;
+      double a[4], b[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sV[buf][kk][wv * 64 + i * 16 + idx];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sC[buf][kk][wq * 32 + j * 16 + idx];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+    }
+  };
+  // chunk c (rows r0 + c * kVK) is fetched into registers while chunk c - 1
+  // runs from LDS, then stashed into the other LDS buffer
+  const int64_t nch = (r1 - r0 + kVK - 1) / kVK;
+  fetch(r0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t c = 0; c < nch; ++c) {
+    const bool more = c + 1 < nch;
+    if (more) fetch(r0 + (c + 1) * kVK);
+    compute(buf);
+    if (more) stash(buf ^ 1);
+    lds_barrier();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t cp = c0 + wq * 32 + j * 16 + idx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ii = wv * 64 + i * 16 + g + 4 * q;
+        if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[i][j][q];
+      }
+    }
+}
+
+// T (pw x pw upper triangular, ld kQrOB) of a reflector block from the Gram
+// G = V^T V held in the first pw columns of W (row l at W + l * nct):
+// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i],  T[i][i] = tau_i.
+__global__ __launch_bounds__(256) void k_qr_larft_ob(const double* __restrict__ W, int64_t nct,
+                                                     int pw, const double* __restrict__ tau,
+                                                     double* __restrict__ T) {
+  __shared__ double sT[kQrOB][kQrOB + 1];
+  __shared__ double gcol[kQrOB];
+  for (int e = threadIdx.x; e < kQrOB * kQrOB; e += 256) sT[e / kQrOB][e % kQrOB] = 0.0;
+  const int l = threadIdx.x;
+  for (int i = 0; i < pw; ++i) {
+    if (l < i) gcol[l] = W[(int64_t)l * nct + i];
+    __syncthreads();
+    double z = 0.0;
+    if (l < i)
+      for (int q = l; q < i; ++q) z += sT[l][q] * gcol[q];
+    const double ti = tau[i];
+    if (l < i) sT[l][i] = -ti * z;
+    if (l == i) sT[i][i] = ti;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kQrOB * kQrOB; e += 256) T[e] = sT[e / kQrOB][e % kQrOB];
+}
+
+// Wn[kk][cp] = -sum_{l <= kk} T[l][kk] W[l][cp] for cp in [pw, nct)  (T with ld ldt):
+// the negated W' = T^T W, so the update kernel adds V Wn to C without a negation
+// on the freshly loaded value (which would wait for the load at once)
+__global__ void k_qr_tw_ld(const double* __restrict__ W, int64_t nct, int pw,
+                           const double* __restrict__ T, int ldt, double* __restrict__ Wt) {
+  const int64_t ntr = nct - pw;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)pw * ntr;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int kk = (int)(e / ntr);
+    const int64_t cp = pw + (e - (int64_t)kk * ntr);
+    double s = 0.0;
+    for (int l = 0; l <= kk; ++l) s += T[l * ldt + kk] * W[(int64_t)l * nct + cp];
+    Wt[(int64_t)kk * nct + cp] = -s;
+  }
+}
+
+// C -= V W' for a reflector block up to 128 wide, persistent over a 128-row
+// block of C: V^T for the rows is staged once in LDS (unit lower trapezoid
+// applied, zero rows beyond pw).  A W' = T^T W tile (128 x 64) is loaded into
+// registers one tile ahead, together with the next C tile (16 + 16 values per
+// thread), and moves through a two-deep LDS ring in 16-deep k chunks, so no
+// global load is waited on inside a tile.  Accumulators start as the C tile.
+// Eight waves: 2 (column halves) x 4 (row quarters), each a 32 x 32 block of
+// (C column, C row) = (matrix-core row, column).
+constexpr int kU3R = 128;
+constexpr int kU3C = 64;
+constexpr int kU3K = kQrOB / 16;  // k chunks per tile
+__global__ __launch_bounds__(512) void k_qr_upd3(double* __restrict__ A, int64_t ld, int64_t m,
+                                                 int64_t j0, int pw, int64_t c_end, int64_t nct,
+                                                 const double* __restrict__ Wn) {
+  __shared__ double sV[kQrOB][kU3R + 8];
+  __shared__ double sW[2][16][kU3C + 4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wc = wave & 1, wr = wave >> 1;
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * kU3R;
+  const int64_t cbeg = j0 + pw;
+  const int ntile = (int)((c_end - cbeg + kU3C - 1) / kU3C);
+  // All kU3K chunks are always run (rows of sV beyond pw are zero): only the
+  // last outer block is narrower than kQrOB, and its trailing part is the
+  // right-hand side alone.  A compile-time chunk count keeps the choice of the
+  // next chunk's source free of selects that would wait on the prefetch.
+  for (int e = threadIdx.x; e < kQrOB * kU3R; e += 512) {
+    const int kk = e / kU3R, x = e % kU3R;
+    const int64_t r = r0 + x;
+    double v = 0.0;
+    if (kk < pw && r < m) {
+      const int64_t rr = r - j0;
+      v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
+    }
+    sV[kk][x] = v;
+  }
+  // -W' tile (Wn): thread t holds, for chunk kc, elements t and t + 512 of the
+  // 16 x 64 chunk (row e / 64, column e % 64)
+  auto load_w = [&](int tile, double (&dst)[kU3K][2]) {
+#pragma unroll
+    for (int kc = 0; kc < kU3K; ++kc)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // Unconditional load from a clamped (valid) address: a guarded load
+        // becomes a branch whose join waits for every load in flight.  No mask
+        // is needed: a clamped k row meets a zero row of sV, a clamped column
+        // only feeds outputs that are never stored, and a tile beyond the last
+        // is never used.
+        const int e = threadIdx.x + h * 512;
+        const int kk = min(kc * 16 + e / kU3C, pw - 1);  // rows >= pw meet zero rows of sV
+        const int64_t c = min(cbeg + (int64_t)min(tile, ntile - 1) * kU3C + (e % kU3C), c_end - 1);
+        dst[kc][h] = Wn[(int64_t)kk * nct + (c - j0)];
+      }
+  };
+  auto store_w = [&](int buf, const double (&src)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + h * 512;
+      sW[buf][e / kU3C][e % kU3C] = src[h];
+    }
+  };
+  auto load_c = [&](int tile, d4v (&dst)[2][2]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // clamped, unconditional (rows or columns outside C are never stored)
+        const int64_t rc = min(r0 + wr * 32 + j * 16 + idx, m - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t c =
+              cbeg + (int64_t)min(tile, ntile - 1) * kU3C + wc * 32 + i * 16 + g + 4 * q;
+          dst[i][j][q] = A[rc + min(c, c_end - 1) * ld];
+        }
+      }
+  };
+  d4v acc[2][2], nxt[2][2];
+  double wcur[kU3K][2], wnxt[kU3K][2];
+  load_c(0, acc);
+  load_w(0, wcur);
+  store_w(0, wcur[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int tile = 0; tile < ntile; ++tile) {
+    load_c(tile + 1, nxt);
+    load_w(tile + 1, wnxt);
+#pragma unroll
+    for (int kc = 0; kc < kU3K; ++kc) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kr = 4 * s4 + g;
+        const int kk = kc * 16 + kr;
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = sW[buf][kr][wc * 32 + i * 16 + idx];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sV[kk][wr * 32 + j * 16 + idx];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+      }
+      // the next chunk: of this tile, or the first of the next tile
+      if (kc + 1 < kU3K)
+        store_w(buf ^ 1, wcur[kc + 1 < kU3K ? kc + 1 : 0]);
+      else
+        store_w(buf ^ 1, wnxt[0]);
+      lds_barrier();
+      buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t r = r0 + wr * 32 + j * 16 + idx;
+        if (r >= m) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t c = cbeg + (int64_t)tile * kU3C + wc * 32 + i * 16 + g + 4 * q;
+          if (c < c_end) A[r + c * ld] = acc[i][j][q];
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = nxt[i][j];
+#pragma unroll
+    for (int kc = 0; kc < kU3K; ++kc) {
+      wcur[kc][0] = wnxt[kc][0];
+      wcur[kc][1] = wnxt[kc][1];
+    }
+  }
 }
 
 // ------------------------------------------------------- triangular solves ----
@@ -1102,9 +1404,9 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
   const int64_t ncols = n + 1;
   const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
   size_t d = 0;
-  d += (size_t)nslab * kQrNB * ncols;        // part
-  d += (size_t)kQrNB * ncols * 2;            // W, Wt
-  d += (size_t)kQrNB * kQrNB;                // T
+  d += (size_t)nslab * kQrOB * ncols;        // part
+  d += (size_t)kQrOB * ncols * 2;            // W, Wt
+  d += (size_t)kQrOB * kQrOB;                // T
   d += (size_t)kQrNB * kCS;                  // colstate
   d += (size_t)kQrNB * kPanelMaxGrid;        // red
   d += (size_t)n + 8;                        // tau
@@ -1116,14 +1418,14 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
   double* p = reinterpret_cast<double*>(base);
   w->part = p;
-  w->part_elems = nslab * kQrNB * ncols;
+  w->part_elems = nslab * kQrOB * ncols;
   p += w->part_elems;
   w->W = p;
-  p += kQrNB * ncols;
+  p += kQrOB * ncols;
   w->Wt = p;
-  p += kQrNB * ncols;
+  p += kQrOB * ncols;
   w->T = p;
-  p += kQrNB * kQrNB;
+  p += kQrOB * kQrOB;
   w->colstate = p;
   p += kQrNB * kCS;
   w->red = p;
@@ -1154,6 +1456,25 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
                      nct, w->Wt);
 }
 
+// The same update for an outer block of up to kQrOB reflectors.
+static void qr_wy_update_ob(double* A, int64_t ld, int64_t m, int64_t j0, int pw, int64_t c_end,
+                            int64_t slab, QrWork* w, hipStream_t st) {
+  const int64_t nct = c_end - j0;
+  if (nct <= pw) return;
+  const int64_t nslab = (m - j0 + slab - 1) / slab;
+  const int64_t n_ct = (nct + kVC - 1) / kVC;
+  const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
+  hipLaunchKernelGGL(k_qr_vtc3, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0, pw,
+                     nct, slab, n_ct, total, per_xcd, w->part);
+  hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
+                     (int64_t)pw * nct, w->W);
+  hipLaunchKernelGGL(k_qr_larft_ob, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
+  hipLaunchKernelGGL(k_qr_tw_ld, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw,
+                     w->T, kQrOB, w->Wt);
+  hipLaunchKernelGGL(k_qr_upd3, dim3(cdiv(m - j0, kU3R)), dim3(512), 0, st, A, ld, m, j0, pw,
+                     c_end, nct, w->Wt);
+}
+
 // Number of k_qr_panel_rr blocks that are co-resident on the current device (0 if unknown).
 static int rr_capacity() {
   static int cap = -1;
@@ -1176,49 +1497,61 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter);
   const int64_t slab = qr_slab_rows(m);
   const int cap = rr_capacity();
-  for (int64_t j0 = 0; j0 < n; j0 += kQrNB) {
-    const int bw = (int)std::min<int64_t>(kQrNB, n - j0);
-    int64_t i0 = j0;
-    while (i0 < j0 + bw) {
-      const int64_t rows = m - i0;
-      const int64_t G_rr = std::min<int64_t>(cap, (rows + kRRT - 1) / kRRT);
-      const bool rr = cap > 0 && rows <= G_rr * kRRT * kRRQ;
-      const int pw = (int)std::min<int64_t>(rr ? kRRW : kPanelW, j0 + bw - i0);
-      tm->begin(TM_QR_PANEL);
-      bool done = false;
-      if (rr) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter + 1);
-        int64_t ld_ = ld, m_ = m, i0_ = i0;
-        int pw_ = pw;
-        double* A_ = A;
-        double* red_ = w->red;
-        double* piv_ = w->T;  // the T scratch is free while a panel is factored
-        unsigned int* arr_ = w->counter + 1;
-        double* tau_ = w->tau;
-        int* err_ = dev_err;
-        void* args[] = {&A_, &ld_, &m_, &i0_, &pw_, &red_, &piv_, &arr_, &tau_, &err_};
-        done = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_qr_panel_rr),
-                                          dim3((unsigned)G_rr), dim3(kRRT), args, 0,
-                                          st) == hipSuccess;
-        if (!done) (void)hipGetLastError();
-      }
-      if (!done) {
-        for (int64_t k = i0; k <= i0 + pw; ++k) {
-          const int64_t r_lo = (k > i0) ? k - 1 : k;
-          const int64_t rr_rows = m - r_lo;
-          const unsigned G = std::max(1u, std::min(cdiv(rr_rows, 512), (unsigned)kPanelMaxGrid));
-          hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, i0, pw, k, w->colstate,
-                             w->red, w->counter, w->tau);
+  // Three levels: 16-wide register-resident panels inside 64-wide blocks
+  // (compact-WY updates within the block), 64-wide blocks inside 128-wide outer
+  // blocks (one 64-wide update of the outer block's second half), and one
+  // 128-wide update of the trailing matrix per outer block.
+  for (int64_t o0 = 0; o0 < n; o0 += kQrOB) {
+    const int ow = (int)std::min<int64_t>(kQrOB, n - o0);
+    for (int64_t j0 = o0; j0 < o0 + ow; j0 += kQrNB) {
+      const int bw = (int)std::min<int64_t>(kQrNB, o0 + ow - j0);
+      int64_t i0 = j0;
+      while (i0 < j0 + bw) {
+        const int64_t rows = m - i0;
+        const int64_t G_rr = std::min<int64_t>(cap, (rows + kRRT - 1) / kRRT);
+        const bool rr = cap > 0 && rows <= G_rr * kRRT * kRRQ;
+        const int pw = (int)std::min<int64_t>(rr ? kRRW : kPanelW, j0 + bw - i0);
+        tm->begin(TM_QR_PANEL);
+        bool done = false;
+        if (rr) {
+          hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter + 1);
+          int64_t ld_ = ld, m_ = m, i0_ = i0;
+          int pw_ = pw;
+          double* A_ = A;
+          double* red_ = w->red;
+          double* piv_ = w->T;  // the T scratch is free while a panel is factored
+          unsigned int* arr_ = w->counter + 1;
+          double* tau_ = w->tau;
+          int* err_ = dev_err;
+          void* args[] = {&A_, &ld_, &m_, &i0_, &pw_, &red_, &piv_, &arr_, &tau_, &err_};
+          done = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_qr_panel_rr),
+                                            dim3((unsigned)G_rr), dim3(kRRT), args, 0,
+                                            st) == hipSuccess;
+          if (!done) (void)hipGetLastError();
         }
+        if (!done) {
+          for (int64_t k = i0; k <= i0 + pw; ++k) {
+            const int64_t r_lo = (k > i0) ? k - 1 : k;
+            const int64_t rr_rows = m - r_lo;
+            const unsigned G = std::max(1u, std::min(cdiv(rr_rows, 512), (unsigned)kPanelMaxGrid));
+            hipLaunchKernelGGL(k_qr_col, dim3(G), dim3(256), 0, st, A, ld, m, i0, pw, k,
+                               w->colstate, w->red, w->counter, w->tau);
+          }
+        }
+        // rest of the 64-wide block with this inner panel's reflectors
+        qr_wy_update(A, ld, m, i0, pw, j0 + bw, slab, w, st);
+        tm->end(TM_QR_PANEL);
+        i0 += pw;
       }
-      // rest of the outer block with this inner panel's reflectors
-      qr_wy_update(A, ld, m, i0, pw, j0 + bw, slab, w, st);
-      tm->end(TM_QR_PANEL);
-      i0 += pw;
+      if (j0 + bw >= o0 + ow) continue;
+      // rest of the outer block with this 64-wide block's reflectors
+      tm->begin(TM_QR_UPDATE);
+      qr_wy_update(A, ld, m, j0, bw, o0 + ow, slab, w, st);
+      tm->end(TM_QR_UPDATE);
     }
-    if (j0 + bw >= ncols) continue;
+    if (o0 + ow >= ncols) continue;
     tm->begin(TM_QR_UPDATE);
-    qr_wy_update(A, ld, m, j0, bw, ncols, slab, w, st);
+    qr_wy_update_ob(A, ld, m, o0, ow, ncols, slab, w, st);
     tm->end(TM_QR_UPDATE);
   }
 }
