@@ -429,7 +429,7 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   Layout L;
   PairWs p;
   layout_pairs(L, N, a->n_pairs, p);
-  const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * M, 1));
+  const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1));
   SplitWs sw;
   size_t jh = 0, jl = 0;
   bool presplit = false;
@@ -478,14 +478,14 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   }
   h->timer.begin(gapk::TM_ENERGY);
   gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N, sp->X,
-                        sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), M,
+                        sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), ld4(M),
                         h->stream);
   h->timer.end(gapk::TM_ENERGY);
   h->timer.begin(gapk::TM_FORCE);
   gapk::force_rows_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, sp->X, sp->ld_x, M,
-                       at<double>(h, S), M, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
-                       at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
-                       h->stream);
+                       at<double>(h, S), ld4(M), at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+                       at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_pairs, a->n_cfg,
+                       Knm, ld, h->stream);
   h->timer.end(gapk::TM_FORCE);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc
           const double p = acc[u][r];
           const double pz1 = ipow(p, zeta - 1);
           e[u] += d2 * pz1 * p;
-          if (col < M) S[rr * ldS + col] = d2z * pz1;
+          if (col < ldS) S[rr * ldS + col] = (col < M) ? d2z * pz1 : 0.0;  // zero row padding
         }
       }
     }

@@ -395,6 +395,149 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12(
   }
 }
 
+// Unconditional 4-wide loads of a Jacobian row segment (32-byte aligned).
+GAP_DEV void ldj4(const double* p, double out[4]) {
+  const d4v v = *reinterpret_cast<const d4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+GAP_DEV void ldj4(const float* p, double out[4]) {
+  const f4v v = *reinterpret_cast<const f4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+
+// The twelve-wave kernel for D % 4 == 0 with no guarded load on its hot path.
+// A load under a condition compiles to a branch whose join waits for the load
+// at once, which would serialise the Jacobian stream; here every load reads a
+// valid address and invalid data is cancelled arithmetically:
+//  - k blocks beyond D read the row's last 4 elements and meet zero rows of X;
+//  - a slot past its degree (or a target past n_atoms) reads a valid pair of
+//    the same target (or pair 0) and its step result is multiplied by a zero S;
+//  - S is read at a clamped (source, column) and multiplied by the validity.
+// Matrix data are finite, so garbage * 0 == 0.  Results equal those of the
+// guarded form up to the order of FP64 additions (identical here: the zero
+// contributions add exact zeros).
+template <typename TJ>
+__global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
+    int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
+    const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t n_pairs, int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct,
+    int64_t total, int64_t per_xcd, int nkb) {
+  extern __shared__ double xs[];  // [nkb][kLdsNC][64 lanes][4]
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int alpha = wave % 3, grp = wave / 3;
+  const int64_t colbase = ct * (16 * kLdsNC);
+
+  for (int e = threadIdx.x; e < nkb * kLdsNC * 64; e += 64 * kW12) {
+    const int kb = e / (kLdsNC * 64), rem = e % (kLdsNC * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + 4 * (ln & 15) + u;  // lane idx of tile u: column 4 idx + u
+    double v[4];
+    if (col < M)
+      load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
+    else
+      zero_frag(v);
+    d4v w = {v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<d4v*>(xs + (size_t)e * 4) = w;
+  }
+  __syncthreads();
+
+  const int64_t slot = (tgb * 4 + grp) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  // step t of this slot reads tgt_pair[pair_slot(t)], always a valid entry
+  const int64_t last = min(seg0 + max(deg - 1, 0), n_pairs - 1);
+  auto pair_slot = [&](int t) -> int64_t { return min(seg0 + t, last); };
+  const int64_t kmax4 = D - 4;
+  // the four columns of a lane are consecutive (4 idx + u), so its S values
+  // for one source are one 32-byte load (S rows padded with zeros to ldS)
+  int64_t colr[kLdsNC];
+#pragma unroll
+  for (int u = 0; u < kLdsNC; ++u) colr[u] = colbase + 4 * idx + u;
+  const int64_t scol = min(colbase + 4 * idx, ldS - 4);
+  d4v acc[kLdsNC];
+#pragma unroll
+  for (int u = 0; u < kLdsNC; ++u) acc[u] = zero4();
+  const d4v* xb = reinterpret_cast<const d4v*>(xs) + lane;
+  if (maxdeg <= 0) {
+    // no pair reaches any of these targets: the rows are zero
+  } else {
+    // Pair metadata runs one step ahead of its use: at step t the pair of
+    // step t + 1 is known, so its source and the pair of step t + 2 are
+    // loaded now and first needed a whole step later.
+    int pair = tgt_pair[pair_slot(0)];
+    int pair_n = tgt_pair[pair_slot(1)];
+    int src = pair_src[pair];
+    double a0[4], a1[4];
+    const TJ* jr = jac + (int64_t)pair * 3 * ldj + alpha * ldj;
+    ldj4(jr + min((int64_t)4 * g, kmax4), a0);
+    for (int t = 0; t < maxdeg; ++t) {
+      const int pair_nn = tgt_pair[pair_slot(t + 2)];
+      const int src_n = pair_src[pair_n];
+      const TJ* jn = jac + (int64_t)pair_n * 3 * ldj + alpha * ldj;
+      d4v G[kLdsNC];
+#pragma unroll
+      for (int u = 0; u < kLdsNC; ++u) G[u] = zero4();
+      for (int kb = 0; kb < nkb; kb += 2) {  // nkb is even
+        ldj4(jr + min((int64_t)(kb + 1) * 16 + 4 * g, kmax4), a1);
+        {
+          d4v b[kLdsNC];
+#pragma unroll
+          for (int u = 0; u < kLdsNC; ++u) b[u] = xb[(kb * kLdsNC + u) * 64];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int u = 0; u < kLdsNC; ++u) G[u] = mfma_f64(a0[s4], b[u][s4], G[u]);
+        }
+        // the next block of this step, or the first block of the next step
+        const TJ* jp = (kb + 2 < nkb) ? jr + (int64_t)(kb + 2) * 16 : jn;
+        ldj4(jp + min((int64_t)4 * g, kmax4 - ((kb + 2 < nkb) ? (int64_t)(kb + 2) * 16 : 0)), a0);
+        {
+          d4v b[kLdsNC];
+#pragma unroll
+          for (int u = 0; u < kLdsNC; ++u) b[u] = xb[((kb + 1) * kLdsNC + u) * 64];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int u = 0; u < kLdsNC; ++u) G[u] = mfma_f64(a1[s4], b[u][s4], G[u]);
+        }
+      }
+      d4v sv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, g + 4 * r);
+        sv[r] = *reinterpret_cast<const d4v*>(S + (int64_t)max(src_r, 0) * ldS + scol);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, g + 4 * r);
+        const int deg_r = __shfl(deg, g + 4 * r);
+        const bool ok_r = t < deg_r && src_r >= 0;
+#pragma unroll
+        for (int u = 0; u < kLdsNC; ++u)
+          acc[u][r] += sv[r][u] * ((ok_r && colr[u] < M) ? 1.0 : 0.0) * G[u][r];
+      }
+      jr = jn;
+      pair_n = pair_nn;
+      src = src_n;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, g + 4 * r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < kLdsNC; ++u)
+      if (colr[u] < M) K[(row0 + 3 * (int64_t)tr + alpha) + colr[u] * ldk] = -acc[u][r];
+  }
+}
+
 // f_pair[p][alpha] = J[p][alpha] . g[src(p)]; one wavefront per pair.
 template <typename TJ>
 __global__ __launch_bounds__(256) void k_pair_dots(const TJ* __restrict__ jac, int64_t ldj,
@@ -501,8 +644,43 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
                     int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* tgt_ptr,
                     const int32_t* tgt_pair, const int32_t* pair_src, const int32_t* order,
-                    int64_t n_atoms, int64_t row0, double* K, int64_t ldk, hipStream_t st) {
+                    int64_t n_atoms, int64_t n_pairs, int64_t row0, double* K, int64_t ldk,
+                    hipStream_t st) {
   if (n_atoms <= 0 || M <= 0) return;
+  if (D <= 16 * kLdsMaxKb && D % 4 == 0 && ldS % 4 == 0 && ldS >= 4 && n_pairs > 0) {
+    const int nkb = (int)(((D + 15) / 16 + 1) / 2 * 2);  // even number of 16-k blocks
+    const int64_t n_ct = (M + 16 * kLdsNC - 1) / (16 * kLdsNC);
+    const int64_t n_tgb = (n_atoms + 63) / 64;
+    const int64_t total = n_ct * n_tgb;
+    const int64_t per_xcd = (total + 7) / 8;
+    const size_t lds = (size_t)nkb * kLdsNC * 64 * 4 * sizeof(double);
+    const int lds_max = 16 * kLdsNC * 64 * 4 * 8;
+    dim3 grid((unsigned)(8 * per_xcd));
+    if (jac_f32) {
+      static bool attr = false;
+      if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_lds12f<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        attr = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_lds12f<float>, grid, dim3(64 * kW12), lds, st,
+                         reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, total,
+                         per_xcd, nkb);
+    } else {
+      static bool attr = false;
+      if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_lds12f<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        attr = true;
+      }
+      hipLaunchKernelGGL(k_force_rows_lds12f<double>, grid, dim3(64 * kW12), lds, st,
+                         reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
+                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, total,
+                         per_xcd, nkb);
+    }
+    return;
+  }
   if (D <= 16 * kLdsMaxKb) {
     const int nkb = (int)(((D + 15) / 16 + 1) / 2 * 2);  // even number of 16-k blocks
     const int64_t n_ct = (M + 16 * kLdsNC - 1) / (16 * kLdsNC);

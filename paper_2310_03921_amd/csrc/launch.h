@@ -120,7 +120,8 @@ void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg
 void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
                     int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* tgt_ptr,
                     const int32_t* tgt_pair, const int32_t* pair_src, const int32_t* order,
-                    int64_t n_atoms, int64_t row0, double* K, int64_t ldk, hipStream_t st);
+                    int64_t n_atoms, int64_t n_pairs, int64_t row0, double* K, int64_t ldk,
+                    hipStream_t st);
 // f_pair[p][alpha] = J[p][alpha] . g[src(p)], then forces[j][alpha] = -sum_{p -> j} f_pair[p][alpha]
 void forces_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* g,
                 int64_t ldg, const int32_t* pair_src, int64_t n_atoms, int64_t n_pairs,

@@ -1006,27 +1006,81 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
 }
 
 // T (pw x pw upper triangular, ld kQrOB) of a reflector block from the Gram
-// G = V^T V held in the first pw columns of W (row l at W + l * nct):
-// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i],  T[i][i] = tau_i.
-__global__ __launch_bounds__(256) void k_qr_larft_ob(const double* __restrict__ W, int64_t nct,
-                                                     int pw, const double* __restrict__ tau,
-                                                     double* __restrict__ T) {
-  __shared__ double sT[kQrOB][kQrOB + 1];
-  __shared__ double gcol[kQrOB];
-  for (int e = threadIdx.x; e < kQrOB * kQrOB; e += 256) sT[e / kQrOB][e % kQrOB] = 0.0;
+// G = V^T V held in the first pw columns of W (row l at W + l * nct), in two
+// steps.  The diagonal 64 x 64 blocks come from the column recursion
+// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i], T[i][i] = tau_i, one block per half
+// (k_qr_larft_half); the coupling block is T12 = -T11 G12 T22 (k_qr_tcouple),
+// since for H = H1 H2 with H_k = I - V_k T_k V_k^T the product is
+// I - [V1 V2] [[T1, -T1 V1^T V2 T2], [0, T2]] [V1 V2]^T.
+__global__ __launch_bounds__(256) void k_qr_larft_half(const double* __restrict__ W,
+                                                       int64_t nct, int pw,
+                                                       const double* __restrict__ tau,
+                                                       double* __restrict__ T) {
+  __shared__ double sT[kQrNB][kQrNB + 1];
+  __shared__ double sG[kQrNB][kQrNB + 1];
+  const int o = blockIdx.x * kQrNB;
+  const int w = min(kQrNB, pw - o);
+  if (w <= 0) return;
+  for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
+    const int l = e / kQrNB, i = e % kQrNB;
+    sG[l][i] = (l < w && i < w) ? W[(int64_t)(o + l) * nct + (o + i)] : 0.0;
+    sT[l][i] = 0.0;
+  }
+  __syncthreads();
   const int l = threadIdx.x;
-  for (int i = 0; i < pw; ++i) {
-    if (l < i) gcol[l] = W[(int64_t)l * nct + i];
-    __syncthreads();
+  for (int i = 0; i < w; ++i) {
     double z = 0.0;
     if (l < i)
-      for (int q = l; q < i; ++q) z += sT[l][q] * gcol[q];
-    const double ti = tau[i];
+      for (int q = l; q < i; ++q) z += sT[l][q] * sG[q][i];
+    __syncthreads();
+    const double ti = tau[o + i];
     if (l < i) sT[l][i] = -ti * z;
     if (l == i) sT[i][i] = ti;
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < kQrOB * kQrOB; e += 256) T[e] = sT[e / kQrOB][e % kQrOB];
+  for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
+    const int r = e / kQrNB, c = e % kQrNB;
+    T[(int64_t)(o + r) * kQrOB + (o + c)] = sT[r][c];
+    if (blockIdx.x == 1) T[(int64_t)(o + r) * kQrOB + c] = 0.0;  // lower-left block
+  }
+}
+
+__global__ __launch_bounds__(256) void k_qr_tcouple(const double* __restrict__ W, int64_t nct,
+                                                    int pw, double* __restrict__ T) {
+  __shared__ double sA[kQrNB][kQrNB + 1];  // T11, then X = G12 T22
+  __shared__ double sB[kQrNB][kQrNB + 1];  // G12
+  __shared__ double sC[kQrNB][kQrNB + 1];  // T22
+  const int w2 = pw - kQrNB;  // width of the second half (> 0)
+  for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
+    const int r = e / kQrNB, c = e % kQrNB;
+    sB[r][c] = (c < w2) ? W[(int64_t)r * nct + (kQrNB + c)] : 0.0;
+    sC[r][c] = (r < w2 && c < w2) ? T[(int64_t)(kQrNB + r) * kQrOB + (kQrNB + c)] : 0.0;
+  }
+  __syncthreads();
+  // X = G12 T22 (T22 upper triangular)
+  double x[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + u * 256, r = e / kQrNB, c = e % kQrNB;
+    double acc = 0.0;
+    for (int q = 0; q <= c; ++q) acc += sB[r][q] * sC[q][c];
+    x[u] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + u * 256;
+    sB[e / kQrNB][e % kQrNB] = x[u];  // sB now holds X
+    sA[e / kQrNB][e % kQrNB] = T[(int64_t)(e / kQrNB) * kQrOB + (e % kQrNB)];
+  }
+  __syncthreads();
+  // T12 = -T11 X (T11 upper triangular)
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + u * 256, r = e / kQrNB, c = e % kQrNB;
+    double acc = 0.0;
+    for (int q = r; q < kQrNB; ++q) acc += sA[r][q] * sB[q][c];
+    T[(int64_t)r * kQrOB + (kQrNB + c)] = -acc;
+  }
 }
 
 // Wn[kk][cp] = -sum_{l <= kk} T[l][kk] W[l][cp] for cp in [pw, nct)  (T with ld ldt):
@@ -1468,7 +1522,10 @@ static void qr_wy_update_ob(double* A, int64_t ld, int64_t m, int64_t j0, int pw
                      nct, slab, n_ct, total, per_xcd, w->part);
   hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
                      (int64_t)pw * nct, w->W);
-  hipLaunchKernelGGL(k_qr_larft_ob, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
+  hipLaunchKernelGGL(k_qr_larft_half, dim3(2), dim3(256), 0, st, w->W, nct, pw, w->tau + j0,
+                     w->T);
+  if (pw > kQrNB)
+    hipLaunchKernelGGL(k_qr_tcouple, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->T);
   hipLaunchKernelGGL(k_qr_tw_ld, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw,
                      w->T, kQrOB, w->Wt);
   hipLaunchKernelGGL(k_qr_upd3, dim3(cdiv(m - j0, kU3R)), dim3(512), 0, st, A, ld, m, j0, pw,
