@@ -171,6 +171,7 @@ bool f32(gap_dtype d) { return d == GAP_DT_F32; }
 // Row strides of internal FP64 row-major buffers: a multiple of 4 doubles so
 // that every row starts 32-byte aligned (vector loads).
 int64_t ld4(int64_t n) { return (n + 3) & ~int64_t(3); }
+int64_t ld8(int64_t n) { return (n + 7) & ~int64_t(7); }
 
 // Split halves of X for the BF16x3 form.
 struct SplitWs {
@@ -457,18 +458,19 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
     h->timer.begin(gapk::TM_ENERGY);
     gapk::energy_rows_bf16x3(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N,
                              at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M, D, sp->zeta,
-                             sp->delta, Knm, ld, at<double>(h, S), M, h->stream);
+                             sp->delta, Knm, ld, at<float>(h, S), ld8(M), h->stream);
     h->timer.end(gapk::TM_ENERGY);
     h->timer.begin(gapk::TM_FORCE);
     bool done = false;
     if (presplit)
       done = gapk::force_rows_bf16x3_split(
           at<__bf16>(h, jh), at<__bf16>(h, jl), D, at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M,
-          at<double>(h, S), M, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
-          at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld, h->stream);
+          at<float>(h, S), ld8(M), at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
+          at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_pairs, a->n_cfg, Knm, ld,
+          h->stream);
     if (!done)
       gapk::force_rows_bf16x3(a->jac, f32(a->jac_dt), a->ld_jac, D, at<__bf16>(h, sw.xh),
-                              at<__bf16>(h, sw.xl), M, at<double>(h, S), M,
+                              at<__bf16>(h, sw.xl), M, at<float>(h, S), ld8(M),
                               at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
                               at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
                               h->stream);

@@ -143,9 +143,9 @@ void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh
 void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                         int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
                         int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                        double* S, int64_t ldS, hipStream_t st);
+                        float* S, int64_t ldS, hipStream_t st);
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
-                       const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                       const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
                        const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
                        int64_t ldk, hipStream_t st);
@@ -154,10 +154,11 @@ void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, i
                   __bf16* Jh, __bf16* Jl, hipStream_t st);
 // Force rows from pre-split Jacobians (returns false when D is too large for it).
 bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, const __bf16* Xh,
-                             const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                             const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                              const int64_t* tgt_ptr, const int32_t* tgt_pair,
                              const int32_t* pair_src, const int32_t* order, int64_t n_atoms,
-                             int64_t row0, double* K, int64_t ldk, hipStream_t st);
+                             int64_t n_pairs, int64_t row0, double* K, int64_t ldk,
+                             hipStream_t st);
 void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                    const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
                    double delta, const double* c, const double* g_e, double* W, int64_t ldw,

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
     const TD* __restrict__ desc, int64_t ldd, const int64_t* __restrict__ cfg_ptr,
     const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t ldp, int64_t M,
     int64_t D, int zeta, double delta, double* __restrict__ K, int64_t ldk,
-    double* __restrict__ S, int64_t ldS, int64_t n_atoms) {
+    float* __restrict__ S, int64_t ldS, int64_t n_atoms) {
   const int64_t c = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = (int64_t)blockIdx.x * 256 + wave * 64;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
           const double p = acc[u][r];
           const double pz1 = ipow(p, zeta - 1);
           e[u] += d2 * pz1 * p;
-          if (col < M) S[rr * ldS + col] = d2z * pz1;
+          if (col < ldS) S[rr * ldS + col] = (col < M) ? (float)(d2z * pz1) : 0.f;
         }
       }
     }
@@ -118,7 +118,7 @@ struct SplitPair {
 template <typename TJ>
 __global__ __launch_bounds__(256) void k_force_rows_b3(
     const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
-    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const double* __restrict__ S,
+    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
     int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
     int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
       const int src_r = __shfl(src, 4 * g + r);
 #pragma unroll
       for (int u = 0; u < kNCF; ++u) {
-        const float sv = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
+        const float sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
       }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
 template <typename TJ>
 __global__ __launch_bounds__(256) void k_force_rows_b3_global(
     const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
-    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const double* __restrict__ S,
+    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
     int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
     int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3_global(
       const int src_r = __shfl(src, 4 * g + r);
 #pragma unroll
       for (int u = 0; u < kNCb; ++u) {
-        const float sv = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
+        const float sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
       }
@@ -337,14 +337,22 @@ __global__ void k_split_j(const TJ* __restrict__ J, int64_t ldj, int64_t rows, i
 // split X halves sit in LDS in matrix-core order.  Pair metadata, the next
 // pair's first Jacobian block and the S values of the current step are
 // fetched ahead, as in the FP64 form.
-template <bool kUnused>
+template <int NKB>
 __global__ __launch_bounds__(768) void k_force_rows_b3s(
     const __bf16* __restrict__ Jh, const __bf16* __restrict__ Jl, int64_t ldp, int64_t D,
     const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t M,
-    const double* __restrict__ S, int64_t ldS, const int64_t* __restrict__ tgt_ptr,
+    const float* __restrict__ S, int64_t ldS, const int64_t* __restrict__ tgt_ptr,
     const int32_t* __restrict__ tgt_pair, const int32_t* __restrict__ pair_src,
-    const int32_t* __restrict__ order, int64_t n_atoms, int64_t row0, double* __restrict__ K,
-    int64_t ldk, int64_t n_ct, int64_t total, int64_t per_xcd, int nkb) {
+    const int32_t* __restrict__ order, int64_t n_atoms, int64_t n_pairs, int64_t row0,
+    double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total, int64_t per_xcd) {
+  constexpr int nkb = NKB;  // 32-deep k blocks (compile time: straight-line, exact waits)
+  // No guarded load on the hot path (a guarded load compiles to a branch whose
+  // join waits for it at once): every load reads a valid address, and invalid
+  // steps are cancelled by a zero S factor.  A slot past its degree (or a
+  // target past n_atoms) re-reads a valid pair of its target (or pair 0); the
+  // split Jacobian rows are zero-padded to ldp, so no k clamp is needed.  Lane
+  // idx of column tile u owns column 8 idx + u, so a lane's eight S values for
+  // one source are 32 contiguous bytes (S rows zero-padded to ldS).
   extern __shared__ SplitPair xs3[];  // [nkb][kNCF][64]
   const int64_t logical = xcd_logical_block(per_xcd);
   if (logical >= total) return;
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 768) {
     const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
     const int u = rem / 64, ln = rem % 64;
-    const int64_t col = colbase + u * 16 + (ln & 15);
+    const int64_t col = colbase + kNCF * (ln & 15) + u;
     SplitPair sp;
     if (col < M) {
       const int64_t k = (int64_t)kb * 32 + 8 * (ln >> 4);
@@ -372,76 +380,70 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
   const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
   const int maxdeg = wave_max16(deg);
-  int64_t colr[kNCF];
-#pragma unroll
-  for (int u = 0; u < kNCF; ++u) colr[u] = colbase + u * 16 + idx;
+  const int64_t last = min(seg0 + max(deg - 1, 0), n_pairs - 1);
+  auto pair_slot = [&](int t) -> int64_t { return min(seg0 + t, last); };
+  auto rowoff = [&](int p) -> int64_t { return ((int64_t)p * 3 + alpha) * ldp + 8 * g; };
+  const int64_t cl0 = colbase + kNCF * idx;           // first column of this lane
+  const int64_t scol = min(cl0, ldS - kNCF);          // clamped (valid) S offset
   f4v acc[kNCF];
 #pragma unroll
   for (int u = 0; u < kNCF; ++u) acc[u] = zero4f();
   const SplitPair* xb = xs3 + lane;
-  auto pair_at = [&](int t) -> int { return t < deg ? tgt_pair[seg0 + t] : -1; };
-  auto rowoff = [&](int p) -> int64_t { return ((int64_t)p * 3 + alpha) * ldp + 8 * g; };
-  int pair = maxdeg > 0 ? pair_at(0) : -1;
-  int src = pair >= 0 ? pair_src[pair] : -1;
-  if (src < 0) pair = -1;
-  bf8v ah, al;
-  if (pair >= 0) {
-    ah = *reinterpret_cast<const bf8v*>(Jh + rowoff(pair));
-    al = *reinterpret_cast<const bf8v*>(Jl + rowoff(pair));
-  } else {
-    zero_split(ah, al);
-  }
-  for (int t = 0; t < maxdeg; ++t) {
-    const bool pv = pair >= 0;
-    const int64_t ro = pv ? rowoff(pair) : 0;
-    int pair_n = pair_at(t + 1);
-    int src_n = -1;
-    float sv[4][kNCF];
+  if (maxdeg > 0) {
+    // pair metadata one step ahead of its use
+    int pair = tgt_pair[pair_slot(0)];
+    int pair_n = tgt_pair[pair_slot(1)];
+    int src = pair_src[pair];
+    int64_t ro = rowoff(pair);
+    bf8v ah = *reinterpret_cast<const bf8v*>(Jh + ro);
+    bf8v al = *reinterpret_cast<const bf8v*>(Jl + ro);
+    for (int t = 0; t < maxdeg; ++t) {
+      const int pair_nn = tgt_pair[pair_slot(t + 2)];
+      const int src_n = pair_src[pair_n];
+      const int64_t ro_n = rowoff(pair_n);
+      // S of this step's sources (rows 4 g + r of the output tile)
+      f4v s_lo[4], s_hi[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int src_r = __shfl(src, 4 * g + r);
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, 4 * g + r);
+        const float* sp = S + (int64_t)max(src_r, 0) * ldS + scol;
+        s_lo[r] = *reinterpret_cast<const f4v*>(sp);
+        s_hi[r] = *reinterpret_cast<const f4v*>(sp + 4);
+      }
+      f4v G[kNCF];
 #pragma unroll
-      for (int u = 0; u < kNCF; ++u)
-        sv[r][u] = (src_r >= 0 && colr[u] < M) ? (float)S[(int64_t)src_r * ldS + colr[u]] : 0.f;
-    }
-    f4v G[kNCF];
+      for (int u = 0; u < kNCF; ++u) G[u] = zero4f();
+#pragma unroll 1
+      for (int kb = 0; kb < nkb; ++kb) {
+        const int64_t nro = (kb + 1 < nkb) ? ro + (int64_t)(kb + 1) * 32 : ro_n;
+        const bf8v nh = *reinterpret_cast<const bf8v*>(Jh + nro);
+        const bf8v nl = *reinterpret_cast<const bf8v*>(Jl + nro);
 #pragma unroll
-    for (int u = 0; u < kNCF; ++u) G[u] = zero4f();
-    for (int kb = 0; kb < nkb; ++kb) {
-      bf8v nh, nl;
-      if (kb == 0) src_n = pair_n >= 0 ? pair_src[pair_n] : -1;
-      if (kb + 1 < nkb) {
-        if (pv) {
-          nh = *reinterpret_cast<const bf8v*>(Jh + ro + (int64_t)(kb + 1) * 32);
-          nl = *reinterpret_cast<const bf8v*>(Jl + ro + (int64_t)(kb + 1) * 32);
-        } else {
-          zero_split(nh, nl);
+        for (int u = 0; u < kNCF; ++u) {
+          const SplitPair b = xb[(kb * kNCF + u) * 64];
+          G[u] = mfma_bf16(ah, b.h, G[u]);
+          G[u] = mfma_bf16(ah, b.l, G[u]);
+          G[u] = mfma_bf16(al, b.h, G[u]);
         }
-      } else {
-        if (src_n < 0) pair_n = -1;
-        if (pair_n >= 0) {
-          nh = *reinterpret_cast<const bf8v*>(Jh + rowoff(pair_n));
-          nl = *reinterpret_cast<const bf8v*>(Jl + rowoff(pair_n));
-        } else {
-          zero_split(nh, nl);
-        }
+        ah = nh;
+        al = nl;
       }
 #pragma unroll
-      for (int u = 0; u < kNCF; ++u) {
-        const SplitPair b = xb[(kb * kNCF + u) * 64];
-        G[u] = mfma_bf16(ah, b.h, G[u]);
-        G[u] = mfma_bf16(ah, b.l, G[u]);
-        G[u] = mfma_bf16(al, b.h, G[u]);
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, 4 * g + r);
+        const int deg_r = __shfl(deg, 4 * g + r);
+        const float ok = (t < deg_r && src_r >= 0) ? 1.f : 0.f;
+#pragma unroll
+        for (int u = 0; u < kNCF; ++u) {
+          const float sv = (u < 4 ? s_lo[r][u & 3] : s_hi[r][u & 3]) *
+                           ((cl0 + u < M) ? ok : 0.f);
+          acc[u][r] += sv * G[u][r];
+        }
       }
-      ah = nh;
-      al = nl;
+      ro = ro_n;
+      pair_n = pair_nn;
+      src = src_n;
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int u = 0; u < kNCF; ++u) acc[u][r] += sv[r][u] * G[u][r];
-    pair = pair_n;
-    src = src_n;
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
     if (tr < 0) continue;
 #pragma unroll
     for (int u = 0; u < kNCF; ++u)
-      if (colr[u] < M) K[(row0 + 3 * (int64_t)tr + alpha) + colr[u] * ldk] = -(double)acc[u][r];
+      if (cl0 + u < M) K[(row0 + 3 * (int64_t)tr + alpha) + (cl0 + u) * ldk] = -(double)acc[u][r];
   }
 }
 
@@ -637,7 +639,7 @@ void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh
 void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                         int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
                         int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                        double* S, int64_t ldS, hipStream_t st) {
+                        float* S, int64_t ldS, hipStream_t st) {
   if (n_cfg <= 0 || M <= 0) return;
   const int64_t ldp = split_ld(D);
   dim3 grid(cdiv(M, 256), (unsigned)n_cfg);
@@ -650,7 +652,7 @@ void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int6
 }
 
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
-                       const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                       const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
                        const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
                        int64_t ldk, hipStream_t st) {
@@ -712,28 +714,42 @@ void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, i
 }
 
 bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, const __bf16* Xh,
-                             const __bf16* Xl, int64_t M, const double* S, int64_t ldS,
+                             const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                              const int64_t* tgt_ptr, const int32_t* tgt_pair,
                              const int32_t* pair_src, const int32_t* order, int64_t n_atoms,
-                             int64_t row0, double* K, int64_t ldk, hipStream_t st) {
+                             int64_t n_pairs, int64_t row0, double* K, int64_t ldk,
+                             hipStream_t st) {
   if (n_atoms <= 0 || M <= 0) return true;
-  if (D > 32 * kMaxKb32) return false;
+  if (D > 32 * kMaxKb32 || n_pairs <= 0 || ldS % 8 != 0 || ldS < 8) return false;
   const int64_t ldp = split_ld(D);
   const int nkb = (int)(ldp / 32);
   const int64_t n_tgb = (n_atoms + 63) / 64;
   const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
   const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
   const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
-  static bool a = false;
-  if (!a) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3s<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)((size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair)));
-    a = true;
+  auto launch = [&](auto kern) {
+    static bool attr[kMaxKb32 + 1] = {};
+    if (!attr[nkb]) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair)));
+      attr[nkb] = true;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * per_xcd)), dim3(768), lds, st, Jh, Jl, ldp, D, Xh,
+                       Xl, M, S, ldS, tgt_ptr, tgt_pair, pair_src, order, n_atoms, n_pairs, row0,
+                       K, ldk, n_ct, total, per_xcd);
+  };
+  switch (nkb) {
+    case 1: launch(k_force_rows_b3s<1>); break;
+    case 2: launch(k_force_rows_b3s<2>); break;
+    case 3: launch(k_force_rows_b3s<3>); break;
+    case 4: launch(k_force_rows_b3s<4>); break;
+    case 5: launch(k_force_rows_b3s<5>); break;
+    case 6: launch(k_force_rows_b3s<6>); break;
+    case 7: launch(k_force_rows_b3s<7>); break;
+    case 8: launch(k_force_rows_b3s<8>); break;
+    default: return false;
   }
-  hipLaunchKernelGGL(k_force_rows_b3s<true>, dim3((unsigned)(8 * per_xcd)), dim3(768), lds, st, Jh,
-                     Jl, ldp, D, Xh, Xl, M, S, ldS, tgt_ptr, tgt_pair, pair_src, order, n_atoms,
-                     row0, K, ldk, n_ct, total, per_xcd, nkb);
   return true;
 }
 
