@@ -28,6 +28,32 @@ METRIC = "GAP fit time (s), K_NM GFLOP/s; mixed vs FP64 at stated force error"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the force-row kernel on the 116k-atom fit, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the same counters read
+# for a device copy of known size; see profiles/force_rows_fp64_fit_fp64_traffic.md.
+# Reported only while the kernel source is the one that was measured.
+FORCE_TRAFFIC = {
+    "workload": "fit_fp64",
+    "source": "paper_2310_03921_amd/csrc/force_f64.hip",
+    "sha256": "edecc09c7f7d54349f8faaddd3e871cb633695fdaf4757f8599ca185da48d4c5",
+    "fetch_kib": 58093000, "fetch_scale": 2.000,
+    "write_kib": 17642676, "write_scale": 1.000,
+}
+
+
+def force_traffic_bytes(w):
+    import hashlib
+    t = FORCE_TRAFFIC
+    if w.name != t["workload"]:
+        return None
+    try:
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+                return None
+    except OSError:
+        return None
+    return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -240,7 +266,8 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in per.items()},
         "roofline": {"kernel": "k_force_rows (force observation rows, FP64 MFMA)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": force_traffic_bytes(w), "traffic_unit": "bytes per launch",
                      "flops_per_launch": force_flops},
         "cpu_baseline": cpu,
         "mixed_bf16x3": mixed,
