@@ -879,6 +879,71 @@ __global__ __launch_bounds__(512) void k_qr_vtc2(const double* __restrict__ A, i
     }
 }
 
+// W = V^T C for a narrow reflector block (pw <= 16) and a narrow C (nct <= 64
+// columns, the panel's own columns first): the update inside a 64-column block
+// after each 16-wide panel.  This is a memory-bound pass over m x nct doubles,
+// so it has no LDS staging: wave u of a block owns C columns [16 u, 16 u + 16)
+// and all 16 V columns, reads 4 consecutive rows of its columns per lane
+// (32-byte loads, K-permuted so lane group g holds rows 4 g .. 4 g + 3 of a
+// 16-row chunk), and keeps two chunks in flight.  Slabs are short (kNarrowSlab
+// rows) so that many blocks stream at once; chunks clear of the V triangle and
+// of the slab end load with no condition.
+constexpr int kNarrowSlab = 512;
+__global__ __launch_bounds__(256) void k_qr_vtc_narrow(const double* __restrict__ A, int64_t ld,
+                                                       int64_t m, int64_t j0, int pw, int64_t nct,
+                                                       double* __restrict__ part) {
+  const int64_t s = blockIdx.x;
+  const int64_t r0 = j0 + s * kNarrowSlab, r1 = std::min(m, r0 + kNarrowSlab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t cp = (int64_t)wave * 16 + idx;  // this lane's C column (relative to j0)
+  if ((int64_t)wave * 16 >= nct) return;
+  const double* vcol = A + (j0 + min(idx, pw - 1)) * ld;
+  const double* ccol = A + (j0 + min(cp, nct - 1)) * ld;
+  d4v acc = zero4();
+  auto chunk = [&](int64_t rk, double (&va)[4], double (&cb)[4]) {
+    const int64_t r = rk + 4 * g;
+    if (rk - j0 >= 16 && rk + 16 <= r1) {  // uniform over the wave
+      const d4v v = *reinterpret_cast<const d4v*>(vcol + r);
+      const d4v c = *reinterpret_cast<const d4v*>(ccol + r);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        va[q] = v[q];
+        cb[q] = c[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t rq = r + q, rr = rq - j0;
+        const bool in = rq < r1;
+        const double v = in ? vcol[rq] : 0.0;
+        const double c = in ? ccol[rq] : 0.0;
+        va[q] = (!in || idx >= pw) ? 0.0 : (rr == idx ? 1.0 : (rr > idx ? v : 0.0));
+        cb[q] = (!in || cp >= nct) ? 0.0
+                                   : (cp < pw ? (rr == cp ? 1.0 : (rr > cp ? c : 0.0)) : c);
+      }
+    }
+  };
+  const int64_t nch = (r1 - r0 + 15) / 16;
+  double va0[4], cb0[4], va1[4], cb1[4];
+  if (nch > 0) chunk(r0, va0, cb0);
+  if (nch > 1) chunk(r0 + 16, va1, cb1);
+  for (int64_t c = 0; c < nch; c += 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = mfma_f64(va0[q], cb0[q], acc);
+    if (c + 2 < nch) chunk(r0 + (c + 2) * 16, va0, cb0);
+    if (c + 1 >= nch) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = mfma_f64(va1[q], cb1[q], acc);
+    if (c + 3 < nch) chunk(r0 + (c + 3) * 16, va1, cb1);
+  }
+  // D layout: lane (g, idx) holds W[V column g + 4 q][C column idx of the tile]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ii = g + 4 * q;
+    if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[q];
+  }
+}
+
 // ---------------------------------------------- outer (128-wide) WY update ----
 // The same two products as above for a reflector block up to kQrOB = 128 wide:
 // one pass over the trailing columns per 128 reflectors halves the HBM traffic
@@ -1458,7 +1523,8 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
   const int64_t ncols = n + 1;
   const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
   size_t d = 0;
-  d += (size_t)nslab * kQrOB * ncols;        // part
+  d += std::max((size_t)nslab * kQrOB * ncols,  // part (128-wide split-K partials)
+                 (size_t)((m + kNarrowSlab - 1) / kNarrowSlab + 1) * 16 * 64);
   d += (size_t)kQrOB * ncols * 2;            // W, Wt
   d += (size_t)kQrOB * kQrOB;                // T
   d += (size_t)kQrNB * kCS;                  // colstate
@@ -1472,7 +1538,8 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
   double* p = reinterpret_cast<double*>(base);
   w->part = p;
-  w->part_elems = nslab * kQrOB * ncols;
+  w->part_elems = std::max(nslab * kQrOB * ncols,
+                           ((m + kNarrowSlab - 1) / kNarrowSlab + 1) * (int64_t)16 * 64);
   p += w->part_elems;
   w->W = p;
   p += kQrOB * ncols;
@@ -1496,13 +1563,21 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
                          int64_t slab, QrWork* w, hipStream_t st) {
   const int64_t nct = c_end - j0;
   if (nct <= pw) return;
-  const int64_t nslab = (m - j0 + slab - 1) / slab;
-  const int64_t n_ct = (nct + kVC - 1) / kVC;
-  const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
-  hipLaunchKernelGGL(k_qr_vtc2, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0, pw,
-                     nct, slab, n_ct, total, per_xcd, w->part);
-  hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
-                     (int64_t)pw * nct, w->W);
+  if (pw <= 16 && nct <= 64) {
+    const int64_t nslab = (m - j0 + kNarrowSlab - 1) / kNarrowSlab;
+    hipLaunchKernelGGL(k_qr_vtc_narrow, dim3((unsigned)nslab), dim3(256), 0, st, A, ld, m, j0, pw,
+                       nct, w->part);
+    // many slabs, few outputs: 16 waves per 64 outputs split the slab sum
+    reduce_rows_f64(w->part, nslab, (int64_t)pw * nct, w->W, st);
+  } else {
+    const int64_t nslab = (m - j0 + slab - 1) / slab;
+    const int64_t n_ct = (nct + kVC - 1) / kVC;
+    const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
+    hipLaunchKernelGGL(k_qr_vtc2, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0,
+                       pw, nct, slab, n_ct, total, per_xcd, w->part);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
+                       (int64_t)pw * nct, w->W);
+  }
   hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
   hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw, w->T,
                      w->Wt);
