@@ -327,8 +327,9 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
 // second barrier.  Partials alternate between two buffers so a block that is
 // one step ahead never overwrites values a slower block is still reading.
 constexpr int kRRW = 16;    // panel width
-constexpr int kRRQ = 3;     // rows per thread
+constexpr int kRRQ = 4;     // rows per thread
 constexpr int kRRT = 512;   // threads per block
+static_assert(kRRW == 16, "the panel's wave reduction is a 16-value butterfly");
 
 GAP_DEV void grid_barrier(unsigned int* arrive, unsigned int target, int* dev_err) {
   wait_mem();  // this wave's cross-block stores (device-scope atomics) have completed
@@ -378,59 +379,72 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
   }
   double beta_p = 0.0, scale_p = 0.0;
   for (int k = 0; k <= pw; ++k) {
-    // 1. apply reflector k-1 to rows >= k-1
+    // 1. apply reflector k-1 to rows >= k-1.  Register arrays are indexed by
+    //    absolute column only (selects against k), never by a k-relative
+    //    index, which would force them out of registers.  tw[j] is zero for
+    //    j <= k-1, and v is zero on rows above the reflector, so the update
+    //    needs no condition.
     if (k > 0) {
+      double tw[kRRW];
+#pragma unroll
+      for (int j = 0; j < kRRW; ++j) tw[j] = s_tw[j];
 #pragma unroll
       for (int q = 0; q < kRRQ; ++q) {
-        if (lrow[q] < k - 1) continue;
-        double v = 0.0;
+        const bool at = lrow[q] == k - 1, below = lrow[q] > k - 1;
+        double ak1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRRW; ++j) ak1 = (j == k - 1) ? a[q][j] : ak1;
+        const double v = at ? 1.0 : (below ? ak1 * scale_p : 0.0);
+        const double nk1 = at ? beta_p : (below ? v : ak1);
 #pragma unroll
         for (int j = 0; j < kRRW; ++j) {
-          if (j == k - 1) {
-            if (lrow[q] == k - 1) {
-              v = 1.0;
-              a[q][j] = beta_p;
-            } else {
-              v = a[q][j] * scale_p;
-              a[q][j] = v;
-            }
-          }
+          a[q][j] = (j == k - 1) ? nk1 : a[q][j];
+          a[q][j] -= tw[j] * v;
         }
-#pragma unroll
-        for (int j = 0; j < kRRW; ++j)
-          if (j >= k && j < pw) a[q][j] -= s_tw[j] * v;
       }
     }
     if (k == pw) break;
-    // 2. partial sums for column k over rows > k; pivot row published
+    // 2. partial sums for column k over rows > k, by absolute column:
+    //    part[k] = sum a_k^2, part[j] = sum a_k a_j (j > k); pivot row published
     double part[kRRW];
 #pragma unroll
     for (int j = 0; j < kRRW; ++j) part[j] = 0.0;
 #pragma unroll
     for (int q = 0; q < kRRQ; ++q) {
-      if (lrow[q] > k) {
-        double ak = 0.0;
+      double ak = 0.0;
 #pragma unroll
-        for (int j = 0; j < kRRW; ++j)
-          if (j == k) ak = a[q][j];
-        part[0] += ak * ak;
+      for (int j = 0; j < kRRW; ++j) ak = (j == k) ? a[q][j] : ak;
+      ak = (lrow[q] > k) ? ak : 0.0;
 #pragma unroll
-        for (int j = 0; j < kRRW; ++j)
-          if (j > k && j < pw) part[j - k] += ak * a[q][j];
-      } else if (lrow[q] == k) {
+      for (int j = 0; j < kRRW; ++j) part[j] += (j >= k) ? ak * a[q][j] : 0.0;
+      if (lrow[q] == k) {
         double* pv = piv + (k & 1) * kRRW;
 #pragma unroll
         for (int j = 0; j < kRRW; ++j) xstore(pv + j, a[q][j]);
       }
     }
-    const int ncnt = pw - k;
+    // wave sums of the 16 partials by a halving butterfly (17 lane exchanges
+    // instead of 16 separate 6-step reductions): lane l ends with the total of
+    // column 8 b5 + 4 b4 + 2 b3 + b2 of its lane bits
+    {
+      double t8[8], t4[4], t2[2], t1;
+      const bool u5 = lane & 32, u4 = lane & 16, u3 = lane & 8, u2 = lane & 4;
 #pragma unroll
-    for (int v = 0; v < kRRW; ++v) {
-      if (v < ncnt) {
-        const double s = wave_sum(part[v]);
-        if (lane == 0) s_wred[wave][v] = s;
-      }
+      for (int i = 0; i < 8; ++i)
+        t8[i] = (u5 ? part[i + 8] : part[i]) + __shfl_xor(u5 ? part[i] : part[i + 8], 32);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        t4[i] = (u4 ? t8[i + 4] : t8[i]) + __shfl_xor(u4 ? t8[i] : t8[i + 4], 16);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        t2[i] = (u3 ? t4[i + 2] : t4[i]) + __shfl_xor(u3 ? t4[i] : t4[i + 2], 8);
+      t1 = (u2 ? t2[1] : t2[0]) + __shfl_xor(u2 ? t2[0] : t2[1], 4);
+      t1 += __shfl_xor(t1, 2);
+      t1 += __shfl_xor(t1, 1);
+      const int jj = (u5 ? 8 : 0) + (u4 ? 4 : 0) + (u3 ? 2 : 0) + (u2 ? 1 : 0);
+      if ((lane & 3) == 0 && jj >= k && jj < pw) s_wred[wave][jj - k] = t1;
     }
+    const int ncnt = pw - k;
     __syncthreads();
     double* rb = red + (size_t)(k & 1) * kRRW * G;
     if (threadIdx.x < ncnt) {
@@ -1640,7 +1654,9 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
       int64_t i0 = j0;
       while (i0 < j0 + bw) {
         const int64_t rows = m - i0;
-        const int64_t G_rr = std::min<int64_t>(cap, (rows + kRRT - 1) / kRRT);
+        // as few blocks as hold the panel: every column costs one grid barrier
+        // and a reduction over the blocks' partials, both growing with the grid
+        const int64_t G_rr = std::min<int64_t>(cap, (rows + kRRT * kRRQ - 1) / (kRRT * kRRQ));
         const bool rr = cap > 0 && rows <= G_rr * kRRT * kRRQ;
         const int pw = (int)std::min<int64_t>(rr ? kRRW : kPanelW, j0 + bw - i0);
         tm->begin(TM_QR_PANEL);
