@@ -424,7 +424,10 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
     int64_t n_pairs, int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct,
     int64_t total, int64_t per_xcd, int nkb) {
-  extern __shared__ double xs[];  // [nkb][kLdsNC][64 lanes][4]
+  // X tiles in LDS: [nkb][kLdsNC][2 halves][64 lanes][2 doubles]: a lane's four
+  // k values of one fragment are split into two 16-byte halves stored 1 KB
+  // apart, so each 16-byte LDS read of the wave is contiguous (no bank conflict)
+  extern __shared__ double xs[];
   const int64_t logical = xcd_logical_block(per_xcd);
   if (logical >= total) return;
   const int64_t ct = logical % n_ct, tgb = logical / n_ct;
@@ -441,8 +444,10 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
       load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
     else
       zero_frag(v);
-    d4v w = {v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<d4v*>(xs + (size_t)e * 4) = w;
+    const d2v lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    double* t = xs + (size_t)(e >> 6) * 256 + 2 * (e & 63);
+    *reinterpret_cast<d2v*>(t) = lo;
+    *reinterpret_cast<d2v*>(t + 128) = hi;
   }
   __syncthreads();
 
@@ -464,7 +469,12 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
   d4v acc[kLdsNC];
 #pragma unroll
   for (int u = 0; u < kLdsNC; ++u) acc[u] = zero4();
-  const d4v* xb = reinterpret_cast<const d4v*>(xs) + lane;
+  const d2v* xb = reinterpret_cast<const d2v*>(xs) + lane;
+  auto xfrag = [&](int tile) -> d4v {
+    const d2v lo = xb[tile * 128], hi = xb[tile * 128 + 64];
+    const d4v f = {lo[0], lo[1], hi[0], hi[1]};
+    return f;
+  };
   if (maxdeg <= 0) {
     // no pair reaches any of these targets: the rows are zero
   } else {
@@ -489,7 +499,7 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
         {
           d4v b[kLdsNC];
 #pragma unroll
-          for (int u = 0; u < kLdsNC; ++u) b[u] = xb[(kb * kLdsNC + u) * 64];
+          for (int u = 0; u < kLdsNC; ++u) b[u] = xfrag(kb * kLdsNC + u);
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -501,7 +511,7 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
         {
           d4v b[kLdsNC];
 #pragma unroll
-          for (int u = 0; u < kLdsNC; ++u) b[u] = xb[((kb + 1) * kLdsNC + u) * 64];
+          for (int u = 0; u < kLdsNC; ++u) b[u] = xfrag((kb + 1) * kLdsNC + u);
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll

@@ -353,7 +353,9 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   // split Jacobian rows are zero-padded to ldp, so no k clamp is needed.  Lane
   // idx of column tile u owns column 8 idx + u, so a lane's eight S values for
   // one source are 32 contiguous bytes (S rows zero-padded to ldS).
-  extern __shared__ SplitPair xs3[];  // [nkb][kNCF][64]
+  // X halves in LDS: [nkb][kNCF][hi | lo][64 lanes] of 16 bytes, so each 16-byte
+  // LDS read of the wave is contiguous (no bank conflict)
+  extern __shared__ SplitPair xs3[];
   const int64_t logical = xcd_logical_block(per_xcd);
   if (logical >= total) return;
   const int64_t ct = logical % n_ct, tgb = logical / n_ct;
@@ -372,7 +374,9 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
     } else {
       zero_split(sp.h, sp.l);
     }
-    xs3[e] = sp;
+    bf8v* t = reinterpret_cast<bf8v*>(xs3) + (size_t)(e >> 6) * 128 + (e & 63);
+    t[0] = sp.h;
+    t[64] = sp.l;
   }
   __syncthreads();
   const int64_t slot = (tgb * 4 + grp) * 16 + idx;
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   f4v acc[kNCF];
 #pragma unroll
   for (int u = 0; u < kNCF; ++u) acc[u] = zero4f();
-  const SplitPair* xb = xs3 + lane;
+  const bf8v* xb = reinterpret_cast<const bf8v*>(xs3) + lane;
   if (maxdeg > 0) {
     // pair metadata one step ahead of its use
     int pair = tgt_pair[pair_slot(0)];
@@ -420,10 +424,10 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
         const bf8v nl = *reinterpret_cast<const bf8v*>(Jl + nro);
 #pragma unroll
         for (int u = 0; u < kNCF; ++u) {
-          const SplitPair b = xb[(kb * kNCF + u) * 64];
-          G[u] = mfma_bf16(ah, b.h, G[u]);
-          G[u] = mfma_bf16(ah, b.l, G[u]);
-          G[u] = mfma_bf16(al, b.h, G[u]);
+          const bf8v bh = xb[(kb * kNCF + u) * 128], bl = xb[(kb * kNCF + u) * 128 + 64];
+          G[u] = mfma_bf16(ah, bh, G[u]);
+          G[u] = mfma_bf16(ah, bl, G[u]);
+          G[u] = mfma_bf16(al, bh, G[u]);
         }
         ah = nh;
         al = nl;
