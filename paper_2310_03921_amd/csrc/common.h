@@ -68,6 +68,16 @@ GAP_DEV void load4(const float* __restrict__ row, int64_t k, int64_t kmax, doubl
   }
 }
 
+// Unconditional 4-wide load (32-byte aligned for double, 16-byte for float).
+GAP_DEV void load4u(const double* p, double out[4]) {
+  const d4v v = *reinterpret_cast<const d4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+GAP_DEV void load4u(const float* p, double out[4]) {
+  const f4v v = *reinterpret_cast<const f4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+
 GAP_DEV void zero_frag(double out[4]) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) out[s] = 0.0;

@@ -241,6 +241,12 @@ struct FragRowKScaled {
 #pragma unroll
     for (int s = 0; s < 4; ++s) out[s] *= (k + s < kmax) ? cs[k + s] : 0.0;
   }
+  GAP_DEV void fast(int64_t k0, int g, double out[4]) const {
+    const int64_t k = k0 + 4 * g;
+    load4u(row + k, out);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] *= cs[k + s];
+  }
 };
 
 // ------------------------------------------------------- out = W X (row-major)

@@ -127,166 +127,19 @@ __global__ __launch_bounds__(256) void k_force_rows(
   }
 }
 
-// LDS-resident variant for D <= 256: the block's 64 sparse-point columns of X
+// LDS-resident forms for D <= 256: the block's 64 sparse-point columns of X
 // stay in LDS for its whole lifetime, stored in the order the matrix core
-// consumes them (per 16-k block, per 16-column tile, per lane: 4 doubles), so
-// every B fragment is one conflict-free 32-byte LDS read.  Each of the four
-// waves owns its own 16-target slot group; a block covers 64 targets x 64
-// columns.  Consecutive logical blocks on one XCD walk the column tiles of
-// the same 64 targets, so their Jacobian rows are fetched from HBM once and
-// then served from that XCD's L2.
+// consumes them.  A block covers 64 targets (four 16-target slot groups) x 64
+// columns.  Consecutive logical blocks on one XCD walk the column tiles of the
+// same 64 targets, so their Jacobian rows are fetched from HBM once and then
+// served mostly from that XCD's L2.
 constexpr int kLdsNC = 4;
 constexpr int kLdsMaxKb = 16;  // D <= 256
 
-template <typename TJ>
-__global__ __launch_bounds__(256) void k_force_rows_lds(
-    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
-    int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
-    const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
-    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
-    int64_t per_xcd, int nkb) {
-  extern __shared__ double xs[];  // [nkb][kLdsNC][64 lanes][4]
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t colbase = ct * (16 * kLdsNC);
-
-  for (int e = threadIdx.x; e < nkb * kLdsNC * 64; e += 256) {
-    const int kb = e / (kLdsNC * 64), rem = e % (kLdsNC * 64);
-    const int u = rem / 64, ln = rem % 64;
-    const int64_t col = colbase + u * 16 + (ln & 15);
-    double v[4];
-    if (col < M)
-      load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
-    else
-      zero_frag(v);
-    d4v w = {v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<d4v*>(xs + (size_t)e * 4) = w;
-  }
-  __syncthreads();
-
-  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
-  const int target = slot < n_atoms ? order[slot] : -1;
-  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
-  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
-  const int maxdeg = wave_max16(deg);
-  int64_t colr[kLdsNC];
-#pragma unroll
-  for (int u = 0; u < kLdsNC; ++u) colr[u] = colbase + u * 16 + idx;
-
-  d4v acc[3][kLdsNC];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int u = 0; u < kLdsNC; ++u) acc[a][u] = zero4();
-
-  const d4v* xb = reinterpret_cast<const d4v*>(xs) + lane;
-  // Software pipeline over pair steps t: the next pair's index, its source
-  // atom and its first Jacobian block are fetched while step t runs on the
-  // matrix cores, and the S values of step t are fetched before its k loop.
-  auto pair_at = [&](int t) -> int { return t < deg ? tgt_pair[seg0 + t] : -1; };
-  int pair = maxdeg > 0 ? pair_at(0) : -1;
-  int src = pair >= 0 ? pair_src[pair] : -1;
-  if (src < 0) pair = -1;
-  double a0[3][4], a1[3][4];
-  {
-    const TJ* jr = jac + (int64_t)(pair >= 0 ? pair : 0) * 3 * ldj;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (pair >= 0) load4(jr + a * ldj, 4 * g, D, a0[a]); else zero_frag(a0[a]);
-    }
-  }
-  for (int t = 0; t < maxdeg; ++t) {
-    const bool pv = pair >= 0;
-    const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
-    int pair_n = pair_at(t + 1);
-    double sv[4][kLdsNC];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int src_r = __shfl(src, g + 4 * r);
-#pragma unroll
-      for (int u = 0; u < kLdsNC; ++u)
-        sv[r][u] = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.0;
-    }
-    int src_n = -1;
-    d4v G[3][kLdsNC];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int u = 0; u < kLdsNC; ++u) G[a][u] = zero4();
-    for (int kb = 0; kb < nkb; kb += 2) {  // nkb is even
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (pv) load4(jr + a * ldj, (int64_t)(kb + 1) * 16 + 4 * g, D, a1[a]); else zero_frag(a1[a]);
-      }
-      if (kb == 0) src_n = pair_n >= 0 ? pair_src[pair_n] : -1;
-      {
-        d4v b[kLdsNC];
-#pragma unroll
-        for (int u = 0; u < kLdsNC; ++u) b[u] = xb[(kb * kLdsNC + u) * 64];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int u = 0; u < kLdsNC; ++u) G[a][u] = mfma_f64(a0[a][s4], b[u][s4], G[a][u]);
-      }
-      if (kb + 2 < nkb) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (pv) load4(jr + a * ldj, (int64_t)(kb + 2) * 16 + 4 * g, D, a0[a]); else zero_frag(a0[a]);
-        }
-      } else {
-        // first block of the next pair step
-        if (src_n < 0) pair_n = -1;
-        const TJ* jn = jac + (int64_t)(pair_n >= 0 ? pair_n : 0) * 3 * ldj;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (pair_n >= 0) load4(jn + a * ldj, 4 * g, D, a0[a]); else zero_frag(a0[a]);
-        }
-      }
-      {
-        d4v b[kLdsNC];
-#pragma unroll
-        for (int u = 0; u < kLdsNC; ++u) b[u] = xb[((kb + 1) * kLdsNC + u) * 64];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int u = 0; u < kLdsNC; ++u) G[a][u] = mfma_f64(a1[a][s4], b[u][s4], G[a][u]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int u = 0; u < kLdsNC; ++u)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv[r][u] * G[a][u][r];
-    pair = pair_n;
-    src = src_n;
-  }
-
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int tr = __shfl(target, g + 4 * r);
-    if (tr < 0) continue;
-#pragma unroll
-    for (int u = 0; u < kLdsNC; ++u) {
-      if (colr[u] >= M) continue;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -acc[a][u][r];
-    }
-  }
-}
-
 // Twelve-wave form: wave w handles Jacobian component alpha = w % 3 of slot
-// group w / 3, so each wave carries a quarter of the accumulators of the
-// three-component form and three waves share a SIMD, hiding each other's
-// Jacobian load latency.  Same block tile (64 targets x 64 columns), same
-// LDS layout of X, same results.
+// group w / 3, so three waves share a SIMD and hide each other's Jacobian load
+// latency.  X in LDS per 16-k block, per 16-column tile, per lane: 4 doubles.
+// (Used when D is not a multiple of 4; k_force_rows_lds12f below otherwise.)
 constexpr int kW12 = 12;
 template <typename TJ>
 __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12(

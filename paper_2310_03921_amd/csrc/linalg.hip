@@ -502,61 +502,6 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
   }
 }
 
-// Panel column c of V (unit lower trapezoidal) or a plain column of A.
-struct FragPanel {
-  const double* col;   // A + column * ld
-  int64_t r0;          // first row of the slab
-  int64_t r1;          // end row (exclusive)
-  int64_t diag;        // global row of the unit diagonal, or -1 for a plain column
-  bool valid;
-  GAP_DEV void frag(int64_t k0, int g, double out[4]) const {
-    const int64_t r = r0 + k0 + 4 * g;
-    if (!valid) {
-      zero_frag(out);
-      return;
-    }
-    load4(col, r, r1, out);
-    if (diag >= 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t rr = r + q;
-        out[q] = (rr == diag) ? 1.0 : (rr > diag ? out[q] : 0.0);
-      }
-    }
-  }
-};
-
-// part[s][i][c'] = sum over rows of slab s of V[r][i] * A[r][j0 + c'],   i < pw, c' < nct
-__global__ __launch_bounds__(256) void k_qr_vtc(const double* __restrict__ A, int64_t ld, int64_t m,
-                                                int64_t j0, int pw, int64_t nct, int64_t slab,
-                                                double* __restrict__ part) {
-  const int64_t s = blockIdx.x;
-  const int64_t r0 = j0 + s * slab, r1 = std::min(m, r0 + slab);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int i = wave * 16 + idx;
-  FragPanel fa{A + (j0 + (i < pw ? i : 0)) * ld, r0, r1, j0 + i, i < pw};
-  FragPanel fb[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t cp = (int64_t)blockIdx.y * 64 + u * 16 + idx;
-    const bool ok = cp < nct;
-    fb[u] = FragPanel{A + (j0 + (ok ? cp : 0)) * ld, r0, r1, (ok && cp < pw) ? j0 + cp : -1, ok};
-  }
-  d4v acc[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = zero4();
-  wave_mma<4>(fa, fb, r1 - r0, g, acc);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t cp = (int64_t)blockIdx.y * 64 + u * 16 + idx;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ii = wave * 16 + g + 4 * q;
-      if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[u][q];
-    }
-  }
-}
-
 __global__ void k_sum_slabs(const double* __restrict__ part, int64_t nslab, int64_t n,
                             double* __restrict__ W) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
@@ -605,59 +550,6 @@ __global__ void k_qr_tw(const double* __restrict__ W, int64_t nct, int pw,
     double s = 0.0;
     for (int l = 0; l <= kk; ++l) s += T[l * kQrNB + kk] * W[(int64_t)l * nct + cp];
     Wt[(int64_t)kk * nct + cp] = -s;
-  }
-}
-
-// Rows of V for the update: element (r, kk) = V[r][kk] read along kk for fixed r.
-struct FragVRow {
-  const double* A;
-  int64_t ld;
-  int64_t r;     // global row
-  int64_t j0;    // panel start
-  int pw;
-  bool valid;
-  GAP_DEV void frag(int64_t k0, int g, double out[4]) const {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t kk = k0 + 4 * g + q;
-      double v = 0.0;
-      if (valid && kk < pw) {
-        const int64_t rr = r - j0;
-        v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
-      }
-      out[q] = v;
-    }
-  }
-};
-
-// C[r][c] -= sum_kk V[r][kk] Wt[kk][c - j0]  for r in [j0, m), c in [j0 + pw, ncols)
-__global__ __launch_bounds__(256) void k_qr_update(double* __restrict__ A, int64_t ld, int64_t m,
-                                                   int64_t j0, int pw, int64_t ncols, int64_t nct,
-                                                   const double* __restrict__ Wt) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t cbase = j0 + pw + (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t rbase = j0 + (int64_t)blockIdx.y * 64;
-  const int64_t c = cbase + idx;
-  FragColK<double> fa{Wt + (c < ncols ? c - j0 : 0), nct, pw, c < ncols};
-  FragVRow fb[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t r = rbase + u * 16 + idx;
-    fb[u] = FragVRow{A, ld, r, j0, pw, r < m};
-  }
-  d4v acc[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = zero4();
-  wave_mma<4>(fa, fb, pw, g, acc);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t r = rbase + u * 16 + idx;
-    if (r >= m) continue;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t cc = cbase + g + 4 * q;
-      if (cc < ncols) A[r + cc * ld] -= acc[u][q];
-    }
   }
 }
 
