@@ -619,10 +619,16 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
       gapk::div_sigma(at<double>(h, rtop), sigma, n_rows, vv, h->stream);
       gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
                                     N, a->n_pairs, vv + nc, at<double>(h, hbuf), ldg, h->stream);
-      gapk::pstage_f64(3, nullptr, false, 0, N, sp->X, sp->ld_x, M, D, sp->zeta, sp->delta,
-                       nullptr, nullptr, at<double>(h, hbuf), ldg, nullptr, 0, nullptr,
-                       at<double>(h, dcp), h->stream, S, ldS);
-      gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, gv, h->stream);
+      if (gapk::resid_colsum_f64(at<double>(h, hbuf), ldg, N, D, sp->X, sp->ld_x, M, S, ldS,
+                                 at<double>(h, dcp), h->stream)) {
+        gapk::reduce_rows_f64(at<double>(h, dcp), gapk::resid_colsum_groups(N, M), M, gv,
+                              h->stream);
+      } else {
+        gapk::pstage_f64(3, nullptr, false, 0, N, sp->X, sp->ld_x, M, D, sp->zeta, sp->delta,
+                         nullptr, nullptr, at<double>(h, hbuf), ldg, nullptr, 0, nullptr,
+                         at<double>(h, dcp), h->stream, S, ldS);
+        gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, gv, h->stream);
+      }
       gapk::gemvt_cm_add_f64(kE, ldke, nc, M, vv, gv, h->stream);
       gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), gv, h->stream);
       gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);

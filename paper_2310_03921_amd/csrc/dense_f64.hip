@@ -225,6 +225,106 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
   }
 }
 
+// Column sums of the refinement residual's force part, column-stationary:
+//   dc_part[rg][m] = -sum over atoms i of row group rg of S[i][m] (h_i . x_m).
+// A block keeps 64 columns of X in LDS for its lifetime (as the force-row
+// kernel does) and streams the atom rows of its row group: each of its 12
+// waves takes 16 rows per step, multiplies them with the X tile on the FP64
+// matrix cores, scales by S and accumulates per-lane column sums in registers;
+// one cross-wave reduction at the end writes the block's 64 sums.  Consecutive
+// logical blocks on an XCD walk the column tiles of one row group, so its h
+// rows are read from HBM about once.  Hot loads are unconditional: rows past n
+// read a clamped valid row (masked out by a zero factor), k blocks past D meet
+// zero rows of X; S rows are zero-padded to ldS (a multiple of 4).
+constexpr int kRcW = 12;       // waves per block
+constexpr int kRcMaxKb = 16;   // D <= 256
+__global__ __launch_bounds__(64 * kRcW) void k_resid_colsum(
+    const double* __restrict__ H, int64_t ldh, int64_t n, int64_t D,
+    const double* __restrict__ X, int64_t ldx, int64_t M, const double* __restrict__ S,
+    int64_t ldS, int64_t rows_per_group, int64_t n_ct, int64_t total, int64_t per_xcd,
+    int nkb, double* __restrict__ dc_part) {
+  extern __shared__ double xs[];  // [nkb][4 tiles][2 halves][64 lanes][2]
+  __shared__ double red[kRcW][64];
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t ct = logical % n_ct, rg = logical / n_ct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t colbase = ct * 64;
+  for (int e = threadIdx.x; e < nkb * 4 * 64; e += 64 * kRcW) {
+    const int kb = e / 256, u = (e / 64) & 3, ln = e & 63;
+    const int64_t col = colbase + 4 * (ln & 15) + u;  // lane idx of tile u: column 4 idx + u
+    double v[4];
+    if (col < M)
+      load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
+    else
+      zero_frag(v);
+    const d2v lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    double* t = xs + (size_t)(e >> 6) * 256 + 2 * (e & 63);
+    *reinterpret_cast<d2v*>(t) = lo;
+    *reinterpret_cast<d2v*>(t + 128) = hi;
+  }
+  __syncthreads();
+  const d2v* xb = reinterpret_cast<const d2v*>(xs) + lane;
+  auto xfrag = [&](int tile) -> d4v {
+    const d2v lo = xb[tile * 128], hi = xb[tile * 128 + 64];
+    const d4v f = {lo[0], lo[1], hi[0], hi[1]};
+    return f;
+  };
+  const int64_t r_lo = rg * rows_per_group, r_hi = min(n, r_lo + rows_per_group);
+  const int64_t kmax4 = ((D + 3) & ~int64_t(3)) - 4;  // last aligned 4-block inside ldh
+  const int64_t scol = min(colbase + 4 * idx, ldS - 4);
+  double csum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r_lo + wave * 16; rb < r_hi; rb += 16 * kRcW) {
+    const double* hrow = H + min(rb + idx, n - 1) * ldh;
+    // S of the step's output rows (rows rb + g + 4 r), used after the matrix work
+    d4v sv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      sv[r] = *reinterpret_cast<const d4v*>(S + min(rb + g + 4 * r, n - 1) * ldS + scol);
+    d4v G[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) G[u] = zero4();
+    double a0[4], a1[4];
+    load4u(hrow + min((int64_t)4 * g, kmax4), a0);
+    for (int kb = 0; kb < nkb; ++kb) {
+      load4u(hrow + min((int64_t)(kb + 1) * 16 + 4 * g, kmax4), a1);
+      d4v b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) b[u] = xfrag(kb * 4 + u);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) G[u] = mfma_f64(a0[s4], b[u][s4], G[u]);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) a0[s4] = a1[s4];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double ok = (rb + g + 4 * r < r_hi) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) csum[u] += sv[r][u] * ok * G[u][r];
+    }
+  }
+  // sum the four row sub-groups (lane groups), then the waves
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    csum[u] += __shfl_xor(csum[u], 16);
+    csum[u] += __shfl_xor(csum[u], 32);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) red[wave][4 * idx + u] = csum[u];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRcW; ++w) t += red[w][threadIdx.x];
+    const int64_t col = colbase + threadIdx.x;
+    if (col < M) dc_part[rg * M + col] = -t;
+  }
+}
+
 // A row of W with every element k scaled by cs[k] (cs: any alignment, length kmax).
 struct FragRowKScaled {
   const double* row;
@@ -480,6 +580,37 @@ void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const doubl
   if (n <= 0 || D <= 0) return;
   hipLaunchKernelGGL(k_gemm_wx, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
                      X, ldx, D, out, ldo);
+}
+
+int64_t resid_colsum_groups(int64_t n, int64_t M) {
+  const int64_t n_ct = (M + 63) / 64;
+  // about three blocks per CU over the whole grid, at least one row step each
+  const int64_t want = std::max<int64_t>(1, (768 + n_ct - 1) / n_ct);
+  return std::max<int64_t>(1, std::min<int64_t>(want, (n + 16 * kRcW - 1) / (16 * kRcW)));
+}
+
+bool resid_colsum_f64(const double* H, int64_t ldh, int64_t n, int64_t D, const double* X,
+                      int64_t ldx, int64_t M, const double* S, int64_t ldS, double* dc_part,
+                      hipStream_t st) {
+  if (n <= 0 || M <= 0) return true;
+  if (D > 16 * kRcMaxKb || D % 4 != 0 || ldS % 4 != 0 || ldS < 4 || ldh % 4 != 0 || D < 4)
+    return false;  // (D % 4: the row padding of H is not written, so it is never read)
+  const int nkb = (int)((D + 15) / 16);
+  const int64_t n_ct = (M + 63) / 64;
+  const int64_t n_rg = resid_colsum_groups(n, M);
+  const int64_t rows = (n + n_rg - 1) / n_rg;
+  const int64_t total = n_ct * n_rg, per_xcd = (total + 7) / 8;
+  const size_t lds = (size_t)nkb * 4 * 64 * 4 * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resid_colsum),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((size_t)kRcMaxKb * 4 * 64 * 4 * sizeof(double)));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_resid_colsum, dim3((unsigned)(8 * per_xcd)), dim3(64 * kRcW), lds, st, H,
+                     ldh, n, D, X, ldx, M, S, ldS, rows, n_ct, total, per_xcd, nkb, dc_part);
+  return true;
 }
 
 void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* cs,

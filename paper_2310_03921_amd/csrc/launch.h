@@ -94,6 +94,13 @@ int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st);
+// dc_part[rg][m] = -sum_{i in row group rg} S[i][m] (H_i . x_m), column-stationary;
+// returns false (nothing launched) when the shape is outside its limits
+// (D <= 256, ldS and ldh multiples of 4).  Groups: resid_colsum_groups(n, M).
+int64_t resid_colsum_groups(int64_t n, int64_t M);
+bool resid_colsum_f64(const double* H, int64_t ldh, int64_t n, int64_t D, const double* X,
+                      int64_t ldx, int64_t M, const double* S, int64_t ldS, double* dc_part,
+                      hipStream_t st);
 // out = (W diag(cs)) X   (cs: [M], any alignment)
 void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* cs,
                         const double* X, int64_t ldx, int64_t D, double* out, int64_t ldo,
