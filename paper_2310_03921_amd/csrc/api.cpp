@@ -508,7 +508,7 @@ gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n,
   gapk::QrWork qw;
   gapk::qr_bind_workspace(at<char>(h, q), m, n, &qw);
   gapk::qr_factor(A, ld, m, n + 1, n, &qw, h->stream, h->dev_err, &h->timer);
-  gapk::back_substitute(A, ld, n, A + n * ld, x, h->dev_small, h->dev_err, h->stream);
+  gapk::back_substitute(A, ld, n, A + n * ld, x, h->dev_small, h->dev_err, h->stream, qw.flags);
   HIP_TRY(h, hipGetLastError());
   double rd[2] = {0, 0};
   HIP_TRY(h, hipMemcpyAsync(rd, h->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -573,7 +573,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   h->timer.end(gapk::TM_CHOL);
   gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream, h->dev_err, &h->timer);
   h->timer.begin(gapk::TM_TRSV);
-  gapk::back_substitute(A, ld, M, A + M * ld, c, h->dev_small, h->dev_err, h->stream);
+  gapk::back_substitute(A, ld, M, A + M * ld, c, h->dev_small, h->dev_err, h->stream, qw.flags);
   h->timer.end(gapk::TM_TRSV);
   HIP_TRY(h, hipGetLastError());
   gap_fit_info inf;
@@ -634,7 +634,7 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
       gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);
       if (step == refine_steps) break;
       // R^T R dc = A^T r ; c += dc
-      gapk::seminormal_solve(A, ld, M, gv, h->stream);
+      gapk::seminormal_solve(A, ld, M, gv, h->stream, qw.flags, at<double>(h, rbot), h->dev_err);
       gapk::axpy_f64(M, 1.0, gv, c, h->stream);
     }
     h->timer.end(gapk::TM_REFINE);

@@ -195,6 +195,7 @@ struct QrWork {
   double* red;        // panel reduction partials
   double* tau;        // tau of every reflector [n]
   unsigned int* counter;
+  unsigned int* flags;  // per-block completion flags of the multi-block triangular solves
 };
 size_t qr_workspace_bytes(int64_t m, int64_t n);
 void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w);
@@ -204,10 +205,15 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
                hipStream_t st, int* dev_err, Timer* tm = nullptr);
 // x = R^-1 z (R upper n x n col-major in A, z = A[0:n][n]); records min/max |R_kk|
 // into rd[0..1] (device) and flags zero/non-finite pivots.
+// flags (QrWork::flags, may be NULL) enables the multi-block solve; x must not
+// alias z when flags are given.
 void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
-                     double* rd, int* dev_err, hipStream_t st);
-// Solve R^T y = z (forward) then R x = y (backward), in place on x.
-void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st);
+                     double* rd, int* dev_err, hipStream_t st, unsigned int* flags = nullptr);
+// Solve R^T y = x (forward) then R x = y (backward), result in x; with flags
+// and an n-element scratch tmp, both solves use the multi-block kernel.
+void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st,
+                      unsigned int* flags = nullptr, double* tmp = nullptr,
+                      int* dev_err = nullptr);
 // r_top[r] = (y_r - kc_r) / sigma_r ; r_bot = -U c ;  also returns sum of squares pieces
 void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
                      const double* L, int64_t ldl, int64_t M, const double* c, double* r_top,

@@ -22,6 +22,7 @@ namespace gapk {
 namespace {
 
 constexpr int kQrNB = 64;      // outer block width (compact-WY trailing update)
+constexpr int kTrsvMaxBlocks = 256;  // multi-block triangular solve: n <= 64 * 256
 constexpr int kPanelW = 32;    // inner panel width (column-by-column factorisation)
 constexpr int kCholNB = 64;    // Cholesky block
 constexpr int kPanelMaxGrid = 256;
@@ -1281,6 +1282,101 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(const double* __restrict__ R,
   for (int64_t i = tid; i < n; i += 1024) x[i] = xs[i];
 }
 
+// Multi-block form of the same solves: block t owns the 64 unknowns of column
+// block b (b = t for the forward solve with R^T, b = nb - 1 - t for back
+// substitution), so every block it depends on has a smaller index and was
+// dispatched earlier; the launch is cooperative, so all blocks are resident.
+// A block folds in each dependency block c as soon as c publishes its 64
+// values (flag[c] == epoch): a 64 x 64 product with the R tile, spread over
+// 4 waves.  Then wave 0 solves the diagonal block (staged in LDS), and the
+// block publishes its values with device-scope stores before its flag
+// (cross-XCD exchange without an L2-flushing fence).  Waits are bounded and
+// set GAP_DEVERR_SYNC on expiry, after which every wait returns at once.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_trsv_coop(const double* __restrict__ R, int64_t ld,
+                                                   int64_t n, const double* z, double* x,
+                                                   unsigned int* __restrict__ flag,
+                                                   unsigned int epoch, int* dev_err) {
+  __shared__ double T[64][65];
+  __shared__ double part[4][64];
+  __shared__ double xd[64];
+  const int nb = (int)((n + 63) / 64);
+  const int b = TRANS ? (int)blockIdx.x : nb - 1 - (int)blockIdx.x;
+  const int64_t j0 = (int64_t)b * 64;
+  const int w = (int)min((int64_t)64, n - j0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    T[r][c] = (r < w && c < w && r <= c) ? R[(j0 + r) + (j0 + c) * ld] : 0.0;
+  }
+  double acc = 0.0;
+  const int ndep = TRANS ? b : nb - 1 - b;
+  for (int d = 0; d < ndep; ++d) {
+    const int c = TRANS ? d : nb - 1 - d;  // in the order the dependencies complete
+    const int64_t c0 = (int64_t)c * 64;
+    if (tid == 0) {
+      uint64_t spins = 0;
+      while (__hip_atomic_load(flag + c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (dev_err && (__hip_atomic_load(dev_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                        GAP_DEVERR_SYNC))
+          break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 22)) {
+          if (dev_err) atomicOr(dev_err, GAP_DEVERR_SYNC);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 64) xd[tid] = (c0 + tid < n) ? vload(x + c0 + tid) : 0.0;
+    __syncthreads();
+    if (lane < w) {
+      if (TRANS) {
+        // unknown j0 + lane needs sum_i R[c0 + i][j0 + lane] y[c0 + i]
+        const double* col = R + (j0 + lane) * ld + c0;
+#pragma unroll 4
+        for (int i = wave * 16; i < wave * 16 + 16; ++i) acc += col[i] * xd[i];
+      } else {
+        // unknown j0 + lane needs sum_j R[j0 + lane][c0 + j] x[c0 + j]
+        // columns past n (the last block) are clamped in range; xd is zero there
+        const double* row = R + (j0 + lane);
+#pragma unroll 4
+        for (int jj = wave * 16; jj < wave * 16 + 16; ++jj)
+          acc += row[min(c0 + jj, n - 1) * ld] * xd[jj];
+      }
+    }
+  }
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    double t = lane < w ? z[j0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) +
+                                          part[3][lane])
+                        : 0.0;
+    bool bad = false;
+    if (TRANS) {
+      for (int c = 0; c < w; ++c) {
+        const double dg = T[c][c];
+        bad |= (dg == 0.0 || !isfinite(dg));
+        const double xc = __shfl(t, c) / dg;
+        if (lane == c) t = xc;
+        else if (lane > c) t -= T[c][lane] * xc;
+      }
+    } else {
+      for (int c = w - 1; c >= 0; --c) {
+        const double dg = T[c][c];
+        bad |= (dg == 0.0 || !isfinite(dg));
+        const double xc = __shfl(t, c) / dg;
+        if (lane == c) t = xc;
+        else if (lane < c) t -= T[lane][c] * xc;
+      }
+    }
+    if (lane < w) xstore(x + j0 + lane, t);
+    if (bad && lane == 0 && dev_err) atomicOr(dev_err, GAP_DEVERR_RANK);
+    wait_mem();
+    if (lane == 0) __hip_atomic_store(flag + b, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_rdiag_minmax(const double* __restrict__ R, int64_t ld,
                                                        int64_t n, double* __restrict__ rd) {
   __shared__ double smin[16], smax[16];
@@ -1391,6 +1487,12 @@ __global__ void k_expand_cfg(const double* __restrict__ v, const int32_t* __rest
   }
 }
 
+__global__ void k_fill_u32(unsigned int* __restrict__ p, int64_t n, unsigned int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 inline unsigned g256(int64_t n) { return std::max(1u, std::min(cdiv(n, 256), 65536u)); }
@@ -1436,7 +1538,7 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
   d += (size_t)kQrNB * kCS;                  // colstate
   d += (size_t)kQrNB * kPanelMaxGrid;        // red
   d += (size_t)n + 8;                        // tau
-  return d * sizeof(double) + 256;
+  return d * sizeof(double) + 256 + sizeof(unsigned int) * kTrsvMaxBlocks;  // counters, flags
 }
 
 void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
@@ -1460,6 +1562,7 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   w->tau = p;
   p += n + 8;
   w->counter = reinterpret_cast<unsigned int*>(p);
+  w->flags = w->counter + 64;
 }
 
 // Compact-WY update of columns [c0, c_end) with the pw reflectors stored in
@@ -1596,18 +1699,54 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
   }
 }
 
-void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
-                     double* rd, int* dev_err, hipStream_t st) {
-  hipLaunchKernelGGL(k_rdiag_minmax, dim3(1), dim3(1024), 0, st, A, ld, n, rd);
-  hipLaunchKernelGGL(k_trsv_blk<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
-                     ld, n, z, x, dev_err);
+// One triangular solve: the multi-block kernel when flags are given and it can
+// be launched cooperatively, else the one-workgroup kernel.  x may alias z only
+// for the one-workgroup form (it reads z into LDS first); the multi-block form
+// reads z[j] only in the block that writes x[j], before it writes it.
+static void trsv(bool trans, const double* A, int64_t ld, int64_t n, const double* z, double* x,
+                 unsigned int* flags, int* dev_err, hipStream_t st) {
+  const int nb = (int)((n + 63) / 64);
+  if (flags && nb <= kTrsvMaxBlocks) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, flags, (int64_t)nb, 0u);
+    unsigned int ep = 1;
+    const double* A_ = A;
+    int64_t ld_ = ld, n_ = n;
+    const double* z_ = z;
+    double* x_ = x;
+    unsigned int* f_ = flags;
+    int* e_ = dev_err;
+    void* args[] = {&A_, &ld_, &n_, &z_, &x_, &f_, &ep, &e_};
+    const void* kern = trans ? reinterpret_cast<const void*>(&k_trsv_coop<true>)
+                             : reinterpret_cast<const void*>(&k_trsv_coop<false>);
+    if (hipLaunchCooperativeKernel(kern, dim3((unsigned)nb), dim3(256), args, 0, st) ==
+        hipSuccess)
+      return;
+    (void)hipGetLastError();
+  }
+  if (trans)
+    hipLaunchKernelGGL(k_trsv_blk<true>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
+                       ld, n, z, x, dev_err);
+  else
+    hipLaunchKernelGGL(k_trsv_blk<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
+                       ld, n, z, x, dev_err);
 }
 
-void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_trsv_blk<true>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A, ld,
-                     n, x, x, nullptr);
-  hipLaunchKernelGGL(k_trsv_blk<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, A,
-                     ld, n, x, x, nullptr);
+void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, double* x,
+                     double* rd, int* dev_err, hipStream_t st, unsigned int* flags) {
+  hipLaunchKernelGGL(k_rdiag_minmax, dim3(1), dim3(1024), 0, st, A, ld, n, rd);
+  trsv(false, A, ld, n, z, x, flags, dev_err, st);
+}
+
+void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st,
+                      unsigned int* flags, double* tmp, int* dev_err) {
+  // R^T y = x, then R x = y; the multi-block form needs y apart from x
+  if (flags && tmp) {
+    trsv(true, A, ld, n, x, tmp, flags, dev_err, st);
+    trsv(false, A, ld, n, tmp, x, flags, dev_err, st);
+  } else {
+    trsv(true, A, ld, n, x, x, nullptr, nullptr, st);
+    trsv(false, A, ld, n, x, x, nullptr, nullptr, st);
+  }
 }
 
 void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
