@@ -75,37 +75,48 @@ __global__ void k_chol_init(double* __restrict__ Lw, int64_t ldl, int64_t M, dou
     Lw[i + j * ldl] = Kmm[i + j * ldk] + (i == j ? jitter : 0.0);
 }
 
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Lw, int64_t ldl, int64_t j0,
-                                                   int nbj, int* dev_err) {
-  __shared__ double s[kCholNB][kCholNB + 1];
-  for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
-    const int r = e % nbj, c = e / nbj;
-    s[r][c] = Lw[(j0 + r) + (j0 + c) * ldl];
-  }
-  __syncthreads();
-  for (int c = 0; c < nbj; ++c) {
-    if (threadIdx.x == 0) {
-      double p = s[c][c];
+// Diagonal block (nbj <= 64) by one wave, left-looking: lane r holds row r of
+// the block in registers.  For column c, lane c publishes the finished part of
+// its row (L[c][0:c]) to LDS; every lane forms the dot product of its row with
+// it (broadcast reads), lane c's residual gives the pivot by a lane shuffle,
+// and lanes below divide.  The column loop is unrolled so that every register
+// index is a compile-time constant.
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ Lw, int64_t ldl, int64_t j0,
+                                                  int nbj, int* dev_err) {
+  __shared__ double rowc[kCholNB];
+  const int l = threadIdx.x;
+  double row[kCholNB];
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c)
+    row[c] = (l < nbj && c < nbj) ? Lw[(j0 + l) + (j0 + c) * ldl] : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c) {
+    if (c < nbj) {
+      if (l == c) {
+#pragma unroll
+        for (int q = 0; q < c; ++q) rowc[q] = row[q];
+      }
+      __syncthreads();
+      double dot = 0.0;
+#pragma unroll
+      for (int q = 0; q < c; ++q) dot += row[q] * rowc[q];
+      const double res = row[c] - dot;
+      double p = __shfl(res, c);
       if (!(p > 0.0) || !isfinite(p)) {
-        atomicOr(dev_err, GAP_DEVERR_NOT_PD);
+        bad = true;
         p = 1.0;
       }
-      s[c][c] = sqrt(p);
+      const double d = sqrt(p);
+      if (l == c) row[c] = d;
+      else if (l > c) row[c] = res / d;
+      __syncthreads();
     }
-    __syncthreads();
-    const double d = s[c][c];
-    for (int r = c + 1 + threadIdx.x; r < nbj; r += 256) s[r][c] /= d;
-    __syncthreads();
-    for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
-      const int r = e % nbj, q = e / nbj;
-      if (q > c && r >= q) s[r][q] -= s[r][c] * s[q][c];
-    }
-    __syncthreads();
   }
-  for (int e = threadIdx.x; e < nbj * nbj; e += 256) {
-    const int r = e % nbj, c = e / nbj;
-    if (r >= c) Lw[(j0 + r) + (j0 + c) * ldl] = s[r][c];
-  }
+  if (bad && l == 0) atomicOr(dev_err, GAP_DEVERR_NOT_PD);
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c)
+    if (c < nbj && l < nbj && l >= c) Lw[(j0 + l) + (j0 + c) * ldl] = row[c];
 }
 
 // Rows below the diagonal block: L[r, j0:j0+nbj] = A[r, j0:j0+nbj] L_dd^-T.
@@ -1511,7 +1522,7 @@ void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const dou
                      jitter, Kmm, ldk);
   for (int64_t j0 = 0; j0 < M; j0 += kCholNB) {
     const int nbj = (int)std::min<int64_t>(kCholNB, M - j0);
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, Lw, ldl, j0, nbj, dev_err);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, Lw, ldl, j0, nbj, dev_err);
     const int64_t rest = M - j0 - nbj;
     if (rest <= 0) break;
     hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rest, 256)), dim3(256), 0, st, Lw, ldl, M, j0, nbj);
