@@ -35,9 +35,9 @@ PEAK_HBM_GBS = 8000.0
 FORCE_TRAFFIC = {
     "workload": "fit_fp64",
     "source": "paper_2310_03921_amd/csrc/force_f64.hip",
-    "sha256": "edecc09c7f7d54349f8faaddd3e871cb633695fdaf4757f8599ca185da48d4c5",
-    "fetch_kib": 58093000, "fetch_scale": 2.000,
-    "write_kib": 17642676, "write_scale": 1.000,
+    "sha256": "1816d6204da7b2be43d4fb748e1f5300119fd5eb6d90b7b98c70912a84ad994e",
+    "fetch_kib": 59492396, "fetch_scale": 2.000,
+    "write_kib": 17669288, "write_scale": 1.000,
 }
 
 
