@@ -93,13 +93,15 @@ GAP_DEV int64_t xcd_logical_block(int64_t per_xcd) {
   return (b & 7) * per_xcd + (b >> 3);
 }
 
-// Workgroup barrier that orders LDS only: waits for this wave's LDS operations
-// (lgkmcnt = 0) but leaves global loads and stores in flight, unlike
-// __syncthreads(), whose release fence drains every outstanding memory access.
-// Encoding (gfx9 s_waitcnt): vmcnt = 63, expcnt = 7, lgkmcnt = 0.
+// Workgroup barrier that orders LDS only: workgroup-scope fences restricted to
+// the local address space (the compiler may not move LDS accesses across them,
+// and the hardware waits only for this wave's LDS operations, lgkmcnt = 0),
+// leaving global loads and stores in flight, unlike __syncthreads(), whose
+// fences drain every outstanding memory access.
 GAP_DEV void lds_barrier() {
-  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 GAP_DEV double wave_sum(double v) {
