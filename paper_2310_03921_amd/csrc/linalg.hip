@@ -1215,6 +1215,152 @@ __global__ __launch_bounds__(512) void k_qr_upd3(double* __restrict__ A, int64_t
   }
 }
 
+// C -= V W' for a full 128-wide reflector block, one barrier per 64-column
+// tile.  Each of the eight waves owns 16 rows of the block's 128 and keeps
+// their V (128 deep) in registers for the whole kernel; -W' (Wn) is the only
+// shared operand and goes through LDS one whole 128 x 64 tile at a time,
+// double-buffered: the next tile's Wn and C are fetched into registers at the
+// start of a tile and Wn is written to the free LDS buffer at its end.  A
+// wave's block is 16 rows x 64 columns (four matrix-core tiles sharing the V
+// operand).  Odd Wn rows are stored with their 16-column halves swapped so that
+// the lane groups reading rows 4t + g and 4t + g + 1 meet different banks.
+//
+// The memory traffic of a tile is issued between its matrix-core products, not
+// around them: the two waves of a SIMD run in step (one barrier per tile), so
+// work issued before or after the products leaves the matrix pipe idle.  For
+// that the previous tile's result is stored during the next tile (from a copy,
+// out), with buffer stores whose out-of-range offset drops the lanes that
+// must not write, so no store sits in a branch.
+//
+// Every global access is a wave-uniform base (scalar registers) plus a 32-bit
+// per-lane byte offset, and no column is clamped: the last tile is shifted left
+// to end at c_end (it needs c_end - cbeg >= 64) and stores only the columns the
+// previous tile did not.  Per-access 64-bit addresses would take 64 registers.
+constexpr int kU5R = 128;  // rows per block (8 waves x 16)
+constexpr int kU5C = 64;   // columns per tile
+// Every global access of the kernel goes through a buffer resource (base in
+// scalar registers) with a 32-bit per-lane offset and a scalar offset: 64-bit
+// per-access vector addresses would take 64 registers.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+GAP_DEV __amdgpu_buffer_rsrc_t uniform_rsrc(const double* p, uint32_t bytes) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((uint64_t)hi << 32 | lo), 0, (int)bytes,
+                                           0x00020000);
+}
+GAP_DEV double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+GAP_DEV void buf_st(double x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+constexpr uint32_t kDropOffset = 0x80000000u;  // beyond any buffer this kernel makes
+__global__ __launch_bounds__(512) void k_qr_upd5(double* __restrict__ A, int64_t ld, int64_t m,
+                                                 int64_t j0, int64_t c_end, int64_t nct,
+                                                 const double* __restrict__ Wn) {
+  __shared__ double sW[2][kQrOB][kU5C];
+  const int lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = j0 + (int64_t)blockIdx.x * kU5R;
+  const int64_t rw = r0 + wave * 16 + idx;  // this lane's C row
+  const int64_t cbeg = j0 + kQrOB;
+  const int ntile = (int)((c_end - cbeg + kU5C - 1) / kU5C);
+  // V(rw, k) for k = 4 t + g
+  double v[kQrOB / 4];
+  {
+    const int64_t rr = rw - j0;
+#pragma unroll
+    for (int t = 0; t < kQrOB / 4; ++t) {
+      const int k = 4 * t + g;
+      double x = 0.0;
+      if (rw < m) x = (rr == k) ? 1.0 : (rr > k ? A[rw + (j0 + k) * ld] : 0.0);
+      v[t] = x;
+    }
+  }
+  // first column of a tile (the last one shifted to end at c_end)
+  auto tile_col = [&](int tile) { return min(cbeg + (int64_t)tile * kU5C, c_end - kU5C); };
+  // Wn tile: thread (wave, lane) holds rows wave + 8 h (h = 0..15), column lane
+  const uint32_t woff = (uint32_t)lane * 8u;
+  const uint32_t wbytes = (uint32_t)(kQrOB * nct * 8);
+  auto load_w = [&](int tile, double (&dst)[kQrOB / 8]) {
+    const auto rs = uniform_rsrc(Wn + (tile_col(min(tile, ntile - 1)) - j0) + (int64_t)wave * nct,
+                                 wbytes);
+#pragma unroll
+    for (int h = 0; h < kQrOB / 8; ++h) dst[h] = buf_ld(rs, woff, (uint32_t)(8 * h * nct * 8));
+  };
+  auto store_w = [&](int buf, const double (&src)[kQrOB / 8]) {
+#pragma unroll
+    for (int h = 0; h < kQrOB / 8; ++h) {
+      const int k = wave + 8 * h;
+      sW[buf][k][lane ^ ((k & 1) << 4)] = src[h];
+    }
+  };
+  // C element (rw, c0 + 16 i + 4 q + g): base column pointer uniform, the row
+  // and the lane group's column in the offset (rows past m read row m - 1)
+  const uint32_t coff = (uint32_t)((min(rw, m - 1) - r0 + g * ld) * 8);
+  const uint32_t cbytes = (uint32_t)(kU5C * ld * 8);  // a tile's extent from its base
+  // C (rows r0.., a tile's 64 columns) as four 16-column groups i: lane holds
+  // (rw, c0 + 16 i + 4 q + g) in q; reads of rows past m read row m - 1
+  auto load_ci = [&](int tile, int i, d4v& dst) {
+    const auto rs = uniform_rsrc(A + r0 + tile_col(min(tile, ntile - 1)) * ld, cbytes);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = buf_ld(rs, coff, (uint32_t)((16 * i + 4 * q) * ld * 8));
+  };
+  // Stores of a tile through a buffer resource based at its first column: a
+  // lane that must not write (row past m, or a column the shifted last tile
+  // shares with the previous one) gets an offset past the buffer's end, which
+  // the hardware drops.  Tile -1 (before the first) stores nothing.
+  auto store_ci = [&](int tile, int i, const d4v& src) {
+    const int64_t c0 = tile_col(max(tile, 0));
+    const int shift = tile < 0 ? kU5C : (int)(cbeg + (int64_t)tile * kU5C - c0);
+    const auto rs = uniform_rsrc(A + r0 + c0 * ld, cbytes);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = rw < m && 16 * i + 4 * q + g >= shift;
+      buf_st(src[q], rs, ok ? coff : kDropOffset, (uint32_t)((16 * i + 4 * q) * ld * 8));
+    }
+  };
+  // a lane reads Wn row 4 t + g, columns 16 i + idx; odd rows are half-swapped
+  const int sw = (g & 1) << 4;
+  auto products = [&](d4v (&acc)[4], int t0, int t1, const double* wb) {
+#pragma unroll
+    for (int t = t0; t < t1; ++t) {
+      double a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = wb[t * 4 * kU5C + ((i * 16) ^ sw)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = mfma_f64(a[i], v[t], acc[i]);
+    }
+  };
+  d4v acc[4], nxt[4];
+  double wst[kQrOB / 8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) load_ci(0, i, acc[i]);
+  load_w(0, wst);
+  store_w(0, wst);
+  // nothing of the prologue may be left in flight at the loop head: a pending
+  // load there would make the wait at the head of every tile wait for the
+  // previous tile's accesses as well
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int buf = 0;
+#pragma clang loop unroll(disable)
+  for (int tile = 0; tile < ntile; ++tile) {
+    load_w(tile + 1, wst);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) load_ci(tile + 1, i, nxt[i]);
+    products(acc, 0, kQrOB / 4, &sW[buf][g][idx]);
+    store_w(buf ^ 1, wst);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) store_ci(tile, i, acc[i]);
+    lds_barrier();
+    buf ^= 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = nxt[i];
+  }
+}
+
 // ------------------------------------------------------- triangular solves ----
 // One workgroup of 16 waves solves R x = z (TRANS = false, back substitution) or
 // R^T x = z (TRANS = true, forward substitution), R upper triangular, col-major (ld).
@@ -1623,8 +1769,14 @@ static void qr_wy_update_ob(double* A, int64_t ld, int64_t m, int64_t j0, int pw
     hipLaunchKernelGGL(k_qr_tcouple, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->T);
   hipLaunchKernelGGL(k_qr_tw_ld, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw,
                      w->T, kQrOB, w->Wt);
-  hipLaunchKernelGGL(k_qr_upd3, dim3(cdiv(m - j0, kU3R)), dim3(512), 0, st, A, ld, m, j0, pw,
-                     c_end, nct, w->Wt);
+  // the barrier-light kernel needs a full block, a full tile of trailing
+  // columns and a 64-column tile of C within 31-bit offsets
+  if (pw == kQrOB && nct - pw >= kU5C && ld < (int64_t)(1 << 22))
+    hipLaunchKernelGGL(k_qr_upd5, dim3(cdiv(m - j0, kU5R)), dim3(512), 0, st, A, ld, m, j0,
+                       c_end, nct, w->Wt);
+  else
+    hipLaunchKernelGGL(k_qr_upd3, dim3(cdiv(m - j0, kU3R)), dim3(512), 0, st, A, ld, m, j0, pw,
+                       c_end, nct, w->Wt);
 }
 
 // Number of k_qr_panel_rr blocks that are co-resident on the current device (0 if unknown).
