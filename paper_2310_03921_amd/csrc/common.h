@@ -93,6 +93,23 @@ GAP_DEV int64_t xcd_logical_block(int64_t per_xcd) {
   return (b & 7) * per_xcd + (b >> 3);
 }
 
+// (group, column tile) of this block, for kernels whose groups come in order of
+// decreasing work (targets sorted by degree).  All column tiles of a group run
+// on one XCD, where they share the group's rows in that XCD's L2, and the
+// groups are dealt to the eight XCDs in turn, so every XCD receives the same
+// mix of heavy and light groups (contiguous group ranges per XCD would leave
+// the XCD with the heaviest groups running long after the others are done).
+// The grid has xcd_group_tile_blocks(n_grp, n_ct) blocks.
+GAP_DEV bool xcd_group_tile(int64_t n_grp, int64_t n_ct, int64_t& grp, int64_t& ct) {
+  const int64_t b = blockIdx.x, j = b >> 3;
+  grp = (j / n_ct) * 8 + (b & 7);
+  ct = j % n_ct;
+  return grp < n_grp;
+}
+inline unsigned xcd_group_tile_blocks(int64_t n_grp, int64_t n_ct) {
+  return (unsigned)(((n_grp + 7) / 8) * 8 * n_ct);
+}
+
 // Workgroup barrier that orders LDS only: workgroup-scope fences restricted to
 // the local address space (the compiler may not move LDS accesses across them,
 // and the hardware waits only for this wave's LDS operations, lgkmcnt = 0),

@@ -29,11 +29,9 @@ __global__ __launch_bounds__(256) void k_force_rows(
     int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
     const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
-    int64_t per_xcd) {
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, grp = logical / n_ct;
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp) {
+  int64_t ct, grp;
+  if (!xcd_group_tile(n_grp, n_ct, grp, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = (ct * 4 + wave) * (16 * kFNC);
   if (colbase >= M) return;
@@ -147,12 +145,10 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12(
     int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
     const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
-    int64_t per_xcd, int nkb) {
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp, int nkb) {
   extern __shared__ double xs[];  // [nkb][kLdsNC][64 lanes][4]
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int alpha = wave % 3, grp = wave / 3;
   const int64_t colbase = ct * (16 * kLdsNC);
@@ -276,14 +272,13 @@ __global__ __launch_bounds__(64 * kW12) void k_force_rows_lds12f(
     const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
     int64_t n_pairs, int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct,
-    int64_t total, int64_t per_xcd, int nkb) {
+    int64_t n_grp, int nkb) {
   // X tiles in LDS: [nkb][kLdsNC][2 halves][64 lanes][2 doubles]: a lane's four
   // k values of one fragment are split into two 16-byte halves stored 1 KB
   // apart, so each 16-byte LDS read of the wave is contiguous (no bank conflict)
   extern __shared__ double xs[];
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int alpha = wave % 3, grp = wave / 3;
   const int64_t colbase = ct * (16 * kLdsNC);
@@ -514,11 +509,10 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
     const int nkb = (int)(((D + 15) / 16 + 1) / 2 * 2);  // even number of 16-k blocks
     const int64_t n_ct = (M + 16 * kLdsNC - 1) / (16 * kLdsNC);
     const int64_t n_tgb = (n_atoms + 63) / 64;
-    const int64_t total = n_ct * n_tgb;
-    const int64_t per_xcd = (total + 7) / 8;
+    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
     const size_t lds = (size_t)nkb * kLdsNC * 64 * 4 * sizeof(double);
     const int lds_max = 16 * kLdsNC * 64 * 4 * 8;
-    dim3 grid((unsigned)(8 * per_xcd));
+    dim3 grid(blocks);
     if (jac_f32) {
       static bool attr = false;
       if (!attr) {
@@ -528,8 +522,8 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
       }
       hipLaunchKernelGGL(k_force_rows_lds12f<float>, grid, dim3(64 * kW12), lds, st,
                          reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, total,
-                         per_xcd, nkb);
+                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb,
+                         nkb);
     } else {
       static bool attr = false;
       if (!attr) {
@@ -539,8 +533,8 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
       }
       hipLaunchKernelGGL(k_force_rows_lds12f<double>, grid, dim3(64 * kW12), lds, st,
                          reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, total,
-                         per_xcd, nkb);
+                         tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb,
+                         nkb);
     }
     return;
   }
@@ -548,10 +542,9 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
     const int nkb = (int)(((D + 15) / 16 + 1) / 2 * 2);  // even number of 16-k blocks
     const int64_t n_ct = (M + 16 * kLdsNC - 1) / (16 * kLdsNC);
     const int64_t n_tgb = (n_atoms + 63) / 64;
-    const int64_t total = n_ct * n_tgb;
-    const int64_t per_xcd = (total + 7) / 8;
+    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
     const size_t lds = (size_t)nkb * kLdsNC * 64 * 4 * sizeof(double);
-    dim3 grid((unsigned)(8 * per_xcd));
+    dim3 grid(blocks);
     if (jac_f32) {
       static bool attr_f = false;
       if (!attr_f) {
@@ -561,7 +554,7 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
       }
       hipLaunchKernelGGL(k_force_rows_lds12<float>, grid, dim3(64 * kW12), lds, st,
                          reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
     } else {
       static bool attr_d = false;
       if (!attr_d) {
@@ -571,23 +564,21 @@ void force_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const
       }
       hipLaunchKernelGGL(k_force_rows_lds12<double>, grid, dim3(64 * kW12), lds, st,
                          reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+                         tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
     }
     return;
   }
   const int64_t n_ct = (M + 4 * 16 * kFNC - 1) / (4 * 16 * kFNC);
   const int64_t n_grp = (n_atoms + 15) / 16;
-  const int64_t total = n_ct * n_grp;
-  const int64_t per_xcd = (total + 7) / 8;
-  dim3 grid((unsigned)(8 * per_xcd));
+  dim3 grid(xcd_group_tile_blocks(n_grp, n_ct));
   if (jac_f32)
     hipLaunchKernelGGL(k_force_rows<float>, grid, dim3(256), 0, st,
                        reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, n_grp);
   else
     hipLaunchKernelGGL(k_force_rows<double>, grid, dim3(256), 0, st,
                        reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, tgt_ptr,
-                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+                       tgt_pair, pair_src, order, n_atoms, row0, K, ldk, n_ct, n_grp);
 }
 
 void forces_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* g,

@@ -121,12 +121,10 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
     int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
-    int64_t per_xcd, int nkb) {
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp, int nkb) {
   extern __shared__ SplitPair xs2[];  // [nkb][kNCF][64]
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = ct * (16 * kNCF);
 
@@ -235,11 +233,9 @@ __global__ __launch_bounds__(256) void k_force_rows_b3_global(
     const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
     int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total,
-    int64_t per_xcd) {
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp) {
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = ct * (16 * kNCb);
   const int64_t slot = (tgb * 4 + wave) * 16 + idx;
@@ -344,7 +340,7 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
     const float* __restrict__ S, int64_t ldS, const int64_t* __restrict__ tgt_ptr,
     const int32_t* __restrict__ tgt_pair, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ order, int64_t n_atoms, int64_t n_pairs, int64_t row0,
-    double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t total, int64_t per_xcd) {
+    double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp) {
   constexpr int nkb = NKB;  // 32-deep k blocks (compile time: straight-line, exact waits)
   // No guarded load on the hot path (a guarded load compiles to a branch whose
   // join waits for it at once): every load reads a valid address, and invalid
@@ -356,9 +352,8 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   // X halves in LDS: [nkb][kNCF][hi | lo][64 lanes] of 16 bytes, so each 16-byte
   // LDS read of the wave is contiguous (no bank conflict)
   extern __shared__ SplitPair xs3[];
-  const int64_t logical = xcd_logical_block(per_xcd);
-  if (logical >= total) return;
-  const int64_t ct = logical % n_ct, tgb = logical / n_ct;
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int alpha = wave % 3, grp = wave / 3;
   const int64_t colbase = ct * (16 * kNCF);
@@ -666,7 +661,7 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
   if (D <= 32 * kMaxKb32) {
     const int nkb = (int)(ldp / 32);
     const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
-    const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
     const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
     const size_t lds_max = (size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair);
     if (jac_f32) {
@@ -676,9 +671,9 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
         a = true;
       }
-      hipLaunchKernelGGL(k_force_rows_b3<float>, dim3((unsigned)(8 * per_xcd)), dim3(256), lds, st,
+      hipLaunchKernelGGL(k_force_rows_b3<float>, dim3(blocks), dim3(256), lds, st,
                          tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+                         pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
     } else {
       static bool a = false;
       if (!a) {
@@ -686,22 +681,22 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
         a = true;
       }
-      hipLaunchKernelGGL(k_force_rows_b3<double>, dim3((unsigned)(8 * per_xcd)), dim3(256), lds,
+      hipLaunchKernelGGL(k_force_rows_b3<double>, dim3(blocks), dim3(256), lds,
                          st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd, nkb);
+                         pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
     }
     return;
   }
   const int64_t n_ct = (M + 16 * kNCb - 1) / (16 * kNCb);
-  const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+  const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
   if (jac_f32)
-    hipLaunchKernelGGL(k_force_rows_b3_global<float>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0,
+    hipLaunchKernelGGL(k_force_rows_b3_global<float>, dim3(blocks), dim3(256), 0,
                        st, tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                       pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb);
   else
-    hipLaunchKernelGGL(k_force_rows_b3_global<double>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0,
+    hipLaunchKernelGGL(k_force_rows_b3_global<double>, dim3(blocks), dim3(256), 0,
                        st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                       pair_src, order, n_atoms, row0, K, ldk, n_ct, total, per_xcd);
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb);
 }
 
 void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
@@ -729,7 +724,7 @@ bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, cons
   const int nkb = (int)(ldp / 32);
   const int64_t n_tgb = (n_atoms + 63) / 64;
   const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
-  const int64_t total = n_ct * n_tgb, per_xcd = (total + 7) / 8;
+  const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
   const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
   auto launch = [&](auto kern) {
     static bool attr[kMaxKb32 + 1] = {};
@@ -739,9 +734,9 @@ bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, cons
                                 (int)((size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair)));
       attr[nkb] = true;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * per_xcd)), dim3(768), lds, st, Jh, Jl, ldp, D, Xh,
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(768), lds, st, Jh, Jl, ldp, D, Xh,
                        Xl, M, S, ldS, tgt_ptr, tgt_pair, pair_src, order, n_atoms, n_pairs, row0,
-                       K, ldk, n_ct, total, per_xcd);
+                       K, ldk, n_ct, n_tgb);
   };
   switch (nkb) {
     case 1: launch(k_force_rows_b3s<1>); break;
