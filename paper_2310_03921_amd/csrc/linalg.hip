@@ -675,6 +675,26 @@ __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t 
   }
 }
 
+// Buffer resources with a base in scalar registers: an access is that base
+// plus a 32-bit per-lane offset plus a scalar offset, so a kernel that walks
+// many columns of the column-major matrix keeps one offset register instead of
+// a 64-bit address per column.  An access at or beyond the resource's size
+// reads zero (a store is dropped).
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+GAP_DEV __amdgpu_buffer_rsrc_t uniform_rsrc(const double* p, uint32_t bytes) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((uint64_t)hi << 32 | lo), 0, (int)bytes,
+                                           0x00020000);
+}
+GAP_DEV double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+GAP_DEV void buf_st(double x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+
 // W = V^T C over row slabs, staged through LDS: a block owns one slab and a
 // 128-wide column tile (relative to the panel start; columns < pw are the
 // panel's own V columns, giving the Gram V^T V).  32-row chunks of V and C are
@@ -871,6 +891,7 @@ constexpr int kQrOB = 128;
 
 // W = V^T C over row slabs with V up to 128 wide.  Eight waves: 2 (64-column
 // halves of V) x 4 (32-column quarters of the 128-column C tile).
+template <bool BUF>
 __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, int64_t ld,
                                                  int64_t m, int64_t j0, int pw, int64_t nct,
                                                  int64_t slab, int64_t n_ct, int64_t total,
@@ -927,11 +948,31 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
       rc[t] = v;
     }
   };
+  // The interior form through buffer resources based at the chunk's first row
+  // of the first V column and of the tile's first C column: the thread's row
+  // and column x0 are its offset, each t adds 16 columns as a scalar offset,
+  // and columns past pw (V) or nct (C) lie outside the resources and read zero.
+  const uint32_t xoff = (uint32_t)(((int64_t)x0 * ld + kk_t) * 8);
+  const uint32_t vbytes = (uint32_t)((int64_t)pw * ld * 8);
+  const uint32_t cbytes = (uint32_t)(std::min<int64_t>(nct - c0, kVC) * ld * 8);
+  auto fetch_buf = [&](int64_t rk) {
+    const auto rsv = uniform_rsrc(A + j0 * ld + rk, vbytes);
+    const auto rsc = uniform_rsrc(A + (j0 + c0) * ld + rk, cbytes);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      rv[t] = buf_ld(rsv, xoff, (uint32_t)(16 * t * ld * 8));
+      rc[t] = buf_ld(rsc, xoff, (uint32_t)(16 * t * ld * 8));
+    }
+  };
   auto fetch = [&](int64_t rk) {
-    if (rk - j0 >= pw && rk + kVK <= r1)
-      fetch_fast(rk);
-    else
+    if (rk - j0 >= pw && rk + kVK <= r1) {
+      if (BUF)
+        fetch_buf(rk);
+      else
+        fetch_fast(rk);
+    } else {
       fetch_masked(rk);
+    }
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -1238,23 +1279,6 @@ __global__ __launch_bounds__(512) void k_qr_upd3(double* __restrict__ A, int64_t
 // previous tile did not.  Per-access 64-bit addresses would take 64 registers.
 constexpr int kU5R = 128;  // rows per block (8 waves x 16)
 constexpr int kU5C = 64;   // columns per tile
-// Every global access of the kernel goes through a buffer resource (base in
-// scalar registers) with a 32-bit per-lane offset and a scalar offset: 64-bit
-// per-access vector addresses would take 64 registers.
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-GAP_DEV __amdgpu_buffer_rsrc_t uniform_rsrc(const double* p, uint32_t bytes) {
-  const uint64_t x = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return __builtin_amdgcn_make_buffer_rsrc((void*)((uint64_t)hi << 32 | lo), 0, (int)bytes,
-                                           0x00020000);
-}
-GAP_DEV double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-GAP_DEV void buf_st(double x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
-}
 constexpr uint32_t kDropOffset = 0x80000000u;  // beyond any buffer this kernel makes
 __global__ __launch_bounds__(512) void k_qr_upd5(double* __restrict__ A, int64_t ld, int64_t m,
                                                  int64_t j0, int64_t c_end, int64_t nct,
@@ -1759,8 +1783,13 @@ static void qr_wy_update_ob(double* A, int64_t ld, int64_t m, int64_t j0, int pw
   const int64_t nslab = (m - j0 + slab - 1) / slab;
   const int64_t n_ct = (nct + kVC - 1) / kVC;
   const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
-  hipLaunchKernelGGL(k_qr_vtc3, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0, pw,
-                     nct, slab, n_ct, total, per_xcd, w->part);
+  // buffer offsets reach 128 columns of the matrix
+  if ((int64_t)kVC * ld * 8 < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(k_qr_vtc3<true>, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld,
+                       m, j0, pw, nct, slab, n_ct, total, per_xcd, w->part);
+  else
+    hipLaunchKernelGGL(k_qr_vtc3<false>, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld,
+                       m, j0, pw, nct, slab, n_ct, total, per_xcd, w->part);
   hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
                      (int64_t)pw * nct, w->W);
   hipLaunchKernelGGL(k_qr_larft_half, dim3(2), dim3(256), 0, st, w->W, nct, pw, w->tau + j0,
