@@ -907,7 +907,7 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
   const int64_t c0 = ct * kVC;
   // each thread stages one row (kk) of a chunk and the columns x0 + 16 t
   const int kk_t = threadIdx.x & (kVK - 1), x0 = threadIdx.x / kVK;
-  double rv[8], rc[8];
+  double rv[8], rc[8], rv2[8], rc2[8];
   // Two fetch forms.  Interior chunks (every row inside the slab and below the
   // V triangle) load from clamped addresses with no condition at all: V
   // columns >= pw only feed W rows >= pw and C columns >= nct only feed W
@@ -915,7 +915,7 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
   // branch that waits for the load on the spot, so guards are kept to the few
   // edge chunks (the V triangle at the top of the first slab, a partial last
   // chunk), which use the masked form.
-  auto fetch_fast = [&](int64_t rk) {
+  auto fetch_fast = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
     const double* rowp = A + (rk + kk_t);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -923,7 +923,7 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
       rc[t] = rowp[(j0 + min(c0 + x0 + 16 * t, nct - 1)) * ld];
     }
   };
-  auto fetch_masked = [&](int64_t rk) {
+  auto fetch_masked = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
     const int64_t r = rk + kk_t;
     const bool rin = r < r1;
     const int64_t rr = r - j0;
@@ -955,7 +955,7 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
   const uint32_t xoff = (uint32_t)(((int64_t)x0 * ld + kk_t) * 8);
   const uint32_t vbytes = (uint32_t)((int64_t)pw * ld * 8);
   const uint32_t cbytes = (uint32_t)(std::min<int64_t>(nct - c0, kVC) * ld * 8);
-  auto fetch_buf = [&](int64_t rk) {
+  auto fetch_buf = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
     const auto rsv = uniform_rsrc(A + j0 * ld + rk, vbytes);
     const auto rsc = uniform_rsrc(A + (j0 + c0) * ld + rk, cbytes);
 #pragma unroll
@@ -964,17 +964,17 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
       rc[t] = buf_ld(rsc, xoff, (uint32_t)(16 * t * ld * 8));
     }
   };
-  auto fetch = [&](int64_t rk) {
+  auto fetch = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
     if (rk - j0 >= pw && rk + kVK <= r1) {
       if (BUF)
-        fetch_buf(rk);
+        fetch_buf(rk, rv, rc);
       else
-        fetch_fast(rk);
+        fetch_fast(rk, rv, rc);
     } else {
-      fetch_masked(rk);
+      fetch_masked(rk, rv, rc);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, const double (&rv)[8], const double (&rc)[8]) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       sV[buf][kk_t][x0 + 16 * t] = rv[t];
@@ -986,9 +986,9 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = zero4();
-  auto compute = [&](int buf) {
+  auto compute = [&](int buf, int k_lo, int k_hi) {
 #pragma unroll
-    for (int k0 = 0; k0 < kVK; k0 += 4) {
+    for (int k0 = k_lo; k0 < k_hi; k0 += 4) {
       const int kk = k0 + g;
       double a[4], b[2];
 #pragma unroll
@@ -1001,20 +1001,58 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
     }
   };
-  // chunk c (rows r0 + c * kVK) is fetched into registers while chunk c - 1
-  // runs from LDS, then stashed into the other LDS buffer
-  const int64_t nch = (r1 - r0 + kVK - 1) / kVK;
-  fetch(r0);
-  stash(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t c = 0; c < nch; ++c) {
-    const bool more = c + 1 < nch;
-    if (more) fetch(r0 + (c + 1) * kVK);
-    compute(buf);
-    if (more) stash(buf ^ 1);
+  // Chunks that meet the unit triangle of V (first slab) or end past the
+  // matrix take the masked fetch one at a time; the interior ones run a
+  // pipeline: chunk c is fetched into a register set two chunks ahead and
+  // written to LDS buffer c & 1 in the middle of chunk c - 1's products (that
+  // buffer was last read by chunk c - 2, before the previous barrier), so the
+  // LDS writes overlap matrix-core work and the loads have a chunk and a half
+  // to arrive.  The pipeline is straight-line code (fetches past the last
+  // interior chunk re-read it, and its extra LDS write is never read), which
+  // lets every wait for a fetch count the newer fetches still in flight.
+  const int64_t nfull = (r1 - r0) / kVK;
+  const int64_t c_lo = std::min<int64_t>(nfull, r0 - j0 >= pw ? 0 : (pw - (r0 - j0) + kVK - 1) / kVK);
+  const int64_t c_hi = nfull;
+  auto single = [&](int64_t c) {
+    fetch_masked(r0 + c * kVK, rv, rc);
     lds_barrier();
-    buf ^= 1;
+    stash(0, rv, rc);
+    lds_barrier();
+    compute(0, 0, kVK);
+  };
+  for (int64_t c = 0; c < c_lo; ++c) single(c);
+  if (c_hi > c_lo) {
+    auto fetch_i = [&](int64_t c, double (&rv_)[8], double (&rc_)[8]) {
+      const int64_t rk = r0 + std::min(c, c_hi - 1) * kVK;
+      if (BUF)
+        fetch_buf(rk, rv_, rc_);
+      else
+        fetch_fast(rk, rv_, rc_);
+    };
+    lds_barrier();
+    fetch_i(c_lo, rv, rc);
+    stash(0, rv, rc);
+    fetch_i(c_lo + 1, rv2, rc2);
+    lds_barrier();
+    auto step = [&](int64_t c, double (&rnext)[8], double (&cnext)[8], double (&rfar)[8],
+                    double (&cfar)[8]) {
+      const int buf = (int)((c - c_lo) & 1);
+      fetch_i(c + 2, rfar, cfar);
+      compute(buf, 0, kVK / 2);
+      stash(buf ^ 1, rnext, cnext);
+      compute(buf, kVK / 2, kVK);
+      lds_barrier();
+    };
+    int64_t c = c_lo;
+    for (; c + 1 < c_hi; c += 2) {
+      step(c, rv2, rc2, rv, rc);      // chunk c + 1 is in set 2, chunk c + 2 goes to set 1
+      step(c + 1, rv, rc, rv2, rc2);  // chunk c + 2 is in set 1, chunk c + 3 goes to set 2
+    }
+    if (c < c_hi) step(c, rv2, rc2, rv, rc);
+  }
+  if (c_hi * kVK < r1 - r0) {
+    lds_barrier();
+    single(c_hi);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
