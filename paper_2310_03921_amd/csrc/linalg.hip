@@ -338,6 +338,7 @@ __global__ __launch_bounds__(256) void k_qr_col(double* __restrict__ A, int64_t 
 // fixed order, so all blocks derive identical reflector parameters without a
 // second barrier.  Partials alternate between two buffers so a block that is
 // one step ahead never overwrites values a slower block is still reading.
+static_assert(kPanelMaxGrid <= 256, "the panel reduction reads at most 4 partials per lane");
 constexpr int kRRW = 16;    // panel width
 constexpr int kRRQ = 4;     // rows per thread
 constexpr int kRRT = 512;   // threads per block
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
   __shared__ double s_tot[kRRW];
   __shared__ double s_tw[kRRW];
   __shared__ double s_par[3];  // tau, beta, scale of the reflector just formed
+  __shared__ double s_pv[kRRW];  // the pivot row of the current column
   const int G = gridDim.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)G * kRRT;
@@ -466,24 +468,39 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
       xstore(rb + (int64_t)threadIdx.x * G + blockIdx.x, s);
     }
     grid_barrier(arrive, (unsigned)(k + 1) * (unsigned)G, dev_err);
-    // 3. every block reduces all partials in the same order
+    // the pivot row, read together with the partials below (one round trip)
+    const double* pv = piv + (k & 1) * kRRW;
+    if (threadIdx.x < kRRW) s_pv[threadIdx.x] = vload(pv + threadIdx.x);
+    // 3. every block reduces all partials in the same order.  A wave reads the
+    //    G <= 256 partials of its two columns (wave, wave + 8) with all eight
+    //    loads in flight together (clamped addresses, out-of-range ones scaled
+    //    by zero), so the reads cost one memory round trip, not one per load.
     if (wave < ncnt) {
-      double s = 0.0;
-      for (int b = lane; b < G; b += 64) s += vload(rb + (int64_t)wave * G + b);
-      s = wave_sum(s);
-      if (lane == 0) s_tot[wave] = s;
-    }
-    if (wave + (kRRT / 64) < ncnt) {
-      const int vv = wave + kRRT / 64;
-      double s = 0.0;
-      for (int b = lane; b < G; b += 64) s += vload(rb + (int64_t)vv * G + b);
-      s = wave_sum(s);
-      if (lane == 0) s_tot[vv] = s;
+      const int v0 = wave, v1 = min(wave + kRRT / 64, ncnt - 1);
+      double x0[4], x1[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int b = min(lane + 64 * i, G - 1);
+        x0[i] = vload(rb + (int64_t)v0 * G + b);
+        x1[i] = vload(rb + (int64_t)v1 * G + b);
+      }
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double w = (lane + 64 * i < G) ? 1.0 : 0.0;
+        s0 += w * x0[i];
+        s1 += w * x1[i];
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == 0) {
+        s_tot[v0] = s0;
+        if (wave + kRRT / 64 < ncnt) s_tot[wave + kRRT / 64] = s1;
+      }
     }
     __syncthreads();
-    const double* pv = piv + (k & 1) * kRRW;
     if (threadIdx.x == 0) {
-      const double alpha = vload(pv + k);
+      const double alpha = s_pv[k];
       const double xnorm = sqrt(s_tot[0]);
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (xnorm > 0.0) {
@@ -499,7 +516,7 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
     __syncthreads();
     if (threadIdx.x < kRRW) {
       const int j = threadIdx.x;
-      s_tw[j] = (j > k && j < pw) ? s_par[0] * (vload(pv + j) + s_par[2] * s_tot[j - k]) : 0.0;
+      s_tw[j] = (j > k && j < pw) ? s_par[0] * (s_pv[j] + s_par[2] * s_tot[j - k]) : 0.0;
     }
     beta_p = s_par[1];
     scale_p = s_par[2];
