@@ -26,6 +26,10 @@ constexpr int kTrsvMaxBlocks = 256;  // multi-block triangular solve: n <= 64 * 
 constexpr int kPanelW = 32;    // inner panel width (column-by-column factorisation)
 constexpr int kCholNB = 64;    // Cholesky block
 constexpr int kPanelMaxGrid = 256;
+// Workspace counter words: [0] the column kernels' counter, [kPanelBar ..
+// kPanelBar + 8 * 16) the cooperative panel's eight arrival counters.
+constexpr int kPanelBar = 64;
+constexpr int kCounterWords = 256;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -366,6 +370,45 @@ GAP_DEV void grid_barrier(unsigned int* arrive, unsigned int target, int* dev_er
   __syncthreads();
 }
 
+// Grid barrier on eight arrival counters, one per XCD slot of the block index
+// (64 bytes apart), instead of one: the atomic adds of a few hundred blocks on a
+// single address serialise at the memory-side atomic unit.  `round` counts the
+// barriers completed including this one; counter x has seen round * n_x arrivals
+// (n_x = blocks with index = x mod 8) when all blocks have arrived.  One wave
+// polls all eight counters with one load per lane.  The counters are zeroed
+// before the launch.
+constexpr int kBarStride = 16;  // uints between arrival counters
+GAP_DEV void grid_barrier_x8(unsigned int* arrive, unsigned int round, int* dev_err) {
+  wait_mem();  // this wave's cross-block stores (device-scope atomics) have completed
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const unsigned G = gridDim.x;
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(arrive + (blockIdx.x & 7) * kBarStride, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned x = threadIdx.x & 7;
+    const unsigned target = round * (G > x ? (G - x + 7) / 8 : 0u);
+    uint64_t spins = 0;
+    // Bounded wait, as in grid_barrier: a timeout sets the error bit, and a
+    // set bit (checked every 64 polls) ends every later wait at once.
+    for (;;) {
+      const unsigned c =
+          __hip_atomic_load(arrive + x * kBarStride, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (__all(c >= target)) break;
+      if ((spins & 63) == 63 &&
+          (__hip_atomic_load(dev_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+           GAP_DEVERR_SYNC))
+        break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1ull << 22)) {
+        if (threadIdx.x == 0) atomicOr(dev_err, GAP_DEVERR_SYNC);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, int64_t ld,
                                                       int64_t m, int64_t i0, int pw,
                                                       double* __restrict__ red,
@@ -467,7 +510,7 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
       for (int w = 0; w < kRRT / 64; ++w) s += s_wred[w][threadIdx.x];
       xstore(rb + (int64_t)threadIdx.x * G + blockIdx.x, s);
     }
-    grid_barrier(arrive, (unsigned)(k + 1) * (unsigned)G, dev_err);
+    grid_barrier_x8(arrive, (unsigned)(k + 1), dev_err);
     // the pivot row, read together with the partials below (one round trip)
     const double* pv = piv + (k & 1) * kRRW;
     if (threadIdx.x < kRRW) s_pv[threadIdx.x] = vload(pv + threadIdx.x);
@@ -1774,7 +1817,7 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
   d += (size_t)kQrNB * kCS;                  // colstate
   d += (size_t)kQrNB * kPanelMaxGrid;        // red
   d += (size_t)n + 8;                        // tau
-  return d * sizeof(double) + 256 + sizeof(unsigned int) * kTrsvMaxBlocks;  // counters, flags
+  return d * sizeof(double) + sizeof(unsigned int) * (kCounterWords + kTrsvMaxBlocks);  // counters, flags
 }
 
 void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
@@ -1798,7 +1841,7 @@ void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   w->tau = p;
   p += n + 8;
   w->counter = reinterpret_cast<unsigned int*>(p);
-  w->flags = w->counter + 64;
+  w->flags = w->counter + kCounterWords;
 }
 
 // Compact-WY update of columns [c0, c_end) with the pw reflectors stored in
@@ -1904,13 +1947,14 @@ void qr_factor(double* A, int64_t ld, int64_t m, int64_t ncols, int64_t n, QrWor
         tm->begin(TM_QR_PANEL);
         bool done = false;
         if (rr) {
-          hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w->counter + 1);
+          hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, w->counter + kPanelBar,
+                             (int64_t)8 * kBarStride, 0u);
           int64_t ld_ = ld, m_ = m, i0_ = i0;
           int pw_ = pw;
           double* A_ = A;
           double* red_ = w->red;
           double* piv_ = w->T;  // the T scratch is free while a panel is factored
-          unsigned int* arr_ = w->counter + 1;
+          unsigned int* arr_ = w->counter + kPanelBar;
           double* tau_ = w->tau;
           int* err_ = dev_err;
           void* args[] = {&A_, &ld_, &m_, &i0_, &pw_, &red_, &piv_, &arr_, &tau_, &err_};
