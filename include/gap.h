@@ -105,8 +105,11 @@ typedef struct {
 } gap_fit_info;
 
 /* Create a handle bound to HIP device `device` and HIP stream `hip_stream`
- * (a hipStream_t; NULL = the legacy default stream).  Fails with GAP_E_HIP if
- * the device is missing or is not gfx950. */
+ * (a hipStream_t; NULL = the legacy default stream).  Every call is ordered on
+ * that stream; a call may also run part of its work on a side stream of the
+ * handle (default priority), forked from and joined back to the caller's
+ * stream with events inside the call.  Fails with GAP_E_HIP if the device is
+ * missing or is not gfx950, or if the side stream cannot be created. */
 gap_status gap_create(gap_handle **h, int device, void *hip_stream);
 gap_status gap_destroy(gap_handle *h);
 /* Message of the last error on this handle ("" if none).  Valid until the

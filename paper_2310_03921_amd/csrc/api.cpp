@@ -16,6 +16,10 @@
 struct gap_handle {
   int device = 0;
   hipStream_t stream = nullptr;
+  // Side stream (default priority) for work that overlaps the caller's stream
+  // inside one call, forked and joined with the two events.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -292,7 +296,12 @@ gap_status gap_create(gap_handle** out, int device, void* hip_stream) {
     return GAP_E_NOMEM;
   }
   int zero = 0;
-  if (hipMemcpy(h->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(h->dev_err, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->side) (void)hipStreamDestroy(h->side);
     (void)hipFree(h->dev_err);
     (void)hipFree(h->dev_small);
     delete h;
@@ -309,6 +318,10 @@ gap_status gap_destroy(gap_handle* h) {
   double ms[gapk::TM_COUNT];
   int64_t n[gapk::TM_COUNT];
   h->timer.collect(ms, n);
+  if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->ws) (void)hipFree(h->ws);
   if (h->dev_err) (void)hipFree(h->dev_err);
   if (h->dev_small) (void)hipFree(h->dev_small);
@@ -568,8 +581,16 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   gapk::qr_bind_workspace(at<char>(h, q), m, M, &qw);
   double* Lm = at<double>(h, Lw);
   h->timer.begin(gapk::TM_CHOL);
-  gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->stream);
-  gapk::scale_stack(A, ld, n_rows, M, y, sigma, Lm, M, h->stream);
+  // The Cholesky factor of K_MM (a chain of small latency-bound kernels) runs on
+  // the side stream while the memory-bound row scaling of [K_NM | y] runs here;
+  // U is stacked below once both are done.
+  HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
+  HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->side);
+  HIP_TRY(h, hipEventRecord(h->ev_join, h->side));
+  gapk::scale_rows(A, ld, n_rows, M, y, sigma, h->stream);
+  HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+  gapk::stack_u(A, ld, n_rows, M, Lm, M, h->stream);
   h->timer.end(gapk::TM_CHOL);
   gapk::qr_factor(A, ld, m, M + 1, M, &qw, h->stream, h->dev_err, &h->timer);
   h->timer.begin(gapk::TM_TRSV);

@@ -177,10 +177,13 @@ void gemm_wtd_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const v
                      hipStream_t st);
 
 // ---- linalg.hip -----------------------------------------------------------
-// A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows;
-// rows n_rows .. n_rows+M-1: U = L^T from the lower factor L (col-major ldl), b = 0.
-void scale_stack(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
-                 const double* sigma, const double* L, int64_t ldl, hipStream_t st);
+// A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows.
+void scale_rows(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
+                const double* sigma, hipStream_t st);
+// Rows n_rows .. n_rows+M-1 of A: U = L^T from the lower factor L (col-major
+// ldl), and 0 in column M.
+void stack_u(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* L, int64_t ldl,
+             hipStream_t st);
 // In-place lower Cholesky of the M x M col-major matrix Lw (ld = ldl) after adding
 // jitter to its diagonal; the strict upper part is left untouched.
 void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const double* Kmm,

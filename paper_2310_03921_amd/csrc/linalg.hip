@@ -51,23 +51,24 @@ GAP_DEV void xstore(double* p, double v) {
 GAP_DEV void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ----------------------------------------------------------- scale/stack ----
-__global__ void k_scale_stack(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
-                              const double* __restrict__ y, const double* __restrict__ sigma,
-                              const double* __restrict__ L, int64_t ldl) {
+// rows r < n_rows: A[r][0:M] /= sigma_r, A[r][M] = y_r / sigma_r
+__global__ void k_scale_rows(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
+                             const double* __restrict__ y, const double* __restrict__ sigma) {
   const int64_t col = blockIdx.y;
-  const int64_t rtot = n_rows + M;
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rtot;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n_rows;
        r += (int64_t)gridDim.x * blockDim.x) {
-    double v;
-    if (r < n_rows) {
-      const double w = 1.0 / sigma[r];
-      v = (col < M) ? A[r + col * ld] * w : y[r] * w;
-    } else {
-      const int64_t i = r - n_rows;  // row i of U = column i of L
-      v = (col < M && col >= i) ? L[col + i * ldl] : 0.0;
-    }
-    A[r + col * ld] = v;
+    const double w = 1.0 / sigma[r];
+    A[r + col * ld] = (col < M) ? A[r + col * ld] * w : y[r] * w;
   }
+}
+
+// rows n_rows + i (i < M): U = L^T (row i of U is column i of L), b = 0
+__global__ void k_stack_u(double* __restrict__ A, int64_t ld, int64_t n_rows, int64_t M,
+                          const double* __restrict__ L, int64_t ldl) {
+  const int64_t col = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+       i += (int64_t)gridDim.x * blockDim.x)
+    A[(n_rows + i) + col * ld] = (col < M && col >= i) ? L[col + i * ldl] : 0.0;
 }
 
 // -------------------------------------------------------------- Cholesky ----
@@ -1778,10 +1779,17 @@ inline unsigned g256(int64_t n) { return std::max(1u, std::min(cdiv(n, 256), 655
 
 }  // namespace
 
-void scale_stack(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
-                 const double* sigma, const double* L, int64_t ldl, hipStream_t st) {
-  dim3 grid(std::min(cdiv(n_rows + M, 256), 4096u), (unsigned)(M + 1));
-  hipLaunchKernelGGL(k_scale_stack, grid, dim3(256), 0, st, A, ld, n_rows, M, y, sigma, L, ldl);
+void scale_rows(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
+                const double* sigma, hipStream_t st) {
+  if (n_rows <= 0) return;
+  dim3 grid(std::min(cdiv(n_rows, 256), 4096u), (unsigned)(M + 1));
+  hipLaunchKernelGGL(k_scale_rows, grid, dim3(256), 0, st, A, ld, n_rows, M, y, sigma);
+}
+
+void stack_u(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* L, int64_t ldl,
+             hipStream_t st) {
+  dim3 grid(cdiv(M, 256), (unsigned)(M + 1));
+  hipLaunchKernelGGL(k_stack_u, grid, dim3(256), 0, st, A, ld, n_rows, M, L, ldl);
 }
 
 void cholesky_lower(double* Lw, int64_t ldl, int64_t M, double jitter, const double* Kmm,
