@@ -161,13 +161,18 @@ void layout_pairs(Layout& L, int64_t n_atoms, int64_t n_pairs, PairWs& p) {
   p.scratch = L.take(sizeof(int32_t) * (n_atoms + 2048));
 }
 
-void run_pairs(gap_handle* h, const gap_atoms* a, const PairWs& p, bool want_order) {
+void run_pairs(gap_handle* h, const gap_atoms* a, const PairWs& p, bool want_order,
+               hipStream_t st = nullptr) {
+  if (!st) st = h->stream;
+  const hipStream_t timer_st = h->timer.st;
+  h->timer.st = st;  // the stage is timed on the stream it runs on
   h->timer.begin(gapk::TM_PAIRS);
   gapk::pair_transpose(a->pair_ptr, a->pair_j, a->n_atoms, a->n_pairs, at<int64_t>(h, p.tgt_ptr),
                        at<int32_t>(h, p.tgt_pair), at<int32_t>(h, p.src),
                        want_order ? at<int32_t>(h, p.order) : nullptr, at<int32_t>(h, p.scratch),
-                       h->dev_err, h->stream);
+                       h->dev_err, st);
   h->timer.end(gapk::TM_PAIRS);
+  h->timer.st = timer_st;
 }
 
 bool f32(gap_dtype d) { return d == GAP_DT_F32; }
@@ -459,7 +464,12 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   }
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
-  run_pairs(h, a, p, true);
+  // The pair transpose (a chain of small kernels) runs on the side stream
+  // while the splits and energy rows run here; the force rows wait for both.
+  HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
+  HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  run_pairs(h, a, p, true, h->side);
+  HIP_TRY(h, hipEventRecord(h->ev_join, h->side));
   if (prec == GAP_BF16X3) {
     run_split(h, sp, sw, false);
     if (presplit) {
@@ -473,6 +483,7 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
                              at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M, D, sp->zeta,
                              sp->delta, Knm, ld, at<float>(h, S), ld8(M), h->stream);
     h->timer.end(gapk::TM_ENERGY);
+    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
     h->timer.begin(gapk::TM_FORCE);
     bool done = false;
     if (presplit)
@@ -496,6 +507,7 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
                         sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), ld4(M),
                         h->stream);
   h->timer.end(gapk::TM_ENERGY);
+  HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
   h->timer.begin(gapk::TM_FORCE);
   gapk::force_rows_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, sp->X, sp->ld_x, M,
                        at<double>(h, S), ld4(M), at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
