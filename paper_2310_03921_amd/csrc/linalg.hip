@@ -1128,6 +1128,189 @@ __global__ __launch_bounds__(512) void k_qr_vtc3(const double* __restrict__ A, i
     }
 }
 
+// The same product with four waves per block (each a 64 x 64 block of W) and
+// 16-row chunks, so that the LDS of a block is 70 KB and two blocks share a
+// compute unit: the two waves on a SIMD then belong to different blocks and
+// are not held in step by one barrier, so one block's LDS writes and barrier
+// overlap the other block's matrix-core products.
+constexpr int kV5K = 16;
+template <bool BUF>
+__global__ __launch_bounds__(256, 2) void k_qr_vtc5(const double* __restrict__ A, int64_t ld,
+                                                 int64_t m, int64_t j0, int pw, int64_t nct,
+                                                 int64_t slab, int64_t n_ct, int64_t total,
+                                                 int64_t per_xcd, double* __restrict__ part) {
+  constexpr int kVK = kV5K;
+  __shared__ double sV[2][kVK][kQrOB + 9];
+  __shared__ double sC[2][kVK][kVC + 9];
+  const int64_t logical = xcd_logical_block(per_xcd);
+  if (logical >= total) return;
+  const int64_t s = logical / n_ct, ct = logical % n_ct;
+  const int64_t r0 = j0 + s * slab, r1 = std::min(m, r0 + slab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wv = wave & 1, wq = wave >> 1;
+  const int64_t c0 = ct * kVC;
+  // each thread stages one row (kk) of a chunk and the columns x0 + 16 t
+  const int kk_t = threadIdx.x & (kVK - 1), x0 = threadIdx.x / kVK;  // x0 < 16
+  double rv[8], rc[8], rv2[8], rc2[8];
+  // Two fetch forms.  Interior chunks (every row inside the slab and below the
+  // V triangle) load from clamped addresses with no condition at all: V
+  // columns >= pw only feed W rows >= pw and C columns >= nct only feed W
+  // columns >= nct, none of which are stored.  A guarded load compiles to a
+  // branch that waits for the load on the spot, so guards are kept to the few
+  // edge chunks (the V triangle at the top of the first slab, a partial last
+  // chunk), which use the masked form.
+  auto fetch_fast = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
+    const double* rowp = A + (rk + kk_t);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      rv[t] = rowp[(j0 + min(x0 + 16 * t, pw - 1)) * ld];
+      rc[t] = rowp[(j0 + min(c0 + x0 + 16 * t, nct - 1)) * ld];
+    }
+  };
+  auto fetch_masked = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
+    const int64_t r = rk + kk_t;
+    const bool rin = r < r1;
+    const int64_t rr = r - j0;
+    const double* rowp = A + (rin ? r : 0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int x = x0 + 16 * t;
+      double v = 0.0;
+      if (rin && x < pw) v = (rr == x) ? 1.0 : (rr > x ? rowp[(j0 + x) * ld] : 0.0);
+      rv[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t cp = c0 + x0 + 16 * t;
+      double v = 0.0;
+      if (rin && cp < nct) {
+        if (cp >= pw)
+          v = rowp[(j0 + cp) * ld];
+        else
+          v = (rr == cp) ? 1.0 : (rr > cp ? rowp[(j0 + cp) * ld] : 0.0);
+      }
+      rc[t] = v;
+    }
+  };
+  // The interior form through buffer resources based at the chunk's first row
+  // of the first V column and of the tile's first C column: the thread's row
+  // and column x0 are its offset, each t adds 16 columns as a scalar offset,
+  // and columns past pw (V) or nct (C) lie outside the resources and read zero.
+  const uint32_t xoff = (uint32_t)(((int64_t)x0 * ld + kk_t) * 8);
+  const uint32_t vbytes = (uint32_t)((int64_t)pw * ld * 8);
+  const uint32_t cbytes = (uint32_t)(std::min<int64_t>(nct - c0, kVC) * ld * 8);
+  auto fetch_buf = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
+    const auto rsv = uniform_rsrc(A + j0 * ld + rk, vbytes);
+    const auto rsc = uniform_rsrc(A + (j0 + c0) * ld + rk, cbytes);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      rv[t] = buf_ld(rsv, xoff, (uint32_t)(16 * t * ld * 8));
+      rc[t] = buf_ld(rsc, xoff, (uint32_t)(16 * t * ld * 8));
+    }
+  };
+  auto fetch = [&](int64_t rk, double (&rv)[8], double (&rc)[8]) {
+    if (rk - j0 >= pw && rk + kVK <= r1) {
+      if (BUF)
+        fetch_buf(rk, rv, rc);
+      else
+        fetch_fast(rk, rv, rc);
+    } else {
+      fetch_masked(rk, rv, rc);
+    }
+  };
+  auto stash = [&](int buf, const double (&rv)[8], const double (&rc)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      sV[buf][kk_t][x0 + 16 * t] = rv[t];
+      sC[buf][kk_t][x0 + 16 * t] = rc[t];
+    }
+  };
+  d4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = zero4();
+  auto compute = [&](int buf, int k_lo, int k_hi) {
+#pragma unroll
+    for (int k0 = k_lo; k0 < k_hi; k0 += 4) {
+      const int kk = k0 + g;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sV[buf][kk][wv * 64 + i * 16 + idx];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sC[buf][kk][wq * 64 + j * 16 + idx];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+    }
+  };
+  // Chunks that meet the unit triangle of V (first slab) or end past the
+  // matrix take the masked fetch one at a time; the interior ones run a
+  // pipeline: chunk c is fetched into a register set two chunks ahead and
+  // written to LDS buffer c & 1 in the middle of chunk c - 1's products (that
+  // buffer was last read by chunk c - 2, before the previous barrier), so the
+  // LDS writes overlap matrix-core work and the loads have a chunk and a half
+  // to arrive.  The pipeline is straight-line code (fetches past the last
+  // interior chunk re-read it, and its extra LDS write is never read), which
+  // lets every wait for a fetch count the newer fetches still in flight.
+  const int64_t nfull = (r1 - r0) / kVK;
+  const int64_t c_lo = std::min<int64_t>(nfull, r0 - j0 >= pw ? 0 : (pw - (r0 - j0) + kVK - 1) / kVK);
+  const int64_t c_hi = nfull;
+  auto single = [&](int64_t c) {
+    fetch_masked(r0 + c * kVK, rv, rc);
+    lds_barrier();
+    stash(0, rv, rc);
+    lds_barrier();
+    compute(0, 0, kVK);
+  };
+  for (int64_t c = 0; c < c_lo; ++c) single(c);
+  if (c_hi > c_lo) {
+    auto fetch_i = [&](int64_t c, double (&rv_)[8], double (&rc_)[8]) {
+      const int64_t rk = r0 + std::min(c, c_hi - 1) * kVK;
+      if (BUF)
+        fetch_buf(rk, rv_, rc_);
+      else
+        fetch_fast(rk, rv_, rc_);
+    };
+    lds_barrier();
+    fetch_i(c_lo, rv, rc);
+    stash(0, rv, rc);
+    fetch_i(c_lo + 1, rv2, rc2);
+    lds_barrier();
+    auto step = [&](int64_t c, double (&rnext)[8], double (&cnext)[8], double (&rfar)[8],
+                    double (&cfar)[8]) {
+      const int buf = (int)((c - c_lo) & 1);
+      fetch_i(c + 2, rfar, cfar);
+      compute(buf, 0, kVK / 2);
+      stash(buf ^ 1, rnext, cnext);
+      compute(buf, kVK / 2, kVK);
+      lds_barrier();
+    };
+    int64_t c = c_lo;
+    for (; c + 1 < c_hi; c += 2) {
+      step(c, rv2, rc2, rv, rc);      // chunk c + 1 is in set 2, chunk c + 2 goes to set 1
+      step(c + 1, rv, rc, rv2, rc2);  // chunk c + 2 is in set 1, chunk c + 3 goes to set 2
+    }
+    if (c < c_hi) step(c, rv2, rc2, rv, rc);
+  }
+  if (c_hi * kVK < r1 - r0) {
+    lds_barrier();
+    single(c_hi);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t cp = c0 + wq * 64 + j * 16 + idx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ii = wv * 64 + i * 16 + g + 4 * q;
+        if (ii < pw && cp < nct) part[(s * pw + ii) * nct + cp] = acc[i][j][q];
+      }
+    }
+}
+
 // T (pw x pw upper triangular, ld kQrOB) of a reflector block from the Gram
 // G = V^T V held in the first pw columns of W (row l at W + l * nct), in two
 // steps.  The diagonal 64 x 64 blocks come from the column recursion
@@ -1891,7 +2074,7 @@ static void qr_wy_update_ob(double* A, int64_t ld, int64_t m, int64_t j0, int pw
   const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
   // buffer offsets reach 128 columns of the matrix
   if ((int64_t)kVC * ld * 8 < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(k_qr_vtc3<true>, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld,
+    hipLaunchKernelGGL(k_qr_vtc5<true>, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, A, ld,
                        m, j0, pw, nct, slab, n_ct, total, per_xcd, w->part);
   else
     hipLaunchKernelGGL(k_qr_vtc3<false>, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld,
