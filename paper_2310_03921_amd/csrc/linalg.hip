@@ -585,12 +585,31 @@ __global__ void k_sum_slabs(const double* __restrict__ part, int64_t nslab, int6
   }
 }
 
+// sum_{q0 <= q < q1} a(q) b(q) with four independent partial sums, so that the
+// LDS reads of four terms are in flight together (a single running sum waits
+// for each read in turn)
+template <class FA, class FB>
+GAP_DEV double dot4(int q0, int q1, FA a, FB b) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = q0;
+  for (; q + 3 < q1; q += 4) {
+    s0 += a(q) * b(q);
+    s1 += a(q + 1) * b(q + 1);
+    s2 += a(q + 2) * b(q + 2);
+    s3 += a(q + 3) * b(q + 3);
+  }
+  for (; q < q1; ++q) s0 += a(q) * b(q);
+  return (s0 + s1) + (s2 + s3);
+}
+
 // T (pw x pw upper, row-major ld kQrNB): T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
 __global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, int64_t nct, int pw,
                                                   const double* __restrict__ tau,
                                                   double* __restrict__ T) {
   __shared__ double sT[kQrNB][kQrNB + 1];
   __shared__ double sG[kQrNB][kQrNB + 1];
+  __shared__ double sTau[kQrNB];  // staged once: a load per column would cost a round trip each
+  if (threadIdx.x < kQrNB) sTau[threadIdx.x] = (int)threadIdx.x < pw ? tau[threadIdx.x] : 0.0;
   for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
     const int l = e / kQrNB, i = e % kQrNB;
     sG[l][i] = (l < pw && i < pw) ? W[(int64_t)l * nct + i] : 0.0;
@@ -598,11 +617,10 @@ __global__ __launch_bounds__(256) void k_qr_larft(const double* __restrict__ W, 
   }
   __syncthreads();
   for (int i = 0; i < pw; ++i) {
-    const double ti = tau[i];
+    const double ti = sTau[i];
     double z = 0.0;
     const int l = threadIdx.x;
-    if (l < i)
-      for (int q = l; q < i; ++q) z += sT[l][q] * sG[q][i];
+    if (l < i) z = dot4(l, i, [&](int q) { return sT[l][q]; }, [&](int q) { return sG[q][i]; });
     __syncthreads();
     if (l < i) sT[l][i] = -ti * z;
     if (l == i) sT[i][i] = ti;
@@ -623,6 +641,44 @@ __global__ void k_qr_tw(const double* __restrict__ W, int64_t nct, int pw,
     double s = 0.0;
     for (int l = 0; l <= kk; ++l) s += T[l * kQrNB + kk] * W[(int64_t)l * nct + cp];
     Wt[(int64_t)kk * nct + cp] = -s;
+  }
+}
+
+// T and Wt = -T^T W of a narrow reflector block (pw <= 16, nct <= 64) in one
+// wave: the same sums in the same order as k_qr_larft followed by k_qr_tw, in
+// one launch instead of two.  W's pw rows and tau are staged in LDS first with
+// all loads in flight at once; the rest works from LDS with a one-wave barrier
+// per column.
+__global__ __launch_bounds__(64) void k_qr_larft_tw16(const double* __restrict__ W, int64_t nct,
+                                                      int pw, const double* __restrict__ tau,
+                                                      double* __restrict__ T,
+                                                      double* __restrict__ Wt) {
+  __shared__ double sW[16][65];
+  __shared__ double sT[16][17];
+  __shared__ double sTau[16];
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    sW[r][l] = (r < pw && l < nct) ? W[(int64_t)r * nct + l] : 0.0;
+  if (l < 16) sTau[l] = l < pw ? tau[l] : 0.0;
+  for (int e = l; e < 256; e += 64) sT[e / 16][e % 16] = 0.0;
+  __syncthreads();
+  for (int i = 0; i < pw; ++i) {
+    const double ti = sTau[i];
+    double z = 0.0;
+    if (l < i) z = dot4(l, i, [&](int q) { return sT[l][q]; }, [&](int q) { return sW[q][i]; });
+    __syncthreads();
+    if (l < i) sT[l][i] = -ti * z;
+    if (l == i) sT[i][i] = ti;
+    __syncthreads();
+  }
+  for (int e = l; e < pw * pw; e += 64) T[(e / pw) * kQrNB + e % pw] = sT[e / pw][e % pw];
+  const int ntr = (int)(nct - pw);
+  for (int e = l; e < pw * ntr; e += 64) {
+    const int kk = e / ntr, cp = pw + (e - kk * ntr);
+    const double acc =
+        dot4(0, kk + 1, [&](int q) { return sT[q][kk]; }, [&](int q) { return sW[q][cp]; });
+    Wt[(int64_t)kk * nct + cp] = -acc;
   }
 }
 
@@ -1327,6 +1383,8 @@ __global__ __launch_bounds__(256) void k_qr_larft_half(const double* __restrict_
   const int o = blockIdx.x * kQrNB;
   const int w = min(kQrNB, pw - o);
   if (w <= 0) return;
+  __shared__ double sTau[kQrNB];  // staged once: a load per column would cost a round trip each
+  if (threadIdx.x < kQrNB) sTau[threadIdx.x] = (int)threadIdx.x < w ? tau[o + threadIdx.x] : 0.0;
   for (int e = threadIdx.x; e < kQrNB * kQrNB; e += 256) {
     const int l = e / kQrNB, i = e % kQrNB;
     sG[l][i] = (l < w && i < w) ? W[(int64_t)(o + l) * nct + (o + i)] : 0.0;
@@ -1336,10 +1394,9 @@ __global__ __launch_bounds__(256) void k_qr_larft_half(const double* __restrict_
   const int l = threadIdx.x;
   for (int i = 0; i < w; ++i) {
     double z = 0.0;
-    if (l < i)
-      for (int q = l; q < i; ++q) z += sT[l][q] * sG[q][i];
+    if (l < i) z = dot4(l, i, [&](int q) { return sT[l][q]; }, [&](int q) { return sG[q][i]; });
     __syncthreads();
-    const double ti = tau[o + i];
+    const double ti = sTau[i];
     if (l < i) sT[l][i] = -ti * z;
     if (l == i) sT[i][i] = ti;
     __syncthreads();
@@ -1368,9 +1425,7 @@ __global__ __launch_bounds__(256) void k_qr_tcouple(const double* __restrict__ W
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = threadIdx.x + u * 256, r = e / kQrNB, c = e % kQrNB;
-    double acc = 0.0;
-    for (int q = 0; q <= c; ++q) acc += sB[r][q] * sC[q][c];
-    x[u] = acc;
+    x[u] = dot4(0, c + 1, [&](int q) { return sB[r][q]; }, [&](int q) { return sC[q][c]; });
   }
   __syncthreads();
 #pragma unroll
@@ -1383,8 +1438,8 @@ __global__ __launch_bounds__(256) void k_qr_tcouple(const double* __restrict__ W
   // T12 = -T11 X (T11 upper triangular)
   for (int u = 0; u < 16; ++u) {
     const int e = threadIdx.x + u * 256, r = e / kQrNB, c = e % kQrNB;
-    double acc = 0.0;
-    for (int q = r; q < kQrNB; ++q) acc += sA[r][q] * sB[q][c];
+    const double acc =
+        dot4(r, kQrNB, [&](int q) { return sA[r][q]; }, [&](int q) { return sB[q][c]; });
     T[(int64_t)r * kQrOB + (kQrNB + c)] = -acc;
   }
 }
@@ -2048,6 +2103,11 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
                        nct, w->part);
     // many slabs, few outputs: 16 waves per 64 outputs split the slab sum
     reduce_rows_f64(w->part, nslab, (int64_t)pw * nct, w->W, st);
+    hipLaunchKernelGGL(k_qr_larft_tw16, dim3(1), dim3(64), 0, st, w->W, nct, pw, w->tau + j0,
+                       w->T, w->Wt);
+    hipLaunchKernelGGL(k_qr_upd, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0, pw,
+                       c_end, nct, w->Wt);
+    return;
   } else {
     const int64_t nslab = (m - j0 + slab - 1) / slab;
     const int64_t n_ct = (nct + kVC - 1) / kVC;
