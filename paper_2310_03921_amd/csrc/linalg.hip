@@ -691,33 +691,52 @@ __global__ __launch_bounds__(64) void k_qr_larft_tw16(const double* __restrict__
 // quarters), each a 32 x 32 block of (C column, C row) = (matrix-core row, col).
 constexpr int kUR = 128;  // rows of C per block
 constexpr int kUC = 64;   // columns per tile
+template <int KW>
 __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t ld, int64_t m,
                                                 int64_t j0, int pw, int64_t c_end, int64_t nct,
                                                 const double* __restrict__ Wt) {
   // padded row strides: the four lane groups of a fragment read (rows kk .. kk+3)
   // fall on different banks
-  __shared__ double sV[kQrNB][kUR + 8];
-  __shared__ double sW[2][kQrNB][kUC + 8];
+  __shared__ double sV[KW][kUR + 8];
+  __shared__ double sW[2][KW][kUC + 8];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int wc = wave & 1, wr = wave >> 1;
   const int64_t r0 = j0 + (int64_t)blockIdx.x * kUR;
   const int64_t cbeg = j0 + pw;
   const int ntile = (int)((c_end - cbeg + kUC - 1) / kUC);
-  for (int e = threadIdx.x; e < kQrNB * kUR; e += 512) {
-    const int kk = e / kUR, x = e % kUR;
-    const int64_t r = r0 + x;
-    double v = 0.0;
-    if (kk < pw && r < m) {
-      const int64_t rr = r - j0;
-      v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
+  if (r0 - j0 >= KW && r0 + kUR <= m) {
+    // below the unit triangle and inside the matrix: all loads issued at once
+    // (rows kk >= pw read row pw - 1 and are zeroed after), not one guarded
+    // load after another
+    constexpr int kN = KW * kUR / 512;
+    double tmp[kN];
+#pragma unroll
+    for (int t = 0; t < kN; ++t) {
+      const int e = threadIdx.x + t * 512, kk = e / kUR, x = e % kUR;
+      tmp[t] = A[(r0 + x) + (j0 + min(kk, pw - 1)) * ld];
     }
-    sV[kk][x] = v;
+#pragma unroll
+    for (int t = 0; t < kN; ++t) {
+      const int e = threadIdx.x + t * 512, kk = e / kUR, x = e % kUR;
+      sV[kk][x] = kk < pw ? tmp[t] : 0.0;
+    }
+  } else {
+    for (int e = threadIdx.x; e < KW * kUR; e += 512) {
+      const int kk = e / kUR, x = e % kUR;
+      const int64_t r = r0 + x;
+      double v = 0.0;
+      if (kk < pw && r < m) {
+        const int64_t rr = r - j0;
+        v = (rr == kk) ? 1.0 : (rr > kk ? A[r + (j0 + kk) * ld] : 0.0);
+      }
+      sV[kk][x] = v;
+    }
   }
   // W' tile in registers first (8 values per thread), written to LDS later
-  double wreg[kQrNB * kUC / 512];
+  double wreg[KW * kUC / 512];
   auto load_w = [&](int tile) {
 #pragma unroll
-    for (int t = 0; t < kQrNB * kUC / 512; ++t) {
+    for (int t = 0; t < KW * kUC / 512; ++t) {
       // clamped, unconditional: rows kk >= pw meet zero rows of sV, columns
       // beyond c_end only feed outputs that are never stored
       const int e = threadIdx.x + t * 512;
@@ -728,7 +747,7 @@ __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t 
   };
   auto store_w = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < kQrNB * kUC / 512; ++t) {
+    for (int t = 0; t < KW * kUC / 512; ++t) {
       const int e = threadIdx.x + t * 512;
       sW[buf][e / kUC][e % kUC] = wreg[t];
     }
@@ -758,7 +777,8 @@ __global__ __launch_bounds__(512) void k_qr_upd(double* __restrict__ A, int64_t 
       load_w(tile + 1);
       load_c(tile + 1, nxt);
     }
-    for (int k0 = 0; k0 < pw; k0 += 4) {
+#pragma unroll
+    for (int k0 = 0; k0 < KW; k0 += 4) {  // rows of sV at and beyond pw are zero
       const int kk = k0 + g;
       double a[2], b[2];
 #pragma unroll
@@ -2105,8 +2125,8 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
     reduce_rows_f64(w->part, nslab, (int64_t)pw * nct, w->W, st);
     hipLaunchKernelGGL(k_qr_larft_tw16, dim3(1), dim3(64), 0, st, w->W, nct, pw, w->tau + j0,
                        w->T, w->Wt);
-    hipLaunchKernelGGL(k_qr_upd, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0, pw,
-                       c_end, nct, w->Wt);
+    hipLaunchKernelGGL(k_qr_upd<16>, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0,
+                       pw, c_end, nct, w->Wt);
     return;
   } else {
     const int64_t nslab = (m - j0 + slab - 1) / slab;
@@ -2120,7 +2140,7 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
   hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
   hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw, w->T,
                      w->Wt);
-  hipLaunchKernelGGL(k_qr_upd, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0, pw, c_end,
+  hipLaunchKernelGGL(k_qr_upd<kQrNB>, dim3(cdiv(m - j0, kUR)), dim3(512), 0, st, A, ld, m, j0, pw, c_end,
                      nct, w->Wt);
 }
 
