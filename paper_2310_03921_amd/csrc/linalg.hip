@@ -2072,12 +2072,20 @@ static int64_t qr_slab_rows(int64_t m) {
   return (s + 31) / 32 * 32;
 }
 
-size_t qr_workspace_bytes(int64_t m, int64_t n) {
+// Elements of the split-K partials buffer: those of the 128-wide updates, or
+// of the 16- and 64-wide ones over short slabs (at most 64 reflectors x 128
+// columns).  Both the workspace size and its binding use this one count.
+static int64_t qr_part_elems(int64_t m, int64_t n) {
   const int64_t ncols = n + 1;
   const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
+  return std::max(nslab * kQrOB * ncols,
+                  ((m + kNarrowSlab - 1) / kNarrowSlab + 1) * (int64_t)kQrNB * 2 * kQrNB);
+}
+
+size_t qr_workspace_bytes(int64_t m, int64_t n) {
+  const int64_t ncols = n + 1;
   size_t d = 0;
-  d += std::max((size_t)nslab * kQrOB * ncols,  // part (128-wide split-K partials)
-                 (size_t)((m + kNarrowSlab - 1) / kNarrowSlab + 1) * 16 * 64);
+  d += (size_t)qr_part_elems(m, n);           // part
   d += (size_t)kQrOB * ncols * 2;            // W, Wt
   d += (size_t)kQrOB * kQrOB;                // T
   d += (size_t)kQrNB * kCS;                  // colstate
@@ -2088,11 +2096,9 @@ size_t qr_workspace_bytes(int64_t m, int64_t n) {
 
 void qr_bind_workspace(void* base, int64_t m, int64_t n, QrWork* w) {
   const int64_t ncols = n + 1;
-  const int64_t nslab = (m + qr_slab_rows(m) - 1) / qr_slab_rows(m);
   double* p = reinterpret_cast<double*>(base);
   w->part = p;
-  w->part_elems = std::max(nslab * kQrOB * ncols,
-                           ((m + kNarrowSlab - 1) / kNarrowSlab + 1) * (int64_t)16 * 64);
+  w->part_elems = qr_part_elems(m, n);
   p += w->part_elems;
   w->W = p;
   p += kQrOB * ncols;
@@ -2129,13 +2135,16 @@ static void qr_wy_update(double* A, int64_t ld, int64_t m, int64_t j0, int pw, i
                        pw, c_end, nct, w->Wt);
     return;
   } else {
-    const int64_t nslab = (m - j0 + slab - 1) / slab;
+    // Short slabs: a 64-wide update has one column tile, so the slabs alone
+    // must give enough blocks to fill the device; the many partials are summed
+    // by the multi-block row reduction.
+    (void)slab;
+    const int64_t nslab = (m - j0 + kNarrowSlab - 1) / kNarrowSlab;
     const int64_t n_ct = (nct + kVC - 1) / kVC;
     const int64_t total = nslab * n_ct, per_xcd = (total + 7) / 8;
     hipLaunchKernelGGL(k_qr_vtc2, dim3((unsigned)(8 * per_xcd)), dim3(512), 0, st, A, ld, m, j0,
-                       pw, nct, slab, n_ct, total, per_xcd, w->part);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(g256(pw * nct)), dim3(256), 0, st, w->part, nslab,
-                       (int64_t)pw * nct, w->W);
+                       pw, nct, (int64_t)kNarrowSlab, n_ct, total, per_xcd, w->part);
+    reduce_rows_f64(w->part, nslab, (int64_t)pw * nct, w->W, st);
   }
   hipLaunchKernelGGL(k_qr_larft, dim3(1), dim3(256), 0, st, w->W, nct, pw, w->tau + j0, w->T);
   hipLaunchKernelGGL(k_qr_tw, dim3(g256(pw * (nct - pw))), dim3(256), 0, st, w->W, nct, pw, w->T,
