@@ -473,8 +473,9 @@ __global__ __launch_bounds__(kRRT) void k_qr_panel_rr(double* __restrict__ A, in
 #pragma unroll
       for (int j = 0; j < kRRW; ++j) ak = (j == k) ? a[q][j] : ak;
       ak = (lrow[q] > k) ? ak : 0.0;
+      // columns j < k are summed too (no select per register) and never used
 #pragma unroll
-      for (int j = 0; j < kRRW; ++j) part[j] += (j >= k) ? ak * a[q][j] : 0.0;
+      for (int j = 0; j < kRRW; ++j) part[j] += ak * a[q][j];
       if (lrow[q] == k) {
         double* pv = piv + (k & 1) * kRRW;
 #pragma unroll
