@@ -177,6 +177,7 @@ __global__ __launch_bounds__(256) void k_pstage(int mode, const TD* __restrict__
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = rowbase + g + 4 * r;
+        if (rv[r] && !cvalid && W && mode < 2 && col < ldw) W[rr * ldw + col] = 0.0;  // row padding
         if (!rv[r] || !cvalid) continue;
         if (mode == 3) {
           csum -= Sx[rr * ldsx + col] * accq[u][r];
@@ -383,6 +384,135 @@ __global__ __launch_bounds__(256) void k_gemm_wx_cs(const double* __restrict__ W
   }
 }
 
+// out = (W diag(cs)) X for D <= 256 (CS false: no scaling, cs unused).  A block
+// of eight waves covers 64 rows and all (up to 256) columns: wave w takes
+// rows 16 (w / 2) .. + 15 and the 8 column tiles of half w % 2.  The
+// contraction runs over 32-wide chunks of k; the block stages chunk c of
+// diag(cs) X in LDS (double-buffered, one barrier per chunk), already in the
+// order the matrix core consumes it, while each wave reads its W rows straight
+// from memory.  The next chunk's loads are issued before
+// the current chunk's matrix work.  Loads in the loop are unconditional: rows
+// past n and k past ldw - 4 are clamped to valid addresses, and the staged X
+// is zero for k >= M, so W's row padding (columns M .. ldw - 1) only needs to
+// be finite; every producer in this library writes it as zero.  Each output
+// element is one sum in a fixed order.
+typedef unsigned wx_u32x2 __attribute__((ext_vector_type(2)));
+GAP_DEV __amdgpu_buffer_rsrc_t wx_rsrc(const double* p, uint32_t bytes) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((uint64_t)hi << 32 | lo), 0, (int)bytes,
+                                           0x00020000);
+}
+// A load through a raw buffer resource: vector offsets at or past its size
+// read zero (every offset that may leave the range is kept in the vector part).
+GAP_DEV double wx_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+constexpr int kSxW = 8;    // waves per block
+constexpr int kSxKC = 32;  // k per chunk
+constexpr int kSxSub = 16 * 256;  // doubles per 16-k sub-chunk: 16 tiles x [2 halves][64 lanes][2]
+constexpr int kSxPer = kSxKC * 256 / (64 * kSxW);  // staged elements per thread
+template <bool CS>
+__global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
+    const double* __restrict__ W, int64_t ldw, int64_t n, int64_t M,
+    const double* __restrict__ cs, const double* __restrict__ X, int64_t ldx, int64_t D,
+    double* __restrict__ out, int64_t ldo) {
+  extern __shared__ __attribute__((aligned(16))) double xs[];  // [2][kSxKC / 16][kSxSub]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int ch = wave & 1;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + (wave >> 1) * 16;
+  const double* wrow = W + min(rowbase + idx, n - 1) * ldw;
+  const int64_t nch = (M + kSxKC - 1) / kSxKC;
+
+  // staging: thread t moves elements e = t + 512 it of the chunk, e = 256 kl + d
+  //   -> sub-chunk kl / 16, tile d / 16, half (kl & 3) / 2, lane 16 ((kl & 15) / 4) + d % 16, kl & 1
+  // kl = (t >> 8) + 2 it, the same in a whole wave.  X is read through a buffer
+  // resource of M rows, so rows k >= M read zero; columns d >= D take an offset
+  // past any row (zero too).  cs[k] is a wave-uniform load, applied when the
+  // element is written to LDS.
+  const int kl0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8), d = threadIdx.x & 255;
+  const auto xr = wx_rsrc(X, (uint32_t)(M * ldx * 8));
+  const uint32_t xoff0 = d < D ? (uint32_t)((kl0 * ldx + d) * 8) : 0x80000000u;
+  const uint32_t xstep = (uint32_t)(2 * ldx * 8);
+  auto soff = [&](int it) {
+    const int kl = kl0 + 2 * it;
+    return (kl >> 4) * kSxSub + (d >> 4) * 256 + ((kl & 3) >> 1) * 128 +
+           (((kl & 15) >> 2) * 16 + (d & 15)) * 2 + (kl & 1);
+  };
+  auto fetch = [&](int64_t c, double v[kSxPer], double sc[kSxPer]) {
+    const uint32_t base = (uint32_t)(c * kSxKC * ldx * 8);
+#pragma unroll
+    for (int it = 0; it < kSxPer; ++it) {
+      v[it] = wx_ld(xr, xoff0 + base + it * xstep, 0);
+      sc[it] = CS ? cs[min(c * kSxKC + kl0 + 2 * it, M - 1)] : 1.0;
+    }
+  };
+  auto stage = [&](double* dst, const double v[kSxPer], const double sc[kSxPer]) {
+#pragma unroll
+    for (int it = 0; it < kSxPer; ++it) dst[soff(it)] = CS ? v[it] * sc[it] : v[it];
+  };
+  // W fragment of sub-chunk h: k = 32 c + 16 h + 4 g + s (any k >= M meets a
+  // zero row of the staged X)
+  auto afrag = [&](int64_t c, double a[8]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t k = c * kSxKC + 16 * h + 4 * g;
+      load4u(wrow + min(k, ldw - 4), a + 4 * h);
+    }
+  };
+
+  double sv[kSxPer], cv[kSxPer], a_cur[8], a_nxt[8];
+  fetch(0, sv, cv);
+  afrag(0, a_cur);
+  stage(xs, sv, cv);
+  __syncthreads();
+
+  d4v acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = zero4();
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t cn = min(c + 1, nch - 1);
+    fetch(cn, sv, cv);
+    afrag(cn, a_nxt);
+    // keep the next chunk's loads ahead of this chunk's matrix work (the
+    // scheduler would otherwise sink them next to their use)
+    __builtin_amdgcn_sched_barrier(0);
+    const double* buf = xs + (c & 1) * (kSxKC / 16) * kSxSub;
+#pragma unroll
+    for (int sc = 0; sc < kSxKC / 16; ++sc) {
+      // step (h, j) of sub-chunk sc consumes k = 32 c + 16 sc + 4 g + 2 h + j
+      const d2v* xb = reinterpret_cast<const d2v*>(buf + sc * kSxSub) + ch * 8 * 128 + lane;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        d2v b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = xb[u * 128 + h * 64];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[4 * sc + 2 * h + j], b[u][j], acc[u]);
+      }
+    }
+    // and their use (scaling, LDS writes) after it
+    __builtin_amdgcn_sched_barrier(0);
+    stage(xs + ((c + 1) & 1) * (kSxKC / 16) * kSxSub, sv, cv);
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 8; ++s4) a_cur[s4] = a_nxt[s4];
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t col = (int64_t)(ch * 8 + u) * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + g + 4 * r;
+      if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
+    }
+  }
+}
+constexpr size_t kSxLds = 2 * (kSxKC / 16) * kSxSub * sizeof(double);
+
 // y[i] = sum_k A[i + k * lda] x[k]  (column-major GEMV): 64 rows per block, 16 waves
 // splitting k, partial sums combined in LDS in a fixed order.
 __global__ __launch_bounds__(1024) void k_gemv_cm(const double* __restrict__ A, int64_t lda,
@@ -575,9 +705,32 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                        ldsx);
 }
 
+// The LDS-staged form needs D <= 256, W rows of whole 32-byte groups
+// (ldw % 4 == 0, W 32-byte aligned) and X under 2 GB; the general form takes
+// any layout.
+inline bool wx_lds_ok(const double* W, int64_t ldw, int64_t M, int64_t ldx,
+                      int64_t D) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_wx_lds<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_wx_lds<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
+    attr = true;
+  }
+  // offsets into X, including a dropped column's, stay below 2^32
+  return D <= 256 && M > 0 && ldw >= 4 && ldw % 4 == 0 &&
+         (reinterpret_cast<uintptr_t>(W) & 31) == 0 && (M + 2 * kSxKC) * ldx * 8 < (1ll << 31);
+}
+
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st) {
   if (n <= 0 || D <= 0) return;
+  if (wx_lds_ok(W, ldw, M, ldx, D)) {
+    hipLaunchKernelGGL(k_gemm_wx_lds<false>, dim3(cdiv(n, 64)), dim3(64 * kSxW), kSxLds, st, W, ldw, n, M,
+                       nullptr, X, ldx, D, out, ldo);
+    return;
+  }
   hipLaunchKernelGGL(k_gemm_wx, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
                      X, ldx, D, out, ldo);
 }
@@ -617,6 +770,11 @@ void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, cons
                         const double* X, int64_t ldx, int64_t D, double* out, int64_t ldo,
                         hipStream_t st) {
   if (n <= 0 || D <= 0) return;
+  if (wx_lds_ok(W, ldw, M, ldx, D)) {
+    hipLaunchKernelGGL(k_gemm_wx_lds<true>, dim3(cdiv(n, 64)), dim3(64 * kSxW), kSxLds, st, W, ldw, n, M,
+                       cs, X, ldx, D, out, ldo);
+    return;
+  }
   hipLaunchKernelGGL(k_gemm_wx_cs, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
                      cs, X, ldx, D, out, ldo);
 }

@@ -495,6 +495,64 @@ __global__ __launch_bounds__(256) void k_jac_t_apply(const TJ* __restrict__ jac,
   }
 }
 
+// The same product for D % 4 == 0 and D <= 256 with no guarded load in its
+// pair loop: a lane reads the 4-element segment min(4 lane, D - 4) of the
+// three Jacobian rows of a pair (lanes past D re-read the last segment and
+// store nothing), and the pair's target and v come from one guarded batch load
+// per 64 pairs, broadcast from lane q with readlane (so they are scalars), so
+// the loads of successive pairs overlap instead of waiting on each other.
+// The association order of the sum (per pair, then over pairs) is the one of
+// k_jac_t_apply.
+GAP_DEV double readlane_f64(double x, int q) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, q);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), q);
+  return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+template <typename TJ>
+__global__ __launch_bounds__(256) void k_jac_t_apply4(const TJ* __restrict__ jac, int64_t ldj,
+                                                      int64_t D,
+                                                      const int64_t* __restrict__ pair_ptr,
+                                                      const int32_t* __restrict__ pair_j,
+                                                      int64_t n_atoms, int64_t n_pairs,
+                                                      const double* __restrict__ v,
+                                                      double* __restrict__ h, int64_t ldh) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n_atoms) return;
+  const int64_t kk = min((int64_t)4 * lane, D - 4);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t lo = max((int64_t)0, pair_ptr[i]), hi = min(n_pairs, pair_ptr[i + 1]);
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t pl = base + lane;
+    const int32_t j = pl < hi ? pair_j[pl] : -1;
+    const bool ok = j >= 0 && j < n_atoms;
+    const double w0 = ok ? v[3 * (int64_t)j] : 0.0;
+    const double w1 = ok ? v[3 * (int64_t)j + 1] : 0.0;
+    const double w2 = ok ? v[3 * (int64_t)j + 2] : 0.0;
+    const int cnt = (int)min((int64_t)64, hi - base);
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const double v0 = readlane_f64(w0, q), v1 = readlane_f64(w1, q), v2 = readlane_f64(w2, q);
+      const bool okq = __builtin_amdgcn_readlane((int)ok, q) != 0;
+      const TJ* jr = jac + (base + q) * 3 * ldj + kk;
+      double j0[4], j1[4], j2[4];
+      ldj4(jr, j0);
+      ldj4(jr + ldj, j1);
+      ldj4(jr + 2 * ldj, j2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double t = acc[u] + (v0 * j0[u] + v1 * j1[u] + v2 * j2[u]);
+        acc[u] = okq ? t : acc[u];  // a left-out pair adds nothing, even a non-finite J row
+      }
+    }
+  }
+  if (4 * lane < D) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) h[i * ldh + 4 * lane + u] = acc[u];
+  }
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -607,6 +665,17 @@ void jac_transpose_apply_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t
                              hipStream_t st) {
   if (n_atoms <= 0) return;
   dim3 grid(cdiv(n_atoms, 4));
+  if (D % 4 == 0 && D >= 4 && D <= 256) {
+    if (jac_f32)
+      hipLaunchKernelGGL(k_jac_t_apply4<float>, grid, dim3(256), 0, st,
+                         reinterpret_cast<const float*>(jac), ldj, D, pair_ptr, pair_j, n_atoms,
+                         n_pairs, v, h, ldh);
+    else
+      hipLaunchKernelGGL(k_jac_t_apply4<double>, grid, dim3(256), 0, st,
+                         reinterpret_cast<const double*>(jac), ldj, D, pair_ptr, pair_j, n_atoms,
+                         n_pairs, v, h, ldh);
+    return;
+  }
   if (jac_f32)
     hipLaunchKernelGGL(k_jac_t_apply<float>, grid, dim3(256), 0, st,
                        reinterpret_cast<const float*>(jac), ldj, D, pair_ptr, pair_j, n_atoms,
