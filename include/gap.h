@@ -175,6 +175,42 @@ gap_status gap_fit(gap_handle *h, double *A, int64_t ld, int64_t n_rows, const d
                    const double *y, const double *sigma, double jitter, const gap_atoms *train,
                    const gap_sparse *sp, int refine_steps, double *c, gap_fit_info *info);
 
+/* Streamed fit: the least-squares problem of gap_fit folded one block of
+ * observation rows at a time, so that A is never held whole.  Sec. "Theory"
+ * gives the QR route; Sec. "Program structure" splits the configurations, and
+ * so the rows of L-hat K_NM (its main memory cost), into groups built apart.
+ * Row order does not change a least-squares problem, and the triangular
+ * factor of [T_prev ; block] is that of all rows seen (T^T T = [A | b]^T [A | b]).
+ * State T: column-major buffer of M + 1 columns with ld >= M + 1 + n_rows of
+ * every fold, ld % 4 == 0, 32-byte aligned.  Rows [0, M + 1) hold the upper
+ * triangular factor of the augmented matrix [A_seen | b_seen] of the rows
+ * folded so far (R of A_seen, then (Q^T b)[0:M] in column M and, in the
+ * corner T[M][M], the norm of the least-squares residual).  Rows
+ * [M + 1, M + 1 + n_rows) are the block area: before gap_fold_rows the caller
+ * writes the block's L-hat K_NM rows there, columns [0, M) (gap_build_knm with
+ * Knm = T + M + 1 and the same ld).  Every call is ordered on the handle's
+ * stream; gap_fold_init and gap_fold_solve wait for it, gap_fold_rows does not
+ * (device-side errors of a fold surface at the next synchronising call).
+ *
+ * gap_fold_init: T = [U 0; 0 0], U the upper Cholesky factor of K_MM + jitter I
+ *   (the rows U_MM of A).  Kmm [M x M] col-major (ld = M).  Rows >= M + 1
+ *   are not touched.  Returns GAP_E_NOT_PD if the Cholesky fails. */
+gap_status gap_fold_init(gap_handle *h, double *T, int64_t ld, int64_t M, const double *Kmm,
+                         double jitter);
+/* gap_fold_rows: fold the n_rows block rows (n_rows >= 0; 0 is a no-op):
+ *   scale row r by 1 / sigma[r], put y[r] / sigma[r] in column M, and replace
+ *   T by the triangular factor of [T ; block] (Householder QR of the stacked
+ *   M + 1 + n_rows rows, then the corner norm).  y, sigma [n_rows] device,
+ *   sigma > 0.  The block area is overwritten (Householder vectors). */
+gap_status gap_fold_rows(gap_handle *h, double *T, int64_t ld, int64_t M, int64_t n_rows,
+                         const double *y, const double *sigma);
+/* gap_fold_solve: c = R^-1 (Q^T b)[0:M] from the state (device c [M]).
+ *   lsq_resid (host, may be NULL) = |T[M][M]| = ||b - A c|| over all rows folded.
+ *   rdiag_minmax (host, may be NULL) = min and max |R_kk|.
+ *   Returns GAP_E_RANK if some R_kk is zero or not finite. */
+gap_status gap_fold_solve(gap_handle *h, const double *T, int64_t ld, int64_t M, double *c,
+                          double *lsq_resid, double *rdiag_minmax);
+
 /* Predict with coefficients c [M] (eq. epsilon and the chain rule for forces):
  *   e_atom [n_atoms]      eps_i = sum_m c_m delta^2 (d_i . x_m)^zeta
  *   e_cfg  [n_cfg]        sum of eps_i over the configuration

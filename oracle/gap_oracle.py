@@ -166,6 +166,63 @@ def fit(Knm, Kmm, y, sigma, jitter):
     return solve_qr(A, b)
 
 
+def augmented_r(A, b):
+    """Upper-triangular factor T of the augmented matrix [A | b] = Q T, (n+1) x (n+1).
+
+    Sec. "Theory", QR route: the first n columns of T are R of A = QR, the last
+    holds (Q^T b)[0:n] and, in the corner, the norm of the part of Q^T b that R
+    leaves over, i.e. +-||b - A c|| for the least-squares c.  One LAPACK QR of
+    [A | b] (zero rows appended when A has fewer than n + 1 rows).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[1]
+    Ab = np.column_stack([A, np.asarray(b, dtype=np.float64)])
+    if Ab.shape[0] < n + 1:
+        Ab = np.vstack([Ab, np.zeros((n + 1 - Ab.shape[0], n + 1))])
+    qr, _, _, info = lapack.dgeqrf(np.asfortranarray(Ab))
+    if info != 0:
+        raise RuntimeError("dgeqrf failed")
+    return np.triu(qr[:n + 1, :n + 1])
+
+
+def fold_init(Kmm, jitter):
+    """State of the streamed fit before any observation: T = [U 0; 0 0].
+
+    The rows U_MM of A with their zero targets (Sec. "Theory"), as an
+    (M+1) x (M+1) upper-triangular factor.
+    """
+    Kmm = np.asarray(Kmm, dtype=np.float64)
+    M = Kmm.shape[0]
+    T = np.zeros((M + 1, M + 1))
+    T[:M, :M] = sla.cholesky(Kmm + jitter * np.eye(M), lower=False)
+    return T
+
+
+def fold_rows(T, Knm_block, y_block, sigma_block):
+    """Fold a block of observation rows into the state: T' = factor of [T ; block].
+
+    The block is Sigma^-1/2 [L-hat K_NM | y] of some configurations (rows of A
+    and b, Sec. "Theory"); Sec. "Program structure" builds K_NM rows by groups of
+    configurations.  Since T^T T is the Gram matrix of the rows seen so far, the
+    factor of [T ; block] is that of all rows seen.
+    """
+    K = np.asarray(Knm_block, dtype=np.float64)
+    M = T.shape[0] - 1
+    if K.shape[0] == 0:
+        return T
+    w = 1.0 / np.asarray(sigma_block, dtype=np.float64)
+    stacked = np.vstack([T[:, :M], w[:, None] * K])
+    rhs = np.concatenate([T[:, M], w * np.asarray(y_block, dtype=np.float64)])
+    return augmented_r(stacked, rhs)
+
+
+def fold_solve(T):
+    """c = R^-1 (Q^T b)[0:M] and the least-squares residual norm |T[M][M]|."""
+    M = T.shape[0] - 1
+    c = sla.solve_triangular(T[:M, :M], T[:M, M], lower=False)
+    return c, abs(T[M, M])
+
+
 def solve_normal_equations(Knm, Kmm, y, sigma, jitter):
     """c = [K_MM + K_MN Sigma^-1 K_NM]^-1 K_MN Sigma^-1 y  (eq. GP_L, jitter on K_MM)."""
     Knm = np.asarray(Knm, dtype=np.float64)

@@ -75,6 +75,9 @@ def lib():
             "gap_build_knm": ([P, P, P, I32, P, I64], S),
             "gap_lstsq": ([P, P, I64, I64, I64, P, P], S),
             "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
+            "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
+            "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
+            "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_forces": ([P, P, P, P], S),
@@ -302,6 +305,45 @@ class Gap:
         return c, {"resid_norm": list(info.resid_norm)[:info.refine_done + 1],
                    "min_abs_rdiag": info.min_abs_rdiag, "max_abs_rdiag": info.max_abs_rdiag,
                    "refine_done": info.refine_done}
+
+    # ------------------------------------------------------- streamed fit
+    def fold_buffer(self, M: int, max_rows: int, device="cuda") -> torch.Tensor:
+        """State of a streamed fit: column-major, M + 1 columns, ld = round4(M + 1 + max_rows)."""
+        return colmajor(M + 1 + max_rows, M + 1, device=device)
+
+    def fold_block(self, T: torch.Tensor, M: int) -> int:
+        """Device address of the block area (row M + 1) of a fold state, for gap_build_knm."""
+        return T.data_ptr() + 8 * (M + 1)
+
+    def build_knm_block(self, atoms: Atoms, sparse: Sparse, T: torch.Tensor,
+                        precision: str = "fp64"):
+        """L-hat K_NM of `atoms` written into the block area of the fold state T."""
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_build_knm(self._h, ctypes.byref(a), ctypes.byref(s),
+                                        PRECISION[precision],
+                                        ctypes.c_void_p(self.fold_block(T, sparse.M)),
+                                        T.shape[1]))
+
+    def fold_init(self, T: torch.Tensor, M: int, Kmm: torch.Tensor, jitter: float):
+        self._check(lib().gap_fold_init(self._h, _ptr(T), T.shape[1], M, _ptr(_f64(Kmm)),
+                                        float(jitter)))
+
+    def fold_rows(self, T: torch.Tensor, M: int, n_rows: int, y: torch.Tensor,
+                  sigma: torch.Tensor):
+        y, sigma = _f64(y), _f64(sigma)
+        self._check(lib().gap_fold_rows(self._h, _ptr(T), T.shape[1], M, n_rows, _ptr(y),
+                                        _ptr(sigma)))
+        # the call is asynchronous: keep the inputs alive until the stream passes it
+        self._keep = (y, sigma)
+
+    def fold_solve(self, T: torch.Tensor, M: int):
+        c = torch.empty(M, dtype=torch.float64, device=T.device)
+        res = ctypes.c_double()
+        rd = (ctypes.c_double * 2)()
+        self._check(lib().gap_fold_solve(self._h, _ptr(T), T.shape[1], M, _ptr(c),
+                                         ctypes.byref(res), rd))
+        self._keep = None
+        return c, res.value, (rd[0], rd[1])
 
     def predict(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, precision: str = "fp64",
                 e_atom=True, e_cfg=True, dEdd=False, forces=False):

@@ -546,6 +546,101 @@ gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n,
   return s;
 }
 
+// ------------------------------------------------------------ streamed fit
+namespace {
+gap_status check_fold_state(gap_handle* h, const double* T, int64_t ld, int64_t M,
+                            int64_t n_rows) {
+  if (!T || M < 1 || n_rows < 0 || ld < M + 1 + n_rows || ld % 4 != 0 || !aligned32(T))
+    return fail(h, GAP_E_INVALID,
+                "fold state needs M >= 1, ld >= M + 1 + n_rows, ld % 4 == 0, 32-byte alignment");
+  if (M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
+  return GAP_OK;
+}
+}  // namespace
+
+gap_status gap_fold_init(gap_handle* h, double* T, int64_t ld, int64_t M, const double* Kmm,
+                         double jitter) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_fold_state(h, T, ld, M, 0);
+  if (s != GAP_OK) return s;
+  if (!Kmm) return fail(h, GAP_E_INVALID, "Kmm is NULL");
+  if (!(jitter >= 0.0) || !std::isfinite(jitter)) return fail(h, GAP_E_INVALID, "bad jitter");
+  Layout L;
+  const size_t Lw = L.take(sizeof(double) * M * M);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  double* Lm = at<double>(h, Lw);
+  h->timer.begin(gapk::TM_CHOL);
+  gapk::cholesky_lower(Lm, M, M, jitter, Kmm, M, h->dev_err, h->stream);
+  gapk::stack_u(T, ld, 0, M, Lm, M, h->stream);  // rows [0, M): U, zero in column M
+  gapk::fold_tidy(T, ld, M, true, h->stream);     // row M: zero
+  h->timer.end(gapk::TM_CHOL);
+  HIP_TRY(h, hipGetLastError());
+  return drain_dev_err(h);
+}
+
+gap_status gap_fold_rows(gap_handle* h, double* T, int64_t ld, int64_t M, int64_t n_rows,
+                         const double* y, const double* sigma) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_fold_state(h, T, ld, M, n_rows);
+  if (s != GAP_OK) return s;
+  if (n_rows == 0) return GAP_OK;
+  if (!y || !sigma) return fail(h, GAP_E_INVALID, "y / sigma NULL");
+  const int64_t m = M + 1 + n_rows;
+  Layout L;
+  const size_t q = L.take(gapk::qr_workspace_bytes(m, M));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::QrWork qw;
+  gapk::qr_bind_workspace(at<char>(h, q), m, M, &qw);
+  h->timer.begin(gapk::TM_CHOL);
+  gapk::scale_rows(T + M + 1, ld, n_rows, M, y, sigma, h->stream);
+  h->timer.end(gapk::TM_CHOL);
+  // [T ; block] = Q T': R of the first M columns, Q^T b in column M; what Q^T b
+  // holds past row M - 1 is the residual, whose norm becomes the corner.
+  gapk::qr_factor(T, ld, m, M + 1, M, &qw, h->stream, h->dev_err, &h->timer);
+  gapk::norm2_f64(T + M + M * ld, n_rows + 1, T + M + M * ld, h->stream);
+  gapk::fold_tidy(T, ld, M, false, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_fold_solve(gap_handle* h, const double* T, int64_t ld, int64_t M, double* c,
+                          double* lsq_resid, double* rdiag_minmax) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_fold_state(h, T, ld, M, 0);
+  if (s != GAP_OK) return s;
+  if (!c) return fail(h, GAP_E_INVALID, "c is NULL");
+  Layout L;
+  const size_t q = L.take(gapk::qr_workspace_bytes(M + 1, M));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::QrWork qw;
+  gapk::qr_bind_workspace(at<char>(h, q), M + 1, M, &qw);
+  h->timer.begin(gapk::TM_TRSV);
+  gapk::back_substitute(T, ld, M, T + M * ld, c, h->dev_small, h->dev_err, h->stream, qw.flags);
+  h->timer.end(gapk::TM_TRSV);
+  HIP_TRY(h, hipGetLastError());
+  double rd[3] = {0, 0, 0};
+  HIP_TRY(h, hipMemcpyAsync(rd, h->dev_small, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(rd + 2, T + M + M * ld, sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  s = drain_dev_err(h);
+  if (rdiag_minmax) {
+    rdiag_minmax[0] = rd[0];
+    rdiag_minmax[1] = rd[1];
+  }
+  if (lsq_resid) *lsq_resid = std::fabs(rd[2]);
+  return s;
+}
+
 gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const double* Kmm,
                    const double* y, const double* sigma, double jitter, const gap_atoms* train,
                    const gap_sparse* sp, int refine_steps, double* c, gap_fit_info* info) {

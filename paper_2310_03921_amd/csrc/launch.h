@@ -228,6 +228,9 @@ void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, doub
 void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st);
 void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st);
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st);
+// Streamed-fit state: clear rows (col, M] of columns [0, M) of T (and T[M][M]
+// when zero_corner).
+void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st);
 // Expand per-configuration weights to atoms: out[i] = v[cfg(i)]
 void expand_cfg(const double* v, const int32_t* atom_cfg, int64_t n_atoms, double* out,
                 hipStream_t st);

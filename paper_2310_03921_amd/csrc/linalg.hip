@@ -2017,6 +2017,18 @@ __global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ x, in
   }
 }
 
+// Streamed-fit state after a fold: the top M + 1 rows of columns [0, M) keep
+// R (upper triangle); what the QR left below the diagonal there (Householder
+// vectors, and row M) is cleared.  With zero_corner (the initial state) row M
+// of column M is cleared too.
+__global__ void k_fold_tidy(double* __restrict__ T, int64_t ld, int64_t M, int zero_corner) {
+  const int64_t col = blockIdx.y;
+  const int64_t r0 = col < M ? col + 1 : (zero_corner ? M : M + 1);
+  for (int64_t r = r0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= M;
+       r += (int64_t)gridDim.x * blockDim.x)
+    T[r + col * ld] = 0.0;
+}
+
 __global__ void k_expand_cfg(const double* __restrict__ v, const int32_t* __restrict__ atom_cfg,
                              int64_t n, double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -2345,6 +2357,13 @@ void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st) {
 
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, x, n, out);
+}
+
+void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st) {
+  // column M has rows > M only below the state, so it needs no clearing unless
+  // the corner itself is reset
+  dim3 grid(cdiv(M + 1, 256), (unsigned)(M + 1));
+  hipLaunchKernelGGL(k_fold_tidy, grid, dim3(256), 0, st, T, ld, M, zero_corner ? 1 : 0);
 }
 
 void expand_cfg(const double* v, const int32_t* atom_cfg, int64_t n_atoms, double* out,

@@ -195,6 +195,41 @@ def check_qr_vs_closed_forms(orc):
     assert np.linalg.norm(c - ref2) <= 1e-10 * np.linalg.norm(ref2)
 
 
+def check_fold_streamed(orc):
+    # Folding the observation rows block by block (an empty and a one-row block
+    # included, in two different orders) must give the least-squares solution of
+    # the whole stacked system (SVD route), the residual norm of that solution in
+    # the corner, a triangular factor whose Gram matrix is that of [A | b], and
+    # one solution whatever the block order.
+    w, b, X, jit = small_fit_problem(seed=5)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    y = np.random.default_rng(11).standard_normal(b.n_rows)
+    sig = synth.sigma_rows(w, b.counts)
+    n = b.n_rows
+    cuts = [0, 3, 3, 4, n // 2, n]
+    blocks = [(cuts[i], cuts[i + 1]) for i in range(len(cuts) - 1)]
+    L = np.linalg.cholesky(Kmm + jit * np.eye(w.M))
+    A = np.vstack([K / sig[:, None], L.T])
+    bb = np.concatenate([y / sig, np.zeros(w.M)])
+    ref = np.linalg.lstsq(A, bb, rcond=None)[0]
+    rnorm = np.linalg.norm(bb - A @ ref)
+    sols = []
+    for order in (blocks, blocks[::-1]):
+        T = orc.fold_init(Kmm, jit)
+        for r0, r1 in order:
+            T = orc.fold_rows(T, K[r0:r1], y[r0:r1], sig[r0:r1])
+        assert np.all(np.tril(T, -1) == 0.0)
+        Ab = np.column_stack([A, bb])
+        G = Ab.T @ Ab
+        assert np.linalg.norm(T.T @ T - G) <= 1e-12 * np.linalg.norm(G)
+        c, res = orc.fold_solve(T)
+        assert np.linalg.norm(c - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert abs(res - rnorm) <= 1e-9 * rnorm
+        sols.append(c)
+    assert np.linalg.norm(sols[0] - sols[1]) <= 1e-10 * np.linalg.norm(sols[0])
+
+
 def check_full_gpr_identity(orc):
     # energy-only observations, sparse set = every atom, no jitter:
     # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
@@ -309,6 +344,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_energy_rows_bruteforce, check_sparse_self_entry,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
+              check_fold_streamed,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

@@ -15,6 +15,8 @@ _orig_design = G.design_matrix
 _orig_predict = G.predict
 _orig_backward = G.predict_backward
 _orig_pt = G.pair_transpose
+_orig_fold_rows = G.fold_rows
+_orig_augr = G.augmented_r
 
 
 def knm_sign_flip(*a):
@@ -97,6 +99,22 @@ def pair_transpose_unstable(pair_ptr, pair_j, n_atoms):
     return tptr, tpair
 
 
+def fold_rows_y_unscaled(T, Knm_block, y_block, sigma_block):
+    return _orig_fold_rows(T, Knm_block, np.asarray(y_block, float) * np.asarray(sigma_block, float),
+                           sigma_block)
+
+
+def fold_rows_drops_state(T, Knm_block, y_block, sigma_block):
+    # factor of the block alone: the rows folded before are lost
+    return _orig_fold_rows(np.zeros_like(T), Knm_block, y_block, sigma_block)
+
+
+def augmented_r_no_corner(A, b):
+    T = _orig_augr(A, b)
+    T[-1, -1] = 0.0
+    return T
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -108,6 +126,9 @@ MUTANTS = [
     ("predict", predict_forces_transposed),
     ("predict_backward", backward_dx_missing_c),
     ("pair_transpose", pair_transpose_unstable),
+    ("fold_rows", fold_rows_y_unscaled),
+    ("fold_rows", fold_rows_drops_state),
+    ("augmented_r", augmented_r_no_corner),
 ]
 
 
