@@ -140,6 +140,16 @@ class Atoms:
                    torch.as_tensor(pair_ptr, dtype=torch.int64).to(device),
                    torch.as_tensor(pair_j, dtype=torch.int32).to(device), j, D)
 
+    def configs(self, c0: int, c1: int) -> "Atoms":
+        """Configurations [c0, c1) of this batch: descriptors and Jacobians are
+        views (no copy); the three index arrays are rebased copies."""
+        cp = self.cfg_ptr[c0:c1 + 1]
+        a0, a1 = int(cp[0]), int(cp[-1])
+        pp = self.pair_ptr[a0:a1 + 1]
+        p0, p1 = int(pp[0]), int(pp[-1])
+        return Atoms(cp - a0, self.desc[a0:a1], pp - p0, self.pair_j[p0:p1] - a0,
+                     None if self.jac is None else self.jac[p0:p1], self.D)
+
     @property
     def n_cfg(self):
         return self.cfg_ptr.numel() - 1

@@ -133,9 +133,14 @@ def test_fold_config_groups_built_in_place(gapx, gap):
         rows_of.append(np.concatenate([np.arange(c0, c1), nc + np.arange(3 * a0, 3 * a1)]))
     T = gap.fold_buffer(M, max(len(r) for r in rows_of))
     gap.fold_init(T, M, gap.build_kmm(sp), w.jitter)
-    for (c0, c1), rows in zip(groups, rows_of):
-        arrs, _ = sub_batch(b, c0, c1)
-        atoms = gapx.Atoms.from_host(*arrs)
+    full = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
+    for i, ((c0, c1), rows) in enumerate(zip(groups, rows_of)):
+        if i % 2 == 0:  # device views of the resident batch
+            atoms = full.configs(c0, c1)
+        else:           # a batch uploaded from host arrays of the group
+            arrs, _ = sub_batch(b, c0, c1)
+            atoms = gapx.Atoms.from_host(*arrs)
+        assert atoms.n_rows == len(rows)
         gap.build_knm_block(atoms, sp, T)
         gap.fold_rows(T, M, len(rows), torch.tensor(y[rows], device="cuda"),
                       torch.tensor(sig[rows], device="cuda"))
