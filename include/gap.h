@@ -148,6 +148,20 @@ gap_status gap_build_kmm(gap_handle *h, const gap_sparse *sp, double *Kmm, int64
 gap_status gap_build_knm(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
                          gap_precision prec, double *Knm, int64_t ld);
 
+/* Local-property rows (Sec. "Local Property": a per-atom property such as a
+ * core-electron binding energy learned directly; a mask marks the atoms that
+ * carry one, so L-hat for such an observation selects a single atom):
+ *   K[r][m] = delta^2 (d_i . x_m)^zeta,  i = atom_idx[r],
+ * column-major n_local x M with ld >= n_local (K may point into a design
+ * buffer below other rows, or into a fold state's block area).  atom_idx
+ * [n_local] int32 device: the compacted mask, 0 <= atom_idx[r] < n_atoms.
+ * Only the descriptors of `atoms` are read (jac may be NULL).  The predicted
+ * property is gap_predict's e_atom; per-species offsets are the caller's
+ * (subtract them from the targets).  Asynchronous; an index out of range gives
+ * a zero row and GAP_E_INVALID at the next synchronising call. */
+gap_status gap_build_local_rows(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                                const int32_t *atom_idx, int64_t n_local, double *K, int64_t ld);
+
 /* Least-squares solve of min ||A x - b|| by blocked Householder QR and back
  * substitution, x = R^-1 (Q^T b)[0:n] (Sec. "Theory", QR route).
  * A is column-major m x (n+1) with ld >= m, m >= n; column n holds b.

@@ -122,6 +122,17 @@ def build_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
     return K
 
 
+def build_local_rows(desc, X, atom_idx, zeta, delta):
+    """Rows of local-property observations: row r is k(d_i, x_m), i = atom_idx[r].
+
+    Sec. "Local Property": a per-atom property is learned directly, a mask
+    selecting the atoms that carry one, so L-hat of such an observation picks
+    one atom's kernel row instead of summing a configuration.
+    """
+    D = np.asarray(desc, dtype=np.float64)[np.asarray(atom_idx, dtype=np.int64)]
+    return poly_kernel(D @ np.asarray(X, dtype=np.float64).T, zeta, delta)
+
+
 def design_matrix(Knm, Kmm, y, sigma, jitter):
     """A = [Sigma^-1/2 L-hat K_NM ; U_MM], b = [Sigma^-1/2 y ; 0].
 

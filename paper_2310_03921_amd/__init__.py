@@ -75,6 +75,7 @@ def lib():
             "gap_build_knm": ([P, P, P, I32, P, I64], S),
             "gap_lstsq": ([P, P, I64, I64, I64, P, P], S),
             "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
+            "gap_build_local_rows": ([P, P, P, P, I64, P, I64], S),
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
@@ -292,6 +293,22 @@ class Gap:
         a, s = atoms.struct(), sparse.struct()
         self._check(lib().gap_build_knm(self._h, ctypes.byref(a), ctypes.byref(s),
                                         PRECISION[precision], _ptr(out), out.shape[1]))
+        return out
+
+    def build_local_rows(self, atoms: Atoms, sparse: Sparse, atom_idx: torch.Tensor,
+                         out: torch.Tensor | None = None, row0: int = 0) -> torch.Tensor:
+        """Local-property rows of the atoms atom_idx (int32, device) written at
+        rows [row0, row0 + n) of the column-major buffer `out` (default: a new
+        n x M buffer)."""
+        n = int(atom_idx.numel())
+        M = sparse.M
+        out = colmajor(n, M, device=sparse.X.device) if out is None else out
+        a, s = atoms.struct(), sparse.struct()
+        idx = atom_idx.to(torch.int32).contiguous()
+        self._check(lib().gap_build_local_rows(
+            self._h, ctypes.byref(a), ctypes.byref(s), _ptr(idx) if n else None, n,
+            ctypes.c_void_p(out.data_ptr() + 8 * row0), out.shape[1]))
+        self._keep_idx = idx
         return out
 
     def lstsq(self, A: torch.Tensor, m: int, n: int):

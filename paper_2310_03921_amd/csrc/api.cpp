@@ -143,7 +143,7 @@ gap_status drain_dev_err(gap_handle* h) {
   if (v & GAP_DEVERR_RANK)
     return fail(h, GAP_E_RANK, "least-squares matrix is rank deficient (zero pivot in R)");
   if (v & GAP_DEVERR_INDEX)
-    return fail(h, GAP_E_INVALID, "index data out of range (pair target or pair_ptr)");
+    return fail(h, GAP_E_INVALID, "index data out of range (pair target, pair_ptr or local-property atom index)");
   if (v & GAP_DEVERR_SYNC)
     return fail(h, GAP_E_HIP, "a grid barrier of the cooperative QR panel kernel timed out");
   return GAP_OK;
@@ -544,6 +544,27 @@ gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n,
     rdiag_minmax[1] = rd[1];
   }
   return s;
+}
+
+gap_status gap_build_local_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                                const int32_t* atom_idx, int64_t n_local, double* K,
+                                int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, false);
+  if (s != GAP_OK) return s;
+  if (n_local < 0 || (n_local > 0 && (!atom_idx || !K)) || ld < n_local)
+    return fail(h, GAP_E_INVALID, "need n_local >= 0, atom_idx and K, ld >= n_local");
+  h->timer.begin(gapk::TM_ENERGY);
+  gapk::local_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->n_atoms, atom_idx, n_local,
+                       sp->X, sp->ld_x, sp->M, sp->D, sp->zeta, sp->delta, K, ld, h->dev_err,
+                       h->stream);
+  h->timer.end(gapk::TM_ENERGY);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
 }
 
 // ------------------------------------------------------------ streamed fit

@@ -59,6 +59,50 @@ __global__ __launch_bounds__(256) void k_kmm(const double* __restrict__ X, int64
   }
 }
 
+// ----------------------------------------------------- local-property rows ----
+// Row r is atom i = idx[r]: K[r][m] = delta^2 (d_i . x_m)^zeta.  Block (column
+// tile, row tile) of 64 x 64; each wave 16 rows (gathered descriptor rows) x
+// 64 columns.  An index outside [0, n_atoms) gives a zero row and raises the
+// index flag.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_local_rows(const TD* __restrict__ desc, int64_t ldd,
+                                                    int64_t n_atoms,
+                                                    const int32_t* __restrict__ idx_list,
+                                                    int64_t n_local, const double* __restrict__ X,
+                                                    int64_t ldx, int64_t M, int64_t D, int zeta,
+                                                    double delta, double* __restrict__ K,
+                                                    int64_t ldk, int* __restrict__ dev_err) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int64_t rowbase = (int64_t)blockIdx.y * 64 + wave * 16;
+  const int64_t row = rowbase + idx;
+  const int64_t atom = row < n_local ? (int64_t)idx_list[row] : -1;
+  const bool ok = atom >= 0 && atom < n_atoms;
+  if (row < n_local && !ok && g == 0 && blockIdx.x == 0) atomicOr(dev_err, GAP_DEVERR_INDEX);
+  FragRowK<TD> fa{desc + (ok ? atom : 0) * ldd, D, ok};
+  FragRowK<double> fb[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = (int64_t)blockIdx.x * 64 + u * 16 + idx;
+    fb[u] = FragRowK<double>{X + (col < M ? col : 0) * ldx, D, col < M};
+  }
+  d4v acc[kNC];
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) acc[u] = zero4();
+  wave_mma<kNC>(fa, fb, D, g, acc);
+  const double d2 = delta * delta;
+#pragma unroll
+  for (int u = 0; u < kNC; ++u) {
+    const int64_t col = (int64_t)blockIdx.x * 64 + u * 16 + idx;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + g + 4 * r;
+      // (the contraction reads a clamped row for an invalid index; the row is zeroed here)
+      const bool rok = __shfl(ok ? 1 : 0, g + 4 * r) != 0;
+      if (rr < n_local && col < M) K[rr + col * ldk] = rok ? d2 * ipow(acc[u][r], zeta) : 0.0;
+    }
+  }
+}
+
 // --------------------------------------------------------- energy rows ----
 // Block (column tile ct, configuration c): the four waves own disjoint 64-column
 // ranges and walk the configuration's atoms 16 at a time.
@@ -684,6 +728,20 @@ void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t
   else
     hipLaunchKernelGGL(k_energy_rows<double>, grid, dim3(256), 0, st, tptr<double>(desc), ldd,
                        cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+}
+
+void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
+                    const int32_t* atom_idx, int64_t n_local, const double* X, int64_t ldx,
+                    int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
+                    int* dev_err, hipStream_t st) {
+  if (n_local <= 0 || M <= 0) return;
+  dim3 grid(cdiv(M, 64), cdiv(n_local, 64));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_local_rows<float>, grid, dim3(256), 0, st, tptr<float>(desc), ldd,
+                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err);
+  else
+    hipLaunchKernelGGL(k_local_rows<double>, grid, dim3(256), 0, st, tptr<double>(desc), ldd,
+                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err);
 }
 
 int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }

@@ -92,6 +92,11 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                 const double* Sx = nullptr, int64_t ldsx = 0);
 int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
+// Local-property rows: K[r][m] = delta^2 (d_{atom_idx[r]} . x_m)^zeta, column-major.
+void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
+                    const int32_t* atom_idx, int64_t n_local, const double* X, int64_t ldx,
+                    int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
+                    int* dev_err, hipStream_t st);
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st);
 // dc_part[rg][m] = -sum_{i in row group rg} S[i][m] (H_i . x_m), column-stationary;

@@ -230,6 +230,28 @@ def check_fold_streamed(orc):
     assert np.linalg.norm(sols[0] - sols[1]) <= 1e-10 * np.linalg.norm(sols[0])
 
 
+def check_local_rows(orc):
+    # Local-property rows of every atom: summed over each configuration they are
+    # the energy rows (L-hat sums the local terms), multiplied by c they are the
+    # predicted local energies, and a brute-force loop gives each entry.
+    w, b, X = tiny_batch()
+    idx = np.arange(b.n_atoms)
+    KL = orc.build_local_rows(b.desc, X, idx, w.zeta, w.delta)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    for c in range(b.n_cfg):
+        s = KL[b.cfg_ptr[c]:b.cfg_ptr[c + 1]].sum(axis=0)
+        assert np.allclose(s, K[c], rtol=1e-13, atol=1e-13 * np.abs(K[c]).max())
+    cc = np.random.default_rng(5).standard_normal(w.M)
+    e, _, _, _ = orc.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, None, X, cc, w.zeta, w.delta)
+    assert np.allclose(KL @ cc, e, rtol=1e-12, atol=1e-12 * np.abs(e).max())
+    sel = np.array([b.n_atoms - 1, 0, 2, 2])
+    KS = orc.build_local_rows(b.desc, X, sel, w.zeta, w.delta)
+    for r, i in enumerate(sel):
+        for m in range(w.M):
+            p = sum(float(b.desc[i][d]) * float(X[m][d]) for d in range(w.D))
+            assert abs(KS[r, m] - w.delta ** 2 * p ** w.zeta) <= 1e-12 * max(1.0, abs(KS[r, m]))
+
+
 def check_full_gpr_identity(orc):
     # energy-only observations, sparse set = every atom, no jitter:
     # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
@@ -344,7 +366,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_energy_rows_bruteforce, check_sparse_self_entry,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
-              check_fold_streamed,
+              check_fold_streamed, check_local_rows,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

@@ -17,6 +17,7 @@ _orig_backward = G.predict_backward
 _orig_pt = G.pair_transpose
 _orig_fold_rows = G.fold_rows
 _orig_augr = G.augmented_r
+_orig_local = G.build_local_rows
 
 
 def knm_sign_flip(*a):
@@ -115,6 +116,17 @@ def augmented_r_no_corner(A, b):
     return T
 
 
+def local_rows_next_atom(desc, X, atom_idx, zeta, delta):
+    n = np.asarray(desc).shape[0]
+    return _orig_local(desc, X, (np.asarray(atom_idx) + 1) % n, zeta, delta)
+
+
+def local_rows_gradient_scale(desc, X, atom_idx, zeta, delta):
+    # the kernel-gradient scale in place of the kernel
+    D = np.asarray(desc, float)[np.asarray(atom_idx, int)]
+    return G.poly_kernel_grad_scale(D @ np.asarray(X, float).T, zeta, delta)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -129,6 +141,8 @@ MUTANTS = [
     ("fold_rows", fold_rows_y_unscaled),
     ("fold_rows", fold_rows_drops_state),
     ("augmented_r", augmented_r_no_corner),
+    ("build_local_rows", local_rows_next_atom),
+    ("build_local_rows", local_rows_gradient_scale),
 ]
 
 
