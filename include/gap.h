@@ -148,6 +148,22 @@ gap_status gap_build_kmm(gap_handle *h, const gap_sparse *sp, double *Kmm, int64
 gap_status gap_build_knm(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
                          gap_precision prec, double *Knm, int64_t ld);
 
+/* Virial rows: the nine components of a configuration's virial stress as
+ * observations (Sec. "Theory": targets are totals of local energies or of
+ * their partial derivatives, virial stresses among them; sigma_virial
+ * regularises them).  The paper gives no formula; the library takes the
+ * strain derivative.  With r_p the displacement r_j(p) - r_i of pair p = (i, k)
+ * (periodic image included) and a homogeneous strain eps acting as
+ * r_p -> (I + eps) r_p,
+ *   W_alpha,beta(c) = - sum_{p in c} r_p,alpha dE/dr_j(p),beta   (= - dE/d eps_beta,alpha)
+ * so row 9 c + 3 alpha + beta, column m of Kv is
+ *   - sum_{p in c} r[p][alpha] delta^2 zeta (d_i . x_m)^(zeta-1) J[p][beta] . x_m.
+ * pair_r [n_pairs][3] FP64 device.  Kv column-major 9 n_cfg x M, ld >= 9 n_cfg
+ * (it may point into a design buffer below other rows, or into a fold
+ * state's block area).  Asynchronous.  FP64 contraction. */
+gap_status gap_build_virial_rows(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                                 const double *pair_r, double *Kv, int64_t ld);
+
 /* Local-property rows (Sec. "Local Property": a per-atom property such as a
  * core-electron binding energy learned directly; a mask marks the atoms that
  * carry one, so L-hat for such an observation selects a single atom):

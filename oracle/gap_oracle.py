@@ -122,6 +122,34 @@ def build_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
     return K
 
 
+def build_virial_rows(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta):
+    """Virial rows: row 9 c + 3 alpha + beta, column m is
+    - sum over the pairs p = (i, k) of configuration c of
+      r_p[alpha] * dk/dr_j(p),beta  with  dk/dr_j,beta = delta^2 zeta p_im^(zeta-1) J[p, beta] . x_m.
+
+    Sec. "Theory": virial stresses are sums of partial derivatives of local
+    energies; the strain form (r_p -> (I + eps) r_p, W = - dE/d eps^T) is the
+    reading taken where the paper gives no formula.
+    """
+    desc = np.asarray(desc, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    jac = np.asarray(jac, dtype=np.float64)
+    r = np.asarray(pair_r, dtype=np.float64)
+    S = poly_kernel_grad_scale(desc @ X.T, zeta, delta)
+    src = pair_sources(pair_ptr)
+    n_cfg = len(cfg_ptr) - 1
+    atom_cfg = np.repeat(np.arange(n_cfg), np.diff(np.asarray(cfg_ptr)))
+    K = np.zeros((9 * n_cfg, X.shape[0]))
+    for p in range(len(src)):
+        i = src[p]
+        G = jac[p] @ X.T                      # [3 (beta), M]
+        c = atom_cfg[i]
+        for a in range(3):
+            for b in range(3):
+                K[9 * c + 3 * a + b] -= r[p, a] * S[i] * G[b]
+    return K
+
+
 def build_local_rows(desc, X, atom_idx, zeta, delta):
     """Rows of local-property observations: row r is k(d_i, x_m), i = atom_idx[r].
 

@@ -76,6 +76,7 @@ def lib():
             "gap_lstsq": ([P, P, I64, I64, I64, P, P], S),
             "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
             "gap_build_local_rows": ([P, P, P, P, I64, P, I64], S),
+            "gap_build_virial_rows": ([P, P, P, P, P, I64], S),
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
@@ -309,6 +310,21 @@ class Gap:
             self._h, ctypes.byref(a), ctypes.byref(s), _ptr(idx) if n else None, n,
             ctypes.c_void_p(out.data_ptr() + 8 * row0), out.shape[1]))
         self._keep_idx = idx
+        return out
+
+    def build_virial_rows(self, atoms: Atoms, sparse: Sparse, pair_r: torch.Tensor,
+                          out: torch.Tensor | None = None, row0: int = 0) -> torch.Tensor:
+        """Virial rows (9 per configuration) written at rows [row0, row0 + 9 n_cfg)
+        of the column-major buffer `out` (default: a new 9 n_cfg x M buffer).
+        pair_r: FP64 [n_pairs, 3] displacement vectors of the pairs."""
+        M, n = sparse.M, 9 * atoms.n_cfg
+        out = colmajor(n, M, device=sparse.X.device) if out is None else out
+        a, s = atoms.struct(), sparse.struct()
+        r = _f64(pair_r)
+        self._check(lib().gap_build_virial_rows(
+            self._h, ctypes.byref(a), ctypes.byref(s), _ptr(r),
+            ctypes.c_void_p(out.data_ptr() + 8 * row0), out.shape[1]))
+        self._keep_r = r
         return out
 
     def lstsq(self, A: torch.Tensor, m: int, n: int):

@@ -567,6 +567,41 @@ gap_status gap_build_local_rows(gap_handle* h, const gap_atoms* a, const gap_spa
   return GAP_OK;
 }
 
+gap_status gap_build_virial_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                                 const double* pair_r, double* Kv, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, true);
+  if (s != GAP_OK) return s;
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D, nc = a->n_cfg;
+  if ((a->n_pairs > 0 && !pair_r) || (nc > 0 && !Kv) || ld < 9 * nc)
+    return fail(h, GAP_E_INVALID, "need pair_r, Kv and ld >= 9 n_cfg");
+  if (nc == 0) return GAP_OK;
+  Layout L;
+  PairWs p;
+  layout_pairs(L, N, a->n_pairs, p);
+  const size_t S = L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1));
+  const size_t ke = L.take(sizeof(double) * nc * M);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  run_pairs(h, a, p, false);  // pair sources (and the index checks)
+  h->timer.begin(gapk::TM_ENERGY);
+  gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, nc, N, sp->X,
+                        sp->ld_x, M, D, sp->zeta, sp->delta, at<double>(h, ke), nc,
+                        at<double>(h, S), ld4(M), h->stream);
+  h->timer.end(gapk::TM_ENERGY);
+  h->timer.begin(gapk::TM_FORCE);
+  gapk::virial_rows_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, sp->X, sp->ld_x, M,
+                        at<double>(h, S), ld4(M), a->cfg_ptr, nc, a->pair_ptr,
+                        at<int32_t>(h, p.src), pair_r, N, a->n_pairs, Kv, ld, h->stream);
+  h->timer.end(gapk::TM_FORCE);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
 // ------------------------------------------------------------ streamed fit
 namespace {
 gap_status check_fold_state(gap_handle* h, const double* T, int64_t ld, int64_t M,

@@ -92,6 +92,12 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                 const double* Sx = nullptr, int64_t ldsx = 0);
 int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
+// Virial rows: K[(9 c + 3 alpha + beta), m] = - sum_{p in c} r[p][alpha] S[src(p)][m] (J[p][beta] . x_m).
+void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
+                     int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* cfg_ptr,
+                     int64_t n_cfg, const int64_t* pair_ptr, const int32_t* pair_src,
+                     const double* pair_r, int64_t n_atoms, int64_t n_pairs, double* K,
+                     int64_t ldk, hipStream_t st);
 // Local-property rows: K[r][m] = delta^2 (d_{atom_idx[r]} . x_m)^zeta, column-major.
 void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
                     const int32_t* atom_idx, int64_t n_local, const double* X, int64_t ldx,

@@ -25,6 +25,8 @@ regenerated alone, which is what sampled parity checks at full size rely on):
 * hidden coefficients c* ~ N(0, 1), stream [seed, 3].
 * observation noise, stream [seed, 4, c]: energy ~ N(0, sigma_E^2 * n_c),
   forces ~ N(0, sigma_F^2) per component.
+* pair displacement vectors (virial rows only), stream [seed, 5, c]: uniform
+  in a ball of radius 5.
 """
 from __future__ import annotations
 
@@ -219,6 +221,24 @@ def noise(w: Workload, cfg_ids: np.ndarray, counts: np.ndarray) -> np.ndarray:
         e[t] = rng.normal(0.0, w.sigma_e * np.sqrt(float(n)))
         f.append(rng.normal(0.0, w.sigma_f, size=3 * int(n)))
     return np.concatenate([e] + f)
+
+
+def pair_vectors(w: Workload, batch: Batch, r_cut: float = 5.0) -> np.ndarray:
+    """Displacement r_j - r_i of every pair (i, k), FP64 [n_pairs, 3].
+
+    Stream [seed, 5, c] per configuration: directions uniform on the sphere,
+    lengths r_cut * U^(1/3) (uniform in the cutoff ball).  A stand-in for the
+    periodic-image vectors of a real neighbour list; only virial rows use it.
+    """
+    out = np.empty((batch.n_pairs, 3))
+    for t, c in enumerate(batch.cfg_ids):
+        a0, a1 = int(batch.cfg_ptr[t]), int(batch.cfg_ptr[t + 1])
+        p0, p1 = int(batch.pair_ptr[a0]), int(batch.pair_ptr[a1])
+        rng = np.random.default_rng([w.seed, 5, int(c)])
+        v = rng.standard_normal((p1 - p0, 3))
+        v /= np.maximum(np.linalg.norm(v, axis=1, keepdims=True), 1e-300)
+        out[p0:p1] = v * (r_cut * rng.random((p1 - p0, 1)) ** (1.0 / 3.0))
+    return out
 
 
 def predict_coefficients(w: Workload) -> np.ndarray:

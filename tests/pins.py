@@ -136,6 +136,42 @@ def check_force_rows_central_fd(orc, h=1e-4):
                     assert abs(K[b.n_cfg + 3 * j + a, m] - ref) <= 1e-7 * scale
 
 
+def strained_energy(w, b, X, r, cfg, m, eps):
+    """E_c^m under the homogeneous strain eps (complex 3x3), r_p -> (I + eps) r_p:
+    delta^2 sum_{i in c} ((d_i + sum_{p of i} J_p . (eps r_p)) . x_m)^zeta, in plain loops."""
+    a0, a1 = int(b.cfg_ptr[cfg]), int(b.cfg_ptr[cfg + 1])
+    E = 0j
+    for i in range(a0, a1):
+        d = b.desc[i].astype(np.complex128)
+        for p in range(int(b.pair_ptr[i]), int(b.pair_ptr[i + 1])):
+            dr = eps @ r[p]
+            for a in range(3):
+                d = d + b.jac[p, a].astype(np.float64) * dr[a]
+        s = 0j
+        for k in range(w.D):
+            s += d[k] * X[m, k]
+        E += s ** w.zeta
+    return w.delta ** 2 * E
+
+
+def check_virial_rows_strain(orc, h=1e-30):
+    # W_ab = - dE / d eps_ba by complex step of the strained, linearised energy,
+    # for every configuration, component and sparse point (virial reading)
+    w, b, X = tiny_batch()
+    r = synth.pair_vectors(w, b)
+    K = orc.build_virial_rows(b.cfg_ptr, b.desc, b.pair_ptr, b.jac, r, X, w.zeta, w.delta)
+    assert K.shape == (9 * b.n_cfg, w.M)
+    for c in range(b.n_cfg):
+        for a in range(3):
+            for bb in range(3):
+                eps = np.zeros((3, 3), dtype=np.complex128)
+                eps[bb, a] = 1j * h
+                for m in range(w.M):
+                    ref = -strained_energy(w, b, X, r, c, m, eps).imag / h
+                    got = K[9 * c + 3 * a + bb, m]
+                    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (c, a, bb, m, got, ref)
+
+
 def permuted_batch(b, rng):
     """Relabel atoms inside each configuration; pairs follow their source."""
     perm = np.empty(b.n_atoms, dtype=np.int64)          # new index of old atom
@@ -366,7 +402,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_energy_rows_bruteforce, check_sparse_self_entry,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
-              check_fold_streamed, check_local_rows,
+              check_fold_streamed, check_local_rows, check_virial_rows_strain,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

@@ -18,6 +18,7 @@ _orig_pt = G.pair_transpose
 _orig_fold_rows = G.fold_rows
 _orig_augr = G.augmented_r
 _orig_local = G.build_local_rows
+_orig_virial = G.build_virial_rows
 
 
 def knm_sign_flip(*a):
@@ -127,6 +128,16 @@ def local_rows_gradient_scale(desc, X, atom_idx, zeta, delta):
     return G.poly_kernel_grad_scale(D @ np.asarray(X, float).T, zeta, delta)
 
 
+def virial_transposed(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta):
+    K = _orig_virial(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta)
+    n = K.shape[0] // 9
+    return K.reshape(n, 3, 3, -1).transpose(0, 2, 1, 3).reshape(K.shape)
+
+
+def virial_sign_flip(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta):
+    return -_orig_virial(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -143,6 +154,8 @@ MUTANTS = [
     ("augmented_r", augmented_r_no_corner),
     ("build_local_rows", local_rows_next_atom),
     ("build_local_rows", local_rows_gradient_scale),
+    ("build_virial_rows", virial_transposed),
+    ("build_virial_rows", virial_sign_flip),
 ]
 
 
