@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--refine-steps", type=int, default=3)
+    ap.add_argument("--no-virial", action="store_true", help="skip timing the virial rows")
     ap.add_argument("--stream-blocks", type=int, default=4,
                     help="configuration groups of the streamed-fit leg (0: skip it)")
     args = ap.parse_args()
@@ -294,6 +295,31 @@ def main():
             f"state {streamed['state_bytes'] / 1e9:.2f} GB vs A {streamed['design_bytes_one_shot'] / 1e9:.2f} GB, "
             f"c rel vs one-shot {streamed['c_rel_vs_one_shot']:.2e}")
 
+    virial = None
+    if not args.no_virial:
+        # nine virial rows per configuration, same pairs and Jacobians
+        pr_ = torch.tensor(synth.pair_vectors(w, b), device="cuda")
+        Kv = gapx.colmajor(9 * b.n_cfg, M)
+        gap.build_virial_rows(atoms, sp, pr_, out=Kv)
+        torch.cuda.synchronize()
+        gap.timing(True)
+        gap.timing_read(reset=True)
+        tv = []
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            gap.build_virial_rows(atoms, sp, pr_, out=Kv)
+            gap.sync()
+            tv.append(time.perf_counter() - ts)
+        vst = gap.timing_read(reset=True)
+        gap.timing(False)
+        vk = vst["force_rows"][0] / args.steps
+        virial = {"rows": 9 * b.n_cfg, "call_s": float(np.mean(tv)),
+                  "kernel_ms": vk, "kernel_tflops": force_flops / (vk * 1e-3) / 1e12,
+                  "stage_ms": {k: round(v[0] / args.steps, 3) for k, v in vst.items() if v[1] > 0}}
+        log(f"virial rows ({9 * b.n_cfg}): call {virial['call_s'] * 1e3:.1f} ms, kernel {vk:.1f} ms "
+            f"({virial['kernel_tflops']:.1f} TFLOP/s)")
+        del Kv, pr_
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on a sample")
@@ -327,6 +353,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed_bf16x3": mixed,
         "streamed_fp64": streamed,
+        "virial_rows_fp64": virial,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
     }
     print(json.dumps(out), flush=True)

@@ -11,9 +11,12 @@
 // with S = delta^2 zeta (d_i . x_m)^(zeta-1) of the pair's source atom.
 //
 // Work decomposition: a block owns one configuration and 64 sparse-point
-// columns; its four waves take the configuration's pairs 16 at a time (wave w
-// the chunks w, w + 4, ...), contract the three Jacobian rows of each pair
-// with the columns' x_m on the FP64 matrix core, and accumulate the nine
+// columns; its eight waves are four pair streams x two 32-column halves.  A
+// stream takes the configuration's pairs 16 at a time (stream s the chunks s,
+// s + 4, ...), contracts the three Jacobian rows of each pair with its columns'
+// x_m on the FP64 matrix core (whole 16-deep steps load unconditionally, the
+// next step's fragments ahead of the current step's matrix work; one guarded
+// step covers a D that is not a multiple of 16), and accumulates the nine
 // weighted sums in registers.  One cross-lane and cross-wave reduction in a
 // fixed order ends the block, so results do not depend on scheduling.
 #include "launch.h"
@@ -23,58 +26,86 @@ namespace gapk {
 
 namespace {
 
+constexpr int kVU = 2;  // 16-column tiles per wave; a wave pair covers the block's 64 columns
 template <typename TJ>
-__global__ __launch_bounds__(256) void k_virial_rows(
+__global__ __launch_bounds__(512) void k_virial_rows(
     const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
     int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
     const int64_t* __restrict__ cfg_ptr, const int64_t* __restrict__ pair_ptr,
     const int32_t* __restrict__ pair_src, const double* __restrict__ pair_r, int64_t n_atoms,
-    int64_t n_pairs, double* __restrict__ K, int64_t ldk) {
+    int64_t n_pairs, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_cfg) {
   __shared__ double red[4][9][64];
-  const int64_t c = blockIdx.y;
-  const int64_t colbase = (int64_t)blockIdx.x * 64;
+  int64_t c, ct;
+  if (!xcd_group_tile(n_cfg, n_ct, c, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int stream = wave >> 1;  // pair chunks stream, stream + 4, ...
+  const int64_t colbase = ct * 64 + (wave & 1) * 16 * kVU;
   const int64_t a0 = min(max(cfg_ptr[c], (int64_t)0), n_atoms);
   const int64_t a1 = min(max(cfg_ptr[c + 1], a0), n_atoms);
   const int64_t p_lo = min(max(pair_ptr[a0], (int64_t)0), n_pairs);
   const int64_t p_hi = min(max(pair_ptr[a1], p_lo), n_pairs);
 
-  FragRowK<double> fb[4];
-  int64_t colr[4];
+  FragRowK<double> fb[kVU];
+  const double* xr[kVU];
+  int64_t colr[kVU];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < kVU; ++u) {
     colr[u] = colbase + u * 16 + idx;
     fb[u] = FragRowK<double>{X + (colr[u] < M ? colr[u] : 0) * ldx, D, colr[u] < M};
+    xr[u] = X + min(colr[u], M - 1) * ldx + 4 * g;  // columns past M are never stored
   }
-  double acc[9][4];
+  double acc[9][kVU];
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
+    for (int u = 0; u < kVU; ++u) acc[q][u] = 0.0;
+  const int64_t kfull = D & ~int64_t(15);  // whole 16-deep steps
 
-  for (int64_t p0 = p_lo + 16 * wave; p0 < p_hi; p0 += 64) {
-    const int64_t p = p0 + idx;
-    const bool pv = p < p_hi;
-    const TJ* jr = jac + (pv ? p : 0) * 3 * ldj;
-    const FragRowK<TJ> fa[3] = {FragRowK<TJ>{jr, D, pv}, FragRowK<TJ>{jr + ldj, D, pv},
-                                FragRowK<TJ>{jr + 2 * ldj, D, pv}};
-    d4v G[3][4];
+  for (int64_t p0 = p_lo + 16 * stream; p0 < p_hi; p0 += 64) {
+    // pairs past the configuration read its last pair's rows (never accumulated)
+    const int64_t p = min(p0 + idx, p_hi - 1);
+    const TJ* jr = jac + p * 3 * ldj + 4 * g;
+    d4v G[3][kVU];
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) G[b][u] = zero4();
-    for (int64_t k0 = 0; k0 < D; k0 += 16) {
-      double a[3][4], bx[4][4];
+      for (int u = 0; u < kVU; ++u) G[b][u] = zero4();
+    // whole 16-deep steps with unconditional loads, the next step's fragments
+    // loaded before this step's matrix work; then one guarded tail step
+    double a[2][3][4], bx[2][kVU][4];
+    auto load = [&](int64_t k0, int st) {
 #pragma unroll
-      for (int b = 0; b < 3; ++b) fa[b].frag(k0, g, a[b]);
+      for (int b = 0; b < 3; ++b) load4u(jr + b * ldj + k0, a[st][b]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) fb[u].frag(k0, g, bx[u]);
+      for (int u = 0; u < kVU; ++u) load4u(xr[u] + k0, bx[st][u]);
+    };
+    auto step = [&](int st) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) G[b][u] = mfma_f64(a[b][s], bx[u][s], G[b][u]);
+          for (int u = 0; u < kVU; ++u) G[b][u] = mfma_f64(a[st][b][s4], bx[st][u][s4], G[b][u]);
+    };
+    int64_t k0 = 0;
+    if (kfull > 0) load(0, 0);
+    for (; k0 + 32 <= kfull; k0 += 32) {
+      load(k0 + 16, 1);
+      step(0);
+      if (k0 + 32 < kfull) load(k0 + 32, 0);
+      step(1);
+    }
+    if (k0 < kfull) {  // an odd number of whole steps: the last one is loaded in set 0
+      step(0);
+      k0 += 16;
+    }
+    if (k0 < D) {
+      const TJ* jt = jac + p * 3 * ldj;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) FragRowK<TJ>{jt + b * ldj, D, true}.frag(k0, g, a[0][b]);
+#pragma unroll
+      for (int u = 0; u < kVU; ++u) fb[u].frag(k0, g, bx[0][u]);
+      step(0);
     }
     // C layout: lane holds pairs p0 + g + 4 r of each tile's column idx
 #pragma unroll
@@ -85,7 +116,7 @@ __global__ __launch_bounds__(256) void k_virial_rows(
       if (src < 0 || src >= n_atoms) continue;
       const double rv[3] = {pair_r[3 * pr], pair_r[3 * pr + 1], pair_r[3 * pr + 2]};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kVU; ++u) {
         const double sv = colr[u] < M ? S[(int64_t)src * ldS + colr[u]] : 0.0;
 #pragma unroll
         for (int al = 0; al < 3; ++al)
@@ -94,11 +125,11 @@ __global__ __launch_bounds__(256) void k_virial_rows(
       }
     }
   }
-  // sum the four lane groups (pair rows), then the waves
+  // sum the four lane groups (pair rows), then the four pair streams
 #pragma unroll
   for (int q = 0; q < 9; ++q)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kVU; ++u) {
       acc[q][u] += __shfl_xor(acc[q][u], 16);
       acc[q][u] += __shfl_xor(acc[q][u], 32);
     }
@@ -106,11 +137,11 @@ __global__ __launch_bounds__(256) void k_virial_rows(
 #pragma unroll
     for (int q = 0; q < 9; ++q)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) red[wave][q][u * 16 + idx] = acc[q][u];
+      for (int u = 0; u < kVU; ++u) red[stream][q][(wave & 1) * 16 * kVU + u * 16 + idx] = acc[q][u];
   }
   __syncthreads();
   if (threadIdx.x < 64) {
-    const int64_t col = colbase + threadIdx.x;
+    const int64_t col = ct * 64 + threadIdx.x;
     if (col < M) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -122,8 +153,6 @@ __global__ __launch_bounds__(256) void k_virial_rows(
   }
 }
 
-inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
-
 }  // namespace
 
 void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
@@ -132,15 +161,19 @@ void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, cons
                      const double* pair_r, int64_t n_atoms, int64_t n_pairs, double* K,
                      int64_t ldk, hipStream_t st) {
   if (n_cfg <= 0 || M <= 0) return;
-  dim3 grid(cdiv(M, 64), (unsigned)n_cfg);
+  // the column tiles of a configuration stay on one XCD (its pairs' Jacobian
+  // rows are then read from HBM once, into that XCD's L2); configurations are
+  // dealt to the XCDs in turn
+  const int64_t n_ct = (M + 63) / 64;
+  dim3 grid(xcd_group_tile_blocks(n_cfg, n_ct));
   if (jac_f32)
-    hipLaunchKernelGGL(k_virial_rows<float>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL(k_virial_rows<float>, grid, dim3(512), 0, st,
                        reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, cfg_ptr,
-                       pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk);
+                       pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk, n_ct, n_cfg);
   else
-    hipLaunchKernelGGL(k_virial_rows<double>, grid, dim3(256), 0, st,
+    hipLaunchKernelGGL(k_virial_rows<double>, grid, dim3(512), 0, st,
                        reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, cfg_ptr,
-                       pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk);
+                       pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk, n_ct, n_cfg);
 }
 
 }  // namespace gapk
