@@ -116,6 +116,55 @@ def test_fit_fullsize_fp64_optimal_and_mixed_agrees(fit_case):
     assert d <= TOL
 
 
+def test_fold_fullsize_matches_one_shot_fit(fit_case):
+    # four configuration groups built into the fold state (device views of the
+    # resident batch), as the benchmark's streamed leg does
+    gx, w, b, X, gap = (fit_case[k] for k in ("gx", "w", "b", "X", "gap"))
+    atoms, sp, K = fit_case["atoms"], fit_case["sp"], fit_case["K"]
+    n_rows, M, nc = b.n_rows, w.M, b.n_cfg
+    Kmm = torch.as_tensor(oracle.build_kmm(X, w.zeta, w.delta), device="cuda")
+    sigma = torch.as_tensor(synth.sigma_rows(w, b.counts), device="cuda")
+    y = torch.as_tensor(np.random.default_rng([w.seed, 8]).standard_normal(n_rows), device="cuda")
+    A = K.clone()
+    c_fit, _ = gap.fit(A, n_rows, Kmm, y, sigma, w.jitter, sp)
+    del A
+    bounds = np.linspace(0, nc, 5).round().astype(int)
+    groups = []
+    for c0, c1 in zip(bounds[:-1], bounds[1:]):
+        a0, a1 = int(b.cfg_ptr[c0]), int(b.cfg_ptr[c1])
+        rows = torch.cat([torch.arange(int(c0), int(c1)), nc + torch.arange(3 * a0, 3 * a1)]).cuda()
+        groups.append((atoms.configs(int(c0), int(c1)), rows))
+    T = gap.fold_buffer(M, max(len(r) for _, r in groups))
+    gap.fold_init(T, M, Kmm, w.jitter)
+    for sub, rows in groups:
+        gap.build_knm_block(sub, sp, T)
+        gap.fold_rows(T, M, sub.n_rows, y[rows].contiguous(), sigma[rows].contiguous())
+    c, res, _ = gap.fold_solve(T, M)
+    d = float((c - c_fit).norm() / c_fit.norm())
+    eta = _optimality(K, n_rows, Kmm.cpu().numpy(), y.cpu().numpy(), sigma.cpu().numpy(),
+                      w.jitter, c)
+    print(f"[fullsize] streamed fit (4 groups) vs one-shot c: rel {d:.2e}; "
+          f"scaled normal-equation residual {eta:.2e}")
+    assert d <= TOL and eta <= OPT_TOL
+
+
+def test_virial_rows_fullsize_sampled_configurations(fit_case):
+    w, b, X, gap = (fit_case[k] for k in ("w", "b", "X", "gap"))
+    atoms, sp = fit_case["atoms"], fit_case["sp"]
+    r = torch.as_tensor(synth.pair_vectors(w, b), device="cuda")
+    Kv = gap.build_virial_rows(atoms, sp, r)
+    gap.sync()
+    for c in sampled_configs(b.counts):
+        sb = synth.generate(w, cfg_ids=[c])
+        ref = oracle.build_virial_rows(sb.cfg_ptr, sb.desc, sb.pair_ptr, sb.jac,
+                                       synth.pair_vectors(w, sb), X, w.zeta, w.delta)
+        got = Kv[:w.M, 9 * c:9 * c + 9].T.cpu().numpy()
+        e = rel_err(got, ref)
+        print(f"[fullsize] virial rows of configuration {c}: rel {e:.2e}")
+        assert e <= TOL, c
+    del Kv
+
+
 # --------------------------------------------------------------- prediction --
 @pytest.fixture(scope="module")
 def predict_case():
