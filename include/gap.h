@@ -205,6 +205,24 @@ gap_status gap_fit(gap_handle *h, double *A, int64_t ld, int64_t n_rows, const d
                    const double *y, const double *sigma, double jitter, const gap_atoms *train,
                    const gap_sparse *sp, int refine_steps, double *c, gap_fit_info *info);
 
+/* Predictive variance of the local energies (Sec. "Regression": gp_predict
+ * also returns the variances the GPR predicts).  The paper gives no formula;
+ * the library takes the sparse (projected-process) GP form that goes with the
+ * coefficients of eq. GP_L:
+ *   var_i = k(d_i, d_i) - k_i^T (K_MM + jitter I)^-1 k_i
+ *           + k_i^T (K_MM + jitter I + K_MN Sigma^-1 K_NM)^-1 k_i,
+ *   k_i[m] = delta^2 (d_i . x_m)^zeta,
+ * evaluated as ||U^-T k_i||^2 and ||R^-T k_i||^2 with U the upper Cholesky factor
+ * of K_MM + jitter I and R the fit's triangular factor (R^T R = A^T A): the
+ * upper triangle of the leading M x M block of A after gap_fit, or of a fold
+ * state T (col-major, ld ldr >= M; entries below the diagonal are not read).
+ * Kmm [M x M] col-major (ld = M), the same jitter as the fit.  var [n_atoms]
+ * device FP64.  Only the descriptors of `atoms` are read.  Synchronous;
+ * GAP_E_NOT_PD if the Cholesky fails, GAP_E_RANK if R has a zero pivot. */
+gap_status gap_predict_variance(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                                const double *Kmm, double jitter, const double *R, int64_t ldr,
+                                double *var);
+
 /* Streamed fit: the least-squares problem of gap_fit folded one block of
  * observation rows at a time, so that A is never held whole.  Sec. "Theory"
  * gives the QR route; Sec. "Program structure" splits the configurations, and

@@ -304,6 +304,27 @@ def predict(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta):
     return e_atom, e_cfg, g, forces
 
 
+def predict_variance(desc, X, Kmm, jitter, R, zeta, delta):
+    """Predictive variance of the local energies in the sparse GP form of eq. GP_L:
+    var_i = k(d_i, d_i) - k_i^T (K_MM + jitter I)^-1 k_i + k_i^T (A^T A)^-1 k_i,
+    with A^T A = K_MM + jitter I + K_MN Sigma^-1 K_NM = R^T R, evaluated as
+    ||U^-T k_i||^2 and ||R^-T k_i||^2 (U^T U = K_MM + jitter I).
+
+    Sec. "Regression": gp_predict returns the variances the GPR predicts; the
+    paper gives no formula, the projected-process form is the reading taken.
+    """
+    desc = np.asarray(desc, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    M = X.shape[0]
+    Kst = poly_kernel(desc @ X.T, zeta, delta)
+    kii = poly_kernel(np.einsum("ij,ij->i", desc, desc), zeta, delta)
+    U = sla.cholesky(np.asarray(Kmm, dtype=np.float64) + jitter * np.eye(M), lower=False)
+    Z1 = sla.solve_triangular(U, Kst.T, trans="T", lower=False)
+    Z2 = sla.solve_triangular(np.triu(np.asarray(R, dtype=np.float64)[:M, :M]), Kst.T, trans="T",
+                              lower=False)
+    return kii - np.sum(Z1 * Z1, axis=0) + np.sum(Z2 * Z2, axis=0)
+
+
 def predict_backward(desc, X, c, g_e, zeta, delta):
     """Gradients of L = sum_i g_e[i] eps_i with respect to d_i, c and x_m.
 

@@ -77,6 +77,7 @@ def lib():
             "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
             "gap_build_local_rows": ([P, P, P, P, I64, P, I64], S),
             "gap_build_virial_rows": ([P, P, P, P, P, I64], S),
+            "gap_predict_variance": ([P, P, P, P, ctypes.c_double, P, I64, P], S),
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
@@ -404,6 +405,18 @@ class Gap:
                                       PRECISION[precision], _ptr(out["e_atom"]),
                                       _ptr(out["e_cfg"]), _ptr(out["dEdd"]), _ptr(out["forces"])))
         return out
+
+    def predict_variance(self, atoms: Atoms, sparse: Sparse, Kmm: torch.Tensor, jitter: float,
+                         R: torch.Tensor) -> torch.Tensor:
+        """Predictive variance of each atom's local energy.  R: the column-major
+        buffer whose leading M x M upper triangle is the fit's triangular factor
+        (A after gap.fit, or a fold state)."""
+        var = torch.empty(atoms.n_atoms, dtype=torch.float64, device=sparse.X.device)
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_predict_variance(self._h, ctypes.byref(a), ctypes.byref(s),
+                                               _ptr(_f64(Kmm)), float(jitter), _ptr(R),
+                                               R.shape[1], _ptr(var)))
+        return var
 
     def predict_backward(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, g_e: torch.Tensor,
                          precision: str = "fp64", d_desc=True, d_c=True, d_X=True):

@@ -602,6 +602,55 @@ gap_status gap_build_virial_rows(gap_handle* h, const gap_atoms* a, const gap_sp
   return GAP_OK;
 }
 
+gap_status gap_predict_variance(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                                const double* Kmm, double jitter, const double* R, int64_t ldr,
+                                double* var) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, false);
+  if (s != GAP_OK) return s;
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  if (!Kmm || !R || ldr < M || (N > 0 && !var))
+    return fail(h, GAP_E_INVALID, "need Kmm, R with ldr >= M, and var");
+  if (!(jitter >= 0.0) || !std::isfinite(jitter)) return fail(h, GAP_E_INVALID, "bad jitter");
+  if (M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
+  if (N == 0) return GAP_OK;
+  const int64_t ldm = ld4(M);
+  Layout L;
+  const size_t Lw = L.take(sizeof(double) * M * M);
+  const size_t Ub = L.take(sizeof(double) * M * (M + 1));
+  const size_t Yu = L.take(sizeof(double) * M * ldm);
+  const size_t Yr = L.take(sizeof(double) * M * ldm);
+  const size_t Ks = L.take(sizeof(double) * N * ldm);
+  const size_t Zb = L.take(sizeof(double) * N * ldm);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  h->timer.begin(gapk::TM_PREDICT);
+  // U (K_MM + jitter I = U^T U) and the inverses of U and R
+  gapk::cholesky_lower(at<double>(h, Lw), M, M, jitter, Kmm, M, h->dev_err, h->stream);
+  gapk::stack_u(at<double>(h, Ub), M, 0, M, at<double>(h, Lw), M, h->stream);
+  gapk::trinv_upper(at<double>(h, Ub), M, M, at<double>(h, Yu), ldm, h->dev_err, h->stream);
+  gapk::trinv_upper(R, ldr, M, at<double>(h, Yr), ldm, h->dev_err, h->stream);
+  // k_i rows, then var_i = k_ii - ||k_i^T U^-1||^2 + ||k_i^T R^-1||^2
+  gapk::local_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, N, nullptr, N, sp->X, sp->ld_x, M,
+                       D, sp->zeta, sp->delta, at<double>(h, Ks), ldm, h->dev_err, h->stream,
+                       true);
+  gapk::gemm_wx_f64(at<double>(h, Ks), ldm, N, M, at<double>(h, Yu), ldm, M, at<double>(h, Zb),
+                    ldm, h->stream);
+  gapk::var_rows(at<double>(h, Zb), ldm, N, M, -1.0, a->desc, f32(a->desc_dt), a->ld_desc, D,
+                 sp->zeta, sp->delta, true, var, h->stream);
+  gapk::gemm_wx_f64(at<double>(h, Ks), ldm, N, M, at<double>(h, Yr), ldm, M, at<double>(h, Zb),
+                    ldm, h->stream);
+  gapk::var_rows(at<double>(h, Zb), ldm, N, M, 1.0, a->desc, f32(a->desc_dt), a->ld_desc, D,
+                 sp->zeta, sp->delta, false, var, h->stream);
+  h->timer.end(gapk::TM_PREDICT);
+  HIP_TRY(h, hipGetLastError());
+  return drain_dev_err(h);
+}
+
 // ------------------------------------------------------------ streamed fit
 namespace {
 gap_status check_fold_state(gap_handle* h, const double* T, int64_t ld, int64_t M,

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_kmm(const double* __restrict__ X, int64
 }
 
 // ----------------------------------------------------- local-property rows ----
-// Row r is atom i = idx[r]: K[r][m] = delta^2 (d_i . x_m)^zeta.  Block (column
+// Row r is atom i = idx[r] (i = r without an index list): K[r][m] = delta^2 (d_i . x_m)^zeta.  Block (column
 // tile, row tile) of 64 x 64; each wave 16 rows (gathered descriptor rows) x
 // 64 columns.  An index outside [0, n_atoms) gives a zero row and raises the
 // index flag.
@@ -71,11 +71,12 @@ __global__ __launch_bounds__(256) void k_local_rows(const TD* __restrict__ desc,
                                                     int64_t n_local, const double* __restrict__ X,
                                                     int64_t ldx, int64_t M, int64_t D, int zeta,
                                                     double delta, double* __restrict__ K,
-                                                    int64_t ldk, int* __restrict__ dev_err) {
+                                                    int64_t ldk, int* __restrict__ dev_err,
+                                                    int row_major) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t rowbase = (int64_t)blockIdx.y * 64 + wave * 16;
   const int64_t row = rowbase + idx;
-  const int64_t atom = row < n_local ? (int64_t)idx_list[row] : -1;
+  const int64_t atom = row < n_local ? (idx_list ? (int64_t)idx_list[row] : row) : -1;
   const bool ok = atom >= 0 && atom < n_atoms;
   if (row < n_local && !ok && g == 0 && blockIdx.x == 0) atomicOr(dev_err, GAP_DEVERR_INDEX);
   FragRowK<TD> fa{desc + (ok ? atom : 0) * ldd, D, ok};
@@ -98,7 +99,12 @@ __global__ __launch_bounds__(256) void k_local_rows(const TD* __restrict__ desc,
       const int64_t rr = rowbase + g + 4 * r;
       // (the contraction reads a clamped row for an invalid index; the row is zeroed here)
       const bool rok = __shfl(ok ? 1 : 0, g + 4 * r) != 0;
-      if (rr < n_local && col < M) K[rr + col * ldk] = rok ? d2 * ipow(acc[u][r], zeta) : 0.0;
+      const double v = (rok && col < M) ? d2 * ipow(acc[u][r], zeta) : 0.0;
+      if (row_major) {  // [n_local][ldk], row padding (columns M .. ldk - 1) written as zero
+        if (rr < n_local && col < ldk) K[rr * ldk + col] = v;
+      } else if (rr < n_local && col < M) {
+        K[rr + col * ldk] = v;
+      }
     }
   }
 }
@@ -733,15 +739,17 @@ void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t
 void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
                     const int32_t* atom_idx, int64_t n_local, const double* X, int64_t ldx,
                     int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                    int* dev_err, hipStream_t st) {
+                    int* dev_err, hipStream_t st, bool row_major) {
   if (n_local <= 0 || M <= 0) return;
-  dim3 grid(cdiv(M, 64), cdiv(n_local, 64));
+  dim3 grid(cdiv(row_major ? ldk : M, 64), cdiv(n_local, 64));
   if (desc_f32)
     hipLaunchKernelGGL(k_local_rows<float>, grid, dim3(256), 0, st, tptr<float>(desc), ldd,
-                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err);
+                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err,
+                       row_major ? 1 : 0);
   else
     hipLaunchKernelGGL(k_local_rows<double>, grid, dim3(256), 0, st, tptr<double>(desc), ldd,
-                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err);
+                       n_atoms, atom_idx, n_local, X, ldx, M, D, zeta, delta, K, ldk, dev_err,
+                       row_major ? 1 : 0);
 }
 
 int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }

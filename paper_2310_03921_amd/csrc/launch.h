@@ -98,11 +98,12 @@ void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, cons
                      int64_t n_cfg, const int64_t* pair_ptr, const int32_t* pair_src,
                      const double* pair_r, int64_t n_atoms, int64_t n_pairs, double* K,
                      int64_t ldk, hipStream_t st);
-// Local-property rows: K[r][m] = delta^2 (d_{atom_idx[r]} . x_m)^zeta, column-major.
+// Local-property rows: K[r][m] = delta^2 (d_{atom_idx[r]} . x_m)^zeta (atom_idx NULL:
+// atom r), column-major, or row-major [n_local][ldk] with zero row padding.
 void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
                     const int32_t* atom_idx, int64_t n_local, const double* X, int64_t ldx,
                     int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                    int* dev_err, hipStream_t st);
+                    int* dev_err, hipStream_t st, bool row_major = false);
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st);
 // dc_part[rg][m] = -sum_{i in row group rg} S[i][m] (H_i . x_m), column-stationary;
@@ -239,6 +240,14 @@ void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, doub
 void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st);
 void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st);
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st);
+// Y = R^-1 (R upper n x n col-major) as a row-major Y[i * ldy + c], zero below
+// the diagonal; one workgroup per column.
+void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy, int* dev_err,
+                 hipStream_t st);
+// var[i] (+)= sign * ||Z[i][0:m]||^2; with init, var[i] = delta^2 (d_i . d_i)^zeta + sign * ...
+void var_rows(const double* Z, int64_t ldz, int64_t n, int64_t m, double sign, const void* desc,
+              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, bool init,
+              double* var, hipStream_t st);
 // Streamed-fit state: clear rows (col, M] of columns [0, M) of T (and T[M][M]
 // when zero_corner).
 void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st);

@@ -1751,13 +1751,9 @@ __global__ __launch_bounds__(512) void k_qr_upd5(double* __restrict__ A, int64_t
 // off-diagonal part is a GEMV over all 16 waves.  x lives in LDS (n doubles).
 // A zero or non-finite diagonal entry sets GAP_DEVERR_RANK (if dev_err).
 template <bool TRANS>
-__global__ __launch_bounds__(1024) void k_trsv_blk(const double* __restrict__ R, int64_t ld,
-                                                   int64_t n, const double* z, double* x,
-                                                   int* dev_err) {
-  extern __shared__ double xs[];
-  __shared__ double T[64][65];
+GAP_DEV void trsv_blk_lds(const double* __restrict__ R, int64_t ld, int64_t n, double* xs,
+                          double (&T)[64][65], int* dev_err) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int64_t i = tid; i < n; i += 1024) xs[i] = z[i];
   const int64_t nb = (n + 63) / 64;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t blk = TRANS ? b : nb - 1 - b;
@@ -1818,7 +1814,64 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(const double* __restrict__ R,
     }
   }
   __syncthreads();
-  for (int64_t i = tid; i < n; i += 1024) x[i] = xs[i];
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(1024) void k_trsv_blk(const double* __restrict__ R, int64_t ld,
+                                                   int64_t n, const double* z, double* x,
+                                                   int* dev_err) {
+  extern __shared__ double xs[];
+  __shared__ double T[64][65];
+  for (int64_t i = threadIdx.x; i < n; i += 1024) xs[i] = z[i];
+  trsv_blk_lds<TRANS>(R, ld, n, xs, T, dev_err);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) x[i] = xs[i];
+}
+
+// Inverse of an upper-triangular R (col-major, ld), one column per workgroup:
+// block c solves R y = e_c, which only involves the leading (c+1) x (c+1)
+// block, and writes y as row-major Y (Y[i * ldy + c] = (R^-1)[i][c], zero
+// below the diagonal).
+__global__ __launch_bounds__(1024) void k_trinv_upper(const double* __restrict__ R, int64_t ld,
+                                                      int64_t n, double* __restrict__ Y,
+                                                      int64_t ldy, int* dev_err) {
+  extern __shared__ double xs[];
+  __shared__ double T[64][65];
+  const int64_t c = blockIdx.x;
+  for (int64_t i = threadIdx.x; i <= c; i += 1024) xs[i] = (i == c) ? 1.0 : 0.0;
+  trsv_blk_lds<false>(R, ld, c + 1, xs, T, dev_err);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) Y[i * ldy + c] = (i <= c) ? xs[i] : 0.0;
+}
+
+// var[i] += sign * sum_j Z[i][j]^2 (row-major Z, one wave per row); with
+// init, var[i] starts at delta^2 (d_i . d_i)^zeta instead.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_var_rows(const double* __restrict__ Z, int64_t ldz,
+                                                  int64_t n, int64_t m, double sign,
+                                                  const TD* __restrict__ desc, int64_t ldd,
+                                                  int64_t D, int zeta, double delta, int init,
+                                                  double* __restrict__ var) {
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = lane; j < m; j += 64) {
+    const double z = Z[i * ldz + j];
+    s += z * z;
+  }
+  s = wave_sum(s);
+  double kii = 0.0;
+  if (init) {
+    double t = 0.0;
+    for (int64_t k = lane; k < D; k += 64) {
+      const double d = (double)desc[i * ldd + k];
+      t += d * d;
+    }
+    t = wave_sum(t);
+    double p = 1.0;
+    for (int q = 0; q < zeta; ++q) p *= t;
+    kii = delta * delta * p;
+  }
+  if (lane == 0) var[i] = (init ? kii : var[i]) + sign * s;
 }
 
 // Multi-block form of the same solves: block t owns the 64 unknowns of column
@@ -2357,6 +2410,28 @@ void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st) {
 
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, x, n, out);
+}
+
+void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy, int* dev_err,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_trinv_upper, dim3((unsigned)n), dim3(1024), (size_t)n * sizeof(double), st,
+                     R, ld, n, Y, ldy, dev_err);
+}
+
+void var_rows(const double* Z, int64_t ldz, int64_t n, int64_t m, double sign, const void* desc,
+              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, bool init,
+              double* var, hipStream_t st) {
+  if (n <= 0) return;
+  dim3 grid(cdiv(n, 4));
+  if (desc_f32)
+    hipLaunchKernelGGL(k_var_rows<float>, grid, dim3(256), 0, st, Z, ldz, n, m, sign,
+                       reinterpret_cast<const float*>(desc), ldd, D, zeta, delta, init ? 1 : 0,
+                       var);
+  else
+    hipLaunchKernelGGL(k_var_rows<double>, grid, dim3(256), 0, st, Z, ldz, n, m, sign,
+                       reinterpret_cast<const double*>(desc), ldd, D, zeta, delta, init ? 1 : 0,
+                       var);
 }
 
 void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st) {

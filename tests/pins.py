@@ -288,6 +288,28 @@ def check_local_rows(orc):
             assert abs(KS[r, m] - w.delta ** 2 * p ** w.zeta) <= 1e-12 * max(1.0, abs(KS[r, m]))
 
 
+def check_predict_variance(orc):
+    # the same variances from the normal-equation matrices solved directly
+    # (no triangular factor), and 0 <= var_i <= k(d_i, d_i)
+    w, b, X, jit = small_fit_problem(seed=6)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    y = np.random.default_rng(12).standard_normal(b.n_rows)
+    sig = synth.sigma_rows(w, b.counts)
+    A, bb = orc.design_matrix(K, Kmm, y, sig, jit)
+    R = orc.augmented_r(A, bb)[:w.M, :w.M]
+    var = orc.predict_variance(b.desc, X, Kmm, jit, R, w.zeta, w.delta)
+    desc = b.desc.astype(np.float64)
+    ks = w.delta ** 2 * (desc @ X.T) ** w.zeta
+    kii = w.delta ** 2 * np.sum(desc * desc, axis=1) ** w.zeta
+    P = Kmm + jit * np.eye(w.M)
+    Q = P + K.T @ (K / sig[:, None] ** 2)
+    ref = kii - np.einsum("im,im->i", ks, np.linalg.solve(P, ks.T).T) \
+        + np.einsum("im,im->i", ks, np.linalg.solve(Q, ks.T).T)
+    assert np.abs(var - ref).max() <= 1e-9 * kii.max()
+    assert np.all(var >= -1e-12 * kii.max()) and np.all(var <= kii * (1 + 1e-12))
+
+
 def check_full_gpr_identity(orc):
     # energy-only observations, sparse set = every atom, no jitter:
     # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
@@ -403,6 +425,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
               check_fold_streamed, check_local_rows, check_virial_rows_strain,
+              check_predict_variance,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

@@ -19,6 +19,7 @@ _orig_fold_rows = G.fold_rows
 _orig_augr = G.augmented_r
 _orig_local = G.build_local_rows
 _orig_virial = G.build_virial_rows
+_orig_var = G.predict_variance
 
 
 def knm_sign_flip(*a):
@@ -138,6 +139,20 @@ def virial_sign_flip(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta):
     return -_orig_virial(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta)
 
 
+def variance_data_term_sign(desc, X, Kmm, jitter, R, zeta, delta):
+    # subtract the data term instead of adding it
+    base = _orig_var(desc, X, Kmm, jitter, np.eye(np.asarray(X).shape[0]) * 1e300, zeta, delta)
+    full = _orig_var(desc, X, Kmm, jitter, R, zeta, delta)
+    return base - (full - base)
+
+
+def variance_prior_only(desc, X, Kmm, jitter, R, zeta, delta):
+    # the prior variance k_ii, the sparse-set term left out
+    d = np.asarray(desc, float)
+    return delta ** 2 * np.sum(d * d, axis=1) ** zeta + 0.0 * _orig_var(desc, X, Kmm, jitter, R,
+                                                                       zeta, delta)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -156,6 +171,8 @@ MUTANTS = [
     ("build_local_rows", local_rows_gradient_scale),
     ("build_virial_rows", virial_transposed),
     ("build_virial_rows", virial_sign_flip),
+    ("predict_variance", variance_data_term_sign),
+    ("predict_variance", variance_prior_only),
 ]
 
 
