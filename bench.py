@@ -295,6 +295,27 @@ def main():
             f"state {streamed['state_bytes'] / 1e9:.2f} GB vs A {streamed['design_bytes_one_shot'] / 1e9:.2f} GB, "
             f"c rel vs one-shot {streamed['c_rel_vs_one_shot']:.2e}")
 
+    variance = None
+    if not args.no_virial:
+        # predictive variance of every atom's local energy from the FP64 fit's R
+        # (A holds the last fit's factor unless the mixed leg refitted it)
+        A64 = gap.design_buffer(atoms, sp)
+        gap.build_kmm(sp, out=Kmm)
+        gap.build_knm(atoms, sp, out=A64)
+        gap.fit(A64, n_rows, Kmm, y, sigma, w.jitter, sp)
+        gap.predict_variance(atoms, sp, Kmm, w.jitter, A64)
+        torch.cuda.synchronize()
+        tvv = []
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            vv = gap.predict_variance(atoms, sp, Kmm, w.jitter, A64)
+            torch.cuda.synchronize()
+            tvv.append(time.perf_counter() - ts)
+        variance = {"atoms": b.n_atoms, "call_s": float(np.mean(tvv)),
+                    "min": float(vv.min()), "max": float(vv.max())}
+        log(f"predictive variance of {b.n_atoms} atoms: {variance['call_s'] * 1e3:.1f} ms")
+        del A64, vv
+
     virial = None
     if not args.no_virial:
         # nine virial rows per configuration, same pairs and Jacobians
@@ -354,6 +375,7 @@ def main():
         "mixed_bf16x3": mixed,
         "streamed_fp64": streamed,
         "virial_rows_fp64": virial,
+        "predict_variance_fp64": variance,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
     }
     print(json.dumps(out), flush=True)

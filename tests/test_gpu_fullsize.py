@@ -165,6 +165,31 @@ def test_virial_rows_fullsize_sampled_configurations(fit_case):
     del Kv
 
 
+def test_variance_fullsize_sampled_atoms(fit_case):
+    # variances of every atom after the full-size fit; sampled atoms against the
+    # oracle's formula given the same K_MM and triangular factor, all within [0, k_ii]
+    w, b, X, gap = (fit_case[k] for k in ("w", "b", "X", "gap"))
+    atoms, sp, K = fit_case["atoms"], fit_case["sp"], fit_case["K"]
+    n_rows, M = b.n_rows, w.M
+    Kmm = oracle.build_kmm(X, w.zeta, w.delta)
+    Kmm_d = torch.as_tensor(Kmm, device="cuda")
+    A = K.clone()
+    y = torch.ones(n_rows, dtype=torch.float64, device="cuda")  # R does not depend on y
+    gap.fit(A, n_rows, Kmm_d, y, torch.as_tensor(synth.sigma_rows(w, b.counts), device="cuda"),
+            w.jitter, sp)
+    var = gap.predict_variance(atoms, sp, Kmm_d, w.jitter, A).cpu().numpy()
+    R = A[:M, :M].T.cpu().numpy()
+    del A
+    d = b.desc.astype(np.float64)
+    kii = w.delta ** 2 * np.sum(d * d, axis=1) ** w.zeta
+    assert np.all(var >= -1e-12 * kii.max()) and np.all(var <= kii * (1 + 1e-12))
+    atoms_s = sorted({0, 1, b.n_atoms // 2, b.n_atoms - 1} | set(range(0, b.n_atoms, 997)))
+    ref = oracle.predict_variance(d[atoms_s], X, Kmm, w.jitter, R, w.zeta, w.delta)
+    err = float(np.abs(var[atoms_s] - ref).max() / kii.max())
+    print(f"[fullsize] predictive variance of {len(atoms_s)} sampled atoms: rel {err:.2e}")
+    assert err <= TOL
+
+
 # --------------------------------------------------------------- prediction --
 @pytest.fixture(scope="module")
 def predict_case():
