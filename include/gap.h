@@ -223,6 +223,23 @@ gap_status gap_predict_variance(gap_handle *h, const gap_atoms *atoms, const gap
                                 const double *Kmm, double jitter, const double *R, int64_t ldr,
                                 double *var);
 
+/* CUR selection of sparse points among the atoms' descriptors (Sec. "Sparse
+ * point selection": cur_points, a CUR decomposition of the data points after
+ * Mahoney & Drineas, whose column choice rests on leverage scores).  With the
+ * rank parameter taken as the full rank of the descriptor matrix D (n_atoms x
+ * D), regularised by jitter, the leverage of atom i is
+ *   l_i = d_i^T (D^T D + jitter I)^-1 d_i.
+ * u == NULL: the n_sparse atoms of largest leverage.  u [n_atoms] device,
+ * uniform in (0, 1]: exact-size weighted sampling without replacement with
+ * weights l_i (keys log(u_i) / l_i, largest first; Efraimidis & Spirakis).
+ * Ties go to the smaller atom index.  out_idx [n_sparse] int32 device, in
+ * decreasing key order; leverage [n_atoms] device FP64 (may be NULL).  Only
+ * the descriptors of `atoms` are read.  Synchronous; GAP_E_NOT_PD if
+ * D^T D + jitter I is not positive definite (use jitter > 0 for descriptor
+ * sets of lower rank). */
+gap_status gap_select_cur(gap_handle *h, const gap_atoms *atoms, int64_t n_sparse, double jitter,
+                          const double *u, int32_t *out_idx, double *leverage);
+
 /* Streamed fit: the least-squares problem of gap_fit folded one block of
  * observation rows at a time, so that A is never held whole.  Sec. "Theory"
  * gives the QR route; Sec. "Program structure" splits the configurations, and

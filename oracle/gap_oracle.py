@@ -161,6 +161,35 @@ def build_local_rows(desc, X, atom_idx, zeta, delta):
     return poly_kernel(D @ np.asarray(X, dtype=np.float64).T, zeta, delta)
 
 
+def cur_leverage(desc, jitter):
+    """Leverage scores of the data points for CUR selection:
+    l_i = d_i^T (D^T D + jitter I)^-1 d_i.
+
+    Sec. "Sparse point selection" (cur_points, after Mahoney & Drineas): the
+    column choice of CUR rests on leverage scores; the rank parameter is taken
+    as the full rank of the descriptor matrix D (reading), regularised by jitter.
+    """
+    Dm = np.asarray(desc, dtype=np.float64)
+    G = Dm.T @ Dm + jitter * np.eye(Dm.shape[1])
+    return np.einsum("ij,ij->i", Dm, np.linalg.solve(G, Dm.T).T)
+
+
+def cur_select(desc, n_sparse, jitter, u=None):
+    """The n_sparse atoms of largest leverage (u None), or exact-size weighted
+    sampling without replacement with weights l_i and uniforms u (keys
+    log(u_i) / l_i, largest first; Efraimidis & Spirakis).  Ties go to the
+    smaller index.  Returns (indices in decreasing key order, leverage)."""
+    lev = cur_leverage(desc, jitter)
+    if u is None:
+        key = lev.copy()
+    else:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            key = np.where(lev > 0, np.log(np.asarray(u, dtype=np.float64)) / lev, -np.inf)
+    key = np.where(np.isnan(key), -np.inf, key)
+    order = np.lexsort((np.arange(len(key)), -key))
+    return order[:n_sparse].astype(np.int64), lev
+
+
 def design_matrix(Knm, Kmm, y, sigma, jitter):
     """A = [Sigma^-1/2 L-hat K_NM ; U_MM], b = [Sigma^-1/2 y ; 0].
 

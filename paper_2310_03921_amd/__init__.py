@@ -78,6 +78,7 @@ def lib():
             "gap_build_local_rows": ([P, P, P, P, I64, P, I64], S),
             "gap_build_virial_rows": ([P, P, P, P, P, I64], S),
             "gap_predict_variance": ([P, P, P, P, ctypes.c_double, P, I64, P], S),
+            "gap_select_cur": ([P, P, I64, ctypes.c_double, P, P, P], S),
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
@@ -417,6 +418,19 @@ class Gap:
                                                _ptr(_f64(Kmm)), float(jitter), _ptr(R),
                                                R.shape[1], _ptr(var)))
         return var
+
+    def select_cur(self, atoms: Atoms, n_sparse: int, jitter: float = 0.0,
+                   u: torch.Tensor | None = None):
+        """CUR sparse-point selection: (indices [n_sparse] int32 in decreasing
+        key order, leverage [n_atoms])."""
+        dev = atoms.desc.device
+        idx = torch.empty(max(n_sparse, 1), dtype=torch.int32, device=dev)
+        lev = torch.empty(atoms.n_atoms, dtype=torch.float64, device=dev)
+        a = atoms.struct()
+        uu = None if u is None else _f64(u)
+        self._check(lib().gap_select_cur(self._h, ctypes.byref(a), int(n_sparse), float(jitter),
+                                         _ptr(uu), _ptr(idx), _ptr(lev)))
+        return idx[:n_sparse], lev
 
     def predict_backward(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, g_e: torch.Tensor,
                          precision: str = "fp64", d_desc=True, d_c=True, d_X=True):

@@ -641,12 +641,60 @@ gap_status gap_predict_variance(gap_handle* h, const gap_atoms* a, const gap_spa
   gapk::gemm_wx_f64(at<double>(h, Ks), ldm, N, M, at<double>(h, Yu), ldm, M, at<double>(h, Zb),
                     ldm, h->stream);
   gapk::var_rows(at<double>(h, Zb), ldm, N, M, -1.0, a->desc, f32(a->desc_dt), a->ld_desc, D,
-                 sp->zeta, sp->delta, true, var, h->stream);
+                 sp->zeta, sp->delta, 1, var, h->stream);
   gapk::gemm_wx_f64(at<double>(h, Ks), ldm, N, M, at<double>(h, Yr), ldm, M, at<double>(h, Zb),
                     ldm, h->stream);
   gapk::var_rows(at<double>(h, Zb), ldm, N, M, 1.0, a->desc, f32(a->desc_dt), a->ld_desc, D,
-                 sp->zeta, sp->delta, false, var, h->stream);
+                 sp->zeta, sp->delta, 0, var, h->stream);
   h->timer.end(gapk::TM_PREDICT);
+  HIP_TRY(h, hipGetLastError());
+  return drain_dev_err(h);
+}
+
+gap_status gap_select_cur(gap_handle* h, const gap_atoms* a, int64_t n_sparse, double jitter,
+                          const double* u, int32_t* out_idx, double* leverage) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  if (!a || !a->desc || a->n_atoms < 0 || a->D < 1 || a->ld_desc < a->D)
+    return fail(h, GAP_E_INVALID, "atoms: need desc with ld_desc >= D >= 1");
+  if (a->desc_dt != GAP_DT_F32 && a->desc_dt != GAP_DT_F64)
+    return fail(h, GAP_E_INVALID, "bad desc dtype");
+  const int64_t N = a->n_atoms, D = a->D;
+  if (n_sparse < 0 || n_sparse > N || (n_sparse > 0 && !out_idx))
+    return fail(h, GAP_E_INVALID, "need 0 <= n_sparse <= n_atoms and out_idx");
+  if (!(jitter >= 0.0) || !std::isfinite(jitter)) return fail(h, GAP_E_INVALID, "bad jitter");
+  if (D > 8000) return fail(h, GAP_E_UNSUPPORTED, "D > 8000");
+  if (N == 0) return GAP_OK;
+  if (N > (int64_t(1) << 30)) return fail(h, GAP_E_UNSUPPORTED, "n_atoms > 2^30");
+  const int64_t ldd = ld4(D), n_pad = gapk::cur_pad(N);
+  Layout L;
+  const size_t Dd = L.take(sizeof(double) * N * ldd);
+  const size_t Gw = L.take(sizeof(double) * D * D);
+  const size_t Lw = L.take(sizeof(double) * D * D);
+  const size_t Ub = L.take(sizeof(double) * D * (D + 1));
+  const size_t Yu = L.take(sizeof(double) * D * ldd);
+  const size_t Zb = L.take(sizeof(double) * N * ldd);
+  const size_t lv = L.take(sizeof(double) * N);
+  const size_t ky = L.take(sizeof(double) * n_pad);
+  const size_t ix = L.take(sizeof(int32_t) * n_pad);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  double* dd = at<double>(h, Dd);
+  double* lev = leverage ? leverage : at<double>(h, lv);
+  // leverage l_i = ||d_i^T U^-1||^2 with U^T U = D^T D + jitter I
+  gapk::desc_f64(a->desc, f32(a->desc_dt), a->ld_desc, N, D, dd, ldd, h->stream);
+  gapk::gemm_wtd_f64(dd, ldd, N, D, dd, false, ldd, D, at<double>(h, Gw), D, h->stream);
+  gapk::cholesky_lower(at<double>(h, Lw), D, D, jitter, at<double>(h, Gw), D, h->dev_err,
+                       h->stream);
+  gapk::stack_u(at<double>(h, Ub), D, 0, D, at<double>(h, Lw), D, h->stream);
+  gapk::trinv_upper(at<double>(h, Ub), D, D, at<double>(h, Yu), ldd, h->dev_err, h->stream);
+  gapk::gemm_wx_f64(dd, ldd, N, D, at<double>(h, Yu), ldd, D, at<double>(h, Zb), ldd, h->stream);
+  gapk::var_rows(at<double>(h, Zb), ldd, N, D, 1.0, dd, false, ldd, D, 1, 1.0, 2, lev, h->stream);
+  gapk::cur_select_sort(lev, u, N, at<double>(h, ky), at<int32_t>(h, ix), h->stream);
+  if (n_sparse > 0)
+    HIP_TRY(h, hipMemcpyAsync(out_idx, at<int32_t>(h, ix), sizeof(int32_t) * n_sparse,
+                              hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(h, hipGetLastError());
   return drain_dev_err(h);
 }

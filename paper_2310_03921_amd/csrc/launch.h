@@ -244,10 +244,19 @@ void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st);
 // the diagonal; one workgroup per column.
 void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy, int* dev_err,
                  hipStream_t st);
-// var[i] (+)= sign * ||Z[i][0:m]||^2; with init, var[i] = delta^2 (d_i . d_i)^zeta + sign * ...
+// var[i] = base + sign * ||Z[i][0:m]||^2 with base var[i] (init 0), delta^2 (d_i . d_i)^zeta
+// (init 1) or 0 (init 2).
 void var_rows(const double* Z, int64_t ldz, int64_t n, int64_t m, double sign, const void* desc,
-              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, bool init,
+              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, int init,
               double* var, hipStream_t st);
+// Descriptors as FP64 rows [n][ldo], zero row padding.
+void desc_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n, int64_t D, double* out,
+              int64_t ldo, hipStream_t st);
+// CUR selection: keys (leverage, or log(u) / leverage) sorted into decreasing
+// order, ties by index; key and idx hold cur_pad(n) entries.
+int64_t cur_pad(int64_t n);
+void cur_select_sort(const double* lev, const double* u, int64_t n, double* key, int32_t* idx,
+                     hipStream_t st);
 // Streamed-fit state: clear rows (col, M] of columns [0, M) of T (and T[M][M]
 // when zero_corner).
 void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st);

@@ -1860,7 +1860,7 @@ __global__ __launch_bounds__(256) void k_var_rows(const double* __restrict__ Z, 
   }
   s = wave_sum(s);
   double kii = 0.0;
-  if (init) {
+  if (init == 1) {
     double t = 0.0;
     for (int64_t k = lane; k < D; k += 64) {
       const double d = (double)desc[i * ldd + k];
@@ -1872,6 +1872,55 @@ __global__ __launch_bounds__(256) void k_var_rows(const double* __restrict__ Z, 
     kii = delta * delta * p;
   }
   if (lane == 0) var[i] = (init ? kii : var[i]) + sign * s;
+}
+
+// Descriptors as FP64 rows [n][ldo] with zero row padding (columns D .. ldo - 1).
+template <typename TD>
+__global__ void k_desc_f64(const TD* __restrict__ desc, int64_t ldd, int64_t n, int64_t D,
+                           double* __restrict__ out, int64_t ldo) {
+  const int64_t i = blockIdx.y;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ldo;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[i * ldo + k] = k < D ? (double)desc[i * ldd + k] : 0.0;
+}
+
+// CUR selection keys, padded to n_pad (a power of two) with -inf / index n_pad:
+// key_i = l_i (u NULL) or log(u_i) / l_i (weighted sampling without replacement).
+__global__ void k_cur_keys(const double* __restrict__ lev, const double* __restrict__ u,
+                           int64_t n, int64_t n_pad, double* __restrict__ key,
+                           int32_t* __restrict__ idx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_pad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double k = -HUGE_VAL;
+    if (i < n) {
+      const double l = lev[i];
+      k = u ? (l > 0.0 ? log(u[i]) / l : -HUGE_VAL) : l;
+      if (!(k == k)) k = -HUGE_VAL;  // NaN sorts last
+    }
+    key[i] = k;
+    idx[i] = (int32_t)i;
+  }
+}
+
+// One compare-exchange stage of a bitonic sort into decreasing key, ties by
+// increasing index (a total order, so the result is unique).
+__global__ void k_bitonic(double* __restrict__ key, int32_t* __restrict__ idx, int64_t n_pad,
+                          int64_t j, int64_t k) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_pad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = i ^ j;
+    if (l <= i) continue;
+    const double ki = key[i], kl = key[l];
+    const int32_t ii = idx[i], il = idx[l];
+    const bool i_first = ki > kl || (ki == kl && ii < il);  // i precedes l in the final order
+    const bool down = (i & k) == 0;                          // this run is sorted in final order
+    if (down != i_first) {
+      key[i] = kl;
+      key[l] = ki;
+      idx[i] = il;
+      idx[l] = ii;
+    }
+  }
 }
 
 // Multi-block form of the same solves: block t owns the 64 unknowns of column
@@ -2420,18 +2469,44 @@ void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy,
 }
 
 void var_rows(const double* Z, int64_t ldz, int64_t n, int64_t m, double sign, const void* desc,
-              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, bool init,
+              bool desc_f32, int64_t ldd, int64_t D, int zeta, double delta, int init,
               double* var, hipStream_t st) {
   if (n <= 0) return;
   dim3 grid(cdiv(n, 4));
   if (desc_f32)
     hipLaunchKernelGGL(k_var_rows<float>, grid, dim3(256), 0, st, Z, ldz, n, m, sign,
-                       reinterpret_cast<const float*>(desc), ldd, D, zeta, delta, init ? 1 : 0,
-                       var);
+                       reinterpret_cast<const float*>(desc), ldd, D, zeta, delta, init, var);
   else
     hipLaunchKernelGGL(k_var_rows<double>, grid, dim3(256), 0, st, Z, ldz, n, m, sign,
-                       reinterpret_cast<const double*>(desc), ldd, D, zeta, delta, init ? 1 : 0,
-                       var);
+                       reinterpret_cast<const double*>(desc), ldd, D, zeta, delta, init, var);
+}
+
+void desc_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n, int64_t D, double* out,
+              int64_t ldo, hipStream_t st) {
+  if (n <= 0) return;
+  dim3 grid(cdiv(ldo, 256), (unsigned)n);
+  if (desc_f32)
+    hipLaunchKernelGGL(k_desc_f64<float>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const float*>(desc), ldd, n, D, out, ldo);
+  else
+    hipLaunchKernelGGL(k_desc_f64<double>, grid, dim3(256), 0, st,
+                       reinterpret_cast<const double*>(desc), ldd, n, D, out, ldo);
+}
+
+int64_t cur_pad(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+void cur_select_sort(const double* lev, const double* u, int64_t n, double* key, int32_t* idx,
+                     hipStream_t st) {
+  const int64_t n_pad = cur_pad(n);
+  const unsigned grid = std::max(1u, std::min(cdiv(n_pad, 256), 65536u));
+  hipLaunchKernelGGL(k_cur_keys, dim3(grid), dim3(256), 0, st, lev, u, n, n_pad, key, idx);
+  for (int64_t k = 2; k <= n_pad; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic, dim3(grid), dim3(256), 0, st, key, idx, n_pad, j, k);
 }
 
 void fold_tidy(double* T, int64_t ld, int64_t M, bool zero_corner, hipStream_t st) {

@@ -310,6 +310,33 @@ def check_predict_variance(orc):
     assert np.all(var >= -1e-12 * kii.max()) and np.all(var <= kii * (1 + 1e-12))
 
 
+def check_cur_leverage(orc):
+    # leverage of full column rank D without jitter: the squared row norms of
+    # the left singular vectors (SVD route), summing to rank D; a descriptor
+    # along a direction no other atom has gets leverage 1 and is picked first;
+    # equal weights make the weighted sampling pick the largest uniforms
+    rng = np.random.default_rng(13)
+    Dm = rng.standard_normal((40, 6))
+    Dm[:, 5] = 0.0
+    Dm[17] = 0.0
+    Dm[17, 5] = 2.5
+    idx, lev = orc.cur_select(Dm, 4, 0.0)
+    Us, sv, _ = np.linalg.svd(Dm, full_matrices=False)
+    ref = np.sum(Us[:, sv > 1e-12 * sv[0]] ** 2, axis=1)
+    assert np.allclose(lev, ref, rtol=1e-12, atol=1e-13)
+    assert abs(lev.sum() - 6.0) <= 1e-11 and abs(lev[17] - 1.0) <= 1e-12
+    assert idx[0] == 17
+    top = sorted(range(40), key=lambda i: (-lev[i], i))[:4]
+    assert list(idx) == top
+    # 39 unit rows, 13 along each axis: every leverage is 1/13
+    Eq = np.zeros((39, 3))
+    Eq[np.arange(39), np.arange(39) % 3] = 1.0
+    u = rng.random(39)
+    idx_u, levq = orc.cur_select(Eq, 5, 0.0, u)
+    assert np.allclose(levq, 1.0 / 13.0, rtol=1e-13)
+    assert list(idx_u) == sorted(range(39), key=lambda i: (-u[i], i))[:5]
+
+
 def check_full_gpr_identity(orc):
     # energy-only observations, sparse set = every atom, no jitter:
     # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
@@ -425,7 +452,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
               check_fold_streamed, check_local_rows, check_virial_rows_strain,
-              check_predict_variance,
+              check_predict_variance, check_cur_leverage,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

@@ -20,6 +20,7 @@ _orig_augr = G.augmented_r
 _orig_local = G.build_local_rows
 _orig_virial = G.build_virial_rows
 _orig_var = G.predict_variance
+_orig_curlev = G.cur_leverage
 
 
 def knm_sign_flip(*a):
@@ -153,6 +154,19 @@ def variance_prior_only(desc, X, Kmm, jitter, R, zeta, delta):
                                                                        zeta, delta)
 
 
+def cur_leverage_no_inverse(desc, jitter):
+    d = np.asarray(desc, float)
+    return np.sum(d * d, axis=1) / max(1.0, float(np.sum(d * d)) / d.shape[1])
+
+
+def cur_leverage_inverse_squared(desc, jitter):
+    # d^T G^-2 d in place of d^T G^-1 d
+    Dm = np.asarray(desc, float)
+    G = Dm.T @ Dm + jitter * np.eye(Dm.shape[1])
+    Z = np.linalg.solve(G, Dm.T).T
+    return np.sum(Z * Z, axis=1)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -173,6 +187,8 @@ MUTANTS = [
     ("build_virial_rows", virial_sign_flip),
     ("predict_variance", variance_data_term_sign),
     ("predict_variance", variance_prior_only),
+    ("cur_leverage", cur_leverage_no_inverse),
+    ("cur_leverage", cur_leverage_inverse_squared),
 ]
 
 
