@@ -316,6 +316,19 @@ def main():
         log(f"predictive variance of {b.n_atoms} atoms: {variance['call_s'] * 1e3:.1f} ms")
         del A64, vv
 
+    cur = None
+    if not args.no_virial:
+        # CUR selection of M sparse points among all the atoms' descriptors
+        gap.select_cur(atoms, M, 0.0)
+        torch.cuda.synchronize()
+        tc = []
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            gap.select_cur(atoms, M, 0.0)
+            tc.append(time.perf_counter() - ts)
+        cur = {"atoms": b.n_atoms, "n_sparse": M, "call_s": float(np.mean(tc))}
+        log(f"CUR selection of {M} of {b.n_atoms} atoms: {cur['call_s'] * 1e3:.1f} ms")
+
     virial = None
     if not args.no_virial:
         # nine virial rows per configuration, same pairs and Jacobians
@@ -376,6 +389,7 @@ def main():
         "streamed_fp64": streamed,
         "virial_rows_fp64": virial,
         "predict_variance_fp64": variance,
+        "cur_selection": cur,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
     }
     print(json.dumps(out), flush=True)

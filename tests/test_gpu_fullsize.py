@@ -190,6 +190,27 @@ def test_variance_fullsize_sampled_atoms(fit_case):
     assert err <= TOL
 
 
+def test_cur_fullsize(fit_case):
+    # leverage of all 116,667 descriptors against the oracle (one FP64 solve on
+    # the host) and the selection of M = 2000 sparse points
+    w, b, gap, atoms = (fit_case[k] for k in ("w", "b", "gap", "atoms"))
+    idx, lev = gap.select_cur(atoms, w.M, 0.0)
+    ref_idx, ref_lev = oracle.cur_select(b.desc, w.M, 0.0)
+    lev = lev.cpu().numpy()
+    e = rel_err(lev, ref_lev)
+    got = idx.cpu().numpy()
+    common = len(set(got.tolist()) & set(ref_idx.tolist()))
+    print(f"[fullsize] CUR leverage of {b.n_atoms} atoms: rel {e:.2e}; "
+          f"{common} of {w.M} picks shared with the oracle")
+    assert e <= TOL
+    order = np.lexsort((np.arange(b.n_atoms), -ref_lev))
+    tol = TOL * ref_lev.max()
+    if ref_lev[order[w.M - 1]] - ref_lev[order[w.M]] > tol:
+        assert common == w.M
+    left = np.setdiff1d(np.arange(b.n_atoms), got)
+    assert ref_lev[got].min() >= ref_lev[left].max() - tol
+
+
 # --------------------------------------------------------------- prediction --
 @pytest.fixture(scope="module")
 def predict_case():
