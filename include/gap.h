@@ -148,6 +148,42 @@ gap_status gap_build_kmm(gap_handle *h, const gap_sparse *sp, double *Kmm, int64
 gap_status gap_build_knm(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
                          gap_precision prec, double *Knm, int64_t ld);
 
+/* Two-body descriptor with the squared-exponential kernel, for models of
+ * several descriptors (Sec. "Descriptors based on interatomic distances":
+ * distance_2b, the pair distance as descriptor, the kernel multiplied by the
+ * cosine cutoff f_cut(r) of width d below r_cut; Sec. "Regression": k_SE).
+ * Each directed pair p = (i, k) of `atoms` (pair_ptr / pair_j) is an instance
+ * with r = |pair_r[p]| (pair_r: displacement r_j - r_i, [n_pairs][3] FP64
+ * device) that carries half of its bond's energy (a full neighbour list holds
+ * each bond twice):
+ *   k(r, x) = delta^2 f_cut(r) f_cut(x) exp(-(r - x)^2 / (2 theta^2)),
+ *   energy row c:         sum_{p in c} k(r_p, x_m) / 2,
+ *   force row (a, alpha): -d/dr_a,alpha of that sum.
+ * The rows have gap_build_knm's layout (n_cfg energies, then 3 per atom), so
+ * a two-body block of columns sits beside a dot-product block in one design
+ * buffer or fold block (K = Knm + M1 * ld), with K_MM block-diagonal.  Only
+ * cfg_ptr, pair_ptr and pair_j of `atoms` are read. */
+typedef struct {
+  int64_t M;         /* sparse distances */
+  const double *x;   /* [M] device */
+  double delta;      /* energy scale */
+  double theta;      /* length scale > 0 */
+  double r_cut;      /* cutoff > 0 */
+  double cut_width;  /* transition width, 0 < cut_width <= r_cut */
+} gap_se2b;
+/* L-hat K_NM block of the two-body descriptor: column-major (n_cfg + 3 n_atoms)
+ * x M, ld >= rows.  Asynchronous. */
+gap_status gap_build_2b_rows(gap_handle *h, const gap_atoms *atoms, const double *pair_r,
+                             const gap_se2b *k2, double *K, int64_t ld);
+/* K_MM[m][m'] = k(x_m, x_m'), column-major M x M, ld >= M, exactly symmetric. */
+gap_status gap_build_kmm_2b(gap_handle *h, const gap_se2b *k2, double *Kmm, int64_t ld);
+/* The two-body part of a prediction with coefficients c [M]: configuration
+ * energies e_cfg [n_cfg] and forces [n_atoms][3] (FP64 device, either may be
+ * NULL), written (add the dot-product part of gap_predict for the model's
+ * total).  Asynchronous. */
+gap_status gap_predict_2b(gap_handle *h, const gap_atoms *atoms, const double *pair_r,
+                          const gap_se2b *k2, const double *c, double *e_cfg, double *forces);
+
 /* Virial rows: the nine components of a configuration's virial stress as
  * observations (Sec. "Theory": targets are totals of local energies or of
  * their partial derivatives, virial stresses among them; sigma_virial

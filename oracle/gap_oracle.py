@@ -190,6 +190,85 @@ def cur_select(desc, n_sparse, jitter, u=None):
     return order[:n_sparse].astype(np.int64), lev
 
 
+def cutoff_fn(r, r_cut, width):
+    """Cosine cutoff of Sec. "Descriptors based on interatomic distances": 1
+    below r_cut - width, 0 from r_cut on, (cos(pi (r - r_cut + width) / width) + 1) / 2
+    between (complex arguments branch on their real part)."""
+    rr = np.real(r)
+    mid = 0.5 * (np.cos(np.pi * (r - r_cut + width) / width) + 1.0)
+    return np.where(rr >= r_cut, 0.0, np.where(rr < r_cut - width, 1.0, mid))
+
+
+def se2b_kernel(r, x, delta, theta, r_cut, width):
+    """k(r, x) = delta^2 f_cut(r) f_cut(x) exp(-(r - x)^2 / (2 theta^2)):
+    k_SE of Sec. "Regression" on a one-dimensional (distance) descriptor, times
+    the cutoff of each distance."""
+    return (delta ** 2 * cutoff_fn(r, r_cut, width) * cutoff_fn(x, r_cut, width)
+            * np.exp(-(r - x) ** 2 / (2.0 * theta ** 2)))
+
+
+def se2b_kernel_dr(r, x, delta, theta, r_cut, width):
+    """dk/dr of se2b_kernel (r real)."""
+    rr = np.asarray(r, dtype=np.float64)
+    trans = (rr >= r_cut - width) & (rr < r_cut)
+    dfc = np.where(trans, -0.5 * np.pi / width * np.sin(np.pi * (rr - r_cut + width) / width), 0.0)
+    e = delta ** 2 * cutoff_fn(x, r_cut, width) * np.exp(-(rr - x) ** 2 / (2.0 * theta ** 2))
+    return e * (dfc - cutoff_fn(rr, r_cut, width) * (rr - x) / theta ** 2)
+
+
+def build_2b_rows(cfg_ptr, pair_ptr, pair_j, pair_r, x, delta, theta, r_cut, width):
+    """Rows of a two-body descriptor (energies, then 3 per atom), each directed
+    pair p = (i, k) an instance with r = |pair_r[p]| carrying half of its bond:
+    energy row c: sum_{p in c} k(r_p, x_m) / 2; force row (a, alpha): minus the
+    derivative of that sum by r_a,alpha (r_p = |r_j - r_i|).
+    Sec. "Descriptors based on interatomic distances" (distance_2b, cutoff)."""
+    x = np.asarray(x, dtype=np.float64)
+    R = np.asarray(pair_r, dtype=np.float64)
+    src = pair_sources(pair_ptr)
+    n_cfg = len(cfg_ptr) - 1
+    N = len(pair_ptr) - 1
+    atom_cfg = np.repeat(np.arange(n_cfg), np.diff(np.asarray(cfg_ptr)))
+    K = np.zeros((n_cfg + 3 * N, len(x)))
+    for p in range(len(src)):
+        i, j = int(src[p]), int(pair_j[p])
+        r = float(np.linalg.norm(R[p]))
+        K[atom_cfg[i]] += 0.5 * se2b_kernel(r, x, delta, theta, r_cut, width)
+        if r > 0.0:
+            dk = se2b_kernel_dr(r, x, delta, theta, r_cut, width)
+            u = R[p] / r
+            for a in range(3):
+                K[n_cfg + 3 * i + a] += 0.5 * dk * u[a]
+                K[n_cfg + 3 * j + a] -= 0.5 * dk * u[a]
+    return K
+
+
+def build_kmm_2b(x, delta, theta, r_cut, width):
+    x = np.asarray(x, dtype=np.float64)
+    return se2b_kernel(x[:, None], x[None, :], delta, theta, r_cut, width)
+
+
+def predict_2b(cfg_ptr, pair_ptr, pair_j, pair_r, x, c, delta, theta, r_cut, width):
+    """Configuration energies and forces of the two-body part with coefficients c."""
+    x = np.asarray(x, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    R = np.asarray(pair_r, dtype=np.float64)
+    src = pair_sources(pair_ptr)
+    n_cfg = len(cfg_ptr) - 1
+    N = len(pair_ptr) - 1
+    atom_cfg = np.repeat(np.arange(n_cfg), np.diff(np.asarray(cfg_ptr)))
+    E = np.zeros(n_cfg)
+    F = np.zeros((N, 3))
+    for p in range(len(src)):
+        i, j = int(src[p]), int(pair_j[p])
+        r = float(np.linalg.norm(R[p]))
+        E[atom_cfg[i]] += 0.5 * float(se2b_kernel(r, x, delta, theta, r_cut, width) @ c)
+        if r > 0.0:
+            g = 0.5 * float(se2b_kernel_dr(r, x, delta, theta, r_cut, width) @ c)
+            F[i] += g * R[p] / r
+            F[j] -= g * R[p] / r
+    return E, F
+
+
 def design_matrix(Knm, Kmm, y, sigma, jitter):
     """A = [Sigma^-1/2 L-hat K_NM ; U_MM], b = [Sigma^-1/2 y ; 0].
 

@@ -79,6 +79,9 @@ def lib():
             "gap_build_virial_rows": ([P, P, P, P, P, I64], S),
             "gap_predict_variance": ([P, P, P, P, ctypes.c_double, P, I64, P], S),
             "gap_select_cur": ([P, P, I64, ctypes.c_double, P, P, P], S),
+            "gap_build_2b_rows": ([P, P, P, P, P, I64], S),
+            "gap_build_kmm_2b": ([P, P, P, I64], S),
+            "gap_predict_2b": ([P, P, P, P, P, P, P], S),
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
@@ -211,6 +214,37 @@ class Sparse:
         s.M, s.D, s.ld_x = self.M, self.D, self.X.shape[1]
         s.X = self.X.data_ptr()
         s.zeta, s.delta = self.zeta, self.delta
+        return s
+
+
+class gap_se2b(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("x", ctypes.c_void_p), ("delta", ctypes.c_double),
+                ("theta", ctypes.c_double), ("r_cut", ctypes.c_double),
+                ("cut_width", ctypes.c_double)]
+
+
+@dataclass
+class SE2b:
+    """Two-body squared-exponential descriptor: sparse distances x (FP64 [M]) and
+    the kernel parameters (see gap_se2b in gap.h)."""
+    x: torch.Tensor
+    delta: float = 1.0
+    theta: float = 0.5
+    r_cut: float = 4.5
+    cut_width: float = 1.0
+
+    @classmethod
+    def from_host(cls, x, device="cuda", **kw):
+        return cls(torch.as_tensor(x, dtype=torch.float64).to(device).contiguous(), **kw)
+
+    @property
+    def M(self):
+        return self.x.numel()
+
+    def struct(self) -> gap_se2b:
+        s = gap_se2b()
+        s.M, s.x = self.M, self.x.data_ptr()
+        s.delta, s.theta, s.r_cut, s.cut_width = self.delta, self.theta, self.r_cut, self.cut_width
         return s
 
 
@@ -356,18 +390,62 @@ class Gap:
         """State of a streamed fit: column-major, M + 1 columns, ld = round4(M + 1 + max_rows)."""
         return colmajor(M + 1 + max_rows, M + 1, device=device)
 
-    def fold_block(self, T: torch.Tensor, M: int) -> int:
-        """Device address of the block area (row M + 1) of a fold state, for gap_build_knm."""
-        return T.data_ptr() + 8 * (M + 1)
+    def fold_block(self, T: torch.Tensor, M: int, col0: int = 0) -> int:
+        """Device address of the block area (row M + 1) of a fold state, column col0."""
+        return T.data_ptr() + 8 * (M + 1 + col0 * T.shape[1])
 
     def build_knm_block(self, atoms: Atoms, sparse: Sparse, T: torch.Tensor,
-                        precision: str = "fp64"):
-        """L-hat K_NM of `atoms` written into the block area of the fold state T."""
+                        precision: str = "fp64", M: int | None = None, col0: int = 0):
+        """L-hat K_NM of `atoms` written into the block area of the fold state T
+        (of M columns, default sparse.M), from column col0 on."""
         a, s = atoms.struct(), sparse.struct()
+        M = sparse.M if M is None else M
         self._check(lib().gap_build_knm(self._h, ctypes.byref(a), ctypes.byref(s),
                                         PRECISION[precision],
-                                        ctypes.c_void_p(self.fold_block(T, sparse.M)),
+                                        ctypes.c_void_p(self.fold_block(T, M, col0)),
                                         T.shape[1]))
+
+    # ------------------------------------------------ two-body SE descriptor
+    def build_2b_rows(self, atoms: Atoms, k2: SE2b, pair_r: torch.Tensor,
+                      out: torch.Tensor | None = None, row0: int = 0, col0: int = 0):
+        """Two-body rows (n_cfg + 3 n_atoms) x k2.M written at (row0, col0) of the
+        column-major buffer `out` (default: a new buffer)."""
+        n = atoms.n_rows
+        out = colmajor(n, k2.M, device=k2.x.device) if out is None else out
+        a, s = atoms.struct(), k2.struct()
+        r = _f64(pair_r)
+        self._check(lib().gap_build_2b_rows(
+            self._h, ctypes.byref(a), _ptr(r), ctypes.byref(s),
+            ctypes.c_void_p(out.data_ptr() + 8 * (row0 + col0 * out.shape[1])), out.shape[1]))
+        self._keep_r = r
+        return out
+
+    def build_2b_block(self, atoms: Atoms, k2: SE2b, pair_r: torch.Tensor, T: torch.Tensor,
+                       M: int, col0: int):
+        """Two-body rows written into the block area of a fold state of M columns."""
+        return self.build_2b_rows(atoms, k2, pair_r, out=T, row0=M + 1, col0=col0)
+
+    def build_kmm_2b(self, k2: SE2b, out: torch.Tensor | None = None, row0: int = 0,
+                     col0: int = 0) -> torch.Tensor:
+        out = colmajor(k2.M, k2.M, k2.M, k2.x.device) if out is None else out
+        s = k2.struct()
+        self._check(lib().gap_build_kmm_2b(
+            self._h, ctypes.byref(s),
+            ctypes.c_void_p(out.data_ptr() + 8 * (row0 + col0 * out.shape[1])), out.shape[1]))
+        return out
+
+    def predict_2b(self, atoms: Atoms, k2: SE2b, pair_r: torch.Tensor, c: torch.Tensor,
+                   e_cfg=True, forces=True):
+        dev = k2.x.device
+        out = {"e_cfg": torch.empty(atoms.n_cfg, dtype=torch.float64, device=dev) if e_cfg else None,
+               "forces": torch.empty(atoms.n_atoms, 3, dtype=torch.float64, device=dev)
+               if forces else None}
+        a, s = atoms.struct(), k2.struct()
+        r, c = _f64(pair_r), _f64(c)
+        self._check(lib().gap_predict_2b(self._h, ctypes.byref(a), _ptr(r), ctypes.byref(s),
+                                         _ptr(c), _ptr(out["e_cfg"]), _ptr(out["forces"])))
+        self._keep_r = (r, c)
+        return out
 
     def fold_init(self, T: torch.Tensor, M: int, Kmm: torch.Tensor, jitter: float):
         self._check(lib().gap_fold_init(self._h, _ptr(T), T.shape[1], M, _ptr(_f64(Kmm)),

@@ -699,6 +699,92 @@ gap_status gap_select_cur(gap_handle* h, const gap_atoms* a, int64_t n_sparse, d
   return drain_dev_err(h);
 }
 
+namespace {
+gap_status check_se2b(gap_handle* h, const gap_se2b* k2) {
+  if (!k2 || k2->M < 1 || !k2->x) return fail(h, GAP_E_INVALID, "se2b: need M >= 1 and x");
+  if (!std::isfinite(k2->delta) || !(k2->theta > 0.0) || !std::isfinite(k2->theta) ||
+      !(k2->r_cut > 0.0) || !std::isfinite(k2->r_cut) || !(k2->cut_width > 0.0) ||
+      k2->cut_width > k2->r_cut)
+    return fail(h, GAP_E_INVALID, "se2b: need finite delta, theta > 0, 0 < cut_width <= r_cut");
+  return GAP_OK;
+}
+gap_status check_pairs_only(gap_handle* h, const gap_atoms* a, const double* pair_r) {
+  if (!a || a->n_cfg < 0 || a->n_atoms < 0 || a->n_pairs < 0 || !a->cfg_ptr || !a->pair_ptr)
+    return fail(h, GAP_E_INVALID, "atoms: need cfg_ptr and pair_ptr");
+  if (a->n_pairs > 0 && (!a->pair_j || !pair_r))
+    return fail(h, GAP_E_INVALID, "atoms: need pair_j and pair_r");
+  if (a->n_pairs >= (int64_t(1) << 31)) return fail(h, GAP_E_UNSUPPORTED, "n_pairs >= 2^31");
+  return GAP_OK;
+}
+}  // namespace
+
+gap_status gap_build_2b_rows(gap_handle* h, const gap_atoms* a, const double* pair_r,
+                             const gap_se2b* k2, double* K, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_se2b(h, k2);
+  if (s != GAP_OK) return s;
+  s = check_pairs_only(h, a, pair_r);
+  if (s != GAP_OK) return s;
+  const int64_t n_rows = a->n_cfg + 3 * a->n_atoms;
+  if (!K || ld < n_rows) return fail(h, GAP_E_INVALID, "K NULL or ld < n_cfg + 3 n_atoms");
+  Layout L;
+  PairWs p;
+  layout_pairs(L, a->n_atoms, a->n_pairs, p);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  run_pairs(h, a, p, false);
+  h->timer.begin(gapk::TM_FORCE);
+  gapk::se2b_rows_f64(pair_r, a->cfg_ptr, a->n_cfg, a->pair_ptr, at<int64_t>(h, p.tgt_ptr),
+                      at<int32_t>(h, p.tgt_pair), a->n_atoms, a->n_pairs, k2->x, k2->M,
+                      k2->delta, k2->theta, k2->r_cut, k2->cut_width, K, ld, h->stream);
+  h->timer.end(gapk::TM_FORCE);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_build_kmm_2b(gap_handle* h, const gap_se2b* k2, double* Kmm, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_se2b(h, k2);
+  if (s != GAP_OK) return s;
+  if (!Kmm || ld < k2->M) return fail(h, GAP_E_INVALID, "Kmm NULL or ld < M");
+  gapk::se2b_kmm_f64(k2->x, k2->M, k2->delta, k2->theta, k2->r_cut, k2->cut_width, Kmm, ld,
+                     h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_predict_2b(gap_handle* h, const gap_atoms* a, const double* pair_r,
+                          const gap_se2b* k2, const double* c, double* e_cfg, double* forces) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_se2b(h, k2);
+  if (s != GAP_OK) return s;
+  s = check_pairs_only(h, a, pair_r);
+  if (s != GAP_OK) return s;
+  if (!c) return fail(h, GAP_E_INVALID, "c is NULL");
+  Layout L;
+  PairWs p;
+  layout_pairs(L, a->n_atoms, a->n_pairs, p);
+  const size_t ep = L.take(sizeof(double) * std::max<int64_t>(a->n_pairs, 1));
+  const size_t gp = L.take(sizeof(double) * std::max<int64_t>(a->n_pairs, 1));
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  if (forces) run_pairs(h, a, p, false);
+  h->timer.begin(gapk::TM_PREDICT);
+  gapk::se2b_predict_f64(pair_r, a->cfg_ptr, a->n_cfg, a->pair_ptr, at<int64_t>(h, p.tgt_ptr),
+                         at<int32_t>(h, p.tgt_pair), a->n_atoms, a->n_pairs, k2->x, c, k2->M,
+                         k2->delta, k2->theta, k2->r_cut, k2->cut_width, at<double>(h, ep),
+                         at<double>(h, gp), e_cfg, forces, h->stream);
+  h->timer.end(gapk::TM_PREDICT);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
 // ------------------------------------------------------------ streamed fit
 namespace {
 gap_status check_fold_state(gap_handle* h, const double* T, int64_t ld, int64_t M,

@@ -92,6 +92,20 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                 const double* Sx = nullptr, int64_t ldsx = 0);
 int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
+// Two-body SE descriptor: rows (energies, then 3 per atom) of the pair-distance
+// kernel, its K_MM, and prediction (per-pair terms in ep / gp, n_pairs each).
+void se2b_rows_f64(const double* pair_r, const int64_t* cfg_ptr, int64_t n_cfg,
+                   const int64_t* pair_ptr, const int64_t* tgt_ptr, const int32_t* tgt_pair,
+                   int64_t n_atoms, int64_t n_pairs, const double* x, int64_t M, double delta,
+                   double theta, double r_cut, double width, double* K, int64_t ldk,
+                   hipStream_t st);
+void se2b_kmm_f64(const double* x, int64_t M, double delta, double theta, double r_cut,
+                  double width, double* K, int64_t ldk, hipStream_t st);
+void se2b_predict_f64(const double* pair_r, const int64_t* cfg_ptr, int64_t n_cfg,
+                      const int64_t* pair_ptr, const int64_t* tgt_ptr, const int32_t* tgt_pair,
+                      int64_t n_atoms, int64_t n_pairs, const double* x, const double* c,
+                      int64_t M, double delta, double theta, double r_cut, double width,
+                      double* ep, double* gp, double* e_cfg, double* forces, hipStream_t st);
 // Virial rows: K[(9 c + 3 alpha + beta), m] = - sum_{p in c} r[p][alpha] S[src(p)][m] (J[p][beta] . x_m).
 void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
                      int64_t ldx, int64_t M, const double* S, int64_t ldS, const int64_t* cfg_ptr,

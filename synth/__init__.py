@@ -25,8 +25,10 @@ regenerated alone, which is what sampled parity checks at full size rely on):
 * hidden coefficients c* ~ N(0, 1), stream [seed, 3].
 * observation noise, stream [seed, 4, c]: energy ~ N(0, sigma_E^2 * n_c),
   forces ~ N(0, sigma_F^2) per component.
-* pair displacement vectors (virial rows only), stream [seed, 5, c]: uniform
-  in a ball of radius 5.
+* pair displacement vectors (virial and two-body rows), stream [seed, 5, c]:
+  uniform in a ball of radius 5.
+* sparse distances of the two-body descriptor, stream [seed, 6]: uniform in
+  [0.5, 5].
 """
 from __future__ import annotations
 
@@ -239,6 +241,12 @@ def pair_vectors(w: Workload, batch: Batch, r_cut: float = 5.0) -> np.ndarray:
         v /= np.maximum(np.linalg.norm(v, axis=1, keepdims=True), 1e-300)
         out[p0:p1] = v * (r_cut * rng.random((p1 - p0, 1)) ** (1.0 / 3.0))
     return out
+
+
+def sparse_distances(w: Workload, M: int, lo: float = 0.5, hi: float = 5.0) -> np.ndarray:
+    """Sparse points of a two-body distance descriptor: M distances uniform in
+    [lo, hi], sorted, stream [seed, 6]."""
+    return np.sort(np.random.default_rng([w.seed, 6]).uniform(lo, hi, size=M))
 
 
 def predict_coefficients(w: Workload) -> np.ndarray:

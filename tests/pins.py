@@ -337,6 +337,61 @@ def check_cur_leverage(orc):
     assert list(idx_u) == sorted(range(39), key=lambda i: (-u[i], i))[:5]
 
 
+SE2B = dict(delta=1.3, theta=0.6, r_cut=4.5, width=1.0)
+
+
+def check_2b_rows(orc, h=1e-30):
+    # force rows: complex-step derivative of the energy rows' pair sum under
+    # atom displacements (pair vectors move by d_j - d_i); pairs past the cutoff
+    # give nothing; K_MM symmetric with diagonal delta^2 fc(x)^2; predict = rows . c
+    w, b, X = tiny_batch()
+    r = synth.pair_vectors(w, b)
+    x = synth.sparse_distances(w, 7)
+    K = orc.build_2b_rows(b.cfg_ptr, b.pair_ptr, b.pair_j, r, x, **SE2B)
+    src = np.repeat(np.arange(b.n_atoms), np.diff(b.pair_ptr))
+    rn = np.linalg.norm(r, axis=1)
+    assert np.any(rn >= SE2B["r_cut"]) and np.any((rn > 3.5) & (rn < 4.5))
+    for a in range(b.n_atoms):
+        c = int(np.searchsorted(b.cfg_ptr, a, side="right") - 1)
+        for al in range(3):
+            e = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+            e[a, al] = 1j * h
+            for m in range(len(x)):
+                E = 0j
+                for p in range(int(b.pair_ptr[b.cfg_ptr[c]]), int(b.pair_ptr[b.cfg_ptr[c + 1]])):
+                    v = r[p] + e[int(b.pair_j[p])] - e[src[p]]
+                    rr = np.sqrt(np.sum(v * v))
+                    d2 = SE2B["delta"] ** 2
+                    fc = orc.cutoff_fn(rr, SE2B["r_cut"], SE2B["width"])
+                    fx = 1.0 if x[m] < SE2B["r_cut"] - SE2B["width"] else \
+                        0.5 * (np.cos(np.pi * (x[m] - SE2B["r_cut"] + SE2B["width"]) / SE2B["width"]) + 1)
+                    fx = 0.0 if x[m] >= SE2B["r_cut"] else fx
+                    E += 0.5 * d2 * fc * fx * np.exp(-(rr - x[m]) ** 2 / (2 * SE2B["theta"] ** 2))
+                ref = -E.imag / h
+                got = K[b.n_cfg + 3 * a + al, m]
+                assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (a, al, m, got, ref)
+    rc, wd = SE2B["r_cut"], SE2B["width"]
+    fcv = orc.cutoff_fn(np.array([rc - wd - 1e-9, rc - 0.75 * wd, rc - 0.5 * wd, rc - 0.25 * wd,
+                                  rc, rc + 1.0]), rc, wd)
+    s2 = 0.5 * np.sqrt(2.0)
+    assert np.allclose(fcv, [1.0, 0.5 + 0.5 * s2, 0.5, 0.5 - 0.5 * s2, 0.0, 0.0], atol=1e-12)
+    Kmm = orc.build_kmm_2b(x, **SE2B)
+    assert np.array_equal(Kmm, Kmm.T)
+    fx = orc.cutoff_fn(x, SE2B["r_cut"], SE2B["width"])
+    assert np.allclose(np.diag(Kmm), SE2B["delta"] ** 2 * fx ** 2, rtol=1e-14)
+    cc = np.random.default_rng(8).standard_normal(len(x))
+    E, F = orc.predict_2b(b.cfg_ptr, b.pair_ptr, b.pair_j, r, x, cc, **SE2B)
+    assert np.allclose(E, K[:b.n_cfg] @ cc, rtol=1e-12, atol=1e-14)
+    assert np.allclose(F.reshape(-1), K[b.n_cfg:] @ cc, rtol=1e-12, atol=1e-14)
+    # a pair moved past the cutoff drops out of its configuration's energy row
+    r2 = r.copy()
+    r2[0] *= (SE2B["r_cut"] + 0.1) / np.linalg.norm(r2[0])
+    K2 = orc.build_2b_rows(b.cfg_ptr, b.pair_ptr, b.pair_j, r2, x, **SE2B)
+    c0 = int(np.searchsorted(b.cfg_ptr, src[0], side="right") - 1)
+    drop = 0.5 * orc.se2b_kernel(np.linalg.norm(r[0]), x, **SE2B)
+    assert np.allclose(K2[c0], K[c0] - drop, rtol=1e-12, atol=1e-14)
+
+
 def check_full_gpr_identity(orc):
     # energy-only observations, sparse set = every atom, no jitter:
     # c = L^T (L K L^T + Sigma)^-1 y  (push-through identity of eq. GP_L)
@@ -452,7 +507,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
               check_fold_streamed, check_local_rows, check_virial_rows_strain,
-              check_predict_variance, check_cur_leverage,
+              check_predict_variance, check_cur_leverage, check_2b_rows,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

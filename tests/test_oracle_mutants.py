@@ -21,6 +21,9 @@ _orig_local = G.build_local_rows
 _orig_virial = G.build_virial_rows
 _orig_var = G.predict_variance
 _orig_curlev = G.cur_leverage
+_orig_dr = G.se2b_kernel_dr
+_orig_2b = G.build_2b_rows
+_orig_fcut = G.cutoff_fn
 
 
 def knm_sign_flip(*a):
@@ -167,6 +170,32 @@ def cur_leverage_inverse_squared(desc, jitter):
     return np.sum(Z * Z, axis=1)
 
 
+def se2b_dr_no_cutoff_slope(r, x, delta, theta, r_cut, width):
+    # drops the f_cut'(r) term of dk/dr
+    rr = np.asarray(r, dtype=np.float64)
+    e = delta ** 2 * G.cutoff_fn(x, r_cut, width) * np.exp(-(rr - x) ** 2 / (2.0 * theta ** 2))
+    return -e * G.cutoff_fn(rr, r_cut, width) * (rr - x) / theta ** 2
+
+
+def build_2b_rows_target_sign(cfg_ptr, pair_ptr, pair_j, pair_r, x, delta, theta, r_cut, width):
+    K = _orig_2b(cfg_ptr, pair_ptr, pair_j, pair_r, x, delta, theta, r_cut, width)
+    n_cfg = len(cfg_ptr) - 1
+    src = G.pair_sources(pair_ptr)
+    R = np.asarray(pair_r, float)
+    for p in range(len(src)):
+        r = float(np.linalg.norm(R[p]))
+        if r > 0:
+            dk = _orig_dr(r, x, delta, theta, r_cut, width)
+            j = int(pair_j[p])
+            for a in range(3):
+                K[n_cfg + 3 * j + a] += dk * R[p, a] / r   # target term added instead of subtracted
+    return K
+
+
+def cutoff_half_width(r, r_cut, width):
+    return _orig_fcut(r, r_cut, 0.5 * width)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -189,6 +218,9 @@ MUTANTS = [
     ("predict_variance", variance_prior_only),
     ("cur_leverage", cur_leverage_no_inverse),
     ("cur_leverage", cur_leverage_inverse_squared),
+    ("se2b_kernel_dr", se2b_dr_no_cutoff_slope),
+    ("build_2b_rows", build_2b_rows_target_sign),
+    ("cutoff_fn", cutoff_half_width),
 ]
 
 
