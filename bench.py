@@ -329,10 +329,24 @@ def main():
         cur = {"atoms": b.n_atoms, "n_sparse": M, "call_s": float(np.mean(tc))}
         log(f"CUR selection of {M} of {b.n_atoms} atoms: {cur['call_s'] * 1e3:.1f} ms")
 
+    twobody = None
     virial = None
     if not args.no_virial:
         # nine virial rows per configuration, same pairs and Jacobians
         pr_ = torch.tensor(synth.pair_vectors(w, b), device="cuda")
+        # a 32-point two-body SE block over the same pairs (every observation row)
+        k2 = gapx.SE2b.from_host(synth.sparse_distances(w, 32))
+        K2 = gap.build_2b_rows(atoms, k2, pr_)
+        torch.cuda.synchronize()
+        t2 = []
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            gap.build_2b_rows(atoms, k2, pr_, out=K2)
+            gap.sync()
+            t2.append(time.perf_counter() - ts)
+        twobody = {"rows": n_rows, "M": 32, "pairs": b.n_pairs, "call_s": float(np.mean(t2))}
+        log(f"two-body rows ({n_rows} x 32): {twobody['call_s'] * 1e3:.1f} ms")
+        del K2
         Kv = gapx.colmajor(9 * b.n_cfg, M)
         gap.build_virial_rows(atoms, sp, pr_, out=Kv)
         torch.cuda.synchronize()
@@ -388,6 +402,7 @@ def main():
         "mixed_bf16x3": mixed,
         "streamed_fp64": streamed,
         "virial_rows_fp64": virial,
+        "two_body_rows_fp64": twobody,
         "predict_variance_fp64": variance,
         "cur_selection": cur,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
