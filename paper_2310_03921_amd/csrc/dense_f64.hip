@@ -434,8 +434,8 @@ __global__ __launch_bounds__(256) void k_gemm_wx_cs(const double* __restrict__ W
   }
 }
 
-// out = (W diag(cs)) X for D <= 256 (CS false: no scaling, cs unused).  A block
-// of eight waves covers 64 rows and all (up to 256) columns: wave w takes
+// out = (W diag(cs)) X (CS false: no scaling, cs unused).  A block of eight
+// waves covers 64 rows and a group of 256 columns (blockIdx.y): wave w takes
 // rows 16 (w / 2) .. + 15 and the 8 column tiles of half w % 2.  The
 // contraction runs over 32-wide chunks of k; the block stages chunk c of
 // diag(cs) X in LDS (double-buffered, one barrier per chunk), already in the
@@ -482,8 +482,9 @@ __global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
   // past any row (zero too).  cs[k] is a wave-uniform load, applied when the
   // element is written to LDS.
   const int kl0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8), d = threadIdx.x & 255;
+  const int64_t cg = (int64_t)blockIdx.y * 256;  // first column of the group
   const auto xr = wx_rsrc(X, (uint32_t)(M * ldx * 8));
-  const uint32_t xoff0 = d < D ? (uint32_t)((kl0 * ldx + d) * 8) : 0x80000000u;
+  const uint32_t xoff0 = cg + d < D ? (uint32_t)((kl0 * ldx + cg + d) * 8) : 0x80000000u;
   const uint32_t xstep = (uint32_t)(2 * ldx * 8);
   auto soff = [&](int it) {
     const int kl = kl0 + 2 * it;
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
   }
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int64_t col = (int64_t)(ch * 8 + u) * 16 + idx;
+    const int64_t col = cg + (int64_t)(ch * 8 + u) * 16 + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t rr = rowbase + g + 4 * r;
@@ -771,9 +772,8 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                        ldsx);
 }
 
-// The LDS-staged form needs D <= 256, W rows of whole 32-byte groups
-// (ldw % 4 == 0, W 32-byte aligned) and X under 2 GB; the general form takes
-// any layout.
+// The LDS-staged form needs W rows of whole 32-byte groups (ldw % 4 == 0, W
+// 32-byte aligned) and X under 2 GB; the general form takes any layout.
 inline bool wx_lds_ok(const double* W, int64_t ldw, int64_t M, int64_t ldx,
                       int64_t D) {
   static bool attr = false;
@@ -785,7 +785,7 @@ inline bool wx_lds_ok(const double* W, int64_t ldw, int64_t M, int64_t ldx,
     attr = true;
   }
   // offsets into X, including a dropped column's, stay below 2^32
-  return D <= 256 && M > 0 && ldw >= 4 && ldw % 4 == 0 &&
+  return D > 0 && M > 0 && ldw >= 4 && ldw % 4 == 0 && D <= (int64_t)256 * 65535 &&
          (reinterpret_cast<uintptr_t>(W) & 31) == 0 && (M + 2 * kSxKC) * ldx * 8 < (1ll << 31);
 }
 
@@ -793,7 +793,8 @@ void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const doubl
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st) {
   if (n <= 0 || D <= 0) return;
   if (wx_lds_ok(W, ldw, M, ldx, D)) {
-    hipLaunchKernelGGL(k_gemm_wx_lds<false>, dim3(cdiv(n, 64)), dim3(64 * kSxW), kSxLds, st, W, ldw, n, M,
+    hipLaunchKernelGGL(k_gemm_wx_lds<false>, dim3(cdiv(n, 64), cdiv(D, 256)), dim3(64 * kSxW),
+                       kSxLds, st, W, ldw, n, M,
                        nullptr, X, ldx, D, out, ldo);
     return;
   }
@@ -837,7 +838,8 @@ void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, cons
                         hipStream_t st) {
   if (n <= 0 || D <= 0) return;
   if (wx_lds_ok(W, ldw, M, ldx, D)) {
-    hipLaunchKernelGGL(k_gemm_wx_lds<true>, dim3(cdiv(n, 64)), dim3(64 * kSxW), kSxLds, st, W, ldw, n, M,
+    hipLaunchKernelGGL(k_gemm_wx_lds<true>, dim3(cdiv(n, 64), cdiv(D, 256)), dim3(64 * kSxW),
+                       kSxLds, st, W, ldw, n, M,
                        cs, X, ldx, D, out, ldo);
     return;
   }
