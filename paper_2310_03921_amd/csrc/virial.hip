@@ -153,6 +153,165 @@ __global__ __launch_bounds__(512) void k_virial_rows(
   }
 }
 
+// Unconditional 4-wide loads of a Jacobian row segment (32-byte aligned).
+GAP_DEV void ldj4(const double* p, double out[4]) {
+  const d4v v = *reinterpret_cast<const d4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+GAP_DEV void ldj4(const float* p, double out[4]) {
+  const f4v v = *reinterpret_cast<const f4v*>(p);
+  out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+}
+
+// The same rows for D % 4 == 0 and D <= 256 with the block's 64 columns of X
+// resident in LDS for its lifetime, stored in the matrix core's operand order
+// (as in the force-row kernel): twelve waves, wave w taking Jacobian component
+// beta = w % 3 of pair stream w / 3, so three waves share a SIMD.  Every load
+// in the pair loop reads a valid address (pairs past the configuration read
+// its last pair, k blocks past D the row's last four elements against zero
+// rows of X) and invalid data are cancelled by zero weights; the next k
+// block's (or the next chunk's first) Jacobian fragment is loaded before the
+// current block's matrix work.
+constexpr int kVW = 12;
+constexpr int kVNC = 4;      // 16-column tiles per block
+constexpr int kVMaxKb = 16;  // D <= 256
+template <typename TJ>
+__global__ __launch_bounds__(64 * kVW) void k_virial_rows_lds(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const double* __restrict__ X,
+    int64_t ldx, int64_t M, const double* __restrict__ S, int64_t ldS,
+    const int64_t* __restrict__ cfg_ptr, const int64_t* __restrict__ pair_ptr,
+    const int32_t* __restrict__ pair_src, const double* __restrict__ pair_r, int64_t n_atoms,
+    int64_t n_pairs, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_cfg, int nkb) {
+  extern __shared__ double xs[];  // [nkb][kVNC][2 halves][64 lanes][2]
+  __shared__ double red[4][9][64];
+  int64_t c, ct;
+  if (!xcd_group_tile(n_cfg, n_ct, c, ct)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int beta = wave % 3, stream = wave / 3;
+  const int64_t colbase = ct * (16 * kVNC);
+  for (int e = threadIdx.x; e < nkb * kVNC * 64; e += 64 * kVW) {
+    const int kb = e / (kVNC * 64), rem = e % (kVNC * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + 4 * (ln & 15) + u;  // lane idx of tile u: column 4 idx + u
+    double v[4];
+    if (col < M)
+      load4(X + col * ldx, (int64_t)kb * 16 + 4 * (ln >> 4), D, v);
+    else
+      zero_frag(v);
+    const d2v lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    double* t = xs + (size_t)(e >> 6) * 256 + 2 * (e & 63);
+    *reinterpret_cast<d2v*>(t) = lo;
+    *reinterpret_cast<d2v*>(t + 128) = hi;
+  }
+  __syncthreads();
+
+  const int64_t a0 = min(max(cfg_ptr[c], (int64_t)0), n_atoms);
+  const int64_t a1 = min(max(cfg_ptr[c + 1], a0), n_atoms);
+  const int64_t p_lo = min(max(pair_ptr[a0], (int64_t)0), n_pairs);
+  const int64_t p_hi = min(max(pair_ptr[a1], p_lo), n_pairs);
+  const int64_t kmax4 = D - 4;
+  double cm[kVNC];
+#pragma unroll
+  for (int u = 0; u < kVNC; ++u) cm[u] = colbase + 4 * idx + u < M ? 1.0 : 0.0;
+  const int64_t scol = min(colbase + 4 * idx, ldS - 4);
+  double acc[3][kVNC];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int u = 0; u < kVNC; ++u) acc[al][u] = 0.0;
+  const d2v* xb = reinterpret_cast<const d2v*>(xs) + lane;
+  auto xfrag = [&](int tile) -> d4v {
+    const d2v lo = xb[tile * 128], hi = xb[tile * 128 + 64];
+    const d4v f = {lo[0], lo[1], hi[0], hi[1]};
+    return f;
+  };
+  if (p_lo < p_hi && p_lo + 16 * stream < p_hi) {
+    auto row_of = [&](int64_t p0) -> const TJ* {
+      return jac + min(p0 + idx, p_hi - 1) * 3 * ldj + beta * ldj;
+    };
+    int64_t p0 = p_lo + 16 * stream;
+    const TJ* jr = row_of(p0);
+    double fa[4], fb[4];
+    ldj4(jr + min((int64_t)4 * g, kmax4), fa);
+    for (; p0 < p_hi; p0 += 64) {
+      const int64_t pn = p0 + 64;
+      const TJ* jn = row_of(pn < p_hi ? pn : p0);
+      d4v G[kVNC];
+#pragma unroll
+      for (int u = 0; u < kVNC; ++u) G[u] = zero4();
+      for (int kb = 0; kb < nkb; kb += 2) {  // nkb is even
+        ldj4(jr + min((int64_t)(kb + 1) * 16 + 4 * g, kmax4), fb);
+        {
+          d4v b[kVNC];
+#pragma unroll
+          for (int u = 0; u < kVNC; ++u) b[u] = xfrag(kb * kVNC + u);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int u = 0; u < kVNC; ++u) G[u] = mfma_f64(fa[s4], b[u][s4], G[u]);
+        }
+        const bool more = kb + 2 < nkb;
+        const TJ* jp = more ? jr + (int64_t)(kb + 2) * 16 : jn;
+        ldj4(jp + min((int64_t)4 * g, kmax4 - (more ? (int64_t)(kb + 2) * 16 : 0)), fa);
+        {
+          d4v b[kVNC];
+#pragma unroll
+          for (int u = 0; u < kVNC; ++u) b[u] = xfrag((kb + 1) * kVNC + u);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int u = 0; u < kVNC; ++u) G[u] = mfma_f64(fb[s4], b[u][s4], G[u]);
+        }
+      }
+      // C layout: lane holds pairs p0 + g + 4 r of its four columns
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t pr = p0 + g + 4 * r;
+        const int64_t pc = min(pr, p_hi - 1);
+        const int32_t src = pair_src[pc];
+        const double ok = (pr < p_hi && src >= 0 && src < n_atoms) ? 1.0 : 0.0;
+        const int64_t sr = min(max((int64_t)src, (int64_t)0), n_atoms - 1);
+        const d4v sv = *reinterpret_cast<const d4v*>(S + sr * ldS + scol);
+        const double rv[3] = {ok * pair_r[3 * pc], ok * pair_r[3 * pc + 1],
+                              ok * pair_r[3 * pc + 2]};
+#pragma unroll
+        for (int u = 0; u < kVNC; ++u) {
+          const double w = sv[u] * cm[u] * G[u][r];
+#pragma unroll
+          for (int al = 0; al < 3; ++al) acc[al][u] += rv[al] * w;
+        }
+      }
+      jr = jn;
+    }
+  }
+  // sum the four lane groups (pair rows), then the four pair streams of each beta
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int u = 0; u < kVNC; ++u) {
+      acc[al][u] += __shfl_xor(acc[al][u], 16);
+      acc[al][u] += __shfl_xor(acc[al][u], 32);
+    }
+  if (g == 0) {
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int u = 0; u < kVNC; ++u) red[stream][3 * al + beta][4 * idx + u] = acc[al][u];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int64_t col = colbase + threadIdx.x;
+    if (col < M) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const double t = red[0][q][threadIdx.x] + red[1][q][threadIdx.x] +
+                         red[2][q][threadIdx.x] + red[3][q][threadIdx.x];
+        K[(9 * c + q) + col * ldk] = -t;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const double* X,
@@ -166,6 +325,28 @@ void virial_rows_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, cons
   // dealt to the XCDs in turn
   const int64_t n_ct = (M + 63) / 64;
   dim3 grid(xcd_group_tile_blocks(n_cfg, n_ct));
+  if (D % 4 == 0 && D >= 4 && D <= 16 * kVMaxKb && ldS % 4 == 0 && ldS >= 4) {
+    const int nkb = 2 * (int)((D + 31) / 32);  // even, 16-deep blocks
+    const size_t lds = (size_t)nkb * kVNC * 64 * 4 * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      const int mx = (int)((size_t)kVMaxKb * kVNC * 64 * 4 * sizeof(double));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_virial_rows_lds<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_virial_rows_lds<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+      attr = true;
+    }
+    if (jac_f32)
+      hipLaunchKernelGGL(k_virial_rows_lds<float>, grid, dim3(64 * kVW), lds, st,
+                         reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, cfg_ptr,
+                         pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk, n_ct, n_cfg, nkb);
+    else
+      hipLaunchKernelGGL(k_virial_rows_lds<double>, grid, dim3(64 * kVW), lds, st,
+                         reinterpret_cast<const double*>(jac), ldj, D, X, ldx, M, S, ldS, cfg_ptr,
+                         pair_ptr, pair_src, pair_r, n_atoms, n_pairs, K, ldk, n_ct, n_cfg, nkb);
+    return;
+  }
   if (jac_f32)
     hipLaunchKernelGGL(k_virial_rows<float>, grid, dim3(512), 0, st,
                        reinterpret_cast<const float*>(jac), ldj, D, X, ldx, M, S, ldS, cfg_ptr,
