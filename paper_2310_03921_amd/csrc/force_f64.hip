@@ -436,6 +436,68 @@ __global__ __launch_bounds__(256) void k_pair_dots(const TJ* __restrict__ jac, i
   }
 }
 
+// The same products for D % 4 == 0, D <= 1024, with every load of a wave
+// issued before any use: a wave takes PB consecutive pairs (PB * IT = 4, IT =
+// 256-element segments per row) and a lane the 4-element segments 4 lane +
+// 256 it of the pairs' three Jacobian rows and source gradients.  Segments
+// past D re-read the row's last four elements and are weighted by zero; a
+// pair past n_pairs re-reads the last pair and is not stored.
+template <typename TJ, int IT, int PB>
+__global__ __launch_bounds__(256) void k_pair_dots4(const TJ* __restrict__ jac, int64_t ldj,
+                                                    int64_t D, const double* __restrict__ gm,
+                                                    int64_t ldg, const int32_t* __restrict__ src,
+                                                    int64_t n_pairs,
+                                                    double* __restrict__ f_pair) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * PB;
+  if (p0 >= n_pairs) return;
+  int64_t kk[IT];
+  double wk[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int64_t k = 4 * lane + 256 * it;
+    kk[it] = min(k, D - 4);
+    wk[it] = k < D ? 1.0 : 0.0;
+  }
+  double gv[PB][IT][4], jv[PB][3][IT][4];
+  int32_t si[PB];
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int64_t p = min(p0 + q, n_pairs - 1);
+    si[q] = src[p];
+    const double* gr = gm + (int64_t)max(si[q], 0) * ldg;
+    const TJ* jr = jac + p * 3 * ldj;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      ldj4(gr + kk[it], gv[q][it]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ldj4(jr + a * ldj + kk[it], jv[q][a][it]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    double s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double t = 0.0;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        double u = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u += jv[q][a][it][e] * gv[q][it][e];
+        t += wk[it] * u;
+      }
+      s[a] = wave_sum(t);
+    }
+    const int64_t p = p0 + q;
+    if (lane == 0 && p < n_pairs) {
+      const double ok = si[q] >= 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) f_pair[p * 3 + a] = ok * s[a];
+    }
+  }
+}
+
 __global__ void k_gather_forces(const double* __restrict__ f_pair,
                                 const int64_t* __restrict__ tgt_ptr,
                                 const int32_t* __restrict__ tgt_pair, int64_t n_atoms,
@@ -644,7 +706,36 @@ void forces_f64(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const dou
                 const int64_t* tgt_ptr, const int32_t* tgt_pair, double* f_pair, double* forces,
                 hipStream_t st) {
   if (n_atoms <= 0) return;
-  if (n_pairs > 0) {
+  if (n_pairs > 0 && D % 4 == 0 && D >= 4 && D <= 1024 && ldg % 4 == 0) {
+    // IT 256-element segments per row and PB = 4 / IT pairs per wave, 4 waves a block
+    const int it = (int)((D + 255) / 256);
+    const unsigned b4 = cdiv(cdiv(n_pairs, 4), 4), b2 = cdiv(cdiv(n_pairs, 2), 4),
+                   b1 = cdiv(n_pairs, 4);
+    const dim3 blk(256);
+    if (jac_f32) {
+      const float* j = reinterpret_cast<const float*>(jac);
+      if (it == 1)
+        hipLaunchKernelGGL((k_pair_dots4<float, 1, 4>), dim3(b4), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+      else if (it == 2)
+        hipLaunchKernelGGL((k_pair_dots4<float, 2, 2>), dim3(b2), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+      else
+        hipLaunchKernelGGL((k_pair_dots4<float, 4, 1>), dim3(b1), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+    } else {
+      const double* j = reinterpret_cast<const double*>(jac);
+      if (it == 1)
+        hipLaunchKernelGGL((k_pair_dots4<double, 1, 4>), dim3(b4), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+      else if (it == 2)
+        hipLaunchKernelGGL((k_pair_dots4<double, 2, 2>), dim3(b2), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+      else
+        hipLaunchKernelGGL((k_pair_dots4<double, 4, 1>), dim3(b1), blk, 0, st, j, ldj, D, g, ldg,
+                           pair_src, n_pairs, f_pair);
+    }
+  } else if (n_pairs > 0) {
     const unsigned blocks = (unsigned)std::min<int64_t>((n_pairs + 3) / 4, 65536);
     if (jac_f32)
       hipLaunchKernelGGL(k_pair_dots<float>, dim3(blocks), dim3(256), 0, st,

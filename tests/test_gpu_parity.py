@@ -266,6 +266,26 @@ def test_predict_and_forces(gapx, gap):
     close(F2.cpu(), F, TOL, "gap_forces")
 
 
+@pytest.mark.parametrize("D,jdt", [(300, None), (300, "f32"), (1024, "f32")])
+def test_predict_forces_wide_descriptors(gapx, gap, D, jdt):
+    # descriptor widths that take two and four 256-element segments per row in
+    # the force contraction
+    w = synth.Workload("wide", 17, n_cfg=5, atoms_lo=6, atoms_hi=19, D=D, nb=5, M=40)
+    b, X = batch_and_sparse(w)
+    jac = b.jac.astype(np.float32) if jdt == "f32" else b.jac
+    c = synth.hidden_coefficients(w)
+    e, ec, g, F = oracle.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, jac, X, c, w.zeta,
+                                 w.delta)
+    atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, jac,
+                                 jac_dtype=torch.float32 if jdt == "f32" else None)
+    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+    out = gap.predict(atoms, sp, torch.tensor(c, device="cuda"), e_atom=True, e_cfg=True,
+                      dEdd=True, forces=True)
+    close(out["e_atom"].cpu().numpy(), e, TOL, "e_atom")
+    close(out["dEdd"].cpu().numpy(), g, TOL, "dEdd")
+    close(out["forces"].cpu().numpy(), F, TOL, "forces")
+
+
 def test_predict_ragged(gapx, gap):
     w = ragged_workload(23)
     b, X = batch_and_sparse(w)
