@@ -35,9 +35,9 @@ PEAK_HBM_GBS = 8000.0
 FORCE_TRAFFIC = {
     "workload": "fit_fp64",
     "sources": ["paper_2310_03921_amd/csrc/force_f64.hip", "paper_2310_03921_amd/csrc/common.h"],
-    "sha256": "7a97e336effa3d9656482b4643fada72e6d9b592ec8a79af823a2792963a2ed9",
-    "fetch_kib": 50290389, "fetch_scale": 2.000,
-    "write_kib": 18375146, "write_scale": 1.000,
+    "sha256": "c4ca57d49ccc1e5b60388b78087865477b7e9d8639a158de8471a7d77c5b8d7c",
+    "fetch_kib": 51599202, "fetch_scale": 2.000,
+    "write_kib": 18350936, "write_scale": 1.000,
 }
 
 
