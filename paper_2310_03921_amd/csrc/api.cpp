@@ -207,6 +207,7 @@ void run_split(gap_handle* h, const gap_sparse* sp, const SplitWs& w, bool trans
 // Predict internals shared by gap_predict and the refinement residual.
 struct PredictWs {
   size_t W, e_atom, g, f_pair;
+  size_t epart = 0;  // per-column-group energy partials of the P-stage
   PairWs pairs;
   SplitWs split;
 };
@@ -217,6 +218,7 @@ void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool ne
   if (bf16) layout_split(L, M, D, true, w.split);
   w.W = need_g ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1)) : 0;
   w.e_atom = need_eatom ? L.take(sizeof(double) * std::max<int64_t>(N, 1)) : 0;
+  w.epart = L.take(sizeof(double) * std::max<int64_t>(N * gapk::pstage_groups(M), 1));
   w.g = need_gbuf ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1)) : 0;
   w.f_pair = need_forces ? L.take(sizeof(double) * std::max<int64_t>(3 * a->n_pairs, 1)) : 0;
   if (need_forces) layout_pairs(L, N, a->n_pairs, w.pairs);
@@ -244,7 +246,8 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
                         ea, nullptr, h->stream);
   } else {
     gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
-                     sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream);
+                     sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream, nullptr, 0,
+                     at<double>(h, w.epart));
   }
   if (e_cfg) gapk::segment_sum_f64(ea, a->cfg_ptr, a->n_cfg, N, e_cfg, h->stream);
   if (forces) {

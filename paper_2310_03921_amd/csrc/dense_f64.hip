@@ -564,6 +564,184 @@ __global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
 }
 constexpr size_t kSxLds = 2 * (kSxKC / 16) * kSxSub * sizeof(double);
 
+// P-stage of predict (MODE 0) and backward (MODE 1) for D % 4 == 0 in the
+// layout of k_gemm_wx_lds: a block of eight waves covers 64 rows and a group of
+// 256 sparse-point columns (blockIdx.y), the contraction over D runs in 32-wide
+// chunks whose X rows are staged in LDS (double-buffered, in the matrix core's
+// operand order, shared by the eight waves), and each wave reads its 16
+// descriptor rows straight from memory.  Loads in the loop are unconditional:
+// rows past n, columns past M and k past D read clamped valid addresses and are
+// cancelled by zero factors when staged (X) or by the zero X rows (descriptors).
+// The epilogue is the one of k_pstage: p = d_i . x_m, W[i][m] (MODE 0: delta^2
+// zeta c_m p^(zeta-1); MODE 1: the same times g_e[i], zero row padding), and
+// MODE 0: per-row energy partials of the column group in e_part[group][i];
+// MODE 1: dc_part[row block][m] = sum over the block's rows of g_e[i] delta^2 p^zeta.
+template <typename TD, int MODE>
+__global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
+    const TD* __restrict__ desc, int64_t ldd, int64_t n, const double* __restrict__ X,
+    int64_t ldx, int64_t M, int64_t D, int zeta, double delta, const double* __restrict__ cc,
+    const double* __restrict__ g_e, double* __restrict__ W, int64_t ldw,
+    double* __restrict__ e_part, double* __restrict__ dc_part) {
+  extern __shared__ __attribute__((aligned(16))) double xs[];  // [2][kSxKC / 16][kSxSub]
+  __shared__ double red[4][2][128];  // [row-group wave][column half][row or column]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int ch = wave & 1, rgw = wave >> 1;
+  const int64_t rowbase = (int64_t)blockIdx.x * 64 + rgw * 16;
+  const int64_t cg = (int64_t)blockIdx.y * 256;
+  const TD* drow = desc + min(rowbase + idx, n - 1) * ldd;
+  const int64_t nch = (D + kSxKC - 1) / kSxKC;
+
+  // staging: thread t moves the 4-element groups gi = t + 512 it (it < 4) of the
+  // chunk: sparse point m = cg + gi / 8, k = 32 c + 4 (gi % 8) .. + 3
+  const double* xrow[4];
+  double xok[4];
+  int soff[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int gi = threadIdx.x + 64 * kSxW * it, ml = gi >> 3, dq = gi & 7;
+    const int64_t m = cg + ml;
+    xrow[it] = X + min(m, M - 1) * ldx;
+    xok[it] = m < M ? 1.0 : 0.0;
+    soff[it] = (dq >> 2) * kSxSub + (ml >> 4) * 256 + ((dq & 3) * 16 + (ml & 15)) * 2;
+  }
+  auto fetch = [&](int64_t c, d4v v[4]) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int dq = (threadIdx.x + 64 * kSxW * it) & 7;
+      v[it] = *reinterpret_cast<const d4v*>(xrow[it] + min(c * kSxKC + 4 * dq, D - 4));
+    }
+  };
+  auto stage = [&](int64_t c, double* dst, const d4v v[4]) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int dq = (threadIdx.x + 64 * kSxW * it) & 7;
+      const double f = (c * kSxKC + 4 * dq < D) ? xok[it] : 0.0;
+      const d2v lo = {f * v[it][0], f * v[it][1]}, hi = {f * v[it][2], f * v[it][3]};
+      *reinterpret_cast<d2v*>(dst + soff[it]) = lo;
+      *reinterpret_cast<d2v*>(dst + soff[it] + 128) = hi;
+    }
+  };
+  auto afrag = [&](int64_t c, double a[8]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t k = min(c * kSxKC + 16 * h + 4 * g, D - 4);
+      load4u(drow + k, a + 4 * h);
+    }
+  };
+
+  d4v sv[4];
+  double a_cur[8], a_nxt[8];
+  fetch(0, sv);
+  afrag(0, a_cur);
+  stage(0, xs, sv);
+  __syncthreads();
+  d4v acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = zero4();
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t cn = min(c + 1, nch - 1);
+    fetch(cn, sv);
+    afrag(cn, a_nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    const double* buf = xs + (c & 1) * (kSxKC / 16) * kSxSub;
+#pragma unroll
+    for (int sc = 0; sc < kSxKC / 16; ++sc) {
+      const d2v* xb = reinterpret_cast<const d2v*>(buf + sc * kSxSub) + ch * 8 * 128 + lane;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        d2v b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = xb[u * 128 + h * 64];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[4 * sc + 2 * h + j], b[u][j], acc[u]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    stage(cn, xs + ((c + 1) & 1) * (kSxKC / 16) * kSxSub, sv);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a_cur[q] = a_nxt[q];
+  }
+
+  const double d2 = delta * delta, d2z = d2 * zeta;
+  double ge[4], esum[4] = {0.0, 0.0, 0.0, 0.0};
+  bool rv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t rr = rowbase + g + 4 * r;
+    rv[r] = rr < n;
+    ge[r] = (MODE == 1 && rv[r]) ? g_e[rr] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t col = cg + ch * 128 + u * 16 + idx;
+    const bool cvalid = col < M;
+    const double cm = cvalid ? cc[col] : 0.0;
+    double csum = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rowbase + g + 4 * r;
+      if (!rv[r]) continue;
+      if (!cvalid) {
+        if (W && col < ldw) W[rr * ldw + col] = 0.0;  // row padding
+        continue;
+      }
+      const double p = acc[u][r];
+      const double pz1 = ipow(p, zeta - 1);
+      const double kval = d2 * pz1 * p;
+      if (MODE == 0) {
+        esum[r] += cm * kval;
+        if (W) W[rr * ldw + col] = d2z * cm * pz1;
+      } else {
+        csum += ge[r] * kval;
+        if (W) W[rr * ldw + col] = ge[r] * d2z * cm * pz1;
+      }
+    }
+    if (MODE == 1) {
+      csum += __shfl_xor(csum, 16);
+      csum += __shfl_xor(csum, 32);
+      if (g == 0) red[rgw][ch][u * 16 + idx] = csum;
+    }
+  }
+  if (MODE == 0) {
+    // row sums over the wave's 128 columns, then the two column halves
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) esum[r] += __shfl_xor(esum[r], o);
+      if (idx == 0) red[rgw][ch][g + 4 * r] = esum[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int rgi = threadIdx.x >> 4, rl = threadIdx.x & 15;
+      const int64_t rr = (int64_t)blockIdx.x * 64 + threadIdx.x;
+      if (e_part && rr < n) e_part[blockIdx.y * n + rr] = red[rgi][0][rl] + red[rgi][1][rl];
+    }
+  } else {
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      const int chh = threadIdx.x >> 7, cl = threadIdx.x & 127;
+      const int64_t col = cg + threadIdx.x;
+      if (col < M)
+        dc_part[(int64_t)blockIdx.x * M + col] =
+            ((red[0][chh][cl] + red[1][chh][cl]) + red[2][chh][cl]) + red[3][chh][cl];
+    }
+  }
+}
+
+// e[i] = sum over the column groups g of part[g][i], in group order
+__global__ void k_sum_groups(const double* __restrict__ part, int64_t ng, int64_t n,
+                             double* __restrict__ e) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t q = 0; q < ng; ++q) s += part[q * n + i];
+    e[i] = s;
+  }
+}
+
 // y[i] = sum_k A[i + k * lda] x[k]  (column-major GEMV): 64 rows per block, 16 waves
 // splitting k, partial sums combined in LDS in a fixed order.
 __global__ __launch_bounds__(1024) void k_gemv_cm(const double* __restrict__ A, int64_t lda,
@@ -755,12 +933,53 @@ void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atom
 
 int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }
 
+int64_t pstage_groups(int64_t M) { return (M + 255) / 256; }
+
 void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
                 const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
                 int64_t ldw, double* e_atom, double* dc_part, hipStream_t st,
-                const double* Sx, int64_t ldsx) {
+                const double* Sx, int64_t ldsx, double* e_part) {
   if (n <= 0 || M <= 0) return;
+  // LDS-staged form: energies (mode 0) go through per-column-group partials
+  const bool lds_ok = D % 4 == 0 && D >= 4 && ldd % 4 == 0 && ldx % 4 == 0 && c &&
+                      (reinterpret_cast<uintptr_t>(desc) & 31) == 0 &&
+                      (reinterpret_cast<uintptr_t>(X) & 31) == 0 &&
+                      ((mode == 0 && (!e_atom || e_part)) || (mode == 1 && g_e));
+  if (lds_ok) {
+    static bool attr = false;
+    if (!attr) {
+      const void* ks[4] = {reinterpret_cast<const void*>(&k_pstage_lds<float, 0>),
+                           reinterpret_cast<const void*>(&k_pstage_lds<float, 1>),
+                           reinterpret_cast<const void*>(&k_pstage_lds<double, 0>),
+                           reinterpret_cast<const void*>(&k_pstage_lds<double, 1>)};
+      for (const void* k : ks)
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
+      attr = true;
+    }
+    const int64_t ng = pstage_groups(M);
+    const dim3 grid((unsigned)pstage_row_blocks(n), (unsigned)ng), blk(64 * kSxW);
+    double* ep = e_atom ? e_part : nullptr;
+    if (desc_f32) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_pstage_lds<float, 0>), grid, blk, kSxLds, st, tptr<float>(desc),
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+      else
+        hipLaunchKernelGGL((k_pstage_lds<float, 1>), grid, blk, kSxLds, st, tptr<float>(desc),
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+    } else {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_pstage_lds<double, 0>), grid, blk, kSxLds, st, tptr<double>(desc),
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+      else
+        hipLaunchKernelGGL((k_pstage_lds<double, 1>), grid, blk, kSxLds, st, tptr<double>(desc),
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+    }
+    if (mode == 0 && e_atom)
+      hipLaunchKernelGGL(k_sum_groups, dim3(std::max(1u, std::min(cdiv(n, 256), 65536u))),
+                         dim3(256), 0, st, e_part, ng, n, e_atom);
+    return;
+  }
   dim3 grid((unsigned)pstage_row_blocks(n));
   if (desc_f32)
     hipLaunchKernelGGL(k_pstage<float>, grid, dim3(256), 0, st, mode, tptr<float>(desc), ldd, n,

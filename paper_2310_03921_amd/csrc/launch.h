@@ -85,11 +85,14 @@ void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t
 //                      (column partial sums of W over the row block)
 //   mode 3 (residual, force part with a stored S): dc_part = column partial sums of
 //                      -S[i][m] q_im, q = H X^T (desc unused)
+// Column groups of the LDS-staged P-stage; e_part (for e_atom in mode 0) holds
+// pstage_groups(M) x n doubles.
+int64_t pstage_groups(int64_t M);
 void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
                 const double* c, const double* g_e, const double* H, int64_t ldh, double* W,
                 int64_t ldw, double* e_atom, double* dc_part, hipStream_t st,
-                const double* Sx = nullptr, int64_t ldsx = 0);
+                const double* Sx = nullptr, int64_t ldsx = 0, double* e_part = nullptr);
 int64_t pstage_row_blocks(int64_t n);
 // out[i][j] = scale_i * sum_k W[i][k] X[k][j]   (n x D, row-major ldo); scale = 1 if row_scale null
 // Two-body SE descriptor: rows (energies, then 3 per atom) of the pair-distance
