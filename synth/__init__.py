@@ -193,13 +193,23 @@ def sparse_points(w: Workload, batch: Batch | None = None) -> np.ndarray:
     gptr = global_atom_offsets(w)
     cfg_of = np.searchsorted(gptr, idx, side="right") - 1
     X = np.empty((w.M, w.D), dtype=np.float64)
-    for c in np.unique(cfg_of):
+
+    def work(c):
         n = int(gptr[c + 1] - gptr[c])
         d = np.empty((n, w.D), dtype=_NP[w.desc_dtype])
         nbr = np.empty((n, w.nb), dtype=np.int64)
         _draw_config(w, int(c), n, False, d, None, nbr)
         sel = np.nonzero(cfg_of == c)[0]
         X[sel] = d[idx[sel] - gptr[c]].astype(np.float64)
+
+    cfgs = np.unique(cfg_of)
+    nthreads = min(16, os.cpu_count() or 1)
+    if nthreads > 1 and len(cfgs) > 1:
+        with ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(work, cfgs))
+    else:
+        for c in cfgs:
+            work(c)
     return X
 
 
