@@ -363,6 +363,35 @@ def fold_rows(T, Knm_block, y_block, sigma_block):
     return augmented_r(stacked, rhs)
 
 
+def refine_rows(Knm_rows, y, sigma, c):
+    """A batch's share of one refinement step of the least-squares fit (Sec.
+    "Theory", least-squares form), taken with exact rows.
+
+    With r = Sigma^-1/2 (y - K c) over the batch's rows, returns
+    (K^T Sigma^-1/2 r, r . r): summed over all batches, the first is the
+    observation rows' part of A^T (b - A c).
+    """
+    K = np.asarray(Knm_rows, dtype=np.float64)
+    w = 1.0 / np.asarray(sigma, dtype=np.float64)
+    r = w * (np.asarray(y, dtype=np.float64) - K @ np.asarray(c, dtype=np.float64))
+    return K.T @ (w * r), float(r @ r)
+
+
+def refine_solve(R, Kmm, jitter, g, c):
+    """c + dc with R^T R dc = g + U^T (0 - U c), the seminormal correction step.
+
+    g is the observation rows' part of A^T r (refine_rows summed over batches);
+    the rows U_MM of A (zero targets) add U^T (0 - U c) = -(K_MM + jitter I) c.
+    R is upper triangular M x M, the factor of A or of an approximation of it.
+    """
+    c = np.asarray(c, dtype=np.float64)
+    Kmm = np.asarray(Kmm, dtype=np.float64)
+    gt = np.asarray(g, dtype=np.float64) - (Kmm @ c + jitter * c)
+    R = np.asarray(R, dtype=np.float64)[:len(c), :len(c)]
+    z = sla.solve_triangular(R, gt, trans="T", lower=False)
+    return c + sla.solve_triangular(R, z, lower=False)
+
+
 def fold_solve(T):
     """c = R^-1 (Q^T b)[0:M] and the least-squares residual norm |T[M][M]|."""
     M = T.shape[0] - 1

@@ -266,6 +266,49 @@ def check_fold_streamed(orc):
     assert np.linalg.norm(sols[0] - sols[1]) <= 1e-10 * np.linalg.norm(sols[0])
 
 
+def check_refine_step(orc):
+    # One seminormal step with the exact factor R of A lands on the least-squares
+    # solution (SVD route) from any starting c, since c + (A^T A)^-1 A^T (b - A c)
+    # = (A^T A)^-1 A^T b; the rows' share is additive over any split into
+    # batches; at the solution the observation rows' share equals
+    # (K_MM + jitter I) c (the normal equations); and with an approximate R
+    # (K perturbed by 1e-3) the steps still converge to that solution.
+    w, b, X, jit = small_fit_problem(seed=9, jitter=1e-2)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal(b.n_rows)
+    sig = synth.sigma_rows(w, b.counts)
+    L = np.linalg.cholesky(Kmm + jit * np.eye(w.M))
+    A = np.vstack([K / sig[:, None], L.T])
+    bb = np.concatenate([y / sig, np.zeros(w.M)])
+    ref = np.linalg.lstsq(A, bb, rcond=None)[0]
+    R = np.linalg.qr(A, mode="r")
+    c0 = rng.standard_normal(w.M)
+    n = b.n_rows
+    g, rr = orc.refine_rows(K, y, sig, c0)
+    g2 = np.zeros(w.M)
+    rr2 = 0.0
+    for r0, r1 in ((0, 4), (4, 4), (4, n // 2), (n // 2, n)):
+        gb, rb = orc.refine_rows(K[r0:r1], y[r0:r1], sig[r0:r1], c0)
+        g2 += gb
+        rr2 += rb
+    assert np.linalg.norm(g2 - g) <= 1e-12 * np.linalg.norm(g)
+    assert abs(rr2 - rr) <= 1e-12 * rr
+    assert abs(rr - np.sum(((y - K @ c0) / sig) ** 2)) <= 1e-12 * rr
+    c1 = orc.refine_solve(R, Kmm, jit, g, c0)
+    assert np.linalg.norm(c1 - ref) <= 1e-8 * np.linalg.norm(ref)
+    gs, _ = orc.refine_rows(K, y, sig, ref)
+    lhs = Kmm @ ref + jit * ref
+    assert np.linalg.norm(gs - lhs) <= 1e-8 * np.linalg.norm(lhs)
+    Kp = K * (1.0 + 1e-3 * rng.standard_normal(K.shape))
+    Rp = np.linalg.qr(np.vstack([Kp / sig[:, None], L.T]), mode="r")
+    c = np.zeros(w.M)
+    for _ in range(8):
+        c = orc.refine_solve(Rp, Kmm, jit, orc.refine_rows(K, y, sig, c)[0], c)
+    assert np.linalg.norm(c - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
 def check_local_rows(orc):
     # Local-property rows of every atom: summed over each configuration they are
     # the energy rows (L-hat sums the local terms), multiplied by c they are the
@@ -506,7 +549,7 @@ ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_energy_rows_bruteforce, check_sparse_self_entry,
               check_force_rows_complex_step, check_force_rows_central_fd,
               check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
-              check_fold_streamed, check_local_rows, check_virial_rows_strain,
+              check_fold_streamed, check_refine_step, check_local_rows, check_virial_rows_strain,
               check_predict_variance, check_cur_leverage, check_2b_rows,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,

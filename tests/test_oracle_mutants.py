@@ -24,6 +24,8 @@ _orig_curlev = G.cur_leverage
 _orig_dr = G.se2b_kernel_dr
 _orig_2b = G.build_2b_rows
 _orig_fcut = G.cutoff_fn
+_orig_refine_rows = G.refine_rows
+_orig_refine_solve = G.refine_solve
 
 
 def knm_sign_flip(*a):
@@ -196,6 +198,23 @@ def cutoff_half_width(r, r_cut, width):
     return _orig_fcut(r, r_cut, 0.5 * width)
 
 
+def refine_rows_unweighted(Knm_rows, y, sigma, c):
+    # A^T r without the second Sigma^-1/2
+    K = np.asarray(Knm_rows, float)
+    w = 1.0 / np.asarray(sigma, float)
+    r = w * (np.asarray(y, float) - K @ c)
+    return K.T @ r, float(r @ r)
+
+
+def refine_solve_no_jitter(R, Kmm, jitter, g, c):
+    return _orig_refine_solve(R, Kmm, 0.0, g, c)
+
+
+def refine_solve_regulariser_sign(R, Kmm, jitter, g, c):
+    c = np.asarray(c, float)
+    return _orig_refine_solve(R, -np.asarray(Kmm, float), -jitter, g, c)
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
     ("build_knm", knm_drop_last_atom),
@@ -221,6 +240,9 @@ MUTANTS = [
     ("se2b_kernel_dr", se2b_dr_no_cutoff_slope),
     ("build_2b_rows", build_2b_rows_target_sign),
     ("cutoff_fn", cutoff_half_width),
+    ("refine_rows", refine_rows_unweighted),
+    ("refine_solve", refine_solve_no_jitter),
+    ("refine_solve", refine_solve_regulariser_sign),
 ]
 
 
