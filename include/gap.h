@@ -312,6 +312,33 @@ gap_status gap_fold_rows(gap_handle *h, double *T, int64_t ld, int64_t M, int64_
 gap_status gap_fold_solve(gap_handle *h, const double *T, int64_t ld, int64_t M, double *c,
                           double *lsq_resid, double *rdiag_minmax);
 
+/* Refinement by batches of observation rows (Sec. "Theory", least-squares
+ * form; the residual is taken in FP64 from the exact rows while R may come from
+ * approximate ones, e.g. BF16X3 rows folded by gap_fold_rows).  One step over
+ * the whole training set, with r = b - A c the residual of the stacked system
+ * [Sigma^-1/2 L-hat K_NM ; U] c = [Sigma^-1/2 y ; 0]:
+ *   g = 0 (device, M doubles); gap_refine_rows for every batch;
+ *   gap_refine_solve, which adds the rows U and computes c += (R^T R)^-1 g.
+ *
+ * gap_refine_rows: for the batch a's rows (its energy rows, then three force
+ *   rows per atom: the row order of gap_build_knm), with K the exact FP64 rows
+ *   computed matrix-free from a's descriptors and Jacobians (needs jac) and
+ *   r = Sigma^-1/2 (y - K c):
+ *     g[0:M] += K^T Sigma^-1/2 r,   rr[0] += r . r   (rr may be NULL).
+ *   c [M], y and sigma [n_cfg + 3 n_atoms], g, rr: device FP64.  D <= 2048.
+ *   Asynchronous on the handle's stream; a batch without rows is a no-op. */
+gap_status gap_refine_rows(gap_handle *h, const gap_atoms *a, const gap_sparse *sp,
+                           const double *c, const double *y, const double *sigma, double *g,
+                           double *rr);
+/* gap_refine_solve: adds the regulariser rows' share U^T (0 - U c) =
+ *   -(K_MM + jitter I) c to g, then solves R^T R dc = g and sets c += dc; g is
+ *   overwritten by dc.  R: the upper triangle of the first M columns of a
+ *   factor with leading dimension ldr >= M (A after gap_fit, or a fold state
+ *   T).  Kmm [M x M] col-major (ld = M), c and g [M]: device.  Synchronous.
+ *   Returns GAP_E_RANK if some R_kk is zero or not finite. */
+gap_status gap_refine_solve(gap_handle *h, const double *R, int64_t ldr, int64_t M,
+                            const double *Kmm, double jitter, double *g, double *c);
+
 /* Predict with coefficients c [M] (eq. epsilon and the chain rule for forces):
  *   e_atom [n_atoms]      eps_i = sum_m c_m delta^2 (d_i . x_m)^zeta
  *   e_cfg  [n_cfg]        sum of eps_i over the configuration

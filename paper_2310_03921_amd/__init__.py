@@ -85,6 +85,8 @@ def lib():
             "gap_fold_init": ([P, P, I64, I64, P, ctypes.c_double], S),
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
+            "gap_refine_rows": ([P, P, P, P, P, P, P, P], S),
+            "gap_refine_solve": ([P, P, I64, I64, P, ctypes.c_double, P, P], S),
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_forces": ([P, P, P, P], S),
@@ -467,6 +469,37 @@ class Gap:
                                          ctypes.byref(res), rd))
         self._keep = None
         return c, res.value, (rd[0], rd[1])
+
+    @staticmethod
+    def _inplace_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise GapError(f"{name} must be a contiguous float64 tensor (updated in place)")
+        return t
+
+    def refine_rows(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, y: torch.Tensor,
+                    sigma: torch.Tensor, g: torch.Tensor, rr: torch.Tensor | None = None):
+        """g += K^T Sigma^-1/2 r (and rr += r . r) over the batch's rows, with
+        r = Sigma^-1/2 (y - K c) and K the exact FP64 rows; y and sigma in the
+        batch's row order (energies of its configurations, then forces)."""
+        c, y, sigma = _f64(c), _f64(y), _f64(sigma)
+        self._inplace_f64(g, "g")
+        if rr is not None:
+            self._inplace_f64(rr, "rr")
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_refine_rows(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
+                                          _ptr(y), _ptr(sigma), _ptr(g), _ptr(rr)))
+        # the call is asynchronous: keep the inputs alive until the stream passes it
+        self._keep = (c, y, sigma)
+
+    def refine_solve(self, R: torch.Tensor, M: int, Kmm: torch.Tensor, jitter: float,
+                     g: torch.Tensor, c: torch.Tensor):
+        """c += (R^T R)^-1 (g - (K_MM + jitter I) c); g is overwritten by the step.
+        R: a column-major factor (A after fit, or a fold state)."""
+        self._inplace_f64(g, "g")
+        self._inplace_f64(c, "c")
+        self._check(lib().gap_refine_solve(self._h, _ptr(R), R.shape[1], M, _ptr(_f64(Kmm)),
+                                           float(jitter), _ptr(g), _ptr(c)))
+        self._keep = None
 
     def predict(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, precision: str = "fp64",
                 e_atom=True, e_cfg=True, dEdd=False, forces=False):

@@ -883,6 +883,81 @@ gap_status gap_fold_solve(gap_handle* h, const double* T, int64_t ld, int64_t M,
   return s;
 }
 
+// Matrix-free FP64 residual of a batch's observation rows (the refinement of
+// a fit whose R came from approximate rows): workspace, the per-batch set-up,
+// and one pass r = Sigma^-1/2 (y - K c), g = K^T Sigma^-1/2 r.
+struct RefineWs {
+  size_t kc = 0, rtop = 0, v = 0, hbuf = 0, gvec = 0, dcp = 0, ke = 0;
+  PredictWs pw{};
+};
+
+void layout_refine(Layout& L, const gap_atoms* a, const gap_sparse* sp, RefineWs& w) {
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  const int64_t n_rows = a->n_cfg + 3 * N;
+  w.kc = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+  w.rtop = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+  w.v = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
+  w.hbuf = L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1));
+  w.gvec = L.take(sizeof(double) * M);
+  w.dcp = L.take(sizeof(double) * gapk::pstage_row_blocks(N) * M + 8);
+  w.ke = L.take(sizeof(double) * std::max<int64_t>(a->n_cfg, 1) * M);
+  // pw.W holds S = delta^2 zeta p^(zeta-1) for every pass over the batch.
+  layout_predict(L, a, sp, true, false, true, true, w.pw);
+}
+
+// Exact FP64 energy rows K_E and force-row weights S of the batch, and its
+// target-major pair view: every residual pass is then K_E c, the J^T
+// contraction of (S diag(c)) X, and their transposes.
+void refine_prepare(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const RefineWs& w) {
+  const int64_t N = a->n_atoms, nc = a->n_cfg, M = sp->M, D = sp->D;
+  gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, nc, N, sp->X,
+                        sp->ld_x, M, D, sp->zeta, sp->delta, at<double>(h, w.ke),
+                        std::max<int64_t>(nc, 1), at<double>(h, w.pw.W), ld4(M), h->stream);
+  run_pairs(h, a, w.pw.pairs, false);
+}
+
+// rtop = Sigma^-1/2 (y - K c) over the batch's rows (energy rows, then three
+// force rows per atom) and gvec = K^T Sigma^-1/2 rtop, K the exact FP64 rows.
+void refine_residual_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                          const RefineWs& w, const double* c, const double* y,
+                          const double* sigma) {
+  const int64_t N = a->n_atoms, nc = a->n_cfg, M = sp->M, D = sp->D;
+  const int64_t n_rows = nc + 3 * N;
+  const int64_t ldS = ld4(M), ldg = ld4(D), ldke = std::max<int64_t>(nc, 1);
+  double* S = at<double>(h, w.pw.W);
+  double* g = at<double>(h, w.pw.g);
+  double* kE = at<double>(h, w.ke);
+  double* kcp = at<double>(h, w.kc);
+  double* vv = at<double>(h, w.v);
+  double* gv = at<double>(h, w.gvec);
+  double* hb = at<double>(h, w.hbuf);
+  double* dcp = at<double>(h, w.dcp);
+  gapk::gemv_cm_f64(kE, ldke, nc, M, c, kcp, h->stream);
+  if (N > 0) {
+    gapk::gemm_wx_scaled_f64(S, ldS, N, M, c, sp->X, sp->ld_x, D, g, ldg, h->stream);
+    gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg,
+                     at<int32_t>(h, w.pw.pairs.src), N, a->n_pairs,
+                     at<int64_t>(h, w.pw.pairs.tgt_ptr), at<int32_t>(h, w.pw.pairs.tgt_pair),
+                     at<double>(h, w.pw.f_pair), kcp + nc, h->stream);
+  }
+  gapk::residual_top(y, sigma, kcp, n_rows, at<double>(h, w.rtop), h->stream);
+  gapk::div_sigma(at<double>(h, w.rtop), sigma, n_rows, vv, h->stream);
+  if (N > 0) {
+    gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
+                                  N, a->n_pairs, vv + nc, hb, ldg, h->stream);
+    if (gapk::resid_colsum_f64(hb, ldg, N, D, sp->X, sp->ld_x, M, S, ldS, dcp, h->stream)) {
+      gapk::reduce_rows_f64(dcp, gapk::resid_colsum_groups(N, M), M, gv, h->stream);
+    } else {
+      gapk::pstage_f64(3, nullptr, false, 0, N, sp->X, sp->ld_x, M, D, sp->zeta, sp->delta,
+                       nullptr, nullptr, hb, ldg, nullptr, 0, nullptr, dcp, h->stream, S, ldS);
+      gapk::reduce_rows_f64(dcp, gapk::pstage_row_blocks(N), M, gv, h->stream);
+    }
+  } else {
+    gapk::fill_f64(gv, M, 0.0, h->stream);
+  }
+  gapk::gemvt_cm_add_f64(kE, ldke, nc, M, vv, gv, h->stream);
+}
+
 gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const double* Kmm,
                    const double* y, const double* sigma, double jitter, const gap_atoms* train,
                    const gap_sparse* sp, int refine_steps, double* c, gap_fit_info* info) {
@@ -909,20 +984,11 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   Layout L;
   const size_t Lw = L.take(sizeof(double) * M * M);
   const size_t q = L.take(gapk::qr_workspace_bytes(m, M));
-  size_t kc = 0, rtop = 0, rbot = 0, v = 0, hbuf = 0, gvec = 0, dcp = 0, ke = 0;
-  PredictWs pw{};
+  size_t rbot = 0;
+  RefineWs rw;
   if (refine_steps > 0) {
-    const int64_t N = train->n_atoms;
-    kc = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
-    rtop = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
     rbot = L.take(sizeof(double) * M);
-    v = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
-    hbuf = L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1));
-    gvec = L.take(sizeof(double) * M);
-    dcp = L.take(sizeof(double) * gapk::pstage_row_blocks(N) * M + 8);
-    ke = L.take(sizeof(double) * std::max<int64_t>(train->n_cfg, 1) * M);
-    // pw.W holds S = delta^2 zeta p^(zeta-1) for the whole refinement.
-    layout_predict(L, train, sp, true, false, true, true, pw);
+    layout_refine(L, train, sp, rw);
   }
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
@@ -960,46 +1026,13 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
     return s;
   }
   if (refine_steps > 0) {
-    const gap_atoms* a = train;
-    const int64_t N = a->n_atoms, nc = a->n_cfg;
-    const int64_t ldS = ld4(M), ldg = ld4(D), ldke = std::max<int64_t>(nc, 1);
-    double* S = at<double>(h, pw.W);
-    double* g = at<double>(h, pw.g);
-    double* kE = at<double>(h, ke);
-    double* kcp = at<double>(h, kc);
-    double* vv = at<double>(h, v);
-    double* gv = at<double>(h, gvec);
+    double* gv = at<double>(h, rw.gvec);
     h->timer.begin(gapk::TM_REFINE);
-    // Exact FP64 energy rows K_E and force-row weights S, once: every residual
-    // below is then K_E c, J^T-contracted (S diag(c)) X, and their transposes.
-    gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, nc, N, sp->X,
-                          sp->ld_x, M, D, sp->zeta, sp->delta, kE, ldke, S, ldS, h->stream);
-    run_pairs(h, a, pw.pairs, false);
+    refine_prepare(h, train, sp, rw);
     for (int step = 0; step <= refine_steps; ++step) {
-      // r = b - A_exact c, matrix-free in FP64: K c = [K_E c ; F(c)].
-      gapk::gemv_cm_f64(kE, ldke, nc, M, c, kcp, h->stream);
-      gapk::gemm_wx_scaled_f64(S, ldS, N, M, c, sp->X, sp->ld_x, D, g, ldg, h->stream);
-      gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg,
-                       at<int32_t>(h, pw.pairs.src), N, a->n_pairs,
-                       at<int64_t>(h, pw.pairs.tgt_ptr), at<int32_t>(h, pw.pairs.tgt_pair),
-                       at<double>(h, pw.f_pair), kcp + nc, h->stream);
-      gapk::refine_residual(y, sigma, kcp, n_rows, Lm, M, M, c, at<double>(h, rtop),
-                            at<double>(h, rbot), h->stream);
-      // A^T r = K_E^T v_E + K_F^T v_F + U^T r_bot,  v = r_top / sigma
-      gapk::div_sigma(at<double>(h, rtop), sigma, n_rows, vv, h->stream);
-      gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
-                                    N, a->n_pairs, vv + nc, at<double>(h, hbuf), ldg, h->stream);
-      if (gapk::resid_colsum_f64(at<double>(h, hbuf), ldg, N, D, sp->X, sp->ld_x, M, S, ldS,
-                                 at<double>(h, dcp), h->stream)) {
-        gapk::reduce_rows_f64(at<double>(h, dcp), gapk::resid_colsum_groups(N, M), M, gv,
-                              h->stream);
-      } else {
-        gapk::pstage_f64(3, nullptr, false, 0, N, sp->X, sp->ld_x, M, D, sp->zeta, sp->delta,
-                         nullptr, nullptr, at<double>(h, hbuf), ldg, nullptr, 0, nullptr,
-                         at<double>(h, dcp), h->stream, S, ldS);
-        gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, gv, h->stream);
-      }
-      gapk::gemvt_cm_add_f64(kE, ldke, nc, M, vv, gv, h->stream);
+      // A^T r = K^T Sigma^-1/2 r_top + U^T r_bot with r = b - A_exact c
+      refine_residual_rows(h, train, sp, rw, c, y, sigma);
+      gapk::residual_bot(Lm, M, M, c, at<double>(h, rbot), h->stream);
       gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), gv, h->stream);
       gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);
       if (step == refine_steps) break;
@@ -1018,6 +1051,68 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   }
   if (info) *info = inf;
   return s;
+}
+
+gap_status gap_refine_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                           const double* c, const double* y, const double* sigma, double* g,
+                           double* rr) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, true);
+  if (s != GAP_OK) return s;
+  if (!c || !g) return fail(h, GAP_E_INVALID, "c / g are NULL");
+  if (sp->M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
+  if (sp->D > 2048) return fail(h, GAP_E_UNSUPPORTED, "refinement needs D <= 2048");
+  const int64_t n_rows = a->n_cfg + 3 * a->n_atoms;
+  if (n_rows == 0) return GAP_OK;
+  if (!y || !sigma) return fail(h, GAP_E_INVALID, "y / sigma are NULL");
+  Layout L;
+  RefineWs rw;
+  layout_refine(L, a, sp, rw);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  h->timer.begin(gapk::TM_REFINE);
+  refine_prepare(h, a, sp, rw);
+  refine_residual_rows(h, a, sp, rw, c, y, sigma);
+  gapk::axpy_f64(sp->M, 1.0, at<double>(h, rw.gvec), g, h->stream);
+  if (rr) gapk::sumsq_add_f64(at<double>(h, rw.rtop), n_rows, rr, h->stream);
+  h->timer.end(gapk::TM_REFINE);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_refine_solve(gap_handle* h, const double* R, int64_t ldr, int64_t M,
+                            const double* Kmm, double jitter, double* g, double* c) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  if (!R || !Kmm || !g || !c) return fail(h, GAP_E_INVALID, "NULL argument");
+  if (M < 1 || ldr < M) return fail(h, GAP_E_INVALID, "needs M >= 1 and ldr >= M");
+  if (M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
+  if (!(jitter >= 0.0) || !std::isfinite(jitter)) return fail(h, GAP_E_INVALID, "bad jitter");
+  Layout L;
+  const size_t q = L.take(gapk::qr_workspace_bytes(M + 1, M));
+  const size_t t1 = L.take(sizeof(double) * M);
+  const size_t t2 = L.take(sizeof(double) * M);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  gapk::QrWork qw;
+  gapk::qr_bind_workspace(at<char>(h, q), M + 1, M, &qw);
+  double* kc = at<double>(h, t1);
+  h->timer.begin(gapk::TM_REFINE);
+  // the regulariser rows U with zero targets: U^T (0 - U c) = -(K_MM + jitter I) c
+  gapk::gemv_cm_f64(Kmm, M, M, M, c, kc, h->stream);
+  gapk::axpy_f64(M, jitter, c, kc, h->stream);
+  gapk::axpy_f64(M, -1.0, kc, g, h->stream);
+  // R^T R dc = A^T r ; c += dc
+  gapk::seminormal_solve(R, ldr, M, g, h->stream, qw.flags, at<double>(h, t2), h->dev_err);
+  gapk::axpy_f64(M, 1.0, g, c, h->stream);
+  h->timer.end(gapk::TM_REFINE);
+  HIP_TRY(h, hipGetLastError());
+  return drain_dev_err(h);
 }
 
 gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,

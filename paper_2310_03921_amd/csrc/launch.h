@@ -246,17 +246,22 @@ void back_substitute(const double* A, int64_t ld, int64_t n, const double* z, do
 void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStream_t st,
                       unsigned int* flags = nullptr, double* tmp = nullptr,
                       int* dev_err = nullptr);
-// r_top[r] = (y_r - kc_r) / sigma_r ; r_bot = -U c ;  also returns sum of squares pieces
-void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
-                     const double* L, int64_t ldl, int64_t M, const double* c, double* r_top,
-                     double* r_bot, hipStream_t st);
+// r_top[r] = (y_r - kc_r) / sigma_r
+void residual_top(const double* y, const double* sigma, const double* kc, int64_t n_rows,
+                  double* r_top, hipStream_t st);
+// r_bot = -U c  (U = L^T, L lower M x M col-major)
+void residual_bot(const double* L, int64_t ldl, int64_t M, const double* c, double* r_bot,
+                  hipStream_t st);
 // g[m] += (U^T r_bot)[m]  (U = L^T)
 void add_ut_r(const double* L, int64_t ldl, int64_t M, const double* r_bot, double* g,
               hipStream_t st);
 // v[r] = r_top[r] / sigma_r (weights for K^T)
 void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, hipStream_t st);
+void fill_f64(double* p, int64_t n, double v, hipStream_t st);
 void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st);
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st);
+// out[0] += x . x
+void sumsq_add_f64(const double* x, int64_t n, double* out, hipStream_t st);
 // Y = R^-1 (R upper n x n col-major) as a row-major Y[i * ldy + c], zero below
 // the diagonal; one workgroup per column.
 void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy, int* dev_err,

@@ -2098,10 +2098,32 @@ __global__ void k_div(const double* __restrict__ a, const double* __restrict__ b
     out[i] = a[i] / b[i];
 }
 
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] += a * x[i];
+}
+
+// out[0] += sum_i x_i^2 (one workgroup; fixed summation order)
+__global__ __launch_bounds__(1024) void k_sumsq_add(const double* __restrict__ x, int64_t n,
+                                                    double* __restrict__ out) {
+  __shared__ double sp[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * x[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sp[w];
+    *out += t;
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ x, int64_t n,
@@ -2435,11 +2457,15 @@ void seminormal_solve(const double* A, int64_t ld, int64_t n, double* x, hipStre
   }
 }
 
-void refine_residual(const double* y, const double* sigma, const double* kc, int64_t n_rows,
-                     const double* L, int64_t ldl, int64_t M, const double* c, double* r_top,
-                     double* r_bot, hipStream_t st) {
+void residual_top(const double* y, const double* sigma, const double* kc, int64_t n_rows,
+                  double* r_top, hipStream_t st) {
+  if (n_rows <= 0) return;
   hipLaunchKernelGGL(k_residual_top, dim3(g256(n_rows)), dim3(256), 0, st, y, sigma, kc, n_rows,
                      r_top);
+}
+
+void residual_bot(const double* L, int64_t ldl, int64_t M, const double* c, double* r_bot,
+                  hipStream_t st) {
   hipLaunchKernelGGL(k_residual_bot, dim3(cdiv(M, 4)), dim3(256), 0, st, L, ldl, M, c, r_bot);
 }
 
@@ -2453,12 +2479,21 @@ void div_sigma(const double* r_top, const double* sigma, int64_t n, double* v, h
   hipLaunchKernelGGL(k_div, dim3(g256(n)), dim3(256), 0, st, r_top, sigma, n, v);
 }
 
+void fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3(g256(n)), dim3(256), 0, st, p, n, v);
+}
+
 void axpy_f64(int64_t n, double a, const double* x, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(g256(n)), dim3(256), 0, st, n, a, x, y);
 }
 
 void norm2_f64(const double* x, int64_t n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, x, n, out);
+}
+
+void sumsq_add_f64(const double* x, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq_add, dim3(1), dim3(1024), 0, st, x, n, out);
 }
 
 void trinv_upper(const double* R, int64_t ld, int64_t n, double* Y, int64_t ldy, int* dev_err,
