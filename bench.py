@@ -106,6 +106,139 @@ def cpu_baseline(w, b, X, n_sample):
             "measured_s": t_knm + t_kmm + t_chol + t_qr}
 
 
+def large_mixed_fit(args, torch, synth, gapx):
+    """The largest fit (4000 configurations of 32-256 atoms, ~576k atoms, D = 1500,
+    40 neighbours, M = 8000, FP32 descriptors and Jacobians).  Its 415 GB of
+    Jacobians do not fit in HBM, so configurations are taken in batches of
+    about --large-rows observation rows: each batch's BF16X3 rows are folded
+    into the streamed factor, then every FP64 refinement pass regenerates the
+    batch on the host (the next batch is drawn on a host thread while the GPU
+    works on the current one) and adds its share of A^T r.  Reported: GPU time
+    of the fit (sum of the library's stage timers: K_MM, assembly, folds,
+    refinement; input generation, host-to-device copies and the target predict
+    excluded), wall time, and ||A^T r|| of the FP64 system after each step."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    w = synth.WORKLOADS["fit_large_mixed"]
+    M, D = w.M, w.D
+    n_cfg = min(w.n_cfg, args.large_cfgs) if args.large_cfgs > 0 else w.n_cfg
+    counts = synth.atom_counts(w)[:n_cfg]
+    rows = 3 * counts + 1
+    cuts, acc = [0], 0
+    for c in range(n_cfg):
+        acc += int(rows[c])
+        if acc >= args.large_rows:
+            cuts.append(c + 1)
+            acc = 0
+    if cuts[-1] != n_cfg:
+        cuts.append(n_cfg)
+    batches = list(zip(cuts[:-1], cuts[1:]))
+    max_rows = max(int(rows[a:b].sum()) for a, b in batches)
+    n_rows, n_atoms = int(rows.sum()), int(counts.sum())
+    n_pairs = n_atoms * w.nb
+    log(f"large fit: {n_atoms} atoms, {n_pairs} pairs, {n_rows} rows in {len(batches)} batches "
+        f"of <= {max_rows} rows")
+    t_wall = time.perf_counter()
+    torch.cuda.set_device(0)
+    gap = gapx.Gap(0)
+    X = synth.sparse_points(w)
+    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+    cstar = torch.tensor(synth.hidden_coefficients(w), device="cuda")
+    pool = ThreadPoolExecutor(1)
+
+    def draw(k):
+        a, b_ = batches[k]
+        return synth.generate(w, np.arange(a, b_))
+
+    def batches_on_device():
+        """Yield (k, atoms, host batch) with batch k + 1 drawn on the host meanwhile."""
+        nxt = pool.submit(draw, 0)
+        for k in range(len(batches)):
+            b = nxt.result()
+            if k + 1 < len(batches):
+                nxt = pool.submit(draw, k + 1)
+            atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
+            yield k, atoms, b
+
+    gap.timing(True)
+    gap.timing_read(reset=True)
+    gpu_ms = {}
+
+    def collect(tag):
+        torch.cuda.synchronize()
+        st = gap.timing_read(reset=True)
+        gpu_ms[tag] = {k: v[0] for k, v in st.items() if v[1] > 0}
+        return sum(gpu_ms[tag].values())
+
+    Kmm = gap.build_kmm(sp)
+    T = gap.fold_buffer(M, max_rows)
+    gap.fold_init(T, M, Kmm, w.jitter)
+    collect("init")
+    ys, sigs = [], []
+    t_fold = 0.0
+    for k, atoms, b in batches_on_device():
+        # targets of the batch: FP64 predict with the hidden coefficients plus seeded noise
+        pr = gap.predict(atoms, sp, cstar, e_atom=False, e_cfg=True, forces=True)
+        y = torch.cat([pr["e_cfg"], pr["forces"].reshape(-1)])
+        y += torch.tensor(synth.noise(w, b.cfg_ids, b.counts), device="cuda")
+        ys.append(y)
+        sigs.append(torch.tensor(synth.sigma_rows(w, b.counts), device="cuda"))
+        collect(f"targets{k}")
+        gap.build_knm_block(atoms, sp, T, precision="bf16x3")
+        gap.fold_rows(T, M, b.n_rows, ys[k], sigs[k])
+        t_fold += collect(f"fold{k}")
+        log(f"batch {k + 1}/{len(batches)} folded ({b.n_rows} rows), GPU {t_fold / 1e3:.1f} s so far")
+    c, lsq, rd = gap.fold_solve(T, M)
+    t_fold += collect("solve")
+    norms, t_ref = [], 0.0
+    for step in range(args.refine_steps + 1):
+        g = torch.zeros(M, dtype=torch.float64, device="cuda")
+        for k, atoms, b in batches_on_device():
+            gap.refine_rows(atoms, sp, c, ys[k], sigs[k], g)
+            t_ref += collect(f"ref{step}.{k}")
+        # ||A^T r|| of the whole FP64 system (regulariser rows included), for the report
+        full = g - (Kmm.T @ c + w.jitter * c)
+        norms.append(float(torch.linalg.vector_norm(full)))
+        log(f"refinement pass {step}: ||A^T r|| = {norms[-1]:.3e}")
+        if step == args.refine_steps:
+            break
+        gap.refine_solve(T, M, Kmm, w.jitter, g, c)
+        t_ref += collect(f"solve{step}")
+    pool.shutdown()
+    gap.timing(False)
+    wall = time.perf_counter() - t_wall
+    assert torch.isfinite(c).all().item(), "non-finite coefficients"
+    stage = {}
+    for tag, st in gpu_ms.items():
+        if tag.startswith("targets"):
+            continue
+        for k, v in st.items():
+            stage[k] = stage.get(k, 0.0) + v
+    fit_ms = sum(stage.values())
+    knm_ms = stage.get("pair_transpose", 0) + stage.get("energy_rows", 0) + \
+        stage.get("force_rows", 0) + stage.get("split_bf16", 0)
+    knm_flops = 2.0 * M * D * (n_atoms + 3.0 * n_pairs)
+    line = {
+        "metric": METRIC, "value": fit_ms / 1e3, "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": fit_ms, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3+f64", "data": "synthetic",
+        "config": {"workload": f"fit_large_mixed: {n_cfg} configurations x U[{w.atoms_lo},"
+                               f"{w.atoms_hi}] atoms ({n_atoms} atoms, {n_pairs} pairs, "
+                               f"{n_rows} observation rows), D={D}, {w.nb} neighbours/atom, "
+                               f"M={M}, zeta={w.zeta}, J f32, BF16X3 rows folded in "
+                               f"{len(batches)} batches, {args.refine_steps} FP64 refinement steps",
+                   "precision": "bf16x3", "n_rows": n_rows, "M": M, "D": D},
+        "gpu_s": {"assembly_and_folds": t_fold / 1e3, "refinement": t_ref / 1e3},
+        "knm_ms": knm_ms, "knm_tflops_algorithmic": knm_flops / (knm_ms * 1e-3) / 1e12,
+        "stage_ms": {k: round(v, 1) for k, v in stage.items()},
+        "wall_s_with_host_generation": wall,
+        "lsq_resid_norm_before_refinement": lsq,
+        "normal_eq_residual_per_step": norms,
+        "min_max_abs_rdiag": list(rd),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +255,10 @@ def main():
                     help="skip the predict / backward leg on the 65,536-atom predict workload")
     ap.add_argument("--stream-blocks", type=int, default=4,
                     help="configuration groups of the streamed-fit leg (0: skip it)")
+    ap.add_argument("--large-rows", type=int, default=200000,
+                    help="observation rows per batch of the fit_large_mixed workload")
+    ap.add_argument("--large-cfgs", type=int, default=0,
+                    help="fit_large_mixed: fit only its first N configurations (0: all 4000)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,6 +271,9 @@ def main():
     import synth
     import paper_2310_03921_amd as gapx
 
+    if args.workload == "fit_large_mixed":
+        large_mixed_fit(args, torch, synth, gapx)
+        return
     w = synth.WORKLOADS[args.workload]
     log(f"generating {w.name} on the host")
     t0 = time.perf_counter()

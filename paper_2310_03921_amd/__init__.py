@@ -120,6 +120,8 @@ def padded_rows(x: torch.Tensor, D: int, dtype=None, device=None) -> torch.Tenso
     """Copy a (..., D) array into a zero-padded (..., round4(D)) contiguous device tensor."""
     x = torch.as_tensor(x)
     dtype = dtype or x.dtype
+    if D % 4 == 0:
+        return x.to(device=device, dtype=dtype).contiguous()
     out = torch.zeros(*x.shape[:-1], _round4(D), dtype=dtype, device=device)
     out[..., :D] = x.to(device=device, dtype=dtype)
     return out
