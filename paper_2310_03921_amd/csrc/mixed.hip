@@ -107,9 +107,12 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
 // one per wave) x 16*NCF columns; the split halves of its X columns sit in
 // LDS in matrix-core order (per 32-k block, per column tile, per lane: 8 hi
 // then 8 lo), so each B fragment pair is one 32-byte LDS read.  Jacobian rows
-// are split in registers.
+// are split in registers.  Descriptors longer than one LDS chunk (256
+// entries) are taken chunk by chunk: a force row is linear in the pair
+// products J . x_m, so every chunk adds S * (J[chunk] . X[chunk]) of every
+// pair into the same per-target accumulators.
 constexpr int kNCF = 8;       // 128 columns per block
-constexpr int kMaxKb32 = 8;   // D <= 256
+constexpr int kMaxKb32 = 8;   // 256 descriptor entries per LDS chunk
 
 struct SplitPair {
   bf8v h, l;
@@ -121,28 +124,13 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
     int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp, int nkb) {
-  extern __shared__ SplitPair xs2[];  // [nkb][kNCF][64]
+    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp,
+    int nkb_all) {
+  extern __shared__ SplitPair xs2[];  // [min(nkb_all, kMaxKb32)][kNCF][64]
   int64_t ct, tgb;
   if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = ct * (16 * kNCF);
-
-  for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 256) {
-    const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
-    const int u = rem / 64, ln = rem % 64;
-    const int64_t col = colbase + u * 16 + (ln & 15);
-    SplitPair sp;
-    if (col < M) {
-      const int64_t k = (int64_t)kb * 32 + 8 * (ln >> 4);
-      sp.h = *reinterpret_cast<const bf8v*>(Xh + col * ldp + k);
-      sp.l = *reinterpret_cast<const bf8v*>(Xl + col * ldp + k);
-    } else {
-      zero_split(sp.h, sp.l);
-    }
-    xs2[e] = sp;
-  }
-  __syncthreads();
 
   const int64_t slot = (tgb * 4 + wave) * 16 + idx;
   const int target = slot < n_atoms ? order[slot] : -1;
@@ -160,6 +148,25 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     for (int u = 0; u < kNCF; ++u) acc[a][u] = zero4f();
 
   const SplitPair* xb = xs2 + lane;
+  for (int kc0 = 0; kc0 < nkb_all; kc0 += kMaxKb32) {
+  const int nkb = min(kMaxKb32, nkb_all - kc0);
+  __syncthreads();  // the previous chunk's products are done with the LDS
+  for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 256) {
+    const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
+    const int u = rem / 64, ln = rem % 64;
+    const int64_t col = colbase + u * 16 + (ln & 15);
+    SplitPair sp;
+    if (col < M) {
+      const int64_t k = (int64_t)(kc0 + kb) * 32 + 8 * (ln >> 4);
+      sp.h = *reinterpret_cast<const bf8v*>(Xh + col * ldp + k);
+      sp.l = *reinterpret_cast<const bf8v*>(Xl + col * ldp + k);
+    } else {
+      zero_split(sp.h, sp.l);
+    }
+    xs2[e] = sp;
+  }
+  __syncthreads();
+  const int64_t k_base = (int64_t)kc0 * 32;
   for (int t = 0; t < maxdeg; ++t) {
     int pair = t < deg ? tgt_pair[seg0 + t] : -1;
     const int src = pair >= 0 ? pair_src[pair] : -1;
@@ -174,7 +181,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     float nx[3][8];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (pv) load8f(jr + a * ldj, 8 * g, D, nx[a]);
+      if (pv) load8f(jr + a * ldj, k_base + 8 * g, D, nx[a]);
       else
 #pragma unroll
         for (int e = 0; e < 8; ++e) nx[a][e] = 0.f;
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
       if (kb + 1 < nkb) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          if (pv) load8f(jr + a * ldj, (int64_t)(kb + 1) * 32 + 8 * g, D, nx[a]);
+          if (pv) load8f(jr + a * ldj, k_base + (int64_t)(kb + 1) * 32 + 8 * g, D, nx[a]);
         }
       }
 #pragma unroll
@@ -211,6 +218,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
       }
     }
   }
+  }
 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -218,89 +226,6 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     if (tr < 0) continue;
 #pragma unroll
     for (int u = 0; u < kNCF; ++u) {
-      if (colr[u] >= M) continue;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        K[(row0 + 3 * (int64_t)tr + a) + colr[u] * ldk] = -(double)acc[a][u][r];
-    }
-  }
-}
-
-// General-D force rows: X halves streamed from global (L2) per wave.
-template <typename TJ>
-__global__ __launch_bounds__(256) void k_force_rows_b3_global(
-    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
-    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
-    int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
-    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp) {
-  int64_t ct, tgb;
-  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t colbase = ct * (16 * kNCb);
-  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
-  const int target = slot < n_atoms ? order[slot] : -1;
-  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
-  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
-  const int maxdeg = wave_max16(deg);
-  Frag32Split fb[kNCb];
-  int64_t colr[kNCb];
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) {
-    colr[u] = colbase + u * 16 + idx;
-    const int64_t cc = colr[u] < M ? colr[u] : 0;
-    fb[u] = Frag32Split{Xh + cc * ldp, Xl + cc * ldp, colr[u] < M};
-  }
-  f4v acc[3][kNCb];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int u = 0; u < kNCb; ++u) acc[a][u] = zero4f();
-  for (int t = 0; t < maxdeg; ++t) {
-    int pair = t < deg ? tgt_pair[seg0 + t] : -1;
-    const int src = pair >= 0 ? pair_src[pair] : -1;
-    if (src < 0) pair = -1;
-    const bool pv = pair >= 0;
-    const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
-    f4v G[3][kNCb];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int u = 0; u < kNCb; ++u) G[a][u] = zero4f();
-    for (int64_t k0 = 0; k0 < D; k0 += 32) {
-      bf8v bh[kNCb], bl[kNCb];
-#pragma unroll
-      for (int u = 0; u < kNCb; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Frag32Row<TJ> fa{jr + a * ldj, D, pv};
-        bf8v ah, al;
-        fa.frag(k0, g, ah, al);
-        f4v tmp[kNCb];
-#pragma unroll
-        for (int u = 0; u < kNCb; ++u) tmp[u] = G[a][u];
-        mma3_block<kNCb>(ah, al, bh, bl, tmp);
-#pragma unroll
-        for (int u = 0; u < kNCb; ++u) G[a][u] = tmp[u];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int src_r = __shfl(src, 4 * g + r);
-#pragma unroll
-      for (int u = 0; u < kNCb; ++u) {
-        const float sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.f;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int tr = __shfl(target, 4 * g + r);
-    if (tr < 0) continue;
-#pragma unroll
-    for (int u = 0; u < kNCb; ++u) {
       if (colr[u] >= M) continue;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -658,11 +583,11 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
   if (n_atoms <= 0 || M <= 0) return;
   const int64_t ldp = split_ld(D);
   const int64_t n_tgb = (n_atoms + 63) / 64;
-  if (D <= 32 * kMaxKb32) {
+  {
     const int nkb = (int)(ldp / 32);
     const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
     const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
-    const size_t lds = (size_t)nkb * kNCF * 64 * sizeof(SplitPair);
+    const size_t lds = (size_t)std::min(nkb, kMaxKb32) * kNCF * 64 * sizeof(SplitPair);
     const size_t lds_max = (size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair);
     if (jac_f32) {
       static bool a = false;
@@ -685,18 +610,7 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
                          st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
                          pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
     }
-    return;
   }
-  const int64_t n_ct = (M + 16 * kNCb - 1) / (16 * kNCb);
-  const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
-  if (jac_f32)
-    hipLaunchKernelGGL(k_force_rows_b3_global<float>, dim3(blocks), dim3(256), 0,
-                       st, tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb);
-  else
-    hipLaunchKernelGGL(k_force_rows_b3_global<double>, dim3(blocks), dim3(256), 0,
-                       st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb);
 }
 
 void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
