@@ -118,7 +118,7 @@ struct SplitPair {
   bf8v h, l;
 };
 
-template <typename TJ>
+template <typename TJ, int NC>
 __global__ __launch_bounds__(256) void k_force_rows_b3(
     const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
     const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
@@ -126,33 +126,33 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
     int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp,
     int nkb_all) {
-  extern __shared__ SplitPair xs2[];  // [min(nkb_all, kMaxKb32)][kNCF][64]
+  extern __shared__ SplitPair xs2[];  // [min(nkb_all, kMaxKb32)][NC][64]
   int64_t ct, tgb;
   if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t colbase = ct * (16 * kNCF);
+  const int64_t colbase = ct * (16 * NC);
 
   const int64_t slot = (tgb * 4 + wave) * 16 + idx;
   const int target = slot < n_atoms ? order[slot] : -1;
   const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
   const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
   const int maxdeg = wave_max16(deg);
-  int64_t colr[kNCF];
+  int64_t colr[NC];
 #pragma unroll
-  for (int u = 0; u < kNCF; ++u) colr[u] = colbase + u * 16 + idx;
+  for (int u = 0; u < NC; ++u) colr[u] = colbase + u * 16 + idx;
 
-  f4v acc[3][kNCF];
+  f4v acc[3][NC];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int u = 0; u < kNCF; ++u) acc[a][u] = zero4f();
+    for (int u = 0; u < NC; ++u) acc[a][u] = zero4f();
 
   const SplitPair* xb = xs2 + lane;
   for (int kc0 = 0; kc0 < nkb_all; kc0 += kMaxKb32) {
   const int nkb = min(kMaxKb32, nkb_all - kc0);
   __syncthreads();  // the previous chunk's products are done with the LDS
-  for (int e = threadIdx.x; e < nkb * kNCF * 64; e += 256) {
-    const int kb = e / (kNCF * 64), rem = e % (kNCF * 64);
+  for (int e = threadIdx.x; e < nkb * NC * 64; e += 256) {
+    const int kb = e / (NC * 64), rem = e % (NC * 64);
     const int u = rem / 64, ln = rem % 64;
     const int64_t col = colbase + u * 16 + (ln & 15);
     SplitPair sp;
@@ -173,11 +173,11 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     if (src < 0) pair = -1;
     const bool pv = pair >= 0;
     const TJ* jr = jac + (int64_t)(pv ? pair : 0) * 3 * ldj;
-    f4v G[3][kNCF];
+    f4v G[3][NC];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int u = 0; u < kNCF; ++u) G[a][u] = zero4f();
+      for (int u = 0; u < NC; ++u) G[a][u] = zero4f();
     float nx[3][8];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -197,8 +197,8 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
         }
       }
 #pragma unroll
-      for (int u = 0; u < kNCF; ++u) {
-        const SplitPair b = xb[(kb * kNCF + u) * 64];
+      for (int u = 0; u < NC; ++u) {
+        const SplitPair b = xb[(kb * NC + u) * 64];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           G[a][u] = mfma_bf16(ah[a], b.h, G[a][u]);
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     for (int r = 0; r < 4; ++r) {
       const int src_r = __shfl(src, 4 * g + r);
 #pragma unroll
-      for (int u = 0; u < kNCF; ++u) {
+      for (int u = 0; u < NC; ++u) {
         const float sv = (src_r >= 0 && colr[u] < M) ? S[(int64_t)src_r * ldS + colr[u]] : 0.f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
     const int tr = __shfl(target, 4 * g + r);
     if (tr < 0) continue;
 #pragma unroll
-    for (int u = 0; u < kNCF; ++u) {
+    for (int u = 0; u < NC; ++u) {
       if (colr[u] >= M) continue;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -583,33 +583,42 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
   if (n_atoms <= 0 || M <= 0) return;
   const int64_t ldp = split_ld(D);
   const int64_t n_tgb = (n_atoms + 63) / 64;
-  {
-    const int nkb = (int)(ldp / 32);
-    const int64_t n_ct = (M + 16 * kNCF - 1) / (16 * kNCF);
-    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
-    const size_t lds = (size_t)std::min(nkb, kMaxKb32) * kNCF * 64 * sizeof(SplitPair);
-    const size_t lds_max = (size_t)kMaxKb32 * kNCF * 64 * sizeof(SplitPair);
-    if (jac_f32) {
-      static bool a = false;
-      if (!a) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3<float>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
-        a = true;
-      }
-      hipLaunchKernelGGL(k_force_rows_b3<float>, dim3(blocks), dim3(256), lds, st,
-                         tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
-    } else {
-      static bool a = false;
-      if (!a) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3<double>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
-        a = true;
-      }
-      hipLaunchKernelGGL(k_force_rows_b3<double>, dim3(blocks), dim3(256), lds,
-                         st, tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
+  const int nkb = (int)(ldp / 32);
+  // Up to 256 descriptor entries: 128 columns per block.  Longer descriptors:
+  // 64 columns per block (half the accumulators), so that two waves share a
+  // SIMD and cover each other's Jacobian loads.
+  const int nc = nkb <= kMaxKb32 ? 8 : 4;
+  const int64_t n_ct = (M + 16 * nc - 1) / (16 * nc);
+  const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
+  const size_t lds = (size_t)std::min(nkb, kMaxKb32) * nc * 64 * sizeof(SplitPair);
+  const int lds_max = (int)((size_t)kMaxKb32 * nc * 64 * sizeof(SplitPair));
+  auto prep = [&](const void* kern, bool& done) {
+    if (!done) {
+      (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+      done = true;
     }
+  };
+  static bool f8 = false, f4 = false, d8 = false, d4 = false;
+  if (jac_f32 && nc == 8) {
+    prep(reinterpret_cast<const void*>(&k_force_rows_b3<float, 8>), f8);
+    hipLaunchKernelGGL((k_force_rows_b3<float, 8>), dim3(blocks), dim3(256), lds, st,
+                       tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
+  } else if (jac_f32) {
+    prep(reinterpret_cast<const void*>(&k_force_rows_b3<float, 4>), f4);
+    hipLaunchKernelGGL((k_force_rows_b3<float, 4>), dim3(blocks), dim3(256), lds, st,
+                       tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
+  } else if (nc == 8) {
+    prep(reinterpret_cast<const void*>(&k_force_rows_b3<double, 8>), d8);
+    hipLaunchKernelGGL((k_force_rows_b3<double, 8>), dim3(blocks), dim3(256), lds, st,
+                       tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
+  } else {
+    prep(reinterpret_cast<const void*>(&k_force_rows_b3<double, 4>), d4);
+    hipLaunchKernelGGL((k_force_rows_b3<double, 4>), dim3(blocks), dim3(256), lds, st,
+                       tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                       pair_src, order, n_atoms, row0, K, ldk, n_ct, n_tgb, nkb);
   }
 }
 
