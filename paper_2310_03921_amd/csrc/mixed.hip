@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
   }
   __syncthreads();
   const int64_t k_base = (int64_t)kc0 * 32;
+  const int nfull = (int)min((int64_t)nkb, (D - k_base) / 32);  // whole 32-blocks inside D
   for (int t = 0; t < maxdeg; ++t) {
     int pair = t < deg ? tgt_pair[seg0 + t] : -1;
     const int src = pair >= 0 ? pair_src[pair] : -1;
@@ -179,21 +180,28 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
 #pragma unroll
       for (int u = 0; u < NC; ++u) G[a][u] = zero4f();
     float nx[3][8];
+    // An absent pair reads pair 0's rows (valid memory, finite values) and is
+    // weighted by S = 0 below.  Blocks of 32 entries inside D load with no
+    // bound; only the block that D ends in takes the bounded load.
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (pv) load8f(jr + a * ldj, k_base + 8 * g, D, nx[a]);
+      if (nfull > 0)
+        load8f_full(jr + a * ldj, k_base + 8 * g, nx[a]);
       else
-#pragma unroll
-        for (int e = 0; e < 8; ++e) nx[a][e] = 0.f;
+        load8f(jr + a * ldj, k_base + 8 * g, D, nx[a]);
     }
     for (int kb = 0; kb < nkb; ++kb) {
       bf8v ah[3], al[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) split8(nx[a], ah[a], al[a]);
       if (kb + 1 < nkb) {
+        const int64_t kn = k_base + (int64_t)(kb + 1) * 32 + 8 * g;
+        if (kb + 1 < nfull) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (pv) load8f(jr + a * ldj, k_base + (int64_t)(kb + 1) * 32 + 8 * g, D, nx[a]);
+          for (int a = 0; a < 3; ++a) load8f_full(jr + a * ldj, kn, nx[a]);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) load8f(jr + a * ldj, kn, D, nx[a]);
         }
       }
 #pragma unroll

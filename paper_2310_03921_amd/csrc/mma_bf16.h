@@ -74,6 +74,28 @@ GAP_DEV void load8f(const float* __restrict__ row, int64_t k, int64_t kmax, floa
   }
 }
 
+// The same eight entries where all of row[k .. k+7] lie inside the row: no
+// bound, so the loads carry no branch.
+GAP_DEV void load8f_full(const float* __restrict__ row, int64_t k, float out[8]) {
+  const f4v v0 = *reinterpret_cast<const f4v*>(row + k);
+  const f4v v1 = *reinterpret_cast<const f4v*>(row + k + 4);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    out[s] = v0[s];
+    out[4 + s] = v1[s];
+  }
+}
+
+GAP_DEV void load8f_full(const double* __restrict__ row, int64_t k, float out[8]) {
+  const d4v v0 = *reinterpret_cast<const d4v*>(row + k);
+  const d4v v1 = *reinterpret_cast<const d4v*>(row + k + 4);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    out[s] = (float)v0[s];
+    out[4 + s] = (float)v1[s];
+  }
+}
+
 // Element (idx, k) at row[k]: contiguous along k, split on the fly.
 template <typename T>
 struct Frag32Row {
