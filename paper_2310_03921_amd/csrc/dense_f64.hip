@@ -575,13 +575,17 @@ constexpr size_t kSxLds = 2 * (kSxKC / 16) * kSxSub * sizeof(double);
 // The epilogue is the one of k_pstage: p = d_i . x_m, W[i][m] (MODE 0: delta^2
 // zeta c_m p^(zeta-1); MODE 1: the same times g_e[i], zero row padding), and
 // MODE 0: per-row energy partials of the column group in e_part[group][i];
-// MODE 1: dc_part[row block][m] = sum over the block's rows of g_e[i] delta^2 p^zeta.
+// MODE 1: dc_part[row block][m] = sum over the block's rows of g_e[i] delta^2 p^zeta;
+// MODE 3 (rows d_i = h_i, the refinement's column sums of the force rows, which
+// carry a minus sign): dc_part[row block][m] = - sum over the block's rows of
+// Sx[i][m] p_im, with no kernel and no W.
 template <typename TD, int MODE>
 __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
     const TD* __restrict__ desc, int64_t ldd, int64_t n, const double* __restrict__ X,
     int64_t ldx, int64_t M, int64_t D, int zeta, double delta, const double* __restrict__ cc,
     const double* __restrict__ g_e, double* __restrict__ W, int64_t ldw,
-    double* __restrict__ e_part, double* __restrict__ dc_part) {
+    double* __restrict__ e_part, double* __restrict__ dc_part, const double* __restrict__ Sx,
+    int64_t ldsx) {
   extern __shared__ __attribute__((aligned(16))) double xs[];  // [2][kSxKC / 16][kSxSub]
   __shared__ double red[4][2][128];  // [row-group wave][column half][row or column]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
   for (int u = 0; u < 8; ++u) {
     const int64_t col = cg + ch * 128 + u * 16 + idx;
     const bool cvalid = col < M;
-    const double cm = cvalid ? cc[col] : 0.0;
+    const double cm = (MODE != 3 && cvalid) ? cc[col] : 0.0;
     double csum = 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -689,6 +693,10 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
         continue;
       }
       const double p = acc[u][r];
+      if (MODE == 3) {
+        csum -= Sx[rr * ldsx + col] * p;
+        continue;
+      }
       const double pz1 = ipow(p, zeta - 1);
       const double kval = d2 * pz1 * p;
       if (MODE == 0) {
@@ -699,7 +707,7 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
         if (W) W[rr * ldw + col] = ge[r] * d2z * cm * pz1;
       }
     }
-    if (MODE == 1) {
+    if (MODE != 0) {
       csum += __shfl_xor(csum, 16);
       csum += __shfl_xor(csum, 32);
       if (g == 0) red[rgw][ch][u * 16 + idx] = csum;
@@ -942,17 +950,22 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                 const double* Sx, int64_t ldsx, double* e_part) {
   if (n <= 0 || M <= 0) return;
   // LDS-staged form: energies (mode 0) go through per-column-group partials
-  const bool lds_ok = D % 4 == 0 && D >= 4 && ldd % 4 == 0 && ldx % 4 == 0 && c &&
-                      (reinterpret_cast<uintptr_t>(desc) & 31) == 0 &&
+  // (mode 3 takes the rows h_i of H as its descriptors)
+  const void* arows = mode == 3 ? static_cast<const void*>(H) : desc;
+  const int64_t lda = mode == 3 ? ldh : ldd;
+  const bool lds_ok = D % 4 == 0 && D >= 4 && lda % 4 == 0 && ldx % 4 == 0 && arows &&
+                      (reinterpret_cast<uintptr_t>(arows) & 31) == 0 &&
                       (reinterpret_cast<uintptr_t>(X) & 31) == 0 &&
-                      ((mode == 0 && (!e_atom || e_part)) || (mode == 1 && g_e));
+                      ((mode == 0 && c && (!e_atom || e_part)) || (mode == 1 && c && g_e) ||
+                       (mode == 3 && Sx));
   if (lds_ok) {
     static bool attr = false;
     if (!attr) {
-      const void* ks[4] = {reinterpret_cast<const void*>(&k_pstage_lds<float, 0>),
+      const void* ks[5] = {reinterpret_cast<const void*>(&k_pstage_lds<float, 0>),
                            reinterpret_cast<const void*>(&k_pstage_lds<float, 1>),
                            reinterpret_cast<const void*>(&k_pstage_lds<double, 0>),
-                           reinterpret_cast<const void*>(&k_pstage_lds<double, 1>)};
+                           reinterpret_cast<const void*>(&k_pstage_lds<double, 1>),
+                           reinterpret_cast<const void*>(&k_pstage_lds<double, 3>)};
       for (const void* k : ks)
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
       attr = true;
@@ -960,20 +973,29 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
     const int64_t ng = pstage_groups(M);
     const dim3 grid((unsigned)pstage_row_blocks(n), (unsigned)ng), blk(64 * kSxW);
     double* ep = e_atom ? e_part : nullptr;
+    if (mode == 3) {
+      hipLaunchKernelGGL((k_pstage_lds<double, 3>), grid, blk, kSxLds, st, H, ldh, n, X, ldx, M,
+                         D, zeta, delta, nullptr, nullptr, nullptr, 0, nullptr, dc_part, Sx, ldsx);
+      return;
+    }
     if (desc_f32) {
       if (mode == 0)
         hipLaunchKernelGGL((k_pstage_lds<float, 0>), grid, blk, kSxLds, st, tptr<float>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
+                           nullptr, 0);
       else
         hipLaunchKernelGGL((k_pstage_lds<float, 1>), grid, blk, kSxLds, st, tptr<float>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
+                           nullptr, 0);
     } else {
       if (mode == 0)
         hipLaunchKernelGGL((k_pstage_lds<double, 0>), grid, blk, kSxLds, st, tptr<double>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
+                           nullptr, 0);
       else
         hipLaunchKernelGGL((k_pstage_lds<double, 1>), grid, blk, kSxLds, st, tptr<double>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part);
+                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
+                           nullptr, 0);
     }
     if (mode == 0 && e_atom)
       hipLaunchKernelGGL(k_sum_groups, dim3(std::max(1u, std::min(cdiv(n, 256), 65536u))),
