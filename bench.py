@@ -1,15 +1,24 @@
 #!/usr/bin/env python3
 """GAP fit benchmark on one MI355X.
 
-One step = the whole fit of the FP64 form on one synthetic batch with the
-shapes of the large FP64 fit (1000 configurations of 16-216 atoms, ~116k atoms,
-D = 252, 30 neighbours per atom, M = 2000, zeta = 4):
-  pair transpose -> K_MM -> energy rows + kernel-gradient scale -> force rows
-  -> Cholesky + scaling/stacking -> blocked Householder QR -> back substitution.
-Inputs are resident in HBM before the timed region.  The JSON line carries the
-fit time (the metric), the K_NM assembly rate, the roofline of the dominant
-kernel (force rows, FP64 matrix cores) from HIP events on the library's stream,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Default (the headline): one step = one whole fit of the largest single-GPU
+workload, 4000 configurations of 32-256 atoms (575,746 atoms, 1.73 M
+observation rows), D = 1500, 40 neighbours per atom, M = 8000, zeta = 4, FP32
+descriptors and Jacobians:
+  K_MM -> fold state -> per batch of configurations: Jacobians drawn on the
+  device, pair transpose, BF16X3 energy and force rows, fold into the FP64
+  Householder QR factor -> back substitution -> FP64 refinement steps (exact
+  residual rows, Jacobians drawn again) -> coefficients.
+Descriptors, pair lists and targets are resident in HBM before the timed
+region; the Jacobians (415 GB) cannot be, so drawing them is part of every
+step and is reported separately.  Each step is timed with HIP events on the
+stream all work is ordered on.  The JSON line carries the fit time (the
+metric), the K_NM assembly rate, the roofline of the dominant kernel (the
+BF16X3 force rows) from the library's HIP-event stage timers, the scaled
+normal-equation residual of the FP64 system, the FP64 CPU oracle timed on a
+bounded sample, and the 116k-atom FP64 fit (D = 252, M = 2000) with its legs.
+
+--workload fit_fp64: the 116k-atom FP64 fit is the headline instead.
 """
 from __future__ import annotations
 
@@ -26,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GAP fit time (s), K_NM GFLOP/s; mixed vs FP64 at stated force error"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the force-row kernel on the 116k-atom fit, from two rocprofv3
@@ -69,15 +79,34 @@ def describe(w, b):
             f"J {w.jac_dtype}")
 
 
-def cpu_baseline(w, b, X, n_sample):
-    """FP64 oracle on the first n_sample configurations, scaled to the whole fit."""
-    import oracle
-    import synth
+def host_info():
+    """Threads the oracle's BLAS uses, the host's logical CPUs, CPU model and BLAS."""
+    info = {"logical_cpus": os.cpu_count()}
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        pools = threadpool_info()
+        info["blas_threads"] = max([p.get("num_threads", 1) for p in pools] or [1])
+        info["blas"] = sorted({f"{p.get('internal_api')} {p.get('version')}" for p in pools
+                               if p.get("user_api") == "blas"})
     except Exception:
-        cores = os.cpu_count() or 1
+        info["blas_threads"] = os.cpu_count() or 1
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(w, b, X, n_sample):
+    """FP64 oracle on the first n_sample configurations of the 116k-atom fit
+    (measured parts listed, and their extrapolation to the whole fit)."""
+    import oracle
+    import synth
+    hi = host_info()
     n_sample = min(n_sample, b.n_cfg)
     a1 = int(b.cfg_ptr[n_sample])
     p1 = int(b.pair_ptr[a1])
@@ -98,145 +127,304 @@ def cpu_baseline(w, b, X, n_sample):
     t_qr = time.perf_counter() - t0
     m_full = b.n_rows + w.M
     est = t_knm * (b.n_cfg / n_sample) + t_kmm + t_chol + t_qr * (m_full / A.shape[0])
-    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle",
+    return {"value": est, "unit": "s", "cores": int(hi["blas_threads"]), "kind": "oracle",
             "sample": (f"oracle K_NM on {n_sample} of {b.n_cfg} configurations "
                        f"({t_knm:.2f} s, scaled x{b.n_cfg / n_sample:.1f}); K_MM {t_kmm:.2f} s; "
                        f"Cholesky+stack {t_chol:.2f} s; LAPACK QR of the {A.shape[0]} x {w.M} "
                        f"sampled system ({t_qr:.2f} s, scaled by rows x{m_full / A.shape[0]:.1f})"),
-            "measured_s": t_knm + t_kmm + t_chol + t_qr}
+            "measured_s": t_knm + t_kmm + t_chol + t_qr, "extrapolated": True, "host": hi}
 
 
-def large_mixed_fit(args, torch, synth, gapx):
-    """The largest fit (4000 configurations of 32-256 atoms, ~576k atoms, D = 1500,
-    40 neighbours, M = 8000, FP32 descriptors and Jacobians).  Its 415 GB of
-    Jacobians do not fit in HBM, so configurations are taken in batches of
-    about --large-rows observation rows: each batch's BF16X3 rows are folded
-    into the streamed factor, then every FP64 refinement pass regenerates the
-    batch on the host (the next batch is drawn on a host thread while the GPU
-    works on the current one) and adds its share of A^T r.  Reported: GPU time
-    of the fit (sum of the library's stage timers: K_MM, assembly, folds,
-    refinement; input generation, host-to-device copies and the target predict
-    excluded), wall time, and ||A^T r|| of the FP64 system after each step."""
-    from concurrent.futures import ThreadPoolExecutor
+def cpu_baseline_full(w, b, X):
+    """FP64 oracle on the whole 116k-atom fit: K_NM of every configuration,
+    K_MM, the stacked least-squares system and its LAPACK QR solve (no sample)."""
+    import oracle
+    import synth
+    hi = host_info()
+    t0 = time.perf_counter()
+    K = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    t_knm = time.perf_counter() - t0
+    log(f"oracle K_NM of the whole fit: {t_knm:.1f} s")
+    t0 = time.perf_counter()
+    Kmm = oracle.build_kmm(X, w.zeta, w.delta)
+    t_kmm = time.perf_counter() - t0
+    y = np.random.default_rng(0).standard_normal(K.shape[0])
+    sig = synth.sigma_rows(w, b.counts)
+    t0 = time.perf_counter()
+    A, bb = oracle.design_matrix(K, Kmm, y, sig, w.jitter)
+    del K
+    t_chol = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve_qr(A, bb)
+    t_qr = time.perf_counter() - t0
+    log(f"oracle QR of the {A.shape[0]} x {w.M} system: {t_qr:.1f} s")
+    tot = t_knm + t_kmm + t_chol + t_qr
+    return {"value": tot, "unit": "s", "cores": int(hi["blas_threads"]), "kind": "oracle",
+            "sample": (f"whole 116k-atom FP64 fit, not sampled: K_NM {t_knm:.1f} s, K_MM "
+                       f"{t_kmm:.2f} s, Cholesky+stack {t_chol:.2f} s, LAPACK QR of the "
+                       f"{A.shape[0]} x {w.M} system {t_qr:.1f} s"),
+            "measured_s": tot, "extrapolated": False, "host": hi}
 
+
+def cpu_baseline_large(synth, n_sample=2):
+    """FP64 oracle on a bounded sample of the 576k-atom fit, timed, never
+    extrapolated (the whole fit would need ~530 GB of host memory): K_NM of its
+    first n_sample configurations (Jacobians drawn on the device and copied
+    back, outside the timing), K_MM of all 8000 sparse points, and the LAPACK QR
+    of the sample's stacked least-squares system."""
+    import oracle
+    import torch
+    hi = host_info()
     w = synth.WORKLOADS["fit_large_mixed"]
-    M, D = w.M, w.D
-    n_cfg = min(w.n_cfg, args.large_cfgs) if args.large_cfgs > 0 else w.n_cfg
-    counts = synth.atom_counts(w)[:n_cfg]
-    rows = 3 * counts + 1
-    cuts, acc = [0], 0
-    for c in range(n_cfg):
-        acc += int(rows[c])
-        if acc >= args.large_rows:
-            cuts.append(c + 1)
-            acc = 0
-    if cuts[-1] != n_cfg:
-        cuts.append(n_cfg)
-    batches = list(zip(cuts[:-1], cuts[1:]))
-    max_rows = max(int(rows[a:b].sum()) for a, b in batches)
-    n_rows, n_atoms = int(rows.sum()), int(counts.sum())
-    n_pairs = n_atoms * w.nb
-    log(f"large fit: {n_atoms} atoms, {n_pairs} pairs, {n_rows} rows in {len(batches)} batches "
-        f"of <= {max_rows} rows")
-    t_wall = time.perf_counter()
-    torch.cuda.set_device(0)
-    gap = gapx.Gap(0)
+    b = synth.generate(w, np.arange(n_sample), jac=False)
+    b.jac = synth.device_jacobians(w, 0, n_sample).cpu().numpy()[:, :, :w.D]
+    torch.cuda.synchronize()
     X = synth.sparse_points(w)
-    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
-    cstar = torch.tensor(synth.hidden_coefficients(w), device="cuda")
-    pool = ThreadPoolExecutor(1)
+    t0 = time.perf_counter()
+    K = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    t_knm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Kmm = oracle.build_kmm(X, w.zeta, w.delta)
+    t_kmm = time.perf_counter() - t0
+    y = np.random.default_rng(0).standard_normal(K.shape[0])
+    sig = synth.sigma_rows(w, b.counts)
+    t0 = time.perf_counter()
+    A, bb = oracle.design_matrix(K, Kmm, y, sig, w.jitter)
+    t_chol = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve_qr(A, bb)
+    t_qr = time.perf_counter() - t0
+    tot = t_knm + t_kmm + t_chol + t_qr
+    return {"value": tot, "unit": "s", "cores": int(hi["blas_threads"]), "kind": "oracle",
+            "sample": (f"{n_sample} of 4000 configurations of the 576k-atom fit ({b.n_atoms} atoms, "
+                       f"{b.n_rows} rows): K_NM {t_knm:.2f} s, K_MM (8000 x 8000, D = 1500) "
+                       f"{t_kmm:.2f} s, Cholesky+stack {t_chol:.2f} s, LAPACK QR of the "
+                       f"{A.shape[0]} x {w.M} sampled system {t_qr:.2f} s; measured, not "
+                       f"extrapolated to the whole fit"),
+            "measured_s": tot, "extrapolated": False, "host": hi}
 
-    def draw(k):
-        a, b_ = batches[k]
-        return synth.generate(w, np.arange(a, b_))
 
-    def batches_on_device():
-        """Yield (k, atoms, host batch) with batch k + 1 drawn on the host meanwhile."""
-        nxt = pool.submit(draw, 0)
-        for k in range(len(batches)):
-            b = nxt.result()
-            if k + 1 < len(batches):
-                nxt = pool.submit(draw, k + 1)
-            atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
-            yield k, atoms, b
+class LargeFit:
+    """The largest fit (4000 configurations of 32-256 atoms, ~576k atoms, D = 1500,
+    40 neighbours, M = 8000, FP32 descriptors and Jacobians, BF16X3 assembly,
+    FP64 QR and refinement).  Its 415 GB of Jacobians do not fit in device
+    memory, so the configurations are taken in batches of about ``rows``
+    observation rows and every pass over the training set draws each batch's
+    Jacobians again on the device (counter-based generator, a stand-in for
+    the descriptor code that would produce them).  One fit:
+      K_MM -> fold state [U 0; 0 0] -> per batch: Jacobians, BF16X3 rows (pair
+      transpose, split, energy rows + S, force rows) into the state's block
+      area, fold (Householder QR of [T; block]) -> back substitution ->
+      ``refine`` steps, each a pass of exact FP64 residual rows (Jacobians drawn
+      again) and a seminormal correction.
+    Descriptors, pair lists and targets stay resident between fits."""
 
+    def __init__(self, args, torch, synth, gapx):
+        self.torch, self.synth, self.gapx = torch, synth, gapx
+        w = synth.WORKLOADS["fit_large_mixed"]
+        self.w = w
+        n_cfg = min(w.n_cfg, args.large_cfgs) if args.large_cfgs > 0 else w.n_cfg
+        self.refine = args.refine_steps
+        t0 = time.perf_counter()
+        log(f"large fit: generating descriptors and neighbour lists of {n_cfg} configurations "
+            f"on the host")
+        b = synth.generate(w, np.arange(n_cfg), jac=False)
+        X = synth.sparse_points(w, b if n_cfg == w.n_cfg else None)
+        rows = 3 * b.counts + 1
+        cuts, acc = [0], 0
+        for c in range(n_cfg):
+            acc += int(rows[c])
+            if acc >= args.large_rows:
+                cuts.append(c + 1)
+                acc = 0
+        if cuts[-1] != n_cfg:
+            cuts.append(n_cfg)
+        self.n_cfg, self.n_atoms, self.n_pairs = n_cfg, b.n_atoms, b.n_pairs
+        self.n_rows = b.n_rows
+        torch.cuda.set_device(0)
+        self.gap = gapx.Gap(0)
+        self.sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+        max_pairs = max(int(b.pair_ptr[b.cfg_ptr[c1]] - b.pair_ptr[b.cfg_ptr[c0]])
+                        for c0, c1 in zip(cuts[:-1], cuts[1:]))
+        self.J = torch.empty(max_pairs, 3, w.D, dtype=torch.float32, device="cuda")
+        self.batches = []
+        for c0, c1 in zip(cuts[:-1], cuts[1:]):
+            a0, a1 = int(b.cfg_ptr[c0]), int(b.cfg_ptr[c1])
+            p0, p1 = int(b.pair_ptr[a0]), int(b.pair_ptr[a1])
+            at = gapx.Atoms(torch.tensor(b.cfg_ptr[c0:c1 + 1] - a0, device="cuda"),
+                            torch.tensor(b.desc[a0:a1], device="cuda"),
+                            torch.tensor(b.pair_ptr[a0:a1 + 1] - p0, device="cuda"),
+                            torch.tensor(b.pair_j[p0:p1] - a0, dtype=torch.int32, device="cuda"),
+                            self.J[:p1 - p0], w.D)
+            self.batches.append({"c0": c0, "c1": c1, "atoms": at, "rows": at.n_rows,
+                                 "counts": b.counts[c0:c1]})
+        del b
+        self.max_rows = max(bt["rows"] for bt in self.batches)
+        self.T = self.gap.fold_buffer(w.M, self.max_rows)
+        self.Kmm = gapx.colmajor(w.M, w.M, w.M)
+        self.t_host = time.perf_counter() - t0
+        self.gen_events = []
+        log(f"large fit: {self.n_atoms} atoms, {self.n_pairs} pairs, {self.n_rows} rows in "
+            f"{len(self.batches)} batches of <= {self.max_rows} rows; state "
+            f"{self.T.numel() * 8 / 1e9:.1f} GB, Jacobian buffer "
+            f"{self.J.numel() * 4 / 1e9:.1f} GB; host set-up {self.t_host:.1f} s")
+        # targets: FP64 predict with the hidden coefficients plus seeded noise
+        cstar = torch.tensor(synth.hidden_coefficients(w), device="cuda")
+        ids = np.arange(n_cfg)
+        for bt in self.batches:
+            self.jacobians(bt)
+            pr = self.gap.predict(bt["atoms"], self.sp, cstar, e_atom=False, e_cfg=True,
+                                  forces=True)
+            y = torch.cat([pr["e_cfg"], pr["forces"].reshape(-1)])
+            y += torch.tensor(synth.noise(w, ids[bt["c0"]:bt["c1"]], bt["counts"]), device="cuda")
+            bt["y"] = y
+            bt["sigma"] = torch.tensor(synth.sigma_rows(w, bt["counts"]), device="cuda")
+        torch.cuda.synchronize()
+        self.gen_events = []
+
+    def jacobians(self, bt):
+        ev = (self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True))
+        ev[0].record()
+        self.synth.device_jacobians(self.w, bt["c0"], bt["c1"], out=self.J)
+        ev[1].record()
+        self.gen_events.append(ev)
+
+    def fit(self, norms=False):
+        """One whole fit; returns c (and, with norms, the block norms for the report)."""
+        gap, w, sp, T, M = self.gap, self.w, self.sp, self.T, self.w.M
+        gap.build_kmm(sp, out=self.Kmm)
+        gap.fold_init(T, M, self.Kmm, w.jitter)
+        fro2 = 0.0
+        for bt in self.batches:
+            self.jacobians(bt)
+            gap.build_knm_block(bt["atoms"], sp, T, precision="bf16x3")
+            if norms:
+                blk = T[:M, M + 1:M + 1 + bt["rows"]]
+                fro2 += float(((blk / bt["sigma"][None, :]) ** 2).sum())
+            gap.fold_rows(T, M, bt["rows"], bt["y"], bt["sigma"])
+        c, lsq, rd = gap.fold_solve(T, M)
+        for _ in range(self.refine):
+            g = self.residual_pass(c)
+            gap.refine_solve(T, M, self.Kmm, w.jitter, g, c)
+        return (c, lsq, rd, fro2) if norms else c
+
+    def residual_pass(self, c, rr=None):
+        g = self.torch.zeros(self.w.M, dtype=self.torch.float64, device="cuda")
+        for bt in self.batches:
+            self.jacobians(bt)
+            self.gap.refine_rows(bt["atoms"], self.sp, c, bt["y"], bt["sigma"], g, rr)
+        return g
+
+    def generation_ms(self):
+        self.torch.cuda.synchronize()
+        t = sum(a.elapsed_time(b) for a, b in self.gen_events)
+        self.gen_events = []
+        return t
+
+    def describe(self):
+        w = self.w
+        return (f"fit_large_mixed: {self.n_cfg} configurations x U[{w.atoms_lo},{w.atoms_hi}] atoms "
+                f"({self.n_atoms} atoms, {self.n_pairs} pairs, {self.n_rows} observation rows), "
+                f"D={w.D}, {w.nb} neighbours/atom, M={w.M}, zeta={w.zeta}, FP32 descriptors and "
+                f"Jacobians (Jacobians drawn on the device each pass), BF16X3 rows folded in "
+                f"{len(self.batches)} batches into an FP64 Householder QR, {self.refine} FP64 "
+                f"refinement steps")
+
+
+def large_fit_bench(args, torch, synth, gapx):
+    """The headline: whole fits of the largest workload, timed end to end with
+    HIP events on the stream every call is ordered on."""
+    L = LargeFit(args, torch, synth, gapx)
+    gap, w, M = L.gap, L.w, L.w.M
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        L.fit()
+        torch.cuda.synchronize()
+        log(f"large warmup {i + 1}/{args.warmup}: {time.perf_counter() - t0:.2f} s")
+    L.generation_ms()
     gap.timing(True)
     gap.timing_read(reset=True)
-    gpu_ms = {}
-
-    def collect(tag):
-        torch.cuda.synchronize()
-        st = gap.timing_read(reset=True)
-        gpu_ms[tag] = {k: v[0] for k, v in st.items() if v[1] > 0}
-        return sum(gpu_ms[tag].values())
-
-    Kmm = gap.build_kmm(sp)
-    T = gap.fold_buffer(M, max_rows)
-    gap.fold_init(T, M, Kmm, w.jitter)
-    collect("init")
-    ys, sigs = [], []
-    t_fold = 0.0
-    for k, atoms, b in batches_on_device():
-        # targets of the batch: FP64 predict with the hidden coefficients plus seeded noise
-        pr = gap.predict(atoms, sp, cstar, e_atom=False, e_cfg=True, forces=True)
-        y = torch.cat([pr["e_cfg"], pr["forces"].reshape(-1)])
-        y += torch.tensor(synth.noise(w, b.cfg_ids, b.counts), device="cuda")
-        ys.append(y)
-        sigs.append(torch.tensor(synth.sigma_rows(w, b.counts), device="cuda"))
-        collect(f"targets{k}")
-        gap.build_knm_block(atoms, sp, T, precision="bf16x3")
-        gap.fold_rows(T, M, b.n_rows, ys[k], sigs[k])
-        t_fold += collect(f"fold{k}")
-        log(f"batch {k + 1}/{len(batches)} folded ({b.n_rows} rows), GPU {t_fold / 1e3:.1f} s so far")
-    c, lsq, rd = gap.fold_solve(T, M)
-    t_fold += collect("solve")
-    norms, t_ref = [], 0.0
-    for step in range(args.refine_steps + 1):
-        g = torch.zeros(M, dtype=torch.float64, device="cuda")
-        for k, atoms, b in batches_on_device():
-            gap.refine_rows(atoms, sp, c, ys[k], sigs[k], g)
-            t_ref += collect(f"ref{step}.{k}")
-        # ||A^T r|| of the whole FP64 system (regulariser rows included), for the report
-        full = g - (Kmm.T @ c + w.jitter * c)
-        norms.append(float(torch.linalg.vector_norm(full)))
-        log(f"refinement pass {step}: ||A^T r|| = {norms[-1]:.3e}")
-        if step == args.refine_steps:
-            break
-        gap.refine_solve(T, M, Kmm, w.jitter, g, c)
-        t_ref += collect(f"solve{step}")
-    pool.shutdown()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    times = []
+    e0.record()
+    for i in range(args.steps):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        c = L.fit()
+        s1.record()
+        s1.synchronize()
+        times.append(s0.elapsed_time(s1))
+        log(f"large step {i + 1}/{args.steps}: {times[-1] / 1e3:.2f} s")
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    gen_ms = L.generation_ms() / args.steps
+    st = gap.timing_read(reset=True)
     gap.timing(False)
-    wall = time.perf_counter() - t_wall
+    per = {k: v[0] / args.steps for k, v in st.items() if v[1] > 0}
+    fit_s = total_ms / args.steps / 1e3
     assert torch.isfinite(c).all().item(), "non-finite coefficients"
-    stage = {}
-    for tag, st in gpu_ms.items():
-        if tag.startswith("targets"):
-            continue
-        for k, v in st.items():
-            stage[k] = stage.get(k, 0.0) + v
-    fit_ms = sum(stage.values())
-    knm_ms = stage.get("pair_transpose", 0) + stage.get("energy_rows", 0) + \
-        stage.get("force_rows", 0) + stage.get("split_bf16", 0)
-    knm_flops = 2.0 * M * D * (n_atoms + 3.0 * n_pairs)
+    # accuracy report outside the timed region: one more fit with the block norms,
+    # and a final pass for r and A^T r of the exact FP64 system
+    c, lsq, rd, fro2_obs = L.fit(norms=True)
+    rr = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = L.residual_pass(c, rr)
+    Kc = L.Kmm.T @ c + w.jitter * c             # (K_MM + jitter I) c = U^T U c
+    atr = g - Kc                                 # A^T r, regulariser rows included
+    r2 = float(rr[0]) + float(c @ Kc)            # ||b - A c||^2 (obs rows + ||U c||^2)
+    fro2 = fro2_obs + float(torch.trace(L.Kmm)) + M * w.jitter   # ||U||_F^2 = trace(K_MM + jitter I)
+    nA, nc = fro2 ** 0.5, float(torch.linalg.vector_norm(c))
+    scaled = float(torch.linalg.vector_norm(atr)) / (nA * (nA * nc + r2 ** 0.5))
+    L.generation_ms()
+    force_ms = per.get("force_rows", float("nan"))
+    D, P = w.D, L.n_pairs
+    force_flops = 2.0 * 3.0 * P * M * D            # algorithmic, per fit (all batches)
+    exec_flops = 3.0 * 2.0 * 3.0 * P * M * ((D + 31) // 32 * 32)
+    knm_ms = sum(per.get(k, 0.0) for k in ("pair_transpose", "energy_rows", "force_rows",
+                                             "split_bf16"))
+    knm_flops = 2.0 * M * D * (L.n_atoms + 3.0 * P)
+    qr_ms = per.get("qr_panel", 0.0) + per.get("qr_update", 0.0)
+    m_all = L.n_rows + len(L.batches) * (M + 1)
+    qr_flops = 2.0 * m_all * (M + 1) ** 2 - len(L.batches) * 2.0 / 3.0 * (M + 1) ** 3
     line = {
-        "metric": METRIC, "value": fit_ms / 1e3, "unit": "s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "ms_per_step": fit_ms, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x3+f64", "data": "synthetic",
-        "config": {"workload": f"fit_large_mixed: {n_cfg} configurations x U[{w.atoms_lo},"
-                               f"{w.atoms_hi}] atoms ({n_atoms} atoms, {n_pairs} pairs, "
-                               f"{n_rows} observation rows), D={D}, {w.nb} neighbours/atom, "
-                               f"M={M}, zeta={w.zeta}, J f32, BF16X3 rows folded in "
-                               f"{len(batches)} batches, {args.refine_steps} FP64 refinement steps",
-                   "precision": "bf16x3", "n_rows": n_rows, "M": M, "D": D},
-        "gpu_s": {"assembly_and_folds": t_fold / 1e3, "refinement": t_ref / 1e3},
-        "knm_ms": knm_ms, "knm_tflops_algorithmic": knm_flops / (knm_ms * 1e-3) / 1e12,
-        "stage_ms": {k: round(v, 1) for k, v in stage.items()},
-        "wall_s_with_host_generation": wall,
-        "lsq_resid_norm_before_refinement": lsq,
-        "normal_eq_residual_per_step": norms,
-        "min_max_abs_rdiag": list(rd),
+        "metric": METRIC, "value": fit_s, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": fit_s * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f64", "data": "synthetic",
+        "config": {"workload": L.describe(), "precision": "bf16x3 assembly, fp64 QR/solve/refinement",
+                   "n_rows": L.n_rows, "M": M, "D": D},
+        "fit_s_per_step": [t / 1e3 for t in times],
+        "jacobian_generation_s": gen_ms / 1e3,
+        "fit_s_excluding_generation": fit_s - gen_ms / 1e3,
+        "knm_ms": knm_ms,
+        "knm_gflops_algorithmic": knm_flops / (knm_ms * 1e-3) / 1e9 if knm_ms > 0 else None,
+        "qr_ms": qr_ms, "qr_tflops": qr_flops / (qr_ms * 1e-3) / 1e12 if qr_ms > 0 else None,
+        "refinement_ms": per.get("refinement", 0.0),
+        "stage_ms": {k: round(v, 1) for k, v in per.items()},
+        "roofline": {"kernel": "k_force_rows_b3 (BF16X3 force observation rows, BF16 MFMA, "
+                               "three products per multiply-add)",
+                     "bound": "mfma", "achieved": exec_flops / (force_ms * 1e-3) / 1e12,
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": exec_flops / (force_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+                     "traffic": None, "traffic_unit": "bytes per launch",
+                     "flops_per_fit_executed": exec_flops,
+                     "flops_per_fit_algorithmic": force_flops,
+                     "algorithmic_tflops": force_flops / (force_ms * 1e-3) / 1e12,
+                     "launches_per_fit": len(L.batches)},
+        "accuracy": {"scaled_normal_eq_residual": scaled,
+                     "normal_eq_residual": float(torch.linalg.vector_norm(atr)),
+                     "lsq_resid_norm_before_refinement": lsq, "resid_norm_after": r2 ** 0.5,
+                     "min_max_abs_rdiag": list(rd)},
+        "host_setup_s": L.t_host,
     }
-    print(json.dumps(line), flush=True)
+    log(f"large fit {fit_s:.2f} s per fit (Jacobian generation {gen_ms / 1e3:.2f} s), force rows "
+        f"{force_ms / 1e3:.2f} s ({line['roofline']['frac']:.2f} of BF16 peak executed), QR "
+        f"{qr_ms / 1e3:.2f} s, refinement {line['refinement_ms'] / 1e3:.2f} s, scaled "
+        f"normal-equation residual {scaled:.2e}")
+    gap.close()
+    del L
+    torch.cuda.empty_cache()
+    return line
 
 
 def main():
@@ -244,8 +432,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fit_fp64")
-    ap.add_argument("--cpu-sample-cfgs", type=int, default=48)
+    ap.add_argument("--workload", default="fit_large_mixed", choices=["fit_large_mixed", "fit_fp64"],
+                    help="headline workload (default: the 576k-atom mixed fit; fit_fp64: the "
+                         "116k-atom FP64 fit alone, with its legs)")
+    ap.add_argument("--cpu-sample-cfgs", type=int, default=48,
+                    help="fit_fp64 headline: configurations of the oracle sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the FP64 oracle on the whole 116k-atom fit (about 30 GB of host "
+                         "memory, minutes of CPU time) instead of a sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--refine-steps", type=int, default=3)
@@ -253,12 +447,14 @@ def main():
                     help="skip timing the virial, two-body, variance and CUR legs")
     ap.add_argument("--no-predict", action="store_true",
                     help="skip the predict / backward leg on the 65,536-atom predict workload")
+    ap.add_argument("--no-fp64-legs", action="store_true",
+                    help="default headline: skip the 116k-atom legs after the large fit")
     ap.add_argument("--stream-blocks", type=int, default=4,
                     help="configuration groups of the streamed-fit leg (0: skip it)")
     ap.add_argument("--large-rows", type=int, default=200000,
-                    help="observation rows per batch of the fit_large_mixed workload")
+                    help="observation rows per batch of the 576k-atom fit")
     ap.add_argument("--large-cfgs", type=int, default=0,
-                    help="fit_large_mixed: fit only its first N configurations (0: all 4000)")
+                    help="576k-atom fit: fit only its first N configurations (0: all 4000)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -271,10 +467,23 @@ def main():
     import synth
     import paper_2310_03921_amd as gapx
 
-    if args.workload == "fit_large_mixed":
-        large_mixed_fit(args, torch, synth, gapx)
+    if args.workload == "fit_fp64":
+        out = fit_fp64_legs(args, torch, synth, gapx, headline=True)
+        print(json.dumps(out), flush=True)
         return
-    w = synth.WORKLOADS[args.workload]
+    line = large_fit_bench(args, torch, synth, gapx)
+    if not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle on a sample of the large fit")
+        line["cpu_baseline"] = cpu_baseline_large(synth)
+    if not args.no_fp64_legs:
+        line["fit_fp64_116k"] = fit_fp64_legs(args, torch, synth, gapx, headline=False)
+    print(json.dumps(line), flush=True)
+
+
+def fit_fp64_legs(args, torch, synth, gapx, headline):
+    """The 116k-atom FP64 fit and its legs (mixed, streamed, variance, CUR, two-body,
+    virial rows, the predict workload); with headline, the CPU oracle too."""
+    w = synth.WORKLOADS["fit_fp64"]
     log(f"generating {w.name} on the host")
     t0 = time.perf_counter()
     b = synth.generate(w)
@@ -569,9 +778,9 @@ def main():
         del atp, dEdd
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the FP64 CPU oracle on a sample")
-        cpu = cpu_baseline(w, b, X, args.cpu_sample_cfgs)
+    if headline and not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle" + (" on the whole fit" if args.cpu_full else " on a sample"))
+        cpu = cpu_baseline_full(w, b, X) if args.cpu_full else cpu_baseline(w, b, X, args.cpu_sample_cfgs)
 
     out = {
         "metric": METRIC,
@@ -608,7 +817,7 @@ def main():
         "cur_selection": cur,
         "fit_info": {"min_abs_rdiag": info["min_abs_rdiag"], "max_abs_rdiag": info["max_abs_rdiag"]},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

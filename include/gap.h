@@ -148,6 +148,24 @@ gap_status gap_build_kmm(gap_handle *h, const gap_sparse *sp, double *Kmm, int64
 gap_status gap_build_knm(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
                          gap_precision prec, double *Knm, int64_t ld);
 
+/* Per-species GP block (Sec. "Theory", eq. 1: the total energy is a sum over
+ * descriptor types of local energies, each type a GP of its own; a descriptor
+ * defined for one central species, as in the multi-species models of the
+ * "Practical examples", gives one such GP per species).  The rows of
+ * gap_build_knm with only the atoms of species z as centres:
+ *   energy row c:        sum_{i in c, species[i] = z} delta^2 (d_i . x_m)^zeta
+ *   force row (j,alpha): - sum_{(i,k): j(i,k)=j, species[i] = z} delta^2 zeta (d_i . x_m)^(zeta-1)
+ *                          J[(i,k),alpha] . x_m
+ * Targets j of any species receive forces.  species [n_atoms] int32 device.
+ * A model of several species puts the blocks side by side (columns of each
+ * block's sparse points, K = Knm + M_prev * ld) in one design buffer or fold
+ * block, with K_MM block-diagonal, and fits them together (gap_fit without
+ * refinement, or the gap_fold_* calls).  Same layout, precision and errors as
+ * gap_build_knm.  Asynchronous. */
+gap_status gap_build_knm_species(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                                 gap_precision prec, const int32_t *species, int32_t z,
+                                 double *Knm, int64_t ld);
+
 /* Two-body descriptor with the squared-exponential kernel, for models of
  * several descriptors (Sec. "Descriptors based on interatomic distances":
  * distance_2b, the pair distance as descriptor, the kernel multiplied by the
@@ -349,6 +367,16 @@ gap_status gap_predict(gap_handle *h, const gap_atoms *atoms, const gap_sparse *
                        const double *c, gap_precision prec, double *e_atom, double *e_cfg,
                        double *dEdd, double *forces);
 
+/* gap_predict of the per-species GP block of species z (see
+ * gap_build_knm_species): eps_i as gap_predict for atoms with species[i] = z,
+ * 0 for the others; e_cfg, dEdd and forces follow from those eps_i.  The
+ * model's prediction is the sum of its species blocks' outputs.
+ * species [n_atoms] int32 device.  Asynchronous. */
+gap_status gap_predict_species(gap_handle *h, const gap_atoms *atoms, const gap_sparse *sp,
+                               const double *c, gap_precision prec, const int32_t *species,
+                               int32_t z, double *e_atom, double *e_cfg, double *dEdd,
+                               double *forces);
+
 /* Backward of e_atom = predict(desc, X, c) for an upstream gradient g_e [n_atoms]
  * (differentiation of eq. epsilon; (d_i . x_m)^(zeta-1) is recomputed):
  *   d_desc [n_atoms][D] = g_e[i] g_i
@@ -364,6 +392,20 @@ gap_status gap_predict_backward(gap_handle *h, const gap_atoms *atoms, const gap
  * dEdd [n_atoms][D] FP64 row-major (ld = D); forces [n_atoms][3] FP64.
  * Deterministic: per-pair contributions are summed per target in pair order. */
 gap_status gap_forces(gap_handle *h, const gap_atoms *atoms, const double *dEdd, double *forces);
+
+/* The split step of the BF16X3 form on its own (the BF16X3 calls apply the
+ * same split to their operands inside; reading of the split-BF16 contraction):
+ * every value x of the row-major rows x cols array `x` (f32 or f64, leading
+ * dimension ld, ld % 4 == 0, 32-byte aligned) becomes
+ *   hi = bf16(fp32(x)),  lo = bf16(fp32(x) - hi)     (each rounding to nearest even)
+ * written as raw bf16 bits to hi and lo [rows][ldp] (16-byte aligned), with
+ * ldp = cols rounded up to a multiple of 32 and the padding zero.  hi_t / lo_t
+ * (FP64 input only; both or neither) also receive the transposed halves
+ * [cols][rows rounded up to 32], zero padded: the layout the library keeps of
+ * the sparse points for W X.  FP64 input with hi_t runs the sparse-point split
+ * kernel, every other call the Jacobian split kernel.  Asynchronous. */
+gap_status gap_split_bf16x3(gap_handle *h, const void *x, gap_dtype dt, int64_t rows, int64_t cols,
+                            int64_t ld, uint16_t *hi, uint16_t *lo, uint16_t *hi_t, uint16_t *lo_t);
 
 /* Stage timing (profiling aid, off by default).  When enabled, the library
  * records HIP events on the handle's stream around each stage it enqueues;

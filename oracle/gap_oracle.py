@@ -122,6 +122,77 @@ def build_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta):
     return K
 
 
+def build_knm_species(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta, species, z):
+    """Rows of the per-species GP of species z: L-hat K_NM with only the atoms
+    of species z as centres of local energies.
+
+    Sec. "Theory", eq. 1: the energy is a sum over descriptor types of local
+    energies, each descriptor type with a GP of its own; a descriptor defined
+    for one central species contributes the local energies of the atoms of that
+    species only.  With s_i the species of atom i:
+        K_E[c, m] = sum_{i in c, s_i = z} k(d_i, x_m)
+        K_F[(j, alpha), m] = - sum_{(i,k): j(i,k)=j, s_i = z} dk/dp(p_im) (J[(i,k), alpha] . x_m)
+    (targets j of any species).  Computed per configuration as build_knm, the
+    kernel values and gradient scales of the other species' centres set to 0.
+    """
+    cfg_ptr = np.asarray(cfg_ptr, dtype=np.int64)
+    pair_ptr = np.asarray(pair_ptr, dtype=np.int64)
+    pair_j = np.asarray(pair_j, dtype=np.int64)
+    species = np.asarray(species)
+    X = np.asarray(X, dtype=np.float64)
+    n_cfg, n_at, M = len(cfg_ptr) - 1, int(cfg_ptr[-1]), X.shape[0]
+    D = X.shape[1]
+    K = np.zeros((n_cfg + 3 * n_at, M))
+    for c in range(n_cfg):
+        a0, a1 = int(cfg_ptr[c]), int(cfg_ptr[c + 1])
+        if a1 == a0:
+            continue
+        centre = (species[a0:a1] == z).astype(np.float64)[:, None]   # 1 for species z
+        d = np.asarray(desc[a0:a1], dtype=np.float64)
+        P = d @ X.T
+        K[c] = (centre * poly_kernel(P, zeta, delta)).sum(axis=0)
+        p0, p1 = int(pair_ptr[a0]), int(pair_ptr[a1])
+        if p1 == p0:
+            continue
+        src = pair_sources(pair_ptr[a0:a1 + 1] - p0)
+        tgt = pair_j[p0:p1] - a0
+        if tgt.min() < 0 or tgt.max() >= a1 - a0:
+            raise ValueError("a neighbour pair leaves its configuration")
+        Jc = np.asarray(jac[p0:p1], dtype=np.float64).reshape(-1, D)
+        G = (Jc @ X.T).reshape(p1 - p0, 3, M)
+        scale = centre * poly_kernel_grad_scale(P, zeta, delta)
+        H = scale[src][:, None, :] * G
+        inc = np.zeros((a1 - a0, p1 - p0))
+        inc[tgt, np.arange(p1 - p0)] = 1.0
+        KF = -(inc @ H.reshape(p1 - p0, 3 * M)).reshape(a1 - a0, 3, M)
+        K[n_cfg + 3 * a0:n_cfg + 3 * a1] = KF.reshape(3 * (a1 - a0), M)
+    return K
+
+
+def predict_species(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta, species, z):
+    """Prediction of the per-species GP of species z (eq. epsilon for the
+    atoms of species z, local energy 0 for the others), with the configuration
+    energies, descriptor gradients and forces that follow from those local
+    energies by the chain rule."""
+    desc = np.asarray(desc, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    centre = (np.asarray(species) == z).astype(np.float64)
+    P = desc @ X.T
+    e_atom = centre * (poly_kernel(P, zeta, delta) @ c)
+    g = centre[:, None] * ((poly_kernel_grad_scale(P, zeta, delta) * c[None, :]) @ X)
+    cfg_ptr = np.asarray(cfg_ptr, dtype=np.int64)
+    e_cfg = np.array([e_atom[cfg_ptr[k]:cfg_ptr[k + 1]].sum() for k in range(len(cfg_ptr) - 1)])
+    forces = None
+    if jac is not None:
+        src = pair_sources(pair_ptr)
+        pj = np.asarray(pair_j, dtype=np.int64)
+        forces = np.zeros((desc.shape[0], 3))
+        Jp = np.asarray(jac, dtype=np.float64)
+        np.add.at(forces, pj, -np.einsum("pad,pd->pa", Jp, g[src]))
+    return e_atom, e_cfg, g, forces
+
+
 def build_virial_rows(cfg_ptr, desc, pair_ptr, jac, pair_r, X, zeta, delta):
     """Virial rows: row 9 c + 3 alpha + beta, column m is
     - sum over the pairs p = (i, k) of configuration c of

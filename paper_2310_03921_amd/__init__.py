@@ -10,8 +10,10 @@ torch tensors of shape (columns, ld): element (row r, column c) is t[c, r].
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -73,6 +75,8 @@ def lib():
             "gap_pair_transpose": ([P, P, P, P], S),
             "gap_build_kmm": ([P, P, P, I64], S),
             "gap_build_knm": ([P, P, P, I32, P, I64], S),
+            "gap_build_knm_species": ([P, P, P, I32, P, I32, P, I64], S),
+            "gap_predict_species": ([P, P, P, P, I32, P, I32, P, P, P, P], S),
             "gap_lstsq": ([P, P, I64, I64, I64, P, P], S),
             "gap_fit": ([P, P, I64, I64, P, P, P, ctypes.c_double, P, P, I32, P, P], S),
             "gap_build_local_rows": ([P, P, P, P, I64, P, I64], S),
@@ -90,6 +94,7 @@ def lib():
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_forces": ([P, P, P, P], S),
+            "gap_split_bf16x3": ([P, P, I32, I64, I64, I64, P, P, P, P], S),
             "gap_timing": ([P, I32], S),
             "gap_timing_read": ([P, P, P, I32], S),
             "gap_timing_name": ([I32], ctypes.c_char_p),
@@ -116,15 +121,30 @@ def _round4(n: int) -> int:
     return (n + 3) // 4 * 4
 
 
+def _aligned(t: torch.Tensor) -> bool:
+    """The ABI's vector loads need 32-byte aligned base pointers."""
+    return t.data_ptr() % 32 == 0
+
+
 def padded_rows(x: torch.Tensor, D: int, dtype=None, device=None) -> torch.Tensor:
-    """Copy a (..., D) array into a zero-padded (..., round4(D)) contiguous device tensor."""
+    """A (..., D) array as a contiguous, 32-byte aligned device tensor of rows
+    zero-padded to round4(D) (the input itself when it already is one)."""
     x = torch.as_tensor(x)
     dtype = dtype or x.dtype
     if D % 4 == 0:
-        return x.to(device=device, dtype=dtype).contiguous()
+        y = x.to(device=device, dtype=dtype).contiguous()
+        return y if _aligned(y) else y.clone()
     out = torch.zeros(*x.shape[:-1], _round4(D), dtype=dtype, device=device)
     out[..., :D] = x.to(device=device, dtype=dtype)
     return out
+
+
+def _aligned_view(t: torch.Tensor | None) -> torch.Tensor | None:
+    """t itself when its base is 32-byte aligned, else an aligned copy (a row
+    range of an FP32 array with an odd row offset starts 16 bytes off)."""
+    if t is None or t.numel() == 0 or _aligned(t):
+        return t
+    return t.clone()
 
 
 @dataclass
@@ -153,13 +173,15 @@ class Atoms:
 
     def configs(self, c0: int, c1: int) -> "Atoms":
         """Configurations [c0, c1) of this batch: descriptors and Jacobians are
-        views (no copy); the three index arrays are rebased copies."""
+        views (no copy) when their first row is 32-byte aligned, else aligned
+        copies; the three index arrays are rebased copies."""
         cp = self.cfg_ptr[c0:c1 + 1]
         a0, a1 = int(cp[0]), int(cp[-1])
         pp = self.pair_ptr[a0:a1 + 1]
         p0, p1 = int(pp[0]), int(pp[-1])
-        return Atoms(cp - a0, self.desc[a0:a1], pp - p0, self.pair_j[p0:p1] - a0,
-                     None if self.jac is None else self.jac[p0:p1], self.D)
+        return Atoms(cp - a0, _aligned_view(self.desc[a0:a1]), pp - p0,
+                     self.pair_j[p0:p1] - a0,
+                     None if self.jac is None else _aligned_view(self.jac[p0:p1]), self.D)
 
     @property
     def n_cfg(self):
@@ -258,6 +280,21 @@ def colmajor(rows: int, cols: int, ld: int | None = None, device="cuda") -> torc
     return torch.zeros(cols, ld, dtype=torch.float64, device=device)
 
 
+# Handles still open when the interpreter exits are closed by an atexit hook,
+# while the HIP runtime is still up, rather than by __del__ during teardown
+# (after the runtime, or a profiler attached to it, may have finalised).
+_open_handles: "weakref.WeakSet[Gap]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_handles():
+    for g in list(_open_handles):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
 class Gap:
     """A libgap handle bound to one device and the current torch stream."""
 
@@ -271,11 +308,13 @@ class Gap:
         st = L.gap_create(ctypes.byref(self._h), self.device, ctypes.c_void_p(self.stream.cuda_stream))
         if st != GAP_OK:
             raise GapError(st, f"gap_create failed on device {self.device}")
+        _open_handles.add(self)
 
     def close(self):
         if self._h:
             lib().gap_destroy(self._h)
             self._h = ctypes.c_void_p()
+        _open_handles.discard(self)
 
     def __del__(self):
         try:
@@ -334,6 +373,43 @@ class Gap:
         a, s = atoms.struct(), sparse.struct()
         self._check(lib().gap_build_knm(self._h, ctypes.byref(a), ctypes.byref(s),
                                         PRECISION[precision], _ptr(out), out.shape[1]))
+        return out
+
+    def build_knm_species(self, atoms: Atoms, sparse: Sparse, species: torch.Tensor, z: int,
+                          precision: str = "fp64", out: torch.Tensor | None = None,
+                          col0: int = 0, row0: int = 0) -> torch.Tensor:
+        """Rows of the per-species GP block of species z (only atoms with
+        species == z are centres) written at (row0, col0) of the column-major
+        buffer `out` (default: a new design buffer)."""
+        out = self.design_buffer(atoms, sparse) if out is None else out
+        a, s = atoms.struct(), sparse.struct()
+        sp_ = species.to(torch.int32).contiguous()
+        self._check(lib().gap_build_knm_species(
+            self._h, ctypes.byref(a), ctypes.byref(s), PRECISION[precision], _ptr(sp_), int(z),
+            ctypes.c_void_p(out.data_ptr() + 8 * (row0 + col0 * out.shape[1])), out.shape[1]))
+        self._keep_species = sp_
+        return out
+
+    def predict_species(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor,
+                        species: torch.Tensor, z: int, precision: str = "fp64", e_atom=True,
+                        e_cfg=True, dEdd=False, forces=False):
+        """gap_predict of the per-species block of species z (other atoms: 0)."""
+        dev = sparse.X.device
+        N, D = atoms.n_atoms, atoms.D
+        out = {
+            "e_atom": torch.empty(N, dtype=torch.float64, device=dev) if e_atom else None,
+            "e_cfg": torch.empty(atoms.n_cfg, dtype=torch.float64, device=dev) if e_cfg else None,
+            "dEdd": torch.empty(N, D, dtype=torch.float64, device=dev) if dEdd else None,
+            "forces": torch.empty(N, 3, dtype=torch.float64, device=dev) if forces else None,
+        }
+        a, s = atoms.struct(), sparse.struct()
+        c = _f64(c)
+        sp_ = species.to(torch.int32).contiguous()
+        self._check(lib().gap_predict_species(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
+                                              PRECISION[precision], _ptr(sp_), int(z),
+                                              _ptr(out["e_atom"]), _ptr(out["e_cfg"]),
+                                              _ptr(out["dEdd"]), _ptr(out["forces"])))
+        self._keep_species = (sp_, c)
         return out
 
     def build_local_rows(self, atoms: Atoms, sparse: Sparse, atom_idx: torch.Tensor,
@@ -566,6 +642,22 @@ class Gap:
         self._check(lib().gap_forces(self._h, ctypes.byref(a), _ptr(dEdd), _ptr(F)))
         return F
 
+    def split_bf16x3(self, x: torch.Tensor, cols: int, transposed: bool = False):
+        """The BF16X3 split of a row-major device array x [rows, ld] (f32 or f64,
+        ld % 4 == 0): raw bf16 bits of hi and lo as int16 tensors [rows,
+        round32(cols)], and with transposed=True (FP64 only) also the transposed
+        halves [cols, round32(rows)]."""
+        rows = x.shape[0]
+        ldp, ldm = (cols + 31) // 32 * 32, (rows + 31) // 32 * 32
+        dev = x.device
+        hi = torch.empty(max(rows, 1), ldp, dtype=torch.int16, device=dev)
+        lo = torch.empty_like(hi)
+        ht = torch.empty(cols, ldm, dtype=torch.int16, device=dev) if transposed else None
+        lt = torch.empty_like(ht) if transposed else None
+        self._check(lib().gap_split_bf16x3(self._h, _ptr(x), _DT[x.dtype], rows, cols, x.shape[1],
+                                           _ptr(hi), _ptr(lo), _ptr(ht), _ptr(lt)))
+        return hi[:rows], lo[:rows], ht, lt
+
 
 _default = {}
 
@@ -591,7 +683,7 @@ class GapPredict(torch.autograd.Function):
         gap = default_handle()
         D = desc.shape[1]
         dev = desc.device
-        desc_p = desc if (D % 4 == 0 and desc.is_contiguous()) else padded_rows(desc.detach(), D, device=dev)
+        desc_p = padded_rows(desc.detach(), D, device=dev)
         atoms = Atoms(torch.tensor([0, desc.shape[0]], dtype=torch.int64, device=dev), desc_p.detach(),
                       torch.zeros(desc.shape[0] + 1, dtype=torch.int64, device=dev),
                       torch.zeros(0, dtype=torch.int32, device=dev), None, D)
@@ -610,7 +702,7 @@ class GapPredict(torch.autograd.Function):
         gap = default_handle()
         D = desc.shape[1]
         dev = desc.device
-        desc_p = desc if (D % 4 == 0 and desc.is_contiguous()) else padded_rows(desc.detach(), D, device=dev)
+        desc_p = padded_rows(desc.detach(), D, device=dev)
         atoms = Atoms(torch.tensor([0, desc.shape[0]], dtype=torch.int64, device=dev), desc_p.detach(),
                       torch.zeros(desc.shape[0] + 1, dtype=torch.int64, device=dev),
                       torch.zeros(0, dtype=torch.int32, device=dev), None, D)

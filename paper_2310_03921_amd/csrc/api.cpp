@@ -1,7 +1,7 @@
 // C ABI of libgap: argument checks, workspace, and the order of kernel launches
 // for each verb.  Every numerical step runs in the gfx950 kernels; this file
 // only validates, lays out device workspace and enqueues.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
@@ -226,7 +226,8 @@ void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool ne
 
 void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
                  const PredictWs& w, double* e_atom, double* e_cfg, double* dEdd,
-                 double* forces, bool bf16 = false) {
+                 double* forces, bool bf16 = false, const int32_t* species = nullptr,
+                 int32_t zsel = 0) {
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   const bool need_g = dEdd || forces;
   double* ea = e_atom ? e_atom : (e_cfg ? at<double>(h, w.e_atom) : nullptr);
@@ -249,6 +250,7 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
                      sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream, nullptr, 0,
                      at<double>(h, w.epart));
   }
+  if (species) gapk::mask_species_rows(species, zsel, N, ea, W, ldw, h->stream);
   if (e_cfg) gapk::segment_sum_f64(ea, a->cfg_ptr, a->n_cfg, N, e_cfg, h->stream);
   if (forces) {
     double* g = at<double>(h, w.g);
@@ -435,8 +437,15 @@ gap_status gap_build_kmm(gap_handle* h, const gap_sparse* sp, double* Kmm, int64
   return GAP_OK;
 }
 
-gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
-                         gap_precision prec, double* Knm, int64_t ld) {
+}  // extern "C"
+
+namespace {
+
+// L-hat K_NM of gap_build_knm; with `species` non-null, the block of the
+// per-species GP of species zsel (only atoms of that species are centres).
+gap_status build_knm_impl(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                          gap_precision prec, double* Knm, int64_t ld, const int32_t* species,
+                          int32_t zsel) {
   if (!h) return GAP_E_INVALID;
   gap_status s = set_device(h);
   if (s != GAP_OK) return s;
@@ -484,7 +493,8 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
     h->timer.begin(gapk::TM_ENERGY);
     gapk::energy_rows_bf16x3(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N,
                              at<__bf16>(h, sw.xh), at<__bf16>(h, sw.xl), M, D, sp->zeta,
-                             sp->delta, Knm, ld, at<float>(h, S), ld8(M), h->stream);
+                             sp->delta, Knm, ld, at<float>(h, S), ld8(M), h->stream, species,
+                             zsel);
     h->timer.end(gapk::TM_ENERGY);
     HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
     h->timer.begin(gapk::TM_FORCE);
@@ -508,7 +518,7 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   h->timer.begin(gapk::TM_ENERGY);
   gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, a->n_cfg, N, sp->X,
                         sp->ld_x, M, D, sp->zeta, sp->delta, Knm, ld, at<double>(h, S), ld4(M),
-                        h->stream);
+                        h->stream, species, zsel);
   h->timer.end(gapk::TM_ENERGY);
   HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
   h->timer.begin(gapk::TM_FORCE);
@@ -519,6 +529,23 @@ gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp
   h->timer.end(gapk::TM_FORCE);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status gap_build_knm(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                         gap_precision prec, double* Knm, int64_t ld) {
+  return build_knm_impl(h, a, sp, prec, Knm, ld, nullptr, 0);
+}
+
+gap_status gap_build_knm_species(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                                 gap_precision prec, const int32_t* species, int32_t z,
+                                 double* Knm, int64_t ld) {
+  if (!h) return GAP_E_INVALID;
+  if (!species && a && a->n_atoms > 0) return fail(h, GAP_E_INVALID, "species is NULL");
+  return build_knm_impl(h, a, sp, prec, Knm, ld, species, z);
 }
 
 gap_status gap_lstsq(gap_handle* h, double* A, int64_t ld, int64_t m, int64_t n, double* x,
@@ -1115,9 +1142,13 @@ gap_status gap_refine_solve(gap_handle* h, const double* R, int64_t ldr, int64_t
   return drain_dev_err(h);
 }
 
-gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
-                       gap_precision prec, double* e_atom, double* e_cfg, double* dEdd,
-                       double* forces) {
+}  // extern "C"
+
+namespace {
+
+gap_status predict_impl(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
+                        gap_precision prec, double* e_atom, double* e_cfg, double* dEdd,
+                        double* forces, const int32_t* species, int32_t zsel) {
   if (!h) return GAP_E_INVALID;
   gap_status s = set_device(h);
   if (s != GAP_OK) return s;
@@ -1135,10 +1166,29 @@ gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, 
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   h->timer.begin(gapk::TM_PREDICT);
-  run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces, bf);
+  run_predict(h, a, sp, c, pw, e_atom, e_cfg, dEdd, forces, bf, species, zsel);
   h->timer.end(gapk::TM_PREDICT);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status gap_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const double* c,
+                       gap_precision prec, double* e_atom, double* e_cfg, double* dEdd,
+                       double* forces) {
+  return predict_impl(h, a, sp, c, prec, e_atom, e_cfg, dEdd, forces, nullptr, 0);
+}
+
+gap_status gap_predict_species(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                               const double* c, gap_precision prec, const int32_t* species,
+                               int32_t z, double* e_atom, double* e_cfg, double* dEdd,
+                               double* forces) {
+  if (!h) return GAP_E_INVALID;
+  if (!species && a && a->n_atoms > 0) return fail(h, GAP_E_INVALID, "species is NULL");
+  return predict_impl(h, a, sp, c, prec, e_atom, e_cfg, dEdd, forces, species, z);
 }
 
 gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
@@ -1223,6 +1273,36 @@ gap_status gap_forces(gap_handle* h, const gap_atoms* a, const double* dEdd, dou
   gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, a->D, g, ldg, at<int32_t>(h, p.src),
                    a->n_atoms, a->n_pairs, at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
                    at<double>(h, fp), forces, h->stream);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_split_bf16x3(gap_handle* h, const void* x, gap_dtype dt, int64_t rows,
+                            int64_t cols, int64_t ld, uint16_t* hi, uint16_t* lo, uint16_t* hi_t,
+                            uint16_t* lo_t) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  if (rows < 0 || cols < 1) return fail(h, GAP_E_INVALID, "rows must be >= 0 and cols >= 1");
+  if (dt != GAP_DT_F32 && dt != GAP_DT_F64) return fail(h, GAP_E_INVALID, "bad dtype");
+  if (rows == 0) return GAP_OK;
+  if (!x || !hi || !lo) return fail(h, GAP_E_INVALID, "x, hi or lo is NULL");
+  if (ld < cols || ld % 4 != 0 || !aligned32(x))
+    return fail(h, GAP_E_INVALID, "ld must be >= cols and a multiple of 4, x 32-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(hi) | reinterpret_cast<uintptr_t>(lo)) & 15u)
+    return fail(h, GAP_E_INVALID, "hi and lo must be 16-byte aligned");
+  if ((hi_t == nullptr) != (lo_t == nullptr))
+    return fail(h, GAP_E_INVALID, "give both transposed halves or neither");
+  if (hi_t) {
+    if (dt != GAP_DT_F64)
+      return fail(h, GAP_E_INVALID, "the transposed halves are produced from FP64 input only");
+    gapk::split_x_bf16(static_cast<const double*>(x), ld, rows, cols,
+                       reinterpret_cast<__bf16*>(hi), reinterpret_cast<__bf16*>(lo),
+                       reinterpret_cast<__bf16*>(hi_t), reinterpret_cast<__bf16*>(lo_t), h->stream);
+  } else {
+    gapk::split_rows_bf16(x, f32(dt), ld, rows, cols, reinterpret_cast<__bf16*>(hi),
+                          reinterpret_cast<__bf16*>(lo), h->stream);
+  }
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }

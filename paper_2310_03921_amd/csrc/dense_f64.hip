@@ -119,7 +119,9 @@ __global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc
                                                      int64_t M, int64_t D, int zeta, double delta,
                                                      double* __restrict__ K, int64_t ldk,
                                                      double* __restrict__ S, int64_t ldS,
-                                                     int64_t n_atoms) {
+                                                     int64_t n_atoms,
+                                                     const int32_t* __restrict__ species,
+                                                     int32_t zsel) {
   const int64_t c = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = (int64_t)blockIdx.x * 256 + wave * 64;
@@ -140,6 +142,10 @@ __global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc
   for (int64_t a = a0; a < a1; a += 16) {
     const int64_t row = a + idx;
     FragRowK<TD> fa{desc + (row < a1 ? row : a0) * ldd, D, row < a1};
+    // species mask of a per-species block: atoms of other species are no
+    // centre of this block's local energies (kernel value and S zero)
+    const double on_lane =
+        (species == nullptr || species[row < a1 ? row : a0] == zsel) ? 1.0 : 0.0;
     d4v acc[kNC];
 #pragma unroll
     for (int u = 0; u < kNC; ++u) acc[u] = zero4();
@@ -150,9 +156,10 @@ __global__ __launch_bounds__(256) void k_energy_rows(const TD* __restrict__ desc
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = a + g + 4 * r;
+        const double on = __shfl(on_lane, g + 4 * r);
         if (rr < a1) {
           const double p = acc[u][r];
-          const double pz1 = ipow(p, zeta - 1);
+          const double pz1 = on * ipow(p, zeta - 1);
           e[u] += d2 * pz1 * p;
           if (col < ldS) S[rr * ldS + col] = (col < M) ? d2z * pz1 : 0.0;  // zero row padding
         }
@@ -912,15 +919,17 @@ void kmm_f64(const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, doubl
 void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                      int64_t n_cfg, int64_t n_atoms, const double* X, int64_t ldx, int64_t M,
                      int64_t D, int zeta, double delta, double* K, int64_t ldk, double* S,
-                     int64_t ldS, hipStream_t st) {
+                     int64_t ldS, hipStream_t st, const int32_t* species, int32_t zsel) {
   if (n_cfg <= 0 || M <= 0) return;
   dim3 grid(cdiv(M, 256), (unsigned)n_cfg);
   if (desc_f32)
     hipLaunchKernelGGL(k_energy_rows<float>, grid, dim3(256), 0, st, tptr<float>(desc), ldd,
-                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms, species,
+                       zsel);
   else
     hipLaunchKernelGGL(k_energy_rows<double>, grid, dim3(256), 0, st, tptr<double>(desc), ldd,
-                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+                       cfg_ptr, X, ldx, M, D, zeta, delta, K, ldk, S, ldS, n_atoms, species,
+                       zsel);
 }
 
 void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atoms,
@@ -1119,6 +1128,27 @@ void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out,
                      hipStream_t st) {
   if (M <= 0) return;
   hipLaunchKernelGGL(k_reduce_rows, dim3(cdiv(M, 64)), dim3(1024), 0, st, part, nparts, M, out);
+}
+
+namespace {
+// Rows of atoms whose species is not zsel: local energy and W row set to zero
+// (a per-species GP predicts only the local energies of its own species).
+__global__ void k_mask_species_rows(const int32_t* __restrict__ species, int32_t zsel, int64_t n,
+                                    double* __restrict__ e_atom, double* __restrict__ W,
+                                    int64_t ldw) {
+  const int64_t i = blockIdx.x;
+  if (i >= n || species[i] == zsel) return;
+  if (e_atom && threadIdx.x == 0) e_atom[i] = 0.0;
+  if (W)
+    for (int64_t m = threadIdx.x; m < ldw; m += blockDim.x) W[i * ldw + m] = 0.0;
+}
+}  // namespace
+
+void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
+                       int64_t ldw, hipStream_t st) {
+  if (n <= 0 || (!e_atom && !W)) return;
+  hipLaunchKernelGGL(k_mask_species_rows, dim3((unsigned)n), dim3(256), 0, st, species, zsel, n,
+                     e_atom, W, ldw);
 }
 
 void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,

@@ -74,7 +74,8 @@ void kmm_f64(const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, doubl
 void energy_rows_f64(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                      int64_t n_cfg, int64_t n_atoms, const double* X, int64_t ldx, int64_t M,
                      int64_t D, int zeta, double delta, double* K, int64_t ldk, double* S,
-                     int64_t ldS, hipStream_t st);
+                     int64_t ldS, hipStream_t st,
+                     const int32_t* species = nullptr, int32_t zsel = 0);
 // P-stage of predict / backward.  For rows i of desc:
 //   mode 0 (forward):  W[i][m] = delta^2 zeta c_m p^(zeta-1)       (if W)
 //                      e_atom[i] = sum_m c_m delta^2 p^zeta         (if e_atom)
@@ -149,6 +150,9 @@ void copy_rows_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int
 // out[m] = sum_rb part[rb][m]
 void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out, hipStream_t st);
 // e_cfg[c] = sum_{i in c} e_atom[i]
+// Zero e_atom[i] and W row i (ldw doubles) of every atom i with species[i] != zsel.
+void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
+                       int64_t ldw, hipStream_t st);
 void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,
                      double* e_cfg, hipStream_t st);
 
@@ -179,7 +183,8 @@ void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh
 void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                         int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
                         int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                        float* S, int64_t ldS, hipStream_t st);
+                        float* S, int64_t ldS, hipStream_t st,
+                        const int32_t* species = nullptr, int32_t zsel = 0);
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
                        const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
@@ -188,6 +193,9 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
 // J -> hi/lo halves [3 n_pairs][split_ld(D)] each.
 void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
                   __bf16* Jh, __bf16* Jl, hipStream_t st);
+// Any row-major rows x D array (ld % 4 == 0) -> hi/lo halves [rows][split_ld(D)].
+void split_rows_bf16(const void* x, bool x_f32, int64_t ld, int64_t rows, int64_t D,
+                     __bf16* hi, __bf16* lo, hipStream_t st);
 // Force rows from pre-split Jacobians (returns false when D is too large for it).
 bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, const __bf16* Xh,
                              const __bf16* Xl, int64_t M, const float* S, int64_t ldS,

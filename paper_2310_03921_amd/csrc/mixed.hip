@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
     const TD* __restrict__ desc, int64_t ldd, const int64_t* __restrict__ cfg_ptr,
     const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t ldp, int64_t M,
     int64_t D, int zeta, double delta, double* __restrict__ K, int64_t ldk,
-    float* __restrict__ S, int64_t ldS, int64_t n_atoms) {
+    float* __restrict__ S, int64_t ldS, int64_t n_atoms,
+    const int32_t* __restrict__ species, int32_t zsel) {
   const int64_t c = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int64_t colbase = (int64_t)blockIdx.x * 256 + wave * 64;
@@ -73,6 +74,9 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
   for (int64_t a = a0; a < a1; a += 16) {
     const int64_t row = a + idx;
     Frag32Row<TD> fa{desc + (row < a1 ? row : a0) * ldd, D, row < a1};
+    // species mask of a per-species block (see the FP64 kernel)
+    const double on_lane =
+        (species == nullptr || species[row < a1 ? row : a0] == zsel) ? 1.0 : 0.0;
     f4v acc[kNCb];
 #pragma unroll
     for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
@@ -83,9 +87,10 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = a + 4 * g + r;
+        const double on = __shfl(on_lane, 4 * g + r);
         if (rr < a1) {
           const double p = acc[u][r];
-          const double pz1 = ipow(p, zeta - 1);
+          const double pz1 = on * ipow(p, zeta - 1);
           e[u] += d2 * pz1 * p;
           if (col < ldS) S[rr * ldS + col] = (col < M) ? (float)(d2z * pz1) : 0.f;
         }
@@ -571,16 +576,19 @@ void split_x_bf16(const double* X, int64_t ldx, int64_t M, int64_t D, __bf16* Xh
 void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int64_t* cfg_ptr,
                         int64_t n_cfg, int64_t n_atoms, const __bf16* Xh, const __bf16* Xl,
                         int64_t M, int64_t D, int zeta, double delta, double* K, int64_t ldk,
-                        float* S, int64_t ldS, hipStream_t st) {
+                        float* S, int64_t ldS, hipStream_t st, const int32_t* species,
+                        int32_t zsel) {
   if (n_cfg <= 0 || M <= 0) return;
   const int64_t ldp = split_ld(D);
   dim3 grid(cdiv(M, 256), (unsigned)n_cfg);
   if (desc_f32)
     hipLaunchKernelGGL(k_energy_rows_b3<float>, grid, dim3(256), 0, st, tp<float>(desc), ldd,
-                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms, species,
+                       zsel);
   else
     hipLaunchKernelGGL(k_energy_rows_b3<double>, grid, dim3(256), 0, st, tp<double>(desc), ldd,
-                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms);
+                       cfg_ptr, Xh, Xl, ldp, M, D, zeta, delta, K, ldk, S, ldS, n_atoms, species,
+                       zsel);
 }
 
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
@@ -632,8 +640,13 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
 
 void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
                   __bf16* Jh, __bf16* Jl, hipStream_t st) {
-  if (n_pairs <= 0) return;
-  const int64_t ldp = split_ld(D), rows = 3 * n_pairs;
+  split_rows_bf16(jac, jac_f32, ldj, 3 * n_pairs, D, Jh, Jl, st);
+}
+
+void split_rows_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t rows, int64_t D,
+                     __bf16* Jh, __bf16* Jl, hipStream_t st) {
+  if (rows <= 0) return;
+  const int64_t ldp = split_ld(D);
   const unsigned g = std::max(1u, std::min(cdiv(rows * (ldp / 8), 256), 65536u));
   if (jac_f32)
     hipLaunchKernelGGL(k_split_j<float>, dim3(g), dim3(256), 0, st, tp<float>(jac), ldj, rows, D,

@@ -29,9 +29,16 @@ regenerated alone, which is what sampled parity checks at full size rely on):
   uniform in a ball of radius 5.
 * sparse distances of the two-body descriptor, stream [seed, 6]: uniform in
   [0.5, 5].
+* device-drawn Jacobians (workloads whose Jacobians do not fit in device
+  memory; ``device_jacobians``): element e = (p * 3 + alpha) * D + d of the
+  global pair p is 0.1 * N(0, 1) from the counter-based stream (seed, JAC_TAG)
+  of ``normal_gen.hip`` (Philox4x32-10 + Box-Muller), so a batch of
+  configurations, or any single one, is regenerated alone on the device and
+  copied back for the oracle when a check needs its values.
 """
 from __future__ import annotations
 
+import ctypes
 import os
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, replace
@@ -262,3 +269,119 @@ def sparse_distances(w: Workload, M: int, lo: float = 0.5, hi: float = 5.0) -> n
 def predict_coefficients(w: Workload) -> np.ndarray:
     """Coefficients for a predict-only workload, c ~ N(0, 1)."""
     return hidden_coefficients(w)
+
+
+# ------------------------------------------------------------------------
+# Counter-based generator (Philox4x32-10; Salmon et al., SC'11): the host
+# definition, and the device library that draws the same stream on the GPU.
+
+JAC_TAG = 0x4A414331          # key word 1 of the device-drawn Jacobian stream
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+_LIBSYNTH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth.so")
+_synth_lib = None
+
+
+def philox4x32_10(counters: np.ndarray, key0: int, key1: int) -> np.ndarray:
+    """Philox4x32-10 of uint32 counters [n, 4] under key (key0, key1): ten
+    rounds of the published round function, the key bumped by the Weyl
+    constants between rounds.  Returns uint32 [n, 4]."""
+    c = [np.asarray(counters, dtype=np.uint64)[:, i].copy() for i in range(4)]
+    mask = np.uint64(0xFFFFFFFF)
+    k0, k1 = np.uint64(key0 & 0xFFFFFFFF), np.uint64(key1 & 0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(_PHILOX_M[0]) * c[0]
+        p1 = np.uint64(_PHILOX_M[1]) * c[2]
+        c = [((p1 >> np.uint64(32)) ^ c[1] ^ k0) & mask, p1 & mask,
+             ((p0 >> np.uint64(32)) ^ c[3] ^ k1) & mask, p0 & mask]
+        k0 = (k0 + np.uint64(_PHILOX_W[0])) & mask
+        k1 = (k1 + np.uint64(_PHILOX_W[1])) & mask
+    return np.stack(c, axis=1).astype(np.uint32)
+
+
+def stream_words(seed: int, tag: int, g0: int, n_groups: int) -> np.ndarray:
+    """Host words of groups g0 .. g0 + n_groups - 1 of stream (seed, tag): counter
+    (g mod 2^32, g / 2^32, 0, 0), key (seed mod 2^32, tag)."""
+    g = np.arange(g0, g0 + n_groups, dtype=np.uint64)
+    ctr = np.zeros((n_groups, 4), dtype=np.uint64)
+    ctr[:, 0] = g & np.uint64(0xFFFFFFFF)
+    ctr[:, 1] = g >> np.uint64(32)
+    return philox4x32_10(ctr, seed, tag)
+
+
+def box_muller(words: np.ndarray) -> np.ndarray:
+    """The four normals of each group of words, in FP64 (host reference of the
+    device transform, which works in FP32)."""
+    w = np.asarray(words, dtype=np.float64)
+    out = np.empty_like(w)
+    for a, b in ((0, 1), (2, 3)):
+        u = (w[:, a] + 1.0) * 2.0 ** -32
+        v = w[:, b] * 2.0 ** -32
+        r = np.sqrt(-2.0 * np.log(u))
+        out[:, a] = r * np.cos(2.0 * np.pi * v)
+        out[:, b] = r * np.sin(2.0 * np.pi * v)
+    return out
+
+
+def synth_lib():
+    """The device generator library (built by synth/build.py)."""
+    global _synth_lib
+    if _synth_lib is None:
+        if not os.path.exists(_LIBSYNTH):
+            raise ImportError(f"{_LIBSYNTH} is missing: run synth.build.build()")
+        L = ctypes.CDLL(_LIBSYNTH)
+        L.synth_philox_words.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]
+        L.synth_philox_words.restype = ctypes.c_int
+        L.synth_normal_rows_f32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                            ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_float, ctypes.c_void_p]
+        L.synth_normal_rows_f32.restype = ctypes.c_int
+        _synth_lib = L
+    return _synth_lib
+
+
+def _stream_ptr(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def device_words(seed: int, tag: int, g0: int, n_groups: int, device="cuda"):
+    """Device words of groups g0 .. g0 + n_groups - 1 (uint32 as int32 tensor [n, 4])."""
+    import torch
+    out = torch.empty(max(n_groups, 1), 4, dtype=torch.int32, device=device)
+    st = synth_lib().synth_philox_words(_stream_ptr(out), seed & 0xFFFFFFFF, tag, g0, n_groups,
+                                        ctypes.c_void_p(out.data_ptr()))
+    if st != 0:
+        raise RuntimeError(f"synth_philox_words failed ({st})")
+    return out[:n_groups]
+
+
+def device_normal_rows(out, seed: int, tag: int, e0: int, D: int, scale: float):
+    """Fill the FP32 device tensor out [rows, ld] (ld >= D) with scale * N(0, 1)
+    elements e0 + r D + d of stream (seed, tag); padding columns untouched."""
+    rows, ld = out.shape[0], out.shape[-1]
+    st = synth_lib().synth_normal_rows_f32(_stream_ptr(out), seed, tag, e0, rows, D, ld,
+                                           float(scale), ctypes.c_void_p(out.data_ptr()))
+    if st != 0:
+        raise RuntimeError(f"synth_normal_rows_f32 failed ({st})")
+    return out
+
+
+def device_jacobians(w: Workload, cfg0: int, cfg1: int, out=None, device="cuda"):
+    """Jacobian slots of configurations [cfg0, cfg1) drawn on the device, FP32
+    [n_pairs, 3, ld] (ld = D rounded up to 4; padding zero when ``out`` is new).
+    Pair p of the whole workload (global numbering) holds elements
+    (p * 3 + alpha) * D + d of stream (seed, JAC_TAG), times 0.1."""
+    import torch
+    gptr = global_atom_offsets(w)
+    p0, p1 = int(gptr[cfg0]) * w.nb, int(gptr[cfg1]) * w.nb
+    ld = (w.D + 3) // 4 * 4
+    if out is None:
+        out = torch.zeros(p1 - p0, 3, ld, dtype=torch.float32, device=device)
+    elif out.shape[0] < p1 - p0 or out.shape[1] != 3 or out.shape[2] < w.D or \
+            out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous FP32 tensor [>= n_pairs, 3, >= D]")
+    device_normal_rows(out.view(-1, out.shape[2])[:3 * (p1 - p0)], w.seed, JAC_TAG,
+                       p0 * 3 * w.D, w.D, 0.1)
+    return out[:p1 - p0]

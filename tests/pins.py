@@ -49,6 +49,32 @@ def linearised_energy(w, b, X, cfg, m, dr):
     return w.delta ** 2 * E
 
 
+def species_of(b, n_species=2, seed=31):
+    """A seeded species label per atom (a stand-in for the element of a
+    multi-species model)."""
+    return np.random.default_rng(seed).integers(0, n_species, b.n_atoms).astype(np.int32)
+
+
+def linearised_energy_species(w, b, X, cfg, m, dr, species, z):
+    """linearised_energy with only the atoms of species z as centres (eq. 1:
+    the local energies of one descriptor type's atoms).  Plain loops."""
+    a0, a1 = int(b.cfg_ptr[cfg]), int(b.cfg_ptr[cfg + 1])
+    E = 0j
+    for i in range(a0, a1):
+        if species[i] != z:
+            continue
+        d = b.desc[i].astype(np.complex128)
+        for p in range(int(b.pair_ptr[i]), int(b.pair_ptr[i + 1])):
+            j = int(b.pair_j[p])
+            for a in range(3):
+                d = d + b.jac[p, a].astype(np.float64) * dr[j, a]
+        s = 0j
+        for k in range(w.D):
+            s += d[k] * X[m, k]
+        E += s ** w.zeta
+    return w.delta ** 2 * E
+
+
 def check_kmm(orc):
     w, b, X = tiny_batch()
     K = orc.build_kmm(X, w.zeta, w.delta)
@@ -195,6 +221,65 @@ def check_permutation(orc):
     assert np.allclose(K2[:b.n_cfg], K[:b.n_cfg], rtol=1e-13, atol=1e-16)
     rows = b.n_cfg + 3 * np.repeat(perm, 3) + np.tile(np.arange(3), b.n_atoms)
     assert np.allclose(K2[rows], K[b.n_cfg:], rtol=1e-12, atol=1e-15)
+
+
+def check_species_blocks(orc, h=1e-30):
+    # per-species GP blocks: (i) energy rows by brute force over the centres of
+    # species z, (ii) force rows equal to the complex-step derivative of that
+    # energy (linearised descriptor), so pairs are masked by their centre,
+    # never by their target, (iii) the blocks of all species add up to the
+    # species-blind rows, (iv) a species no atom has gives zero rows
+    w, b, X = tiny_batch(TINY.with_(n_cfg=3, atoms_lo=2, atoms_hi=5))
+    spc = species_of(b)
+    assert 0 < spc.sum() < b.n_atoms
+    total = np.zeros((b.n_rows, w.M))
+    for z in (0, 1):
+        K = orc.build_knm_species(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta,
+                                  w.delta, spc, z)
+        total += K
+        zero = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+        for c in range(b.n_cfg):
+            for m in range(w.M):
+                ref = linearised_energy_species(w, b, X, c, m, zero, spc, z).real
+                assert abs(K[c, m] - ref) <= 1e-12 * max(1.0, abs(ref))
+            for j in range(int(b.cfg_ptr[c]), int(b.cfg_ptr[c + 1])):
+                for a in range(3):
+                    dr = np.zeros((b.n_atoms, 3), dtype=np.complex128)
+                    dr[j, a] = 1j * h
+                    for m in range(w.M):
+                        ref = -linearised_energy_species(w, b, X, c, m, dr, spc, z).imag / h
+                        got = K[b.n_cfg + 3 * j + a, m]
+                        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (z, c, j, a, m)
+    K = orc.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    assert np.allclose(total, K, rtol=1e-13, atol=1e-13 * np.abs(K).max())
+    K5 = orc.build_knm_species(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta,
+                               w.delta, spc, 5)
+    assert not K5.any()
+
+
+def check_predict_species(orc):
+    # a species block's prediction: its energies and forces are its rows times
+    # c, its local energies vanish on the other species, and the blocks of all
+    # species add up to the species-blind prediction
+    w, b, X = tiny_batch(TINY.with_(n_cfg=3, atoms_lo=2, atoms_hi=5))
+    spc = species_of(b)
+    cc = np.random.default_rng(8).standard_normal(w.M)
+    tot = [np.zeros(b.n_atoms), np.zeros(b.n_cfg), np.zeros((b.n_atoms, w.D)),
+           np.zeros((b.n_atoms, 3))]
+    for z in (0, 1):
+        e, ec, g, F = orc.predict_species(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, cc,
+                                          w.zeta, w.delta, spc, z)
+        K = orc.build_knm_species(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta,
+                                  w.delta, spc, z)
+        Kc = K @ cc
+        assert np.allclose(ec, Kc[:b.n_cfg], rtol=1e-12, atol=1e-12)
+        assert np.allclose(F.reshape(-1), Kc[b.n_cfg:], rtol=1e-12, atol=1e-12)
+        assert not e[spc != z].any() and not g[spc != z].any()
+        for t, v in zip(tot, (e, ec, g, F)):
+            t += v
+    ref = orc.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, cc, w.zeta, w.delta)
+    for t, r in zip(tot, ref):
+        assert np.allclose(t, r, rtol=1e-12, atol=1e-12 * max(1.0, np.abs(r).max()))
 
 
 def check_pair_transpose(orc):
@@ -351,6 +436,42 @@ def check_predict_variance(orc):
         + np.einsum("im,im->i", ks, np.linalg.solve(Q, ks.T).T)
     assert np.abs(var - ref).max() <= 1e-9 * kii.max()
     assert np.all(var >= -1e-12 * kii.max()) and np.all(var <= kii * (1 + 1e-12))
+
+
+def check_predict_variance_full_gp(orc):
+    # Full-GP limit: every training atom is a sparse point, each observation is
+    # one atom's local property (L-hat = identity) and the jitter is 0.  The
+    # projected-process variance must then be the textbook full-GP posterior
+    # variance k** - k*^T (K + Sigma)^-1 k*, both at the training atoms and at
+    # descriptors outside the training set (where k** - k*^T K^-1 k* > 0, so a
+    # form that keeps only the data term is wrong).
+    w = TINY.with_(n_cfg=3, atoms_lo=2, atoms_hi=3, D=10, zeta=2, delta=0.9)
+    b = synth.generate(w, threads=1)
+    X = b.desc.astype(np.float64)
+    N = X.shape[0]
+    idx = np.arange(N)
+    K = orc.build_local_rows(X, X, idx, w.zeta, w.delta)
+    Kmm = orc.build_kmm(X, w.zeta, w.delta)
+    sig = np.linspace(0.2, 0.5, N)
+    y = np.random.default_rng(21).standard_normal(N)
+    A, bb = orc.design_matrix(K, Kmm, y, sig, 0.0)
+    R = orc.augmented_r(A, bb)[:N, :N]
+    rng = np.random.default_rng(22)
+    T = rng.standard_normal((5, w.D))
+    T /= np.linalg.norm(T, axis=1)[:, None]
+    Q = np.vstack([X, T])
+    var = orc.predict_variance(Q, X, Kmm, 0.0, R, w.zeta, w.delta)
+    # textbook GP posterior variance, kernel entries by explicit loops
+    def k(u, v):
+        return w.delta ** 2 * float(np.dot(u, v)) ** w.zeta
+    Kf = np.array([[k(u, v) for v in X] for u in X])
+    ref = []
+    for q in Q:
+        ks = np.array([k(q, v) for v in X])
+        ref.append(k(q, q) - ks @ np.linalg.solve(Kf + np.diag(sig ** 2), ks))
+    ref = np.array(ref)
+    assert np.all(ref[N:] > 1e-3), "test descriptors must lie outside the training span"
+    assert np.abs(var - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
 
 
 def check_cur_leverage(orc):
@@ -548,9 +669,9 @@ def check_backward(orc, h=1e-30):
 ALL_CHECKS = [check_kmm, check_energy_rows_zeta1, check_energy_rows_zeta2,
               check_energy_rows_bruteforce, check_sparse_self_entry,
               check_force_rows_complex_step, check_force_rows_central_fd,
-              check_permutation, check_pair_transpose, check_qr_vs_closed_forms,
+              check_permutation, check_species_blocks, check_predict_species, check_pair_transpose, check_qr_vs_closed_forms,
               check_fold_streamed, check_refine_step, check_local_rows, check_virial_rows_strain,
-              check_predict_variance, check_cur_leverage, check_2b_rows,
+              check_predict_variance, check_predict_variance_full_gp, check_cur_leverage, check_2b_rows,
               check_full_gpr_identity, check_delta_scaling,
               check_predict_energy_and_gradient, check_predict_forces,
               check_predict_matches_knm, check_backward]

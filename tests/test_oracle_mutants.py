@@ -26,6 +26,8 @@ _orig_2b = G.build_2b_rows
 _orig_fcut = G.cutoff_fn
 _orig_refine_rows = G.refine_rows
 _orig_refine_solve = G.refine_solve
+_orig_knm_species = G.build_knm_species
+_orig_predict_species = G.predict_species
 
 
 def knm_sign_flip(*a):
@@ -159,6 +161,16 @@ def variance_prior_only(desc, X, Kmm, jitter, R, zeta, delta):
                                                                        zeta, delta)
 
 
+def variance_data_term_only(desc, X, Kmm, jitter, R, zeta, delta):
+    # subset-of-regressors form k_i^T (A^T A)^-1 k_i: the k_ii - k_i^T K_MM^-1 k_i
+    # part left out (inside [0, k_ii], so the bound alone does not catch it)
+    d = np.asarray(desc, float)
+    kii = delta ** 2 * np.sum(d * d, axis=1) ** zeta
+    full = _orig_var(desc, X, Kmm, jitter, R, zeta, delta)
+    base = _orig_var(desc, X, Kmm, jitter, np.eye(np.asarray(X).shape[0]) * 1e300, zeta, delta)
+    return full - base + 0.0 * kii
+
+
 def cur_leverage_no_inverse(desc, jitter):
     d = np.asarray(desc, float)
     return np.sum(d * d, axis=1) / max(1.0, float(np.sum(d * d)) / d.shape[1])
@@ -215,8 +227,39 @@ def refine_solve_regulariser_sign(R, Kmm, jitter, g, c):
     return _orig_refine_solve(R, -np.asarray(Kmm, float), -jitter, g, c)
 
 
+def species_mask_by_target(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta, species, z):
+    # force rows kept for pairs whose TARGET has species z (energy rows right)
+    K = _orig_knm_species(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta, species, z)
+    Kall = _orig_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta)
+    n_cfg = len(cfg_ptr) - 1
+    tmask = np.repeat((np.asarray(species) == z).astype(float), 3)[:, None]
+    K[n_cfg:] = tmask * Kall[n_cfg:]
+    return K
+
+
+def species_forces_unmasked(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta, species, z):
+    # energy rows masked, force rows of every centre
+    K = _orig_knm_species(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta, species, z)
+    Kall = _orig_knm(cfg_ptr, desc, pair_ptr, pair_j, jac, X, zeta, delta)
+    n_cfg = len(cfg_ptr) - 1
+    K[n_cfg:] = Kall[n_cfg:]
+    return K
+
+
+def predict_species_unmasked_gradient(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta,
+                                      species, z):
+    # local energies masked, descriptor gradients (and so forces) of every atom
+    e, ec, _, _ = _orig_predict_species(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta,
+                                        species, z)
+    _, _, g, F = _orig_predict(cfg_ptr, desc, pair_ptr, pair_j, jac, X, c, zeta, delta)
+    return e, ec, g, F
+
+
 MUTANTS = [
     ("build_knm", knm_sign_flip),
+    ("build_knm_species", species_mask_by_target),
+    ("build_knm_species", species_forces_unmasked),
+    ("predict_species", predict_species_unmasked_gradient),
     ("build_knm", knm_drop_last_atom),
     ("build_knm", knm_scale_by_target),
     ("poly_kernel_grad_scale", grad_wrong_power),
@@ -235,6 +278,7 @@ MUTANTS = [
     ("build_virial_rows", virial_sign_flip),
     ("predict_variance", variance_data_term_sign),
     ("predict_variance", variance_prior_only),
+    ("predict_variance", variance_data_term_only),
     ("cur_leverage", cur_leverage_no_inverse),
     ("cur_leverage", cur_leverage_inverse_squared),
     ("se2b_kernel_dr", se2b_dr_no_cutoff_slope),
