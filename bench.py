@@ -204,6 +204,38 @@ def cpu_baseline_large(synth, n_sample=2):
             "measured_s": tot, "extrapolated": False, "host": hi}
 
 
+def measured_peaks(torch):
+    """Dense FP64 and BF16 matrix-core rates of this device, from the probe
+    library (independent products, no memory traffic): the measured
+    denominators reported beside the spec peaks."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2310_03921_amd", "libgap_peak.so")
+    if not os.path.exists(path):
+        return None
+    L = ctypes.CDLL(path)
+    L.gap_peak_mfma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]
+    L.gap_peak_mfma.restype = ctypes.c_int
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 2 * cus                     # two waves per SIMD
+    out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"cus": cus, "blocks": blocks}
+    for kind, name, iters in ((0, "fp64", 200_000), (1, "bf16", 800_000)):
+        ms, fl = ctypes.c_double(), ctypes.c_double()
+        best = 0.0
+        for it in (iters // 20, iters, iters):
+            if L.gap_peak_mfma(st, kind, it, blocks, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.byref(ms), ctypes.byref(fl)) != 0:
+                return None
+            best = max(best, fl.value / (ms.value * 1e-3) / 1e12)
+        res[name + "_tflops"] = best
+    log(f"measured matrix-core peaks: FP64 {res['fp64_tflops']:.1f} TFLOP/s, "
+        f"BF16 {res['bf16_tflops']:.0f} TFLOP/s")
+    return res
+
+
 class LargeFit:
     """The largest fit (4000 configurations of 32-256 atoms, ~576k atoms, D = 1500,
     40 neighbours, M = 8000, FP32 descriptors and Jacobians, BF16X3 assembly,
@@ -261,6 +293,11 @@ class LargeFit:
         del b
         self.max_rows = max(bt["rows"] for bt in self.batches)
         self.T = self.gap.fold_buffer(w.M, self.max_rows)
+        # each batch's exact FP64 kernel-gradient scale, formed once per fit and
+        # kept for every refinement pass
+        ldS = (w.M + 3) // 4 * 4
+        for bt in self.batches:
+            bt["S"] = torch.empty(bt["atoms"].n_atoms, ldS, dtype=torch.float64, device="cuda")
         self.Kmm = gapx.colmajor(w.M, w.M, w.M)
         self.t_host = time.perf_counter() - t0
         self.gen_events = []
@@ -303,6 +340,9 @@ class LargeFit:
                 fro2 += float(((blk / bt["sigma"][None, :]) ** 2).sum())
             gap.fold_rows(T, M, bt["rows"], bt["y"], bt["sigma"])
         c, lsq, rd = gap.fold_solve(T, M)
+        if self.refine > 0:
+            for bt in self.batches:
+                gap.refine_weights(bt["atoms"], sp, out=bt["S"])
         for _ in range(self.refine):
             g = self.residual_pass(c)
             gap.refine_solve(T, M, self.Kmm, w.jitter, g, c)
@@ -312,7 +352,7 @@ class LargeFit:
         g = self.torch.zeros(self.w.M, dtype=self.torch.float64, device="cuda")
         for bt in self.batches:
             self.jacobians(bt)
-            self.gap.refine_rows(bt["atoms"], self.sp, c, bt["y"], bt["sigma"], g, rr)
+            self.gap.refine_rows_s(bt["atoms"], self.sp, bt["S"], c, bt["y"], bt["sigma"], g, rr)
         return g
 
     def generation_ms(self):
@@ -368,6 +408,9 @@ def large_fit_bench(args, torch, synth, gapx):
     # accuracy report outside the timed region: one more fit with the block norms,
     # and a final pass for r and A^T r of the exact FP64 system
     c, lsq, rd, fro2_obs = L.fit(norms=True)
+    if L.refine == 0:
+        for bt in L.batches:
+            gap.refine_weights(bt["atoms"], L.sp, out=bt["S"])
     rr = torch.zeros(1, dtype=torch.float64, device="cuda")
     g = L.residual_pass(c, rr)
     Kc = L.Kmm.T @ c + w.jitter * c             # (K_MM + jitter I) c = U^T U c
@@ -471,7 +514,13 @@ def main():
         out = fit_fp64_legs(args, torch, synth, gapx, headline=True)
         print(json.dumps(out), flush=True)
         return
+    peaks = measured_peaks(torch)
     line = large_fit_bench(args, torch, synth, gapx)
+    line["measured_peaks"] = peaks
+    if peaks:
+        rf = line["roofline"]
+        rf["peak_measured"] = peaks["bf16_tflops"]
+        rf["frac_of_measured_peak"] = rf["achieved"] / peaks["bf16_tflops"]
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on a sample of the large fit")
         line["cpu_baseline"] = cpu_baseline_large(synth)

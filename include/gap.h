@@ -348,6 +348,19 @@ gap_status gap_fold_solve(gap_handle *h, const double *T, int64_t ld, int64_t M,
 gap_status gap_refine_rows(gap_handle *h, const gap_atoms *a, const gap_sparse *sp,
                            const double *c, const double *y, const double *sigma, double *g,
                            double *rr);
+/* gap_refine_weights / gap_refine_rows_s: the same step with the batch's
+ *   exact FP64 kernel-gradient scale kept by the caller between passes,
+ *     S[i][m] = delta^2 zeta (d_i . x_m)^(zeta-1),
+ *   row-major [n_atoms][ldS] FP64 device (ldS >= M, ldS % 4 == 0, 32-byte
+ *   aligned; 8 n_atoms ldS bytes), so that a pass over a batch needs no
+ *   descriptor product of its own.  gap_refine_weights writes S of batch a
+ *   (columns M .. ldS - 1 zero); gap_refine_rows_s is gap_refine_rows with that
+ *   S (the same batch and sparse points).  Both asynchronous. */
+gap_status gap_refine_weights(gap_handle *h, const gap_atoms *a, const gap_sparse *sp, double *S,
+                              int64_t ldS);
+gap_status gap_refine_rows_s(gap_handle *h, const gap_atoms *a, const gap_sparse *sp,
+                             const double *S, int64_t ldS, const double *c, const double *y,
+                             const double *sigma, double *g, double *rr);
 /* gap_refine_solve: adds the regulariser rows' share U^T (0 - U c) =
  *   -(K_MM + jitter I) c to g, then solves R^T R dc = g and sets c += dc; g is
  *   overwritten by dc.  R: the upper triangle of the first M columns of a

@@ -90,6 +90,8 @@ def lib():
             "gap_fold_rows": ([P, P, I64, I64, I64, P, P], S),
             "gap_fold_solve": ([P, P, I64, I64, P, P, P], S),
             "gap_refine_rows": ([P, P, P, P, P, P, P, P], S),
+            "gap_refine_weights": ([P, P, P, P, I64], S),
+            "gap_refine_rows_s": ([P, P, P, P, I64, P, P, P, P, P], S),
             "gap_refine_solve": ([P, P, I64, I64, P, ctypes.c_double, P, P], S),
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
@@ -551,7 +553,7 @@ class Gap:
     @staticmethod
     def _inplace_f64(t: torch.Tensor, name: str) -> torch.Tensor:
         if t.dtype != torch.float64 or not t.is_contiguous():
-            raise GapError(f"{name} must be a contiguous float64 tensor (updated in place)")
+            raise GapError(GAP_E_INVALID, f"{name} must be a contiguous float64 tensor (updated in place)")
         return t
 
     def refine_rows(self, atoms: Atoms, sparse: Sparse, c: torch.Tensor, y: torch.Tensor,
@@ -567,6 +569,32 @@ class Gap:
         self._check(lib().gap_refine_rows(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(c),
                                           _ptr(y), _ptr(sigma), _ptr(g), _ptr(rr)))
         # the call is asynchronous: keep the inputs alive until the stream passes it
+        self._keep = (c, y, sigma)
+
+    def refine_weights(self, atoms: Atoms, sparse: Sparse, out: torch.Tensor | None = None):
+        """The batch's exact FP64 kernel-gradient scale S [n_atoms, round4(M)],
+        kept between refinement passes (gap_refine_rows_s)."""
+        M = sparse.M
+        if out is None:
+            out = torch.empty(max(atoms.n_atoms, 1), _round4(M), dtype=torch.float64,
+                              device=sparse.X.device)
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_refine_weights(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(out),
+                                             out.shape[1]))
+        return out
+
+    def refine_rows_s(self, atoms: Atoms, sparse: Sparse, S: torch.Tensor, c: torch.Tensor,
+                      y: torch.Tensor, sigma: torch.Tensor, g: torch.Tensor,
+                      rr: torch.Tensor | None = None):
+        """refine_rows with the batch's S from refine_weights."""
+        c, y, sigma = _f64(c), _f64(y), _f64(sigma)
+        self._inplace_f64(g, "g")
+        if rr is not None:
+            self._inplace_f64(rr, "rr")
+        a, s = atoms.struct(), sparse.struct()
+        self._check(lib().gap_refine_rows_s(self._h, ctypes.byref(a), ctypes.byref(s), _ptr(S),
+                                            S.shape[1], _ptr(c), _ptr(y), _ptr(sigma), _ptr(g),
+                                            _ptr(rr)))
         self._keep = (c, y, sigma)
 
     def refine_solve(self, R: torch.Tensor, M: int, Kmm: torch.Tensor, jitter: float,

@@ -56,5 +56,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+PEAK_LIB = os.path.join(HERE, "libgap_peak.so")
+
+
+def build_peak(verbose: bool = False) -> str:
+    """The matrix-core throughput probe the benchmark uses for measured peaks."""
+    src = os.path.join(HERE, "peak", "mfma_peak.hip")
+    tmp = PEAK_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, "-shared", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAK_LIB)
+    if verbose:
+        print("built", PEAK_LIB)
+    return PEAK_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_peak(verbose=True)

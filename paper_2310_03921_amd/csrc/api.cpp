@@ -509,8 +509,8 @@ gap_status build_knm_impl(gap_handle* h, const gap_atoms* a, const gap_sparse* s
       gapk::force_rows_bf16x3(a->jac, f32(a->jac_dt), a->ld_jac, D, at<__bf16>(h, sw.xh),
                               at<__bf16>(h, sw.xl), M, at<float>(h, S), ld8(M),
                               at<int64_t>(h, p.tgt_ptr), at<int32_t>(h, p.tgt_pair),
-                              at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_cfg, Knm, ld,
-                              h->stream);
+                              at<int32_t>(h, p.src), at<int32_t>(h, p.order), N, a->n_pairs,
+                              a->n_cfg, Knm, ld, h->stream);
     h->timer.end(gapk::TM_FORCE);
     HIP_TRY(h, hipGetLastError());
     return GAP_OK;
@@ -914,7 +914,7 @@ gap_status gap_fold_solve(gap_handle* h, const double* T, int64_t ld, int64_t M,
 // a fit whose R came from approximate rows): workspace, the per-batch set-up,
 // and one pass r = Sigma^-1/2 (y - K c), g = K^T Sigma^-1/2 r.
 struct RefineWs {
-  size_t kc = 0, rtop = 0, v = 0, hbuf = 0, gvec = 0, dcp = 0, ke = 0;
+  size_t kc = 0, rtop = 0, v = 0, hbuf = 0, gvec = 0, dcp = 0, ones = 0;
   PredictWs pw{};
 };
 
@@ -926,52 +926,63 @@ void layout_refine(Layout& L, const gap_atoms* a, const gap_sparse* sp, RefineWs
   w.v = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
   w.hbuf = L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1));
   w.gvec = L.take(sizeof(double) * M);
-  w.dcp = L.take(sizeof(double) * gapk::pstage_row_blocks(N) * M + 8);
-  w.ke = L.take(sizeof(double) * std::max<int64_t>(a->n_cfg, 1) * M);
-  // pw.W holds S = delta^2 zeta p^(zeta-1) for every pass over the batch.
+  w.dcp = L.take(sizeof(double) * std::max(gapk::pstage_row_blocks(N),
+                                           gapk::resid_colsum_groups(N, M)) * M + 8);
+  w.ones = L.take(sizeof(double) * M);
+  // pw.W holds S = delta^2 zeta p^(zeta-1) unless the caller keeps it
   layout_predict(L, a, sp, true, false, true, true, w.pw);
 }
 
-// Exact FP64 energy rows K_E and force-row weights S of the batch, and its
-// target-major pair view: every residual pass is then K_E c, the J^T
-// contraction of (S diag(c)) X, and their transposes.
-void refine_prepare(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const RefineWs& w) {
-  const int64_t N = a->n_atoms, nc = a->n_cfg, M = sp->M, D = sp->D;
-  gapk::energy_rows_f64(a->desc, f32(a->desc_dt), a->ld_desc, a->cfg_ptr, nc, N, sp->X,
-                        sp->ld_x, M, D, sp->zeta, sp->delta, at<double>(h, w.ke),
-                        std::max<int64_t>(nc, 1), at<double>(h, w.pw.W), ld4(M), h->stream);
-  run_pairs(h, a, w.pw.pairs, false);
+// The exact FP64 kernel-gradient scale S[i][m] = delta^2 zeta (d_i . x_m)^(zeta-1)
+// of a batch (row-major, ld4(M), padding zero): the P-stage with unit
+// coefficients, whose weights W = S diag(c) are then S itself.
+void refine_weights(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const RefineWs& w,
+                    double* S, int64_t ldS) {
+  const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
+  double* ones = at<double>(h, w.ones);
+  gapk::fill_f64(ones, M, 1.0, h->stream);
+  gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                   sp->delta, ones, nullptr, nullptr, 0, S, ldS, nullptr, nullptr, h->stream,
+                   nullptr, 0, nullptr);
 }
 
 // rtop = Sigma^-1/2 (y - K c) over the batch's rows (energy rows, then three
-// force rows per atom) and gvec = K^T Sigma^-1/2 rtop, K the exact FP64 rows.
+// force rows per atom) and gvec = K^T Sigma^-1/2 rtop, K the exact FP64 rows,
+// from the batch's S (ldS) and target-major pair view (run_pairs before):
+//   g_i = (S diag c)_i X,  energy row c: sum_{i in c} d_i . g_i / zeta (Euler:
+//   eps_i is homogeneous of degree zeta in d_i), force rows: -J^T g,
+//   K^T v = -sum_i S_im (h~_i . x_m) with h~_i = J^T v_F (rows of atom i) -
+//   (v_c(i) / zeta) d_i (k(d_i, x_m) = S_im (d_i . x_m) / zeta).
 void refine_residual_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
-                          const RefineWs& w, const double* c, const double* y,
-                          const double* sigma) {
+                          const RefineWs& w, const double* S, int64_t ldS, const double* c,
+                          const double* y, const double* sigma) {
   const int64_t N = a->n_atoms, nc = a->n_cfg, M = sp->M, D = sp->D;
   const int64_t n_rows = nc + 3 * N;
-  const int64_t ldS = ld4(M), ldg = ld4(D), ldke = std::max<int64_t>(nc, 1);
-  double* S = at<double>(h, w.pw.W);
+  const int64_t ldg = ld4(D);
   double* g = at<double>(h, w.pw.g);
-  double* kE = at<double>(h, w.ke);
   double* kcp = at<double>(h, w.kc);
   double* vv = at<double>(h, w.v);
   double* gv = at<double>(h, w.gvec);
   double* hb = at<double>(h, w.hbuf);
   double* dcp = at<double>(h, w.dcp);
-  gapk::gemv_cm_f64(kE, ldke, nc, M, c, kcp, h->stream);
   if (N > 0) {
     gapk::gemm_wx_scaled_f64(S, ldS, N, M, c, sp->X, sp->ld_x, D, g, ldg, h->stream);
+    gapk::cfg_energy_from_grad(a->desc, f32(a->desc_dt), a->ld_desc, g, ldg, a->cfg_ptr, nc, N, D,
+                               sp->zeta, kcp, h->stream);
     gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, g, ldg,
                      at<int32_t>(h, w.pw.pairs.src), N, a->n_pairs,
                      at<int64_t>(h, w.pw.pairs.tgt_ptr), at<int32_t>(h, w.pw.pairs.tgt_pair),
                      at<double>(h, w.pw.f_pair), kcp + nc, h->stream);
+  } else {
+    gapk::fill_f64(kcp, std::max<int64_t>(nc, 1), 0.0, h->stream);
   }
   gapk::residual_top(y, sigma, kcp, n_rows, at<double>(h, w.rtop), h->stream);
   gapk::div_sigma(at<double>(h, w.rtop), sigma, n_rows, vv, h->stream);
   if (N > 0) {
     gapk::jac_transpose_apply_f64(a->jac, f32(a->jac_dt), a->ld_jac, D, a->pair_ptr, a->pair_j,
                                   N, a->n_pairs, vv + nc, hb, ldg, h->stream);
+    gapk::sub_cfg_desc(hb, ldg, a->desc, f32(a->desc_dt), a->ld_desc, vv, a->cfg_ptr, nc, N, D,
+                       sp->zeta, h->stream);
     if (gapk::resid_colsum_f64(hb, ldg, N, D, sp->X, sp->ld_x, M, S, ldS, dcp, h->stream)) {
       gapk::reduce_rows_f64(dcp, gapk::resid_colsum_groups(N, M), M, gv, h->stream);
     } else {
@@ -982,7 +993,6 @@ void refine_residual_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* s
   } else {
     gapk::fill_f64(gv, M, 0.0, h->stream);
   }
-  gapk::gemvt_cm_add_f64(kE, ldke, nc, M, vv, gv, h->stream);
 }
 
 gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const double* Kmm,
@@ -1055,10 +1065,12 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   if (refine_steps > 0) {
     double* gv = at<double>(h, rw.gvec);
     h->timer.begin(gapk::TM_REFINE);
-    refine_prepare(h, train, sp, rw);
+    double* Sref = at<double>(h, rw.pw.W);
+    refine_weights(h, train, sp, rw, Sref, ld4(M));
+    run_pairs(h, train, rw.pw.pairs, false);
     for (int step = 0; step <= refine_steps; ++step) {
       // A^T r = K^T Sigma^-1/2 r_top + U^T r_bot with r = b - A_exact c
-      refine_residual_rows(h, train, sp, rw, c, y, sigma);
+      refine_residual_rows(h, train, sp, rw, Sref, ld4(M), c, y, sigma);
       gapk::residual_bot(Lm, M, M, c, at<double>(h, rbot), h->stream);
       gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), gv, h->stream);
       gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);
@@ -1080,9 +1092,15 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
   return s;
 }
 
-gap_status gap_refine_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
-                           const double* c, const double* y, const double* sigma, double* g,
-                           double* rr) {
+}  // extern "C"
+
+namespace {
+
+// One batch's share of a refinement step, with S from the caller (S != null)
+// or computed into the workspace.
+gap_status refine_rows_impl(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                            const double* S, int64_t ldS, const double* c, const double* y,
+                            const double* sigma, double* g, double* rr) {
   if (!h) return GAP_E_INVALID;
   gap_status s = set_device(h);
   if (s != GAP_OK) return s;
@@ -1093,6 +1111,8 @@ gap_status gap_refine_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* 
   if (!c || !g) return fail(h, GAP_E_INVALID, "c / g are NULL");
   if (sp->M > 8000) return fail(h, GAP_E_UNSUPPORTED, "M > 8000");
   if (sp->D > 2048) return fail(h, GAP_E_UNSUPPORTED, "refinement needs D <= 2048");
+  if (S && (ldS < sp->M || ldS % 4 != 0 || !aligned32(S)))
+    return fail(h, GAP_E_INVALID, "S needs ldS >= M, ldS % 4 == 0 and 32-byte alignment");
   const int64_t n_rows = a->n_cfg + 3 * a->n_atoms;
   if (n_rows == 0) return GAP_OK;
   if (!y || !sigma) return fail(h, GAP_E_INVALID, "y / sigma are NULL");
@@ -1102,13 +1122,61 @@ gap_status gap_refine_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* 
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   h->timer.begin(gapk::TM_REFINE);
-  refine_prepare(h, a, sp, rw);
-  refine_residual_rows(h, a, sp, rw, c, y, sigma);
+  if (!S) {
+    S = at<double>(h, rw.pw.W);
+    ldS = ld4(sp->M);
+    refine_weights(h, a, sp, rw, at<double>(h, rw.pw.W), ldS);
+  }
+  run_pairs(h, a, rw.pw.pairs, false);
+  refine_residual_rows(h, a, sp, rw, S, ldS, c, y, sigma);
   gapk::axpy_f64(sp->M, 1.0, at<double>(h, rw.gvec), g, h->stream);
   if (rr) gapk::sumsq_add_f64(at<double>(h, rw.rtop), n_rows, rr, h->stream);
   h->timer.end(gapk::TM_REFINE);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status gap_refine_rows(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                           const double* c, const double* y, const double* sigma, double* g,
+                           double* rr) {
+  return refine_rows_impl(h, a, sp, nullptr, 0, c, y, sigma, g, rr);
+}
+
+gap_status gap_refine_weights(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, double* S,
+                              int64_t ldS) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_sparse(h, sp);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, sp, false);
+  if (s != GAP_OK) return s;
+  if (!S && a->n_atoms > 0) return fail(h, GAP_E_INVALID, "S is NULL");
+  if (ldS < sp->M || ldS % 4 != 0 || (S && !aligned32(S)))
+    return fail(h, GAP_E_INVALID, "S needs ldS >= M, ldS % 4 == 0 and 32-byte alignment");
+  if (a->n_atoms == 0) return GAP_OK;
+  Layout L;
+  RefineWs rw;
+  rw.ones = L.take(sizeof(double) * sp->M);
+  s = ensure_ws(h, L.off);
+  if (s != GAP_OK) return s;
+  h->timer.begin(gapk::TM_REFINE);
+  refine_weights(h, a, sp, rw, S, ldS);
+  h->timer.end(gapk::TM_REFINE);
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_refine_rows_s(gap_handle* h, const gap_atoms* a, const gap_sparse* sp,
+                             const double* S, int64_t ldS, const double* c, const double* y,
+                             const double* sigma, double* g, double* rr) {
+  if (!h) return GAP_E_INVALID;
+  if (!S && a && a->n_atoms > 0) return fail(h, GAP_E_INVALID, "S is NULL");
+  return refine_rows_impl(h, a, sp, S, ldS, c, y, sigma, g, rr);
 }
 
 gap_status gap_refine_solve(gap_handle* h, const double* R, int64_t ldr, int64_t M,

@@ -1131,6 +1131,50 @@ void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out,
 }
 
 namespace {
+// e_cfg[c] = sum_{i in c} (d_i . g_i) / zeta: configuration energies from the
+// descriptor gradients g_i = d eps_i / d d_i (eps is homogeneous of degree zeta
+// in d, so d . d eps / d d = zeta eps).  One block per configuration, fixed
+// reduction order.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_cfg_energy_from_grad(
+    const TD* __restrict__ desc, int64_t ldd, const double* __restrict__ g, int64_t ldg,
+    const int64_t* __restrict__ cfg_ptr, int64_t n, int64_t D, double inv_zeta,
+    double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  const int64_t a0 = max((int64_t)0, min(cfg_ptr[c], n));
+  const int64_t a1 = max(a0, min(cfg_ptr[c + 1], n));
+  double s = 0.0;
+  for (int64_t i = a0; i < a1; ++i)
+    for (int64_t k = threadIdx.x; k < D; k += 256) s += (double)desc[i * ldd + k] * g[i * ldg + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0] * inv_zeta;
+}
+
+// H[i] -= (v[c(i)] / zeta) d_i for the atoms i of every configuration c: folds
+// the energy rows' share of A^T v into the force rows' column sums
+// (k(d_i, x_m) = S_im (d_i . x_m) / zeta).  One block per configuration.
+template <typename TD>
+__global__ __launch_bounds__(256) void k_sub_cfg_desc(double* __restrict__ H, int64_t ldh,
+                                                      const TD* __restrict__ desc, int64_t ldd,
+                                                      const double* __restrict__ v,
+                                                      const int64_t* __restrict__ cfg_ptr,
+                                                      int64_t n, int64_t D, double inv_zeta) {
+  const int64_t c = blockIdx.x;
+  const int64_t a0 = max((int64_t)0, min(cfg_ptr[c], n));
+  const int64_t a1 = max(a0, min(cfg_ptr[c + 1], n));
+  const double f = v[c] * inv_zeta;
+  for (int64_t e = threadIdx.x; e < (a1 - a0) * D; e += 256) {
+    const int64_t i = a0 + e / D, k = e % D;
+    H[i * ldh + k] -= f * (double)desc[i * ldd + k];
+  }
+}
+
 // Rows of atoms whose species is not zsel: local energy and W row set to zero
 // (a per-species GP predicts only the local energies of its own species).
 __global__ void k_mask_species_rows(const int32_t* __restrict__ species, int32_t zsel, int64_t n,
@@ -1143,6 +1187,30 @@ __global__ void k_mask_species_rows(const int32_t* __restrict__ species, int32_t
     for (int64_t m = threadIdx.x; m < ldw; m += blockDim.x) W[i * ldw + m] = 0.0;
 }
 }  // namespace
+
+void cfg_energy_from_grad(const void* desc, bool desc_f32, int64_t ldd, const double* g,
+                          int64_t ldg, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n, int64_t D,
+                          int zeta, double* out, hipStream_t st) {
+  if (n_cfg <= 0) return;
+  if (desc_f32)
+    hipLaunchKernelGGL(k_cfg_energy_from_grad<float>, dim3((unsigned)n_cfg), dim3(256), 0, st,
+                       tptr<float>(desc), ldd, g, ldg, cfg_ptr, n, D, 1.0 / zeta, out);
+  else
+    hipLaunchKernelGGL(k_cfg_energy_from_grad<double>, dim3((unsigned)n_cfg), dim3(256), 0, st,
+                       tptr<double>(desc), ldd, g, ldg, cfg_ptr, n, D, 1.0 / zeta, out);
+}
+
+void sub_cfg_desc(double* H, int64_t ldh, const void* desc, bool desc_f32, int64_t ldd,
+                  const double* v, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n, int64_t D,
+                  int zeta, hipStream_t st) {
+  if (n_cfg <= 0 || n <= 0) return;
+  if (desc_f32)
+    hipLaunchKernelGGL(k_sub_cfg_desc<float>, dim3((unsigned)n_cfg), dim3(256), 0, st, H, ldh,
+                       tptr<float>(desc), ldd, v, cfg_ptr, n, D, 1.0 / zeta);
+  else
+    hipLaunchKernelGGL(k_sub_cfg_desc<double>, dim3((unsigned)n_cfg), dim3(256), 0, st, H, ldh,
+                       tptr<double>(desc), ldd, v, cfg_ptr, n, D, 1.0 / zeta);
+}
 
 void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
                        int64_t ldw, hipStream_t st) {

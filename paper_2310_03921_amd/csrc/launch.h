@@ -150,6 +150,14 @@ void copy_rows_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int
 // out[m] = sum_rb part[rb][m]
 void reduce_rows_f64(const double* part, int64_t nparts, int64_t M, double* out, hipStream_t st);
 // e_cfg[c] = sum_{i in c} e_atom[i]
+// e_cfg[c] = sum_{i in c} (d_i . g_i) / zeta (energies from descriptor gradients).
+void cfg_energy_from_grad(const void* desc, bool desc_f32, int64_t ldd, const double* g,
+                          int64_t ldg, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n, int64_t D,
+                          int zeta, double* out, hipStream_t st);
+// H[i] -= (v[c(i)] / zeta) d_i for every atom i of configuration c.
+void sub_cfg_desc(double* H, int64_t ldh, const void* desc, bool desc_f32, int64_t ldd,
+                  const double* v, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n, int64_t D,
+                  int zeta, hipStream_t st);
 // Zero e_atom[i] and W row i (ldw doubles) of every atom i with species[i] != zsel.
 void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
                        int64_t ldw, hipStream_t st);
@@ -188,8 +196,8 @@ void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int6
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
                        const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
-                       const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
-                       int64_t ldk, hipStream_t st);
+                       const int32_t* order, int64_t n_atoms, int64_t n_pairs, int64_t row0,
+                       double* K, int64_t ldk, hipStream_t st);
 // J -> hi/lo halves [3 n_pairs][split_ld(D)] each.
 void split_j_bf16(const void* jac, bool jac_f32, int64_t ldj, int64_t n_pairs, int64_t D,
                   __bf16* Jh, __bf16* Jl, hipStream_t st);

@@ -247,6 +247,193 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
   }
 }
 
+// BF16x3 force rows for D % 4 == 0 (any length): four waves, each holding 16
+// targets (a slot group) for all three components and 128 columns; the split
+// X halves of the block's columns are staged through LDS 256 descriptor
+// entries at a time (a force row is linear in J . x, so each chunk adds
+// S * (J[chunk] . X[chunk]) of every pair into the same per-target
+// accumulators).  Every B fragment read from LDS feeds nine matrix-core
+// products (three components x three split products), which keeps the LDS
+// traffic well below its bandwidth.  The hot loop holds no guarded load (a
+// guarded load compiles to a branch whose join waits for it at once):
+//  - Jacobian blocks are two 4-wide loads clamped to the row's last four
+//    entries; entries past D meet zero-padded X halves;
+//  - a slot past its degree re-reads its target's last pair (or pair 0 past
+//    n_atoms) and its products are cancelled by a zero weight;
+//  - the next step's pair index, source and first Jacobian block, and this
+//    step's S values (one 32-byte row segment per source: lane idx of tile u
+//    owns column 8 idx + u), are loaded a step or a block ahead of their use.
+constexpr int kNCW = 8;  // 16-column tiles per block: 128 columns
+#ifndef GAP_B3W_TILES_PER_WAVE
+#define GAP_B3W_TILES_PER_WAVE 8
+#endif
+constexpr int kB3wTilesPerWave = GAP_B3W_TILES_PER_WAVE;
+
+template <typename TJ>
+GAP_DEV void jblock8(const TJ* __restrict__ row, int64_t k, int64_t kmax4, float out[8]) {
+  const int64_t o0 = min(k, kmax4), o1 = min(k + 4, kmax4);
+  if constexpr (sizeof(TJ) == 4) {
+    const f4v v0 = *reinterpret_cast<const f4v*>(row + o0);
+    const f4v v1 = *reinterpret_cast<const f4v*>(row + o1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      out[s] = v0[s];
+      out[4 + s] = v1[s];
+    }
+  } else {
+    const d4v v0 = *reinterpret_cast<const d4v*>(row + o0);
+    const d4v v1 = *reinterpret_cast<const d4v*>(row + o1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      out[s] = (float)v0[s];
+      out[4 + s] = (float)v1[s];
+    }
+  }
+}
+
+// NT tiles per wave: NT = 8, four waves (one per SIMD); NT = 4, eight waves
+// (two per SIMD, each slot group's 128 columns split between two waves, which
+// then read the same Jacobian rows, the second time from the L1 cache).
+template <typename TJ, int NT>
+__global__ __launch_bounds__(256 * (kNCW / NT), 1) void k_force_rows_b3w(
+    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
+    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
+    int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
+    int64_t n_pairs, int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct,
+    int64_t n_grp, int nkb_all) {
+  // X halves of one chunk: [kb][tile u][hi | lo][64 lanes] of 16 bytes, so each
+  // 16-byte LDS read of the wave is contiguous (no bank conflict)
+  extern __shared__ bf8v xw[];
+  int64_t ct, tgb;
+  if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
+  constexpr int kThreads = 256 * (kNCW / NT);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int grp = wave & 3, u0 = (wave >> 2) * NT;  // slot group, first tile of this wave
+  const int64_t colbase = ct * (16 * kNCW);
+  const int64_t cl0 = colbase + kNCW * idx + u0;  // column of tile u0 + u: cl0 + u
+  const int64_t scol = min(cl0, ldS - NT);        // clamped (valid) S offset
+  float colok[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) colok[u] = (cl0 + u < M) ? 1.f : 0.f;
+
+  const int64_t slot = (tgb * 4 + grp) * 16 + idx;
+  const int target = slot < n_atoms ? order[slot] : -1;
+  const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
+  const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
+  const int maxdeg = wave_max16(deg);
+  const int64_t last = min(seg0 + max(deg - 1, 0), n_pairs - 1);
+  auto pair_slot = [&](int t) -> int64_t { return min(seg0 + t, last); };
+  const int64_t kmax4 = D - 4;
+
+  f4v acc[3][NT];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[a][u] = zero4f();
+  const bf8v* xb = xw + lane + u0 * 128;
+
+  for (int kc0 = 0; kc0 < nkb_all; kc0 += kMaxKb32) {
+    const int nkb = min(kMaxKb32, nkb_all - kc0);
+    __syncthreads();  // the previous chunk's products are done with the LDS
+    for (int e = threadIdx.x; e < nkb * kNCW * 64; e += kThreads) {
+      const int kb = e / (kNCW * 64), rem = e % (kNCW * 64);
+      const int u = rem / 64, ln = rem % 64;
+      const int64_t col = colbase + kNCW * (ln & 15) + u;
+      bf8v h, l;
+      if (col < M) {
+        const int64_t k = (int64_t)(kc0 + kb) * 32 + 8 * (ln >> 4);
+        h = *reinterpret_cast<const bf8v*>(Xh + col * ldp + k);
+        l = *reinterpret_cast<const bf8v*>(Xl + col * ldp + k);
+      } else {
+        zero_split(h, l);
+      }
+      bf8v* t = xw + (size_t)(e >> 6) * 128 + (e & 63);
+      t[0] = h;
+      t[64] = l;
+    }
+    __syncthreads();
+    if (maxdeg <= 0) continue;
+    const int64_t kb0 = (int64_t)kc0 * 32 + 8 * g;  // this lane's first k in the chunk
+    // pair metadata one step ahead of its use
+    int pair = tgt_pair[pair_slot(0)];
+    int pair_n = tgt_pair[pair_slot(1)];
+    int src = pair_src[pair];
+    const TJ* jr = jac + (int64_t)pair * 3 * ldj;
+    float nx[3][8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jblock8(jr + a * ldj, kb0, kmax4, nx[a]);
+    for (int t = 0; t < maxdeg; ++t) {
+      const int pair_nn = tgt_pair[pair_slot(t + 2)];
+      const int src_n = pair_src[pair_n];
+      const TJ* jn = jac + (int64_t)pair_n * 3 * ldj;
+      // S of this step's sources (rows 4 g + r of the output tile)
+      f4v s_v[4][NT / 4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, 4 * g + r);
+        const float* sp = S + (int64_t)max(src_r, 0) * ldS + scol;
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) s_v[r][q] = *reinterpret_cast<const f4v*>(sp + 4 * q);
+      }
+      f4v G[3][NT];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) G[a][u] = zero4f();
+      for (int kb = 0; kb < nkb; ++kb) {
+        bf8v ah[3], al[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) split8(nx[a], ah[a], al[a]);
+        // the next block of this step, or the first block of the next step
+        const bool more = kb + 1 < nkb;
+        const TJ* jp = more ? jr : jn;
+        const int64_t kn = more ? kb0 + (int64_t)(kb + 1) * 32 : kb0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jblock8(jp + a * ldj, kn, kmax4, nx[a]);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const bf8v bh = xb[(kb * kNCW + u) * 128], bl = xb[(kb * kNCW + u) * 128 + 64];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            G[a][u] = mfma_bf16(ah[a], bh, G[a][u]);
+            G[a][u] = mfma_bf16(ah[a], bl, G[a][u]);
+            G[a][u] = mfma_bf16(al[a], bh, G[a][u]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src_r = __shfl(src, 4 * g + r);
+        const int deg_r = __shfl(deg, 4 * g + r);
+        const float ok = (t < deg_r && src_r >= 0) ? 1.f : 0.f;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const float sv = s_v[r][u >> 2][u & 3] * (ok * colok[u]);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
+        }
+      }
+      jr = jn;
+      pair_n = pair_nn;
+      src = src_n;
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int tr = __shfl(target, 4 * g + r);
+    if (tr < 0) continue;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      if (cl0 + u >= M) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        K[(row0 + 3 * (int64_t)tr + a) + (cl0 + u) * ldk] = -(double)acc[a][u][r];
+    }
+  }
+}
+
 // Jacobian rows split once into hi/lo halves, [n_pairs][3][ldp] each (ldp = D
 // rounded up to 32, zero padded), so the force-row kernel streams 4 bytes per
 // element and does no splitting in its inner loop.
@@ -594,12 +781,41 @@ void energy_rows_bf16x3(const void* desc, bool desc_f32, int64_t ldd, const int6
 void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, const __bf16* Xh,
                        const __bf16* Xl, int64_t M, const float* S, int64_t ldS,
                        const int64_t* tgt_ptr, const int32_t* tgt_pair, const int32_t* pair_src,
-                       const int32_t* order, int64_t n_atoms, int64_t row0, double* K,
-                       int64_t ldk, hipStream_t st) {
+                       const int32_t* order, int64_t n_atoms, int64_t n_pairs, int64_t row0,
+                       double* K, int64_t ldk, hipStream_t st) {
   if (n_atoms <= 0 || M <= 0) return;
   const int64_t ldp = split_ld(D);
   const int64_t n_tgb = (n_atoms + 63) / 64;
   const int nkb = (int)(ldp / 32);
+  if (D % 4 == 0 && D >= 4 && n_pairs > 0 && ldj % 4 == 0 && ldS % 8 == 0 && ldS >= 8) {
+    const int64_t n_ct = (M + 16 * kNCW - 1) / (16 * kNCW);
+    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
+    const size_t lds = (size_t)std::min(nkb, kMaxKb32) * kNCW * 128 * sizeof(bf8v);
+    const int lds_max = (int)((size_t)kMaxKb32 * kNCW * 128 * sizeof(bf8v));
+    constexpr int NT = kB3wTilesPerWave;
+    constexpr int threads = 256 * (kNCW / NT);
+    static bool fw = false, dw = false;
+    if (jac_f32) {
+      if (!fw) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3w<float, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        fw = true;
+      }
+      hipLaunchKernelGGL((k_force_rows_b3w<float, NT>), dim3(blocks), dim3(threads), lds, st,
+                         tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                         pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb, nkb);
+    } else {
+      if (!dw) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3w<double, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        dw = true;
+      }
+      hipLaunchKernelGGL((k_force_rows_b3w<double, NT>), dim3(blocks), dim3(threads), lds, st,
+                         tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
+                         pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb, nkb);
+    }
+    return;
+  }
   // Up to 256 descriptor entries: 128 columns per block.  Longer descriptors:
   // 64 columns per block (half the accumulators), so that two waves share a
   // SIMD and cover each other's Jacobian loads.

@@ -170,6 +170,10 @@ void pair_transpose(const int64_t* pair_ptr, const int32_t* pair_j, int64_t n_at
   if (n_pairs > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n_pairs)), dim3(256), 0, st, pair_src, n_pairs,
                        -1);
+    // entries past the last valid target's segment (pairs dropped for an
+    // out-of-range target) hold pair 0, a valid index for readers that clamp
+    // a slot to the end of the list
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n_pairs)), dim3(256), 0, st, tgt_pair, n_pairs, 0);
     hipLaunchKernelGGL(k_count_targets, dim3(grid_for(n_pairs)), dim3(256), 0, st, pair_j, n_pairs,
                        n_atoms, cnt, dev_err);
   }

@@ -46,11 +46,16 @@ def setup(gapx, w):
 
 
 @pytest.mark.parametrize("wname,jdt", [("fit_small_mixed", "f64"), ("fit_small_mixed", "f32"),
-                                       ("ragged", "f64")])
+                                       ("ragged", "f64"), ("wide", "f32"), ("wide", "f64")])
 def test_knm_bf16x3(gapx, gap, wname, jdt):
     if wname == "ragged":
         w = synth.Workload("ragged", 31, n_cfg=9, atoms_lo=1, atoms_hi=23, D=37, nb=3, M=23,
                            zeta=3, delta=1.7, precision="bf16x3")
+    elif wname == "wide":
+        # descriptors longer than one LDS chunk (D % 4 == 0, a partial last
+        # 32-block), a partial last 128-column tile, ragged atom counts
+        w = synth.Workload("wide", 33, n_cfg=11, atoms_lo=1, atoms_hi=40, D=300 if jdt == "f32" else 260,
+                           nb=7, M=150, precision="bf16x3", jac_dtype=jdt, desc_dtype=jdt)
     else:
         w = synth.WORKLOADS[wname].with_(jac_dtype=jdt, desc_dtype=jdt)
     b, X, atoms, sp = setup(gapx, w)

@@ -89,6 +89,41 @@ def test_one_step_exact_r(gapx, gap, wname):
     assert relmax(cd.cpu().numpy(), c_ref) <= TOL
 
 
+@pytest.mark.parametrize("wname", ["fit_small", "ragged"])
+def test_cached_weights_step(gapx, gap, wname):
+    # S kept by the caller (gap_refine_weights) and passed to every pass
+    # (gap_refine_rows_s): S against the oracle's kernel-gradient scale, and
+    # the rows' share of A^T r and r . r as in the uncached step
+    w = ragged() if wname == "ragged" else synth.WORKLOADS[wname]
+    b, X, K, Kmm, y, sig = problem(w)
+    c0 = np.random.default_rng(18).standard_normal(w.M)
+    g_ref, rr_ref = oracle.refine_rows(K, y, sig, c0)
+    atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
+    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+    Sd = gap.refine_weights(atoms, sp).cpu().numpy()
+    S_ref = oracle.poly_kernel_grad_scale(b.desc.astype(np.float64) @ X.T, w.zeta, w.delta)
+    assert relmax(Sd[:, :w.M], S_ref) <= TOL
+    assert not Sd[:, w.M:].any()
+    g = torch.zeros(w.M, dtype=torch.float64, device="cuda")
+    rr = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cd = torch.tensor(c0, device="cuda")
+    cuts = [0, 1, b.n_cfg // 3, b.n_cfg]
+    for k0, k1 in zip(cuts[:-1], cuts[1:]):
+        rows = batch_rows(b, k0, k1)
+        ab = atoms.configs(k0, k1)
+        Sb = gap.refine_weights(ab, sp)
+        for _ in range(2):   # the same S serves every pass
+            gb = torch.zeros(w.M, dtype=torch.float64, device="cuda")
+            gap.refine_rows_s(ab, sp, Sb, cd, torch.tensor(y[rows], device="cuda"),
+                              torch.tensor(sig[rows], device="cuda"), gb)
+        g += gb
+        gap.refine_rows_s(ab, sp, Sb, cd, torch.tensor(y[rows], device="cuda"),
+                          torch.tensor(sig[rows], device="cuda"), torch.zeros_like(g), rr)
+    gap.sync()
+    assert relmax(g.cpu().numpy(), g_ref) <= TOL
+    assert abs(float(rr[0]) - rr_ref) <= TOL * rr_ref
+
+
 def test_streamed_mixed_fit_refined(gapx, gap):
     w = synth.WORKLOADS["fit_small_mixed"]
     b, X, K, Kmm, y, sig = problem(w)
@@ -109,12 +144,20 @@ def test_streamed_mixed_fit_refined(gapx, gap):
     c, _, _ = gap.fold_solve(T, M)
     err0 = np.linalg.norm(c.cpu().numpy() - c_fit) / np.linalg.norm(c_fit)
     errs = []
+    Ss = [gap.refine_weights(ab, sp) for ab, _, _ in dev]
+    c2 = c.clone()
     for step in range(3):
         g = torch.zeros(M, dtype=torch.float64, device="cuda")
         for ab, yb, sb in dev:
             gap.refine_rows(ab, sp, c, yb, sb, g)
         gap.refine_solve(T, M, Kmm_d, w.jitter, g, c)
         errs.append(np.linalg.norm(c.cpu().numpy() - c_fit) / np.linalg.norm(c_fit))
+        # the same steps with the batches' S kept between passes
+        g2 = torch.zeros(M, dtype=torch.float64, device="cuda")
+        for (ab, yb, sb), Sb in zip(dev, Ss):
+            gap.refine_rows_s(ab, sp, Sb, c2, yb, sb, g2)
+        gap.refine_solve(T, M, Kmm_d, w.jitter, g2, c2)
+    assert np.linalg.norm((c2 - c).cpu().numpy()) <= TOL * np.linalg.norm(c_fit)
     print(f"\nstreamed BF16X3 fit: c rel {err0:.2e} -> " + " -> ".join(f"{e:.2e}" for e in errs))
     assert err0 > 1e-9 and errs[-1] <= TOL
     # gap_fit's own refinement of the one-shot BF16X3 fit reaches the same c

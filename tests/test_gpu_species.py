@@ -51,7 +51,7 @@ def problem(w, seed=41):
 @pytest.mark.parametrize("wname,D", [("fit_small", None), ("ragged", 37)])
 def test_species_rows(gapx, gap, wname, D):
     w = synth.WORKLOADS["fit_small"] if wname == "fit_small" else \
-        synth.Workload("species_ragged", 43, n_cfg=9, atoms_lo=1, atoms_hi=13, D=D, nb=5, M=23)
+        synth.Workload("species_ragged", 43, n_cfg=9, atoms_lo=1, atoms_hi=13, D=D, nb=5, M=15)
     b, spc, Xs = problem(w)
     atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
     st = torch.tensor(spc, device="cuda")
