@@ -420,6 +420,20 @@ gap_status gap_forces(gap_handle *h, const gap_atoms *atoms, const double *dEdd,
 gap_status gap_split_bf16x3(gap_handle *h, const void *x, gap_dtype dt, int64_t rows, int64_t cols,
                             int64_t ld, uint16_t *hi, uint16_t *lo, uint16_t *hi_t, uint16_t *lo_t);
 
+/* gap_forces without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as gap_forces;
+ * its pair transposition and per-pair products live in a static device array
+ * of 64 MiB (one per GPU, held until the process ends) instead of the handle's
+ * workspace.  It needs 16 n_atoms + 32 n_pairs bytes plus about 10 KB
+ * (and 8 n_atoms round4(D) more when dEdd is not 32-byte aligned or D % 4 != 0),
+ * e.g. up to about 2 million pairs; larger inputs return GAP_E_INVALID before
+ * anything is enqueued.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (several handles or streams) race and must be ordered by
+ * the caller.  Asynchronous. */
+gap_status gap_forces_noalloc(gap_handle *h, const gap_atoms *atoms, const double *dEdd,
+                              double *forces);
+
 /* Stage timing (profiling aid, off by default).  When enabled, the library
  * records HIP events on the handle's stream around each stage it enqueues;
  * gap_timing_read waits for them and returns the accumulated milliseconds and

@@ -96,6 +96,7 @@ def lib():
             "gap_predict": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_predict_backward": ([P, P, P, P, I32, P, P, P, P], S),
             "gap_forces": ([P, P, P, P], S),
+            "gap_forces_noalloc": ([P, P, P, P], S),
             "gap_split_bf16x3": ([P, P, I32, I64, I64, I64, P, P, P, P], S),
             "gap_timing": ([P, I32], S),
             "gap_timing_read": ([P, P, P, I32], S),
@@ -685,6 +686,16 @@ class Gap:
         self._check(lib().gap_split_bf16x3(self._h, _ptr(x), _DT[x.dtype], rows, cols, x.shape[1],
                                            _ptr(hi), _ptr(lo), _ptr(ht), _ptr(lt)))
         return hi[:rows], lo[:rows], ht, lt
+
+    def forces_noalloc(self, atoms: Atoms, dEdd: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """gap_forces with no device allocation inside the library: `out`
+        (FP64 [n_atoms, 3]) is the caller's, the scratch is the library's static
+        array.  dEdd must already be a contiguous FP64 device tensor."""
+        if dEdd.dtype != torch.float64 or not dEdd.is_contiguous():
+            raise GapError(GAP_E_INVALID, "dEdd must be a contiguous float64 tensor")
+        a = atoms.struct()
+        self._check(lib().gap_forces_noalloc(self._h, ctypes.byref(a), _ptr(dEdd), _ptr(out)))
+        return out
 
 
 _default = {}

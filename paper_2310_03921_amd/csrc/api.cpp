@@ -8,10 +8,24 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/gap.h"
 #include "launch.h"
+
+// Device scratch of the allocation-free entry point gap_forces_noalloc: one
+// copy per GPU, held until the process ends.  Host code never passes this
+// name to a kernel (on the host it is only a stand-in for the symbol); it
+// looks up each device's address once, in gap_create, and uses that.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
 
 struct gap_handle {
   int device = 0;
@@ -28,6 +42,7 @@ struct gap_handle {
   gapk::Timer timer;
   double tm_ms[gapk::TM_COUNT] = {};
   int64_t tm_n[gapk::TM_COUNT] = {};
+  void* noalloc_scratch = nullptr;  // this device's address of `scratch`
 };
 
 namespace {
@@ -295,6 +310,23 @@ gap_status gap_create(gap_handle** out, int device, void* hip_stream) {
   if (hipSetDevice(device) != hipSuccess || check_gfx950(h) != GAP_OK) {
     delete h;
     return GAP_E_HIP;
+  }
+  {
+    // this device's copy of the allocation-free scratch, looked up once
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device >= kMaxDevices) {
+      delete h;
+      return GAP_E_HIP;
+    }
+    if (!g_scratch_ptr[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        delete h;
+        return GAP_E_HIP;
+      }
+      g_scratch_ptr[device] = p;
+    }
+    h->noalloc_scratch = g_scratch_ptr[device];
   }
   if (hipMalloc(&h->dev_err, 256) != hipSuccess) {
     delete h;
@@ -1371,6 +1403,50 @@ gap_status gap_split_bf16x3(gap_handle* h, const void* x, gap_dtype dt, int64_t 
     gapk::split_rows_bf16(x, f32(dt), ld, rows, cols, reinterpret_cast<__bf16*>(hi),
                           reinterpret_cast<__bf16*>(lo), h->stream);
   }
+  HIP_TRY(h, hipGetLastError());
+  return GAP_OK;
+}
+
+gap_status gap_forces_noalloc(gap_handle* h, const gap_atoms* a, const double* dEdd,
+                              double* forces) {
+  if (!h) return GAP_E_INVALID;
+  gap_status s = set_device(h);
+  if (s != GAP_OK) return s;
+  s = check_atoms(h, a, nullptr, true);
+  if (s != GAP_OK) return s;
+  if (!dEdd || !forces) return fail(h, GAP_E_INVALID, "dEdd or forces is NULL");
+  if (!h->noalloc_scratch) return fail(h, GAP_E_HIP, "no allocation-free scratch on this device");
+  // the same slices as gap_forces, laid out in the static scratch
+  const bool direct = aligned32(dEdd) && a->D % 4 == 0;
+  Layout L;
+  PairWs p;
+  layout_pairs(L, a->n_atoms, a->n_pairs, p);
+  const size_t fp = L.take(sizeof(double) * std::max<int64_t>(3 * a->n_pairs, 1));
+  const size_t gp = direct ? 0 : L.take(sizeof(double) * std::max<int64_t>(a->n_atoms * ld4(a->D), 1));
+  if (L.off > kNoAllocScratchBytes)
+    return fail(h, GAP_E_INVALID,
+                "gap_forces_noalloc needs %zu bytes of scratch for %lld atoms and %lld pairs; "
+                "its static scratch holds %zu (use gap_forces)",
+                L.off, (long long)a->n_atoms, (long long)a->n_pairs, kNoAllocScratchBytes);
+  char* base = static_cast<char*>(h->noalloc_scratch);
+  const double* g = dEdd;
+  int64_t ldg = a->D;
+  if (!direct) {
+    ldg = ld4(a->D);
+    gapk::copy_rows_f64(dEdd, a->D, reinterpret_cast<double*>(base + gp), ldg, a->n_atoms, a->D,
+                        h->stream);
+    g = reinterpret_cast<const double*>(base + gp);
+  }
+  gapk::pair_transpose(a->pair_ptr, a->pair_j, a->n_atoms, a->n_pairs,
+                       reinterpret_cast<int64_t*>(base + p.tgt_ptr),
+                       reinterpret_cast<int32_t*>(base + p.tgt_pair),
+                       reinterpret_cast<int32_t*>(base + p.src), nullptr,
+                       reinterpret_cast<int32_t*>(base + p.scratch), h->dev_err, h->stream);
+  gapk::forces_f64(a->jac, f32(a->jac_dt), a->ld_jac, a->D, g, ldg,
+                   reinterpret_cast<int32_t*>(base + p.src), a->n_atoms, a->n_pairs,
+                   reinterpret_cast<int64_t*>(base + p.tgt_ptr),
+                   reinterpret_cast<int32_t*>(base + p.tgt_pair),
+                   reinterpret_cast<double*>(base + fp), forces, h->stream);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;
 }
