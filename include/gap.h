@@ -118,6 +118,14 @@ const char *gap_last_error(const gap_handle *h);
 /* Wait for the handle's stream and report deferred device-side errors. */
 gap_status gap_sync(gap_handle *h);
 
+/* Cap, in bytes, on the optional workspace the handle may take for speed
+ * (0, the default: no cap).  Today that is the Jacobians of a BF16X3
+ * gap_build_knm with D <= 256 split once into hi / lo halves (4 bytes per
+ * entry, at most 16 GB), which the call otherwise takes whenever they fit in
+ * 85% of the free device memory; under the cap the rows are split in registers
+ * instead (same results, more time).  Required workspace is not capped. */
+gap_status gap_set_workspace_limit(gap_handle *h, size_t bytes);
+
 /* Workspace bytes the handle will hold for a fit of `atoms` with `sp`
  * (K_NM and the least-squares matrix excluded: those are caller buffers);
  * the equivalent of a dry run (cf. the gap_fit `dryrun` argument). */

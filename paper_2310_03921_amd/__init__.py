@@ -98,6 +98,7 @@ def lib():
             "gap_forces": ([P, P, P, P], S),
             "gap_forces_noalloc": ([P, P, P, P], S),
             "gap_split_bf16x3": ([P, P, I32, I64, I64, I64, P, P, P, P], S),
+            "gap_set_workspace_limit": ([P, ctypes.c_size_t], S),
             "gap_timing": ([P, I32], S),
             "gap_timing_read": ([P, P, P, I32], S),
             "gap_timing_name": ([I32], ctypes.c_char_p),
@@ -331,6 +332,10 @@ class Gap:
 
     def sync(self):
         self._check(lib().gap_sync(self._h))
+
+    def set_workspace_limit(self, nbytes: int):
+        """Cap the optional workspace (pre-split Jacobians); 0 removes the cap."""
+        self._check(lib().gap_set_workspace_limit(self._h, int(nbytes)))
 
     def timing(self, enable: bool = True):
         """Record HIP events around each library stage on this handle's stream."""

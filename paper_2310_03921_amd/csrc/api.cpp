@@ -43,6 +43,7 @@ struct gap_handle {
   double tm_ms[gapk::TM_COUNT] = {};
   int64_t tm_n[gapk::TM_COUNT] = {};
   void* noalloc_scratch = nullptr;  // this device's address of `scratch`
+  size_t ws_limit = 0;               // cap on optional workspace (0: none)
 };
 
 namespace {
@@ -231,9 +232,14 @@ void layout_predict(Layout& L, const gap_atoms* a, const gap_sparse* sp, bool ne
                     bool bf16 = false) {
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   if (bf16) layout_split(L, M, D, true, w.split);
-  w.W = need_g ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(M), 1)) : 0;
+  // the BF16X3 P-stage writes an FP32 W, always (its epilogue forms W with the energies)
+  w.W = (need_g || bf16) ? L.take((bf16 ? sizeof(float) : sizeof(double)) *
+                                  std::max<int64_t>(N * ld4(M), 1))
+                         : 0;
   w.e_atom = need_eatom ? L.take(sizeof(double) * std::max<int64_t>(N, 1)) : 0;
-  w.epart = L.take(sizeof(double) * std::max<int64_t>(N * gapk::pstage_groups(M), 1));
+  w.epart = L.take(sizeof(double) *
+                   std::max<int64_t>(N * std::max(gapk::pstage_groups(M),
+                                                  gapk::gemm_b3_col_blocks(M)), 1));
   w.g = need_gbuf ? L.take(sizeof(double) * std::max<int64_t>(N * ld4(D), 1)) : 0;
   w.f_pair = need_forces ? L.take(sizeof(double) * std::max<int64_t>(3 * a->n_pairs, 1)) : 0;
   if (need_forces) layout_pairs(L, N, a->n_pairs, w.pairs);
@@ -246,26 +252,30 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   const bool need_g = dEdd || forces;
   double* ea = e_atom ? e_atom : (e_cfg ? at<double>(h, w.e_atom) : nullptr);
-  double* W = need_g ? at<double>(h, w.W) : nullptr;
+  double* W = (need_g && !bf16) ? at<double>(h, w.W) : nullptr;
+  float* W32 = bf16 ? at<float>(h, w.W) : nullptr;
   const int64_t ldw = ld4(M);
   auto wx = [&](double* out, int64_t ldo) {
     if (bf16)
-      gapk::gemm_wx_bf16x3(W, ldw, N, M, at<__bf16>(h, w.split.xth), at<__bf16>(h, w.split.xtl), D,
-                           out, ldo, h->stream);
+      gapk::gemm_b3_wx(W32, ldw, N, M, at<__bf16>(h, w.split.xth), at<__bf16>(h, w.split.xtl), D,
+                       out, ldo, h->stream);
     else
       gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, out, ldo, h->stream);
   };
   if (bf16) {
-    run_split(h, sp, w.split, true);
-    gapk::pstage_bf16x3(0, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, w.split.xh),
-                        at<__bf16>(h, w.split.xl), M, D, sp->zeta, sp->delta, c, nullptr, W, ldw,
-                        ea, nullptr, h->stream);
+    if (need_g) run_split(h, sp, w.split, true);
+    gapk::pstage_b3t(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                     sp->delta, c, nullptr, W32, ldw, nullptr, 0, at<double>(h, w.epart), nullptr,
+                     h->stream);
+    if (ea)
+      gapk::sum_parts_f64(at<double>(h, w.epart), gapk::gemm_b3_col_blocks(M), N, ea, 1, N, N,
+                          h->stream);
   } else {
     gapk::pstage_f64(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
                      sp->delta, c, nullptr, nullptr, 0, W, ldw, ea, nullptr, h->stream, nullptr, 0,
                      at<double>(h, w.epart));
   }
-  if (species) gapk::mask_species_rows(species, zsel, N, ea, W, ldw, h->stream);
+  if (species) gapk::mask_species_rows(species, zsel, N, ea, W, ldw, h->stream, W32);
   if (e_cfg) gapk::segment_sum_f64(ea, a->cfg_ptr, a->n_cfg, N, e_cfg, h->stream);
   if (forces) {
     double* g = at<double>(h, w.g);
@@ -384,6 +394,12 @@ static const char* kTimerNames[gapk::TM_COUNT] = {
     "pair_transpose", "kmm", "energy_rows", "force_rows", "cholesky_stack", "qr_panel",
     "qr_update", "back_substitution", "predict", "predict_backward", "refinement", "split_bf16"};
 
+gap_status gap_set_workspace_limit(gap_handle* h, size_t bytes) {
+  if (!h) return GAP_E_INVALID;
+  h->ws_limit = bytes;
+  return GAP_OK;
+}
+
 gap_status gap_timing(gap_handle* h, int enable) {
   if (!h) return GAP_E_INVALID;
   h->timer.on = enable != 0;
@@ -499,8 +515,17 @@ gap_status build_knm_impl(gap_handle* h, const gap_atoms* a, const gap_sparse* s
   if (prec == GAP_BF16X3) {
     layout_split(L, M, D, false, sw);
     const size_t jbytes = (size_t)3 * a->n_pairs * gapk::split_ld(D) * 2;
-    // pre-split Jacobians when the halves fit comfortably in the workspace
-    presplit = a->n_pairs > 0 && D <= 256 && jbytes <= (size_t)16 << 30;
+    // Pre-split the Jacobians once for descriptors of up to 256 entries (the
+    // twelve-wave kernel then streams hi / lo halves with no split in its
+    // loop) when both halves fit in the workspace with room to spare.  Longer
+    // descriptors stream the FP32 / FP64 rows and split them in registers:
+    // measured on the 576k-atom fit, the wide kernel on pre-split rows took
+    // 6.7 s against 5.1 s on the original rows.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    double room = std::min(0.85 * (double)(free_b + h->ws_bytes), (double)((size_t)16 << 30));
+    if (h->ws_limit > 0) room = std::min(room, (double)h->ws_limit);
+    presplit = a->n_pairs > 0 && D <= 256 && (double)(L.off + 2 * jbytes) * 1.125 <= room;
     if (presplit) {
       jh = L.take(jbytes);
       jl = L.take(jbytes);
@@ -950,7 +975,8 @@ struct RefineWs {
   PredictWs pw{};
 };
 
-void layout_refine(Layout& L, const gap_atoms* a, const gap_sparse* sp, RefineWs& w) {
+void layout_refine(Layout& L, const gap_atoms* a, const gap_sparse* sp, RefineWs& w,
+                   bool need_S = true) {
   const int64_t N = a->n_atoms, M = sp->M, D = sp->D;
   const int64_t n_rows = a->n_cfg + 3 * N;
   w.kc = L.take(sizeof(double) * std::max<int64_t>(n_rows, 1));
@@ -962,7 +988,7 @@ void layout_refine(Layout& L, const gap_atoms* a, const gap_sparse* sp, RefineWs
                                            gapk::resid_colsum_groups(N, M)) * M + 8);
   w.ones = L.take(sizeof(double) * M);
   // pw.W holds S = delta^2 zeta p^(zeta-1) unless the caller keeps it
-  layout_predict(L, a, sp, true, false, true, true, w.pw);
+  layout_predict(L, a, sp, need_S, false, true, true, w.pw);
 }
 
 // The exact FP64 kernel-gradient scale S[i][m] = delta^2 zeta (d_i . x_m)^(zeta-1)
@@ -1150,7 +1176,7 @@ gap_status refine_rows_impl(gap_handle* h, const gap_atoms* a, const gap_sparse*
   if (!y || !sigma) return fail(h, GAP_E_INVALID, "y / sigma are NULL");
   Layout L;
   RefineWs rw;
-  layout_refine(L, a, sp, rw);
+  layout_refine(L, a, sp, rw, S == nullptr);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   h->timer.begin(gapk::TM_REFINE);
@@ -1308,40 +1334,57 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
   Layout L;
   const bool needW = d_desc || d_X;
   const int64_t ldw = ld4(M);
+  if (bf) {
+    // tiled BF16X3 path: FP32 W and W^T from the P-stage, then W X and W^T D
+    const int64_t ldwt = ld4(N);
+    const size_t W32 = L.take(sizeof(float) * std::max<int64_t>(N * ldw, 1));
+    const size_t WT32 = L.take(sizeof(float) * std::max<int64_t>(M * ldwt, 1));
+    const size_t dcp = L.take(sizeof(double) * (gapk::gemm_b3_row_blocks(N) * M + 8));
+    const size_t DT = d_X ? L.take(sizeof(float) * std::max<int64_t>(D * ldwt, 1)) : 0;
+    const int64_t base = gapk::gemm_b3_col_blocks(M) * gapk::gemm_b3_col_blocks(D);
+    const int nz = (int)std::max<int64_t>(
+        1, std::min<int64_t>({32, (2048 + base - 1) / base, std::max<int64_t>(N / 512, 1)}));
+    const size_t part = d_X ? L.take(sizeof(double) * std::max<int64_t>(nz * M * D, 1)) : 0;
+    SplitWs sw;
+    layout_split(L, M, D, true, sw);
+    s = ensure_ws(h, L.off);
+    if (s != GAP_OK) return s;
+    h->timer.begin(gapk::TM_BACKWARD);
+    if (d_desc) run_split(h, sp, sw, true);
+    gapk::pstage_b3t(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
+                     sp->delta, c, g_e, at<float>(h, W32), ldw, at<float>(h, WT32), ldwt, nullptr,
+                     at<double>(h, dcp), h->stream);
+    if (d_c)
+      gapk::sum_parts_f64(at<double>(h, dcp), gapk::gemm_b3_row_blocks(N), M, d_c, 1, M, M,
+                          h->stream);
+    if (d_desc)
+      gapk::gemm_b3_wx(at<float>(h, W32), ldw, N, M, at<__bf16>(h, sw.xth),
+                       at<__bf16>(h, sw.xtl), D, d_desc, D, h->stream);
+    if (d_X) {
+      gapk::transpose_f32(a->desc, f32(a->desc_dt), a->ld_desc, N, D, at<float>(h, DT), ldwt,
+                          h->stream);
+      gapk::gemm_b3_wtd(at<float>(h, WT32), ldwt, M, N, at<float>(h, DT), ldwt, D,
+                        at<double>(h, part), nz, d_X, D, h->stream);
+    }
+    h->timer.end(gapk::TM_BACKWARD);
+    HIP_TRY(h, hipGetLastError());
+    return GAP_OK;
+  }
   const size_t W = needW ? L.take(sizeof(double) * std::max<int64_t>(N * ldw, 1)) : 0;
   const size_t dcp = L.take(sizeof(double) * (gapk::pstage_row_blocks(N) * M + 8));
-  SplitWs sw;
-  if (bf) layout_split(L, M, D, true, sw);
   s = ensure_ws(h, L.off);
   if (s != GAP_OK) return s;
   double* Wp = needW ? at<double>(h, W) : nullptr;
   h->timer.begin(gapk::TM_BACKWARD);
-  if (bf) {
-    run_split(h, sp, sw, true);
-    gapk::pstage_bf16x3(1, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, sw.xh),
-                        at<__bf16>(h, sw.xl), M, D, sp->zeta, sp->delta, c, g_e, Wp, ldw, nullptr,
-                        at<double>(h, dcp), h->stream);
-  } else {
+  {
     gapk::pstage_f64(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
                      sp->delta, c, g_e, nullptr, 0, Wp, ldw, nullptr, at<double>(h, dcp),
                      h->stream);
   }
   if (d_c) gapk::reduce_rows_f64(at<double>(h, dcp), gapk::pstage_row_blocks(N), M, d_c, h->stream);
-  if (d_desc) {
-    if (bf)
-      gapk::gemm_wx_bf16x3(Wp, ldw, N, M, at<__bf16>(h, sw.xth), at<__bf16>(h, sw.xtl), D, d_desc,
-                           D, h->stream);
-    else
-      gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
-  }
-  if (d_X) {
-    if (bf)
-      gapk::gemm_wtd_bf16x3(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D,
-                            h->stream);
-    else
-      gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D,
-                         h->stream);
-  }
+  if (d_desc) gapk::gemm_wx_f64(Wp, ldw, N, M, sp->X, sp->ld_x, D, d_desc, D, h->stream);
+  if (d_X)
+    gapk::gemm_wtd_f64(Wp, ldw, N, M, a->desc, f32(a->desc_dt), a->ld_desc, D, d_X, D, h->stream);
   h->timer.end(gapk::TM_BACKWARD);
   HIP_TRY(h, hipGetLastError());
   return GAP_OK;

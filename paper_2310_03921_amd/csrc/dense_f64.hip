@@ -1179,12 +1179,14 @@ __global__ __launch_bounds__(256) void k_sub_cfg_desc(double* __restrict__ H, in
 // (a per-species GP predicts only the local energies of its own species).
 __global__ void k_mask_species_rows(const int32_t* __restrict__ species, int32_t zsel, int64_t n,
                                     double* __restrict__ e_atom, double* __restrict__ W,
-                                    int64_t ldw) {
+                                    float* __restrict__ W32, int64_t ldw) {
   const int64_t i = blockIdx.x;
   if (i >= n || species[i] == zsel) return;
   if (e_atom && threadIdx.x == 0) e_atom[i] = 0.0;
   if (W)
     for (int64_t m = threadIdx.x; m < ldw; m += blockDim.x) W[i * ldw + m] = 0.0;
+  if (W32)
+    for (int64_t m = threadIdx.x; m < ldw; m += blockDim.x) W32[i * ldw + m] = 0.f;
 }
 }  // namespace
 
@@ -1213,10 +1215,10 @@ void sub_cfg_desc(double* H, int64_t ldh, const void* desc, bool desc_f32, int64
 }
 
 void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
-                       int64_t ldw, hipStream_t st) {
-  if (n <= 0 || (!e_atom && !W)) return;
+                       int64_t ldw, hipStream_t st, float* W32) {
+  if (n <= 0 || (!e_atom && !W && !W32)) return;
   hipLaunchKernelGGL(k_mask_species_rows, dim3((unsigned)n), dim3(256), 0, st, species, zsel, n,
-                     e_atom, W, ldw);
+                     e_atom, W, W32, ldw);
 }
 
 void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,

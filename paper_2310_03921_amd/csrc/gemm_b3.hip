@@ -1,0 +1,444 @@
+// Tiled BF16x3 GEMM for the predict and backward contractions (eq. epsilon and
+// its derivatives): C[i][j] = sum_k A[i][k] B[j][k], both operands K-contiguous,
+// every value split hi = bf16(fp32(x)), lo = bf16(fp32(x) - hi) while it is
+// staged into LDS, products hi*hi + hi*lo + lo*hi on the BF16 matrix cores with
+// FP32 accumulation (see mma_bf16.h).
+//
+// A block computes a 128 x 128 tile of C with four waves (64 x 64 each: four
+// A and four B fragments, sixteen accumulators), over 32-deep k blocks whose
+// split A and B halves are double-buffered in LDS in matrix-core operand
+// order; the next k block is loaded into registers while the current one
+// feeds the matrix cores.  Each fragment read from LDS feeds twelve products,
+// so the LDS traffic stays below its bandwidth.
+//
+// Epilogues:
+//   kPlain   C (FP64, row-major), or a split-K partial C + z * zstride;
+//   kPEnergy P-stage of predict: P = D X^T, e_part[y][i] = sum over the
+//            block's columns of c_m k(p_im), W[i][m] = delta^2 zeta c_m p^(zeta-1)
+//            (FP32, the forward W, whose product with X is the descriptor gradient);
+//   kPBack   P-stage of the backward: dc_part[x][m] = sum over the block's rows of
+//            g_e[i] k(p_im), W[i][m] = g_e[i] delta^2 zeta c_m p^(zeta-1) and its
+//            transpose WT[m][i] (FP32).
+#include <algorithm>
+#include <type_traits>
+
+#include "launch.h"
+#include "mma_bf16.h"
+
+namespace gapk {
+
+namespace {
+
+constexpr int kGT = 128;            // tile rows and columns
+constexpr int kGStage = kGT * 32;   // elements of one operand per k block
+constexpr int kGStageV = kGStage / 8 * 2;   // 16-byte LDS entries of one split block
+constexpr int kGLds = 4 * kGStageV * 16;   // dynamic LDS bytes of a block
+constexpr int kPlain = 0, kPEnergy = 1, kPBack = 2;
+
+inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Pre-split operand rows: hi and lo halves [rows][ld], ld a multiple of 32,
+// zero padded along k.
+struct SplitRows {
+  const __bf16* hi;
+  const __bf16* lo;
+};
+
+// Thread t stages rows (t >> 2) and (t >> 2) + 64, k group 8 (t & 3) .. + 7, of
+// a 128 x 32 operand block: eight values each, split into 16-byte hi / lo
+// halves stored at [tile][hi | lo][lane] (lane = row % 16 + 16 group).
+template <typename T>
+GAP_DEV void stage_load(const T* __restrict__ p, int64_t ld, int64_t rows, int64_t K,
+                        int64_t r0, int64_t k0, float (&v)[2][8]) {
+  const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = r0 + (t >> 2) + 64 * h;
+    const int64_t k = k0 + 8 * grp;
+    const T* row = p + min(r, rows - 1) * ld;
+    const float ok = r < rows ? 1.f : 0.f;
+    if (k + 8 <= K) {
+      load8f_full(row, k, v[h]);
+    } else {
+      load8f(row, k, K, v[h]);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[h][e] *= ok;
+  }
+}
+
+GAP_DEV void stage_store(const float (&v)[2][8], bf8v* __restrict__ dst) {
+  const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = (t >> 2) + 64 * h;
+    bf8v hi, lo;
+    split8(v[h], hi, lo);
+    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+    d[0] = hi;
+    d[64] = lo;
+  }
+}
+
+// Pre-split rows: 16-byte loads of both halves, no split.
+struct PreSplit {
+  bf8v hi[2], lo[2];
+};
+GAP_DEV void stage_load_split(const SplitRows& s, int64_t ld, int64_t rows, int64_t r0,
+                              int64_t k0, PreSplit& v) {
+  const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = r0 + (t >> 2) + 64 * h;
+    const int64_t off = min(r, rows - 1) * ld + k0 + 8 * grp;
+    v.hi[h] = *reinterpret_cast<const bf8v*>(s.hi + off);
+    v.lo[h] = *reinterpret_cast<const bf8v*>(s.lo + off);
+    if (r >= rows) zero_split(v.hi[h], v.lo[h]);
+  }
+}
+GAP_DEV void stage_store_split(const PreSplit& v, bf8v* __restrict__ dst) {
+  const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = (t >> 2) + 64 * h;
+    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+    d[0] = v.hi[h];
+    d[64] = v.lo[h];
+  }
+}
+
+template <typename TB>
+struct BStage {
+  float v[2][8];
+};
+template <>
+struct BStage<SplitRows> {
+  PreSplit v;
+};
+
+struct EpiArgs {
+  int zeta;
+  double delta;
+  const double* c;      // [n_b] coefficients (P-stages)
+  const double* g_e;    // [n_a] upstream gradient (backward P-stage)
+  float* W;             // [n_a][ldw]
+  int64_t ldw;
+  float* WT;            // [n_b][ldwt] (backward)
+  int64_t ldwt;
+  double* e_part;       // [gridDim.y][n_a]
+  double* dc_part;      // [gridDim.x][n_b]
+  double* C;            // plain: [n_a][ldc] (+ z * zstride)
+  int64_t ldc;
+  int64_t zstride;
+};
+
+template <typename TA, typename TB, int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, int64_t lda,
+                                                    int64_t n_a, TB B, int64_t ldb, int64_t n_b,
+                                                    int64_t K, int64_t k_per_z, EpiArgs ep) {
+  // split operand blocks, double-buffered: [A | B][buf][8 tiles x (hi | lo) x 64 lanes]
+  extern __shared__ bf8v smem[];
+  auto sA = [&](int buf) { return smem + buf * kGStageV; };
+  auto sB = [&](int buf) { return smem + (2 + buf) * kGStageV; };
+  __shared__ double red[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
+  const int wr = wave & 1, wc = wave >> 1;   // 64-row and 64-column half of the tile
+  const int64_t i0 = (int64_t)blockIdx.x * kGT, j0 = (int64_t)blockIdx.y * kGT;
+  const int64_t kz0 = (int64_t)blockIdx.z * k_per_z;
+  const int64_t kz1 = min(K, kz0 + k_per_z);
+  const int nkb = (int)((kz1 - kz0 + 31) / 32);
+
+  f4v acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero4f();
+
+  float va[2][8];
+  BStage<TB> vb;
+  auto load_b = [&](int64_t k0) {
+    if constexpr (std::is_same<TB, SplitRows>::value)
+      stage_load_split(B, ldb, n_b, j0, k0, vb.v);
+    else
+      stage_load(B, ldb, n_b, kz1, j0, k0, vb.v);
+  };
+  auto store_b = [&](int buf) {
+    if constexpr (std::is_same<TB, SplitRows>::value)
+      stage_store_split(vb.v, sB(buf));
+    else
+      stage_store(vb.v, sB(buf));
+  };
+  if (nkb > 0) {
+    stage_load(A, lda, n_a, kz1, i0, kz0, va);
+    load_b(kz0);
+    stage_store(va, sA(0));
+    store_b(0);
+  }
+  __syncthreads();
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int buf = kb & 1;
+    const bool more = kb + 1 < nkb;
+    if (more) {
+      stage_load(A, lda, n_a, kz1, i0, kz0 + (int64_t)(kb + 1) * 32, va);
+      load_b(kz0 + (int64_t)(kb + 1) * 32);
+    }
+    const bf8v* xa = sA(buf) + lane + wr * 4 * 128;
+    const bf8v* xb = sB(buf) + lane + wc * 4 * 128;
+    bf8v ah[4], al[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ah[a] = xa[a * 128];
+      al[a] = xa[a * 128 + 64];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const bf8v bh = xb[b * 128], bl = xb[b * 128 + 64];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        acc[a][b] = mfma_bf16(ah[a], bh, acc[a][b]);
+        acc[a][b] = mfma_bf16(ah[a], bl, acc[a][b]);
+        acc[a][b] = mfma_bf16(al[a], bh, acc[a][b]);
+      }
+    }
+    if (more) {
+      stage_store(va, sA(buf ^ 1));
+      store_b(buf ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // C[4 g + r][idx] of fragment (a, b): row i0 + 64 wr + 16 a + 4 g + r,
+  // column j0 + 64 wc + 16 b + idx
+  if constexpr (EPI == kPlain) {
+    double* C = ep.C + blockIdx.z * ep.zstride;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
+        if (i >= n_a) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t j = j0 + 64 * wc + 16 * b + idx;
+          if (j < n_b) C[i * ep.ldc + j] = (double)acc[a][b][r];
+        }
+      }
+  } else {
+    const double d2 = ep.delta * ep.delta, d2z = d2 * ep.zeta;
+    double cm[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t j = j0 + 64 * wc + 16 * b + idx;
+      cm[b] = j < n_b ? ep.c[j] : 0.0;
+    }
+    double rowsum[4][4];   // kPEnergy: [a][r] partial row sums over this lane's columns
+    double colsum[4];      // kPBack: [b] partial column sums over this lane's rows
+#pragma unroll
+    for (int b = 0; b < 4; ++b) colsum[b] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        rowsum[a][r] = 0.0;
+        const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
+        const bool iv = i < n_a;
+        const double ge = (EPI == kPBack && iv) ? ep.g_e[i] : 1.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t j = j0 + 64 * wc + 16 * b + idx;
+          const bool jv = j < n_b;
+          const double p = acc[a][b][r];
+          const double pz1 = ipow(p, ep.zeta - 1);
+          const double kv = d2 * pz1 * p;
+          const double w = (EPI == kPBack ? ge : 1.0) * d2z * cm[b] * pz1;
+          if (iv && jv) {
+            if (EPI == kPEnergy) rowsum[a][r] += cm[b] * kv;
+            if (EPI == kPBack) colsum[b] += ge * kv;
+            ep.W[i * ep.ldw + j] = (float)w;
+            if (EPI == kPBack) ep.WT[j * ep.ldwt + i] = (float)w;
+          }
+        }
+      }
+    }
+    if constexpr (EPI == kPEnergy) {
+      // row sums over the 16 columns of each fragment (lanes idx), then the
+      // two column halves of the tile in a fixed order
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) rowsum[a][r] += __shfl_xor(rowsum[a][r], o);
+        }
+      if (wc == 1 && idx == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wr * 2 + 0][16 * a + 4 * g + r] = rowsum[a][r];
+      }
+      __syncthreads();
+      if (wc == 0 && idx == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
+            if (i < n_a)
+              ep.e_part[blockIdx.y * n_a + i] = rowsum[a][r] + red[wr * 2][16 * a + 4 * g + r];
+          }
+      }
+    } else {
+      // column sums over the 16 rows of each fragment (lanes g, r), then the
+      // two row halves
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        colsum[b] += __shfl_xor(colsum[b], 16);
+        colsum[b] += __shfl_xor(colsum[b], 32);
+      }
+      if (wr == 1 && g == 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) red[wc][16 * b + idx] = colsum[b];
+      }
+      __syncthreads();
+      if (wr == 0 && g == 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t j = j0 + 64 * wc + 16 * b + idx;
+          if (j < n_b) ep.dc_part[blockIdx.x * n_b + j] = colsum[b] + red[wc][16 * b + idx];
+        }
+      }
+    }
+  }
+}
+
+// dst[k][i] = src[i][k] as FP32 (K-contiguous rows of the transpose), 32 x 32
+// tiles through LDS; columns i >= n of the padded rows are written zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_f32(const T* __restrict__ src, int64_t lds,
+                                                       int64_t n, int64_t K,
+                                                       float* __restrict__ dst, int64_t ldd) {
+  __shared__ float t[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, k0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows per pass
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + y, k = k0 + tx;
+    t[y][tx] = (i < n && k < K) ? (float)src[i * lds + k] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t k = k0 + y, i = i0 + tx;
+    if (k < K && i < ldd) dst[k * ldd + i] = t[tx][y];
+  }
+}
+
+// out[j] = sum over z of part[z][j] (fixed order)
+__global__ void k_sum_parts(const double* __restrict__ part, int64_t nz, int64_t n,
+                            int64_t stride, double* __restrict__ out, int64_t rows,
+                            int64_t ldo, int64_t cols) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * cols;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e - i * cols;
+    double s = 0.0;
+    for (int64_t z = 0; z < nz; ++z) s += part[z * stride + i * cols + j];
+    out[i * ldo + j] = s;
+  }
+}
+
+template <typename TA, typename TB, int EPI>
+void launch_gemm(const TA* A, int64_t lda, int64_t n_a, TB B, int64_t ldb, int64_t n_b, int64_t K,
+                 int nz, const EpiArgs& ep, hipStream_t st) {
+  const int64_t kpz = ((K + nz - 1) / nz + 31) / 32 * 32;
+  const dim3 grid(cdiv_u(n_a, kGT), cdiv_u(n_b, kGT), (unsigned)cdiv_u(K, kpz));
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_b3<TA, TB, EPI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kGLds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gemm_b3<TA, TB, EPI>), grid, dim3(256), kGLds, st, A, lda, n_a, B, ldb,
+                     n_b, K, kpz, ep);
+}
+
+}  // namespace
+
+int64_t gemm_b3_col_blocks(int64_t n_b) { return (n_b + kGT - 1) / kGT; }
+int64_t gemm_b3_row_blocks(int64_t n_a) { return (n_a + kGT - 1) / kGT; }
+
+void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+                const double* c, const double* g_e, float* W, int64_t ldw, float* WT,
+                int64_t ldwt, double* e_part, double* dc_part, hipStream_t st) {
+  if (n <= 0 || M <= 0) return;
+  EpiArgs ep{};
+  ep.zeta = zeta;
+  ep.delta = delta;
+  ep.c = c;
+  ep.g_e = g_e;
+  ep.W = W;
+  ep.ldw = ldw;
+  ep.WT = WT;
+  ep.ldwt = ldwt;
+  ep.e_part = e_part;
+  ep.dc_part = dc_part;
+  if (mode == 0) {
+    if (desc_f32)
+      launch_gemm<float, const double*, kPEnergy>(static_cast<const float*>(desc), ldd, n, X, ldx,
+                                                  M, D, 1, ep, st);
+    else
+      launch_gemm<double, const double*, kPEnergy>(static_cast<const double*>(desc), ldd, n, X,
+                                                   ldx, M, D, 1, ep, st);
+  } else {
+    if (desc_f32)
+      launch_gemm<float, const double*, kPBack>(static_cast<const float*>(desc), ldd, n, X, ldx,
+                                                M, D, 1, ep, st);
+    else
+      launch_gemm<double, const double*, kPBack>(static_cast<const double*>(desc), ldd, n, X,
+                                                 ldx, M, D, 1, ep, st);
+  }
+}
+
+void gemm_b3_wx(const float* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
+                const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st) {
+  if (n <= 0 || D <= 0) return;
+  EpiArgs ep{};
+  ep.C = out;
+  ep.ldc = ldo;
+  launch_gemm<float, SplitRows, kPlain>(W, ldw, n, SplitRows{Xth, Xtl}, split_ld(M), D, M, 1, ep,
+                                        st);
+}
+
+void gemm_b3_wtd(const float* WT, int64_t ldwt, int64_t M, int64_t n, const float* DT,
+                 int64_t lddt, int64_t D, double* part, int nz, double* out, int64_t ldo,
+                 hipStream_t st) {
+  if (M <= 0 || D <= 0) return;
+  EpiArgs ep{};
+  ep.C = part;
+  ep.ldc = D;
+  ep.zstride = M * D;
+  launch_gemm<float, const float*, kPlain>(WT, ldwt, M, DT, lddt, D, n, nz, ep, st);
+  const unsigned g = std::max(1u, std::min(cdiv_u(M * D, 256), 65536u));
+  hipLaunchKernelGGL(k_sum_parts, dim3(g), dim3(256), 0, st, part, (int64_t)nz, M * D, M * D, out,
+                     M, ldo, D);
+}
+
+void sum_parts_f64(const double* part, int64_t nz, int64_t stride, double* out, int64_t rows,
+                   int64_t ldo, int64_t cols, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  const unsigned g = std::max(1u, std::min(cdiv_u(rows * cols, 256), 65536u));
+  hipLaunchKernelGGL(k_sum_parts, dim3(g), dim3(256), 0, st, part, nz, rows * cols, stride, out,
+                     rows, ldo, cols);
+}
+
+void transpose_f32(const void* src, bool src_f32, int64_t lds, int64_t n, int64_t K, float* dst,
+                   int64_t ldd, hipStream_t st) {
+  if (n <= 0 || K <= 0) return;
+  const dim3 grid(cdiv_u(std::max(n, ldd), 32), cdiv_u(K, 32));
+  if (src_f32)
+    hipLaunchKernelGGL(k_transpose_f32<float>, grid, dim3(256), 0, st,
+                       static_cast<const float*>(src), lds, n, K, dst, ldd);
+  else
+    hipLaunchKernelGGL(k_transpose_f32<double>, grid, dim3(256), 0, st,
+                       static_cast<const double*>(src), lds, n, K, dst, ldd);
+}
+
+}  // namespace gapk

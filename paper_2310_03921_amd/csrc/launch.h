@@ -160,7 +160,7 @@ void sub_cfg_desc(double* H, int64_t ldh, const void* desc, bool desc_f32, int64
                   int zeta, hipStream_t st);
 // Zero e_atom[i] and W row i (ldw doubles) of every atom i with species[i] != zsel.
 void mask_species_rows(const int32_t* species, int32_t zsel, int64_t n, double* e_atom, double* W,
-                       int64_t ldw, hipStream_t st);
+                       int64_t ldw, hipStream_t st, float* W32 = nullptr);
 void segment_sum_f64(const double* e_atom, const int64_t* cfg_ptr, int64_t n_cfg, int64_t n,
                      double* e_cfg, hipStream_t st);
 
@@ -211,16 +211,29 @@ bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, cons
                              const int32_t* pair_src, const int32_t* order, int64_t n_atoms,
                              int64_t n_pairs, int64_t row0, double* K, int64_t ldk,
                              hipStream_t st);
-void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
-                   const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
-                   double delta, const double* c, const double* g_e, double* W, int64_t ldw,
-                   double* e_atom, double* dc_part, hipStream_t st);
-void gemm_wx_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
-                    const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st);
-void gemm_wtd_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
-                     bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
-                     hipStream_t st);
-
+// ---- gemm_b3.hip (tiled BF16x3 GEMM for predict and backward) --------------
+// Column / row blocks of its 128 x 128 tiles (sizes of the e / dc partials).
+int64_t gemm_b3_col_blocks(int64_t n_b);
+int64_t gemm_b3_row_blocks(int64_t n_a);
+// P-stage: mode 0 e_part[cb][i] (cb < gemm_b3_col_blocks(M)) and W (FP32 [n][ldw]);
+// mode 1 dc_part[rb][m] (rb < gemm_b3_row_blocks(n)), W and WT (FP32 [M][ldwt]).
+void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
+                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
+                const double* c, const double* g_e, float* W, int64_t ldw, float* WT,
+                int64_t ldwt, double* e_part, double* dc_part, hipStream_t st);
+// out[i][d] = sum_m W[i][m] X[m][d] from FP32 W and the split transposed X halves.
+void gemm_b3_wx(const float* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
+                const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st);
+// out[m][d] = sum_i WT[m][i] DT[d][i] with nz split-K partials in part [nz][M][D].
+void gemm_b3_wtd(const float* WT, int64_t ldwt, int64_t M, int64_t n, const float* DT,
+                 int64_t lddt, int64_t D, double* part, int nz, double* out, int64_t ldo,
+                 hipStream_t st);
+// out[i][j] = sum_z part[z * stride + i * cols + j].
+void sum_parts_f64(const double* part, int64_t nz, int64_t stride, double* out, int64_t rows,
+                   int64_t ldo, int64_t cols, hipStream_t st);
+// dst[k][i] = src[i][k] (FP32), K rows of length ldd (columns n .. ldd - 1 zero).
+void transpose_f32(const void* src, bool src_f32, int64_t lds, int64_t n, int64_t K, float* dst,
+                   int64_t ldd, hipStream_t st);
 // ---- linalg.hip -----------------------------------------------------------
 // A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows.
 void scale_rows(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,

@@ -263,11 +263,7 @@ __global__ __launch_bounds__(256) void k_force_rows_b3(
 //  - the next step's pair index, source and first Jacobian block, and this
 //    step's S values (one 32-byte row segment per source: lane idx of tile u
 //    owns column 8 idx + u), are loaded a step or a block ahead of their use.
-constexpr int kNCW = 8;  // 16-column tiles per block: 128 columns
-#ifndef GAP_B3W_TILES_PER_WAVE
-#define GAP_B3W_TILES_PER_WAVE 8
-#endif
-constexpr int kB3wTilesPerWave = GAP_B3W_TILES_PER_WAVE;
+constexpr int kNCW = 8;  // 16-column tiles per wave and per block: 128 columns
 
 template <typename TJ>
 GAP_DEV void jblock8(const TJ* __restrict__ row, int64_t k, int64_t kmax4, float out[8]) {
@@ -291,52 +287,62 @@ GAP_DEV void jblock8(const TJ* __restrict__ row, int64_t k, int64_t kmax4, float
   }
 }
 
-// NT tiles per wave: NT = 8, four waves (one per SIMD); NT = 4, eight waves
-// (two per SIMD, each slot group's 128 columns split between two waves, which
-// then read the same Jacobian rows, the second time from the L1 cache).
-template <typename TJ, int NT>
-__global__ __launch_bounds__(256 * (kNCW / NT), 1) void k_force_rows_b3w(
-    const TJ* __restrict__ jac, int64_t ldj, int64_t D, const __bf16* __restrict__ Xh,
-    const __bf16* __restrict__ Xl, int64_t ldp, int64_t M, const float* __restrict__ S,
-    int64_t ldS, const int64_t* __restrict__ tgt_ptr, const int32_t* __restrict__ tgt_pair,
-    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ order, int64_t n_atoms,
-    int64_t n_pairs, int64_t row0, double* __restrict__ K, int64_t ldk, int64_t n_ct,
-    int64_t n_grp, int nkb_all) {
+// Jacobian source of the wide kernel: FP32 / FP64 rows [3 n_pairs][ld], eight
+// entries per lane loaded as two clamped 4-wide loads and split in registers.
+// (Rows split once up front and streamed as hi / lo halves ran slower here,
+// 6.7 s against 5.1 s on the 576k-atom fit.)
+template <typename TJ>
+struct JRows {
+  const TJ* base;
+  int64_t ld, kmax4;
+  struct Frag {
+    float x[8];
+  };
+  GAP_DEV int64_t row(int pair) const { return (int64_t)pair * 3 * ld; }
+  GAP_DEV void load(int64_t r, int a, int64_t k, Frag& f) const {
+    jblock8(base + r + a * ld, k, kmax4, f.x);
+  }
+  GAP_DEV void ops(const Frag& f, bf8v& h, bf8v& l) const { split8(f.x, h, l); }
+};
+template <class JS>
+__global__ __launch_bounds__(256, 1) void k_force_rows_b3w(
+    JS js, int64_t D, const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int64_t ldp,
+    int64_t M, const float* __restrict__ S, int64_t ldS, const int64_t* __restrict__ tgt_ptr,
+    const int32_t* __restrict__ tgt_pair, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ order, int64_t n_atoms, int64_t n_pairs, int64_t row0,
+    double* __restrict__ K, int64_t ldk, int64_t n_ct, int64_t n_grp, int nkb_all) {
   // X halves of one chunk: [kb][tile u][hi | lo][64 lanes] of 16 bytes, so each
   // 16-byte LDS read of the wave is contiguous (no bank conflict)
   extern __shared__ bf8v xw[];
   int64_t ct, tgb;
   if (!xcd_group_tile(n_grp, n_ct, tgb, ct)) return;
-  constexpr int kThreads = 256 * (kNCW / NT);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int grp = wave & 3, u0 = (wave >> 2) * NT;  // slot group, first tile of this wave
   const int64_t colbase = ct * (16 * kNCW);
-  const int64_t cl0 = colbase + kNCW * idx + u0;  // column of tile u0 + u: cl0 + u
-  const int64_t scol = min(cl0, ldS - NT);        // clamped (valid) S offset
-  float colok[NT];
+  const int64_t cl0 = colbase + kNCW * idx;     // column of tile u: cl0 + u
+  const int64_t scol = min(cl0, ldS - kNCW);    // clamped (valid) S offset
+  float colok[kNCW];
 #pragma unroll
-  for (int u = 0; u < NT; ++u) colok[u] = (cl0 + u < M) ? 1.f : 0.f;
+  for (int u = 0; u < kNCW; ++u) colok[u] = (cl0 + u < M) ? 1.f : 0.f;
 
-  const int64_t slot = (tgb * 4 + grp) * 16 + idx;
+  const int64_t slot = (tgb * 4 + wave) * 16 + idx;
   const int target = slot < n_atoms ? order[slot] : -1;
   const int64_t seg0 = target >= 0 ? tgt_ptr[target] : 0;
   const int deg = target >= 0 ? (int)(tgt_ptr[target + 1] - seg0) : 0;
   const int maxdeg = wave_max16(deg);
   const int64_t last = min(seg0 + max(deg - 1, 0), n_pairs - 1);
   auto pair_slot = [&](int t) -> int64_t { return min(seg0 + t, last); };
-  const int64_t kmax4 = D - 4;
 
-  f4v acc[3][NT];
+  f4v acc[3][kNCW];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int u = 0; u < NT; ++u) acc[a][u] = zero4f();
-  const bf8v* xb = xw + lane + u0 * 128;
+    for (int u = 0; u < kNCW; ++u) acc[a][u] = zero4f();
+  const bf8v* xb = xw + lane;
 
   for (int kc0 = 0; kc0 < nkb_all; kc0 += kMaxKb32) {
     const int nkb = min(kMaxKb32, nkb_all - kc0);
     __syncthreads();  // the previous chunk's products are done with the LDS
-    for (int e = threadIdx.x; e < nkb * kNCW * 64; e += kThreads) {
+    for (int e = threadIdx.x; e < nkb * kNCW * 64; e += 256) {
       const int kb = e / (kNCW * 64), rem = e % (kNCW * 64);
       const int u = rem / 64, ln = rem % 64;
       const int64_t col = colbase + kNCW * (ln & 15) + u;
@@ -359,40 +365,40 @@ __global__ __launch_bounds__(256 * (kNCW / NT), 1) void k_force_rows_b3w(
     int pair = tgt_pair[pair_slot(0)];
     int pair_n = tgt_pair[pair_slot(1)];
     int src = pair_src[pair];
-    const TJ* jr = jac + (int64_t)pair * 3 * ldj;
-    float nx[3][8];
+    int64_t jr = js.row(pair);
+    typename JS::Frag nx[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) jblock8(jr + a * ldj, kb0, kmax4, nx[a]);
+    for (int a = 0; a < 3; ++a) js.load(jr, a, kb0, nx[a]);
     for (int t = 0; t < maxdeg; ++t) {
       const int pair_nn = tgt_pair[pair_slot(t + 2)];
       const int src_n = pair_src[pair_n];
-      const TJ* jn = jac + (int64_t)pair_n * 3 * ldj;
+      const int64_t jn = js.row(pair_n);
       // S of this step's sources (rows 4 g + r of the output tile)
-      f4v s_v[4][NT / 4];
+      f4v s_lo[4], s_hi[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int src_r = __shfl(src, 4 * g + r);
         const float* sp = S + (int64_t)max(src_r, 0) * ldS + scol;
-#pragma unroll
-        for (int q = 0; q < NT / 4; ++q) s_v[r][q] = *reinterpret_cast<const f4v*>(sp + 4 * q);
+        s_lo[r] = *reinterpret_cast<const f4v*>(sp);
+        s_hi[r] = *reinterpret_cast<const f4v*>(sp + 4);
       }
-      f4v G[3][NT];
+      f4v G[3][kNCW];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int u = 0; u < NT; ++u) G[a][u] = zero4f();
+        for (int u = 0; u < kNCW; ++u) G[a][u] = zero4f();
       for (int kb = 0; kb < nkb; ++kb) {
         bf8v ah[3], al[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) split8(nx[a], ah[a], al[a]);
+        for (int a = 0; a < 3; ++a) js.ops(nx[a], ah[a], al[a]);
         // the next block of this step, or the first block of the next step
         const bool more = kb + 1 < nkb;
-        const TJ* jp = more ? jr : jn;
+        const int64_t rn = more ? jr : jn;
         const int64_t kn = more ? kb0 + (int64_t)(kb + 1) * 32 : kb0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) jblock8(jp + a * ldj, kn, kmax4, nx[a]);
+        for (int a = 0; a < 3; ++a) js.load(rn, a, kn, nx[a]);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
+        for (int u = 0; u < kNCW; ++u) {
           const bf8v bh = xb[(kb * kNCW + u) * 128], bl = xb[(kb * kNCW + u) * 128 + 64];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -408,8 +414,8 @@ __global__ __launch_bounds__(256 * (kNCW / NT), 1) void k_force_rows_b3w(
         const int deg_r = __shfl(deg, 4 * g + r);
         const float ok = (t < deg_r && src_r >= 0) ? 1.f : 0.f;
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          const float sv = s_v[r][u >> 2][u & 3] * (ok * colok[u]);
+        for (int u = 0; u < kNCW; ++u) {
+          const float sv = (u < 4 ? s_lo[r][u & 3] : s_hi[r][u & 3]) * (ok * colok[u]);
 #pragma unroll
           for (int a = 0; a < 3; ++a) acc[a][u][r] += sv * G[a][u][r];
         }
@@ -425,13 +431,35 @@ __global__ __launch_bounds__(256 * (kNCW / NT), 1) void k_force_rows_b3w(
     const int tr = __shfl(target, 4 * g + r);
     if (tr < 0) continue;
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
+    for (int u = 0; u < kNCW; ++u) {
       if (cl0 + u >= M) continue;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
         K[(row0 + 3 * (int64_t)tr + a) + (cl0 + u) * ldk] = -(double)acc[a][u][r];
     }
   }
+}
+
+template <class JS>
+void launch_b3w(JS js, int64_t D, const __bf16* Xh, const __bf16* Xl, int64_t ldp, int64_t M,
+                const float* S, int64_t ldS, const int64_t* tgt_ptr, const int32_t* tgt_pair,
+                const int32_t* pair_src, const int32_t* order, int64_t n_atoms, int64_t n_pairs,
+                int64_t row0, double* K, int64_t ldk, hipStream_t st) {
+  const int nkb = (int)(ldp / 32);
+  const int64_t n_tgb = (n_atoms + 63) / 64;
+  const int64_t n_ct = (M + 16 * kNCW - 1) / (16 * kNCW);
+  const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
+  const size_t lds = (size_t)std::min(nkb, kMaxKb32) * kNCW * 128 * sizeof(bf8v);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3w<JS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((size_t)kMaxKb32 * kNCW * 128 * sizeof(bf8v)));
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_force_rows_b3w<JS>), dim3(blocks), dim3(256), lds, st, js, D, Xh, Xl, ldp,
+                     M, S, ldS, tgt_ptr, tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk,
+                     n_ct, n_tgb, nkb);
 }
 
 // Jacobian rows split once into hi/lo halves, [n_pairs][3][ldp] each (ldp = D
@@ -579,164 +607,6 @@ __global__ __launch_bounds__(768) void k_force_rows_b3s(
   }
 }
 
-// ------------------------------------------------------------- P-stage ----
-template <typename TD>
-__global__ __launch_bounds__(256) void k_pstage_b3(int mode, const TD* __restrict__ desc,
-                                                   int64_t ldd, int64_t n,
-                                                   const __bf16* __restrict__ Xh,
-                                                   const __bf16* __restrict__ Xl, int64_t ldp,
-                                                   int64_t M, int64_t D, int zeta, double delta,
-                                                   const double* __restrict__ cc,
-                                                   const double* __restrict__ g_e,
-                                                   double* __restrict__ W, int64_t ldw,
-                                                   double* __restrict__ e_atom,
-                                                   double* __restrict__ dc_part) {
-  __shared__ double colsum[4][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t row = rowbase + idx;
-  const bool rvalid = row < n;
-  Frag32Row<TD> fa{desc + (rvalid ? row : 0) * ldd, D, rvalid};
-  const double d2 = delta * delta, d2z = d2 * zeta;
-  double ge[4];
-  bool rv[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t rr = rowbase + 4 * g + r;
-    rv[r] = rr < n;
-    ge[r] = (mode != 0 && rv[r]) ? g_e[rr] : 0.0;
-  }
-  double esum[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t col0 = 0; col0 < M; col0 += 16 * kNCb) {
-    Frag32Split fb[kNCb];
-#pragma unroll
-    for (int u = 0; u < kNCb; ++u) {
-      const int64_t col = col0 + u * 16 + idx;
-      const int64_t c2 = col < M ? col : 0;
-      fb[u] = Frag32Split{Xh + c2 * ldp, Xl + c2 * ldp, col < M};
-    }
-    f4v acc[kNCb];
-#pragma unroll
-    for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
-    wave_mma_bf16x3<kNCb>(fa, fb, D, g, acc);
-#pragma unroll
-    for (int u = 0; u < kNCb; ++u) {
-      const int64_t col = col0 + u * 16 + idx;
-      const bool cvalid = col < M;
-      const double cm = (cvalid && cc) ? cc[col] : 0.0;
-      double csum = 0.0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t rr = rowbase + 4 * g + r;
-        if (!rv[r] || !cvalid) continue;
-        const double p = acc[u][r];
-        const double pz1 = ipow(p, zeta - 1);
-        const double kval = d2 * pz1 * p;
-        if (mode == 0) {
-          esum[r] += cm * kval;
-          if (W) W[rr * ldw + col] = d2z * cm * pz1;
-        } else {
-          csum += ge[r] * kval;
-          if (W) W[rr * ldw + col] = ge[r] * d2z * cm * pz1;
-        }
-      }
-      if (mode != 0) {
-        csum += __shfl_xor(csum, 16);
-        csum += __shfl_xor(csum, 32);
-        if (g == 0) colsum[wave][u * 16 + idx] = csum;
-      }
-    }
-    if (mode != 0) {
-      __syncthreads();
-      if (threadIdx.x < 64) {
-        const int64_t col = col0 + threadIdx.x;
-        if (col < M)
-          dc_part[(int64_t)blockIdx.x * M + col] =
-              ((colsum[0][threadIdx.x] + colsum[1][threadIdx.x]) + colsum[2][threadIdx.x]) +
-              colsum[3][threadIdx.x];
-      }
-      __syncthreads();
-    }
-  }
-  if (mode == 0 && e_atom) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double v = esum[r];
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
-      const int64_t rr = rowbase + 4 * g + r;
-      if (idx == 0 && rr < n) e_atom[rr] = v;
-    }
-  }
-}
-
-// out[i][d] = sum_m W[i][m] X[m][d]  with X^T halves [D][ldm]
-__global__ __launch_bounds__(256) void k_gemm_wx_b3(const double* __restrict__ W, int64_t ldw,
-                                                    int64_t n, int64_t M,
-                                                    const __bf16* __restrict__ Xth,
-                                                    const __bf16* __restrict__ Xtl, int64_t ldm,
-                                                    int64_t D, double* __restrict__ out,
-                                                    int64_t ldo) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t row = rowbase + idx;
-  const int64_t colbase = (int64_t)blockIdx.y * 64;
-  Frag32Row<double> fa{W + (row < n ? row : 0) * ldw, M, row < n};
-  Frag32Split fb[kNCb];
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) {
-    const int64_t col = colbase + u * 16 + idx;
-    const int64_t c2 = col < D ? col : 0;
-    fb[u] = Frag32Split{Xth + c2 * ldm, Xtl + c2 * ldm, col < D};
-  }
-  f4v acc[kNCb];
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
-  wave_mma_bf16x3<kNCb>(fa, fb, M, g, acc);
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) {
-    const int64_t col = colbase + u * 16 + idx;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t rr = rowbase + 4 * g + r;
-      if (rr < n && col < D) out[rr * ldo + col] = acc[u][r];
-    }
-  }
-}
-
-// out[m][d] = sum_i W[i][m] desc[i][d]
-template <typename TD>
-__global__ __launch_bounds__(256) void k_gemm_wtd_b3(const double* __restrict__ W, int64_t ldw,
-                                                     int64_t n, int64_t M,
-                                                     const TD* __restrict__ desc, int64_t ldd,
-                                                     int64_t D, double* __restrict__ out,
-                                                     int64_t ldo) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int64_t rowbase = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t row = rowbase + idx;
-  const int64_t colbase = (int64_t)blockIdx.y * 64;
-  Frag32Col<double> fa{W + (row < M ? row : 0), ldw, n, row < M};
-  Frag32Col<TD> fb[kNCb];
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) {
-    const int64_t col = colbase + u * 16 + idx;
-    fb[u] = Frag32Col<TD>{desc + (col < D ? col : 0), ldd, n, col < D};
-  }
-  f4v acc[kNCb];
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
-  wave_mma_bf16x3<kNCb>(fa, fb, n, g, acc);
-#pragma unroll
-  for (int u = 0; u < kNCb; ++u) {
-    const int64_t col = colbase + u * 16 + idx;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t rr = rowbase + 4 * g + r;
-      if (rr < M && col < D) out[rr * ldo + col] = acc[u][r];
-    }
-  }
-}
-
 template <typename T>
 inline const T* tp(const void* p) {
   return reinterpret_cast<const T*>(p);
@@ -788,32 +658,12 @@ void force_rows_bf16x3(const void* jac, bool jac_f32, int64_t ldj, int64_t D, co
   const int64_t n_tgb = (n_atoms + 63) / 64;
   const int nkb = (int)(ldp / 32);
   if (D % 4 == 0 && D >= 4 && n_pairs > 0 && ldj % 4 == 0 && ldS % 8 == 0 && ldS >= 8) {
-    const int64_t n_ct = (M + 16 * kNCW - 1) / (16 * kNCW);
-    const unsigned blocks = xcd_group_tile_blocks(n_tgb, n_ct);
-    const size_t lds = (size_t)std::min(nkb, kMaxKb32) * kNCW * 128 * sizeof(bf8v);
-    const int lds_max = (int)((size_t)kMaxKb32 * kNCW * 128 * sizeof(bf8v));
-    constexpr int NT = kB3wTilesPerWave;
-    constexpr int threads = 256 * (kNCW / NT);
-    static bool fw = false, dw = false;
-    if (jac_f32) {
-      if (!fw) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3w<float, NT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-        fw = true;
-      }
-      hipLaunchKernelGGL((k_force_rows_b3w<float, NT>), dim3(blocks), dim3(threads), lds, st,
-                         tp<float>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb, nkb);
-    } else {
-      if (!dw) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_rows_b3w<double, NT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-        dw = true;
-      }
-      hipLaunchKernelGGL((k_force_rows_b3w<double, NT>), dim3(blocks), dim3(threads), lds, st,
-                         tp<double>(jac), ldj, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr, tgt_pair,
-                         pair_src, order, n_atoms, n_pairs, row0, K, ldk, n_ct, n_tgb, nkb);
-    }
+    if (jac_f32)
+      launch_b3w(JRows<float>{tp<float>(jac), ldj, D - 4}, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr,
+                 tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, st);
+    else
+      launch_b3w(JRows<double>{tp<double>(jac), ldj, D - 4}, D, Xh, Xl, ldp, M, S, ldS, tgt_ptr,
+                 tgt_pair, pair_src, order, n_atoms, n_pairs, row0, K, ldk, st);
     return;
   }
   // Up to 256 descriptor entries: 128 columns per block.  Longer descriptors:
@@ -912,39 +762,7 @@ bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, cons
   return true;
 }
 
-void pstage_bf16x3(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
-                   const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
-                   double delta, const double* c, const double* g_e, double* W, int64_t ldw,
-                   double* e_atom, double* dc_part, hipStream_t st) {
-  if (n <= 0 || M <= 0) return;
-  const int64_t ldp = split_ld(D);
-  dim3 grid((unsigned)((n + 63) / 64));
-  if (desc_f32)
-    hipLaunchKernelGGL(k_pstage_b3<float>, grid, dim3(256), 0, st, mode, tp<float>(desc), ldd, n,
-                       Xh, Xl, ldp, M, D, zeta, delta, c, g_e, W, ldw, e_atom, dc_part);
-  else
-    hipLaunchKernelGGL(k_pstage_b3<double>, grid, dim3(256), 0, st, mode, tp<double>(desc), ldd,
-                       n, Xh, Xl, ldp, M, D, zeta, delta, c, g_e, W, ldw, e_atom, dc_part);
-}
 
-void gemm_wx_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
-                    const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st) {
-  if (n <= 0 || D <= 0) return;
-  hipLaunchKernelGGL(k_gemm_wx_b3, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
-                     Xth, Xtl, split_ld(M), D, out, ldo);
-}
 
-void gemm_wtd_bf16x3(const double* W, int64_t ldw, int64_t n, int64_t M, const void* desc,
-                     bool desc_f32, int64_t ldd, int64_t D, double* out, int64_t ldo,
-                     hipStream_t st) {
-  if (M <= 0 || D <= 0) return;
-  dim3 grid(cdiv(M, 64), cdiv(D, 64));
-  if (desc_f32)
-    hipLaunchKernelGGL(k_gemm_wtd_b3<float>, grid, dim3(256), 0, st, W, ldw, n, M,
-                       tp<float>(desc), ldd, D, out, ldo);
-  else
-    hipLaunchKernelGGL(k_gemm_wtd_b3<double>, grid, dim3(256), 0, st, W, ldw, n, M,
-                       tp<double>(desc), ldd, D, out, ldo);
-}
 
 }  // namespace gapk

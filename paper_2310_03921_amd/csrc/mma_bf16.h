@@ -113,24 +113,6 @@ struct Frag32Row {
   }
 };
 
-// Element (idx, k) at col[k * ld]: contiguous along idx, split on the fly.
-template <typename T>
-struct Frag32Col {
-  const T* col;
-  int64_t ld;
-  int64_t kmax;
-  bool valid;
-  GAP_DEV void frag(int64_t k0, int g, bf8v& hi, bf8v& lo) const {
-    float x[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = k0 + 8 * g + e;
-      x[e] = (valid && k < kmax) ? (float)col[k * ld] : 0.f;
-    }
-    split8(x, hi, lo);
-  }
-};
-
 // Pre-split rows: hi/lo arrays padded with zeros to a multiple of 32 along k.
 struct Frag32Split {
   const __bf16* hi;
@@ -166,20 +148,5 @@ GAP_DEV void wave_mma_bf16x3(const FA& fa, const FB (&fb)[NC], int64_t K, int g,
 #pragma unroll
     for (int u = 0; u < NC; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
     mma3_block<NC>(ah, al, bh, bl, acc);
-  }
-}
-
-// Two A operands against the same B tiles.
-template <int NC, class FA0, class FA1, class FB>
-GAP_DEV void wave_mma2_bf16x3(const FA0& fa0, const FA1& fa1, const FB (&fb)[NC], int64_t K, int g,
-                              f4v (&acc0)[NC], f4v (&acc1)[NC]) {
-  for (int64_t k0 = 0; k0 < K; k0 += 32) {
-    bf8v a0h, a0l, a1h, a1l, bh[NC], bl[NC];
-    fa0.frag(k0, g, a0h, a0l);
-    fa1.frag(k0, g, a1h, a1l);
-#pragma unroll
-    for (int u = 0; u < NC; ++u) fb[u].frag(k0, g, bh[u], bl[u]);
-    mma3_block<NC>(a0h, a0l, bh, bl, acc0);
-    mma3_block<NC>(a1h, a1l, bh, bl, acc1);
   }
 }

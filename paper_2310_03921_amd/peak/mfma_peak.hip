@@ -19,9 +19,14 @@ __global__ __launch_bounds__(256) void k_peak_f64(int64_t iters, double seed, do
 #pragma unroll
   for (int u = 0; u < kAcc; ++u) acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
   const double a = seed * (1 + (threadIdx.x & 3)), b = seed * (1 + (threadIdx.x >> 6));
-  for (int64_t it = 0; it < iters; ++it) {
+  // iters is a multiple of 16; the 16-fold unrolled body keeps the
+  // accumulators in place across the loop (no copies between iterations)
+  for (int64_t it = 0; it < iters; it += 16) {
 #pragma unroll
-    for (int u = 0; u < kAcc; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+    for (int rep = 0; rep < 16; ++rep)
+#pragma unroll
+      for (int u = 0; u < kAcc; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
   }
   double s = 0.0;
 #pragma unroll
@@ -39,9 +44,12 @@ __global__ __launch_bounds__(256) void k_peak_bf16(int64_t iters, float seed, do
     a[e] = (__bf16)(seed * (e + 1));
     b[e] = (__bf16)(seed * (8 - e));
   }
-  for (int64_t it = 0; it < iters; ++it) {
+  for (int64_t it = 0; it < iters; it += 16) {
 #pragma unroll
-    for (int u = 0; u < kAcc; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[u], 0, 0, 0);
+    for (int rep = 0; rep < 16; ++rep)
+#pragma unroll
+      for (int u = 0; u < kAcc; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[u], 0, 0, 0);
   }
   float s = 0.f;
 #pragma unroll
@@ -55,12 +63,14 @@ extern "C" {
 
 // kind 0: FP64 (v_mfma_f64_16x16x4f64, 2048 flop per wave instruction);
 // kind 1: BF16 (v_mfma_f32_16x16x32_bf16, 16384 flop).  `blocks` workgroups of
-// four waves each run `iters` x 8 products.  Returns the elapsed milliseconds
+// four waves each run `iters` x 8 products (iters a multiple of 16).  Returns the elapsed milliseconds
 // (HIP events on `stream`) and the flops performed.  out: device scratch of
 // blocks * 256 doubles.
 int gap_peak_mfma(void* stream, int kind, int64_t iters, int blocks, double* out, double* ms,
                   double* flops) {
-  if (blocks < 1 || iters < 1 || !out || !ms || !flops || (kind != 0 && kind != 1)) return -1;
+  if (blocks < 1 || iters < 16 || iters % 16 != 0 || !out || !ms || !flops ||
+      (kind != 0 && kind != 1))
+    return -1;
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;

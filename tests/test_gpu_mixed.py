@@ -45,9 +45,15 @@ def setup(gapx, w):
     return b, X, atoms, sp
 
 
-@pytest.mark.parametrize("wname,jdt", [("fit_small_mixed", "f64"), ("fit_small_mixed", "f32"),
-                                       ("ragged", "f64"), ("wide", "f32"), ("wide", "f64")])
-def test_knm_bf16x3(gapx, gap, wname, jdt):
+@pytest.mark.parametrize("wname,jdt,limit", [("fit_small_mixed", "f64", 0),
+                                             ("fit_small_mixed", "f32", 0),
+                                             ("fit_small_mixed", "f32", 1), ("ragged", "f64", 0),
+                                             ("wide", "f32", 0), ("wide", "f64", 0),
+                                             ("wide", "f32", 1), ("wide", "f64", 1)])
+def test_knm_bf16x3(gapx, gap, wname, jdt, limit):
+    # limit = 1: a one-byte cap on the optional workspace, so the Jacobian rows
+    # are split in registers instead of once up front (the other kernel path)
+    gap.set_workspace_limit(limit)
     if wname == "ragged":
         w = synth.Workload("ragged", 31, n_cfg=9, atoms_lo=1, atoms_hi=23, D=37, nb=3, M=23,
                            zeta=3, delta=1.7, precision="bf16x3")
@@ -64,7 +70,8 @@ def test_knm_bf16x3(gapx, gap, wname, jdt):
     ref = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
     e_e = relmax(got[:b.n_cfg], ref[:b.n_cfg])
     e_f = relmax(got[b.n_cfg:], ref[b.n_cfg:])
-    print(f"\n{wname}/{jdt}: K_E rel {e_e:.2e}, K_F rel {e_f:.2e}")
+    print(f"\n{wname}/{jdt}/limit {limit}: K_E rel {e_e:.2e}, K_F rel {e_f:.2e}")
+    gap.set_workspace_limit(0)
     assert e_e <= MIXED_TOL and e_f <= MIXED_TOL
     assert e_f > 0  # the split path really ran (not the FP64 kernels)
 
