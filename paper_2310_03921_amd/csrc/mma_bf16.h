@@ -24,13 +24,27 @@ GAP_DEV f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
 
 GAP_DEV f4v zero4f() { f4v z = {0.f, 0.f, 0.f, 0.f}; return z; }
 
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// Pairs of values are rounded together (one packed conversion, round to
+// nearest even, per pair for hi and per pair for lo); hi is widened back to
+// FP32 by placing its 16 bits at the top of a word, so x - hi is exact.
 GAP_DEV void split8(const float x[8], bf8v& hi, bf8v& lo) {
+  u4v hp, lp;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)x[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(x[e] - (float)h);
+  for (int q = 0; q < 4; ++q) {
+    const f2v v = {x[2 * q], x[2 * q + 1]};
+    const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2v));
+    const float h0 = __builtin_bit_cast(float, hb << 16);
+    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+    const f2v r = {x[2 * q] - h0, x[2 * q + 1] - h1};
+    hp[q] = hb;
+    lp[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf2v));
   }
+  hi = __builtin_bit_cast(bf8v, hp);
+  lo = __builtin_bit_cast(bf8v, lp);
 }
 
 GAP_DEV void zero_split(bf8v& hi, bf8v& lo) {
