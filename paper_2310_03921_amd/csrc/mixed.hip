@@ -397,15 +397,25 @@ __global__ __launch_bounds__(256, 1) void k_force_rows_b3w(
         const int64_t kn = more ? kb0 + (int64_t)(kb + 1) * 32 : kb0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) js.load(rn, a, kn, nx[a]);
+        // X halves one tile ahead of their products, so that each tile's LDS
+        // reads are in flight under the previous tile's nine products
+        const bf8v* xk = xb + (size_t)kb * kNCW * 128;
+        bf8v bh = xk[0], bl = xk[64];
 #pragma unroll
         for (int u = 0; u < kNCW; ++u) {
-          const bf8v bh = xb[(kb * kNCW + u) * 128], bl = xb[(kb * kNCW + u) * 128 + 64];
+          bf8v nh = bh, nl = bl;
+          if (u + 1 < kNCW) {
+            nh = xk[(u + 1) * 128];
+            nl = xk[(u + 1) * 128 + 64];
+          }
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             G[a][u] = mfma_bf16(ah[a], bh, G[a][u]);
             G[a][u] = mfma_bf16(ah[a], bl, G[a][u]);
             G[a][u] = mfma_bf16(al[a], bh, G[a][u]);
           }
+          bh = nh;
+          bl = nl;
         }
       }
 #pragma unroll

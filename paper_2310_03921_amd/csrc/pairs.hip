@@ -11,6 +11,9 @@
 // Targets are also ordered by decreasing in-degree: the force-row kernel
 // processes 16 targets per wavefront, one incoming pair of each per step, and
 // grouping targets of similar degree keeps those steps nearly all useful.
+// Within one degree the order is increasing atom index, so the 16 targets of
+// a wavefront usually come from one or two neighbouring configurations and
+// their incoming pairs' Jacobian rows lie close together in memory.
 #include "common.h"
 #include "launch.h"
 
@@ -132,13 +135,38 @@ __global__ __launch_bounds__(kDegBuckets) void k_degree_offsets(int32_t* __restr
   hist[b] = s[t] - hist[b];
 }
 
-__global__ void k_degree_place(const int64_t* __restrict__ tgt_ptr, int64_t n_atoms,
-                               int32_t* __restrict__ off, int32_t* __restrict__ order) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_atoms;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t d = tgt_ptr[j + 1] - tgt_ptr[j];
-    const int32_t pos = atomicAdd(&off[d < kDegBuckets ? d : kDegBuckets - 1], 1);
-    order[pos] = (int32_t)j;
+// Stable placement: one workgroup, thread b owns degree bucket b and walks the
+// atoms in index order, a chunk of kDegBuckets degrees at a time staged in
+// LDS.  Waves whose 64 buckets are all empty only help with the staging.
+__global__ __launch_bounds__(kDegBuckets) void k_degree_place(const int64_t* __restrict__ tgt_ptr,
+                                                              int64_t n_atoms,
+                                                              const int32_t* __restrict__ off,
+                                                              int32_t* __restrict__ order) {
+  __shared__ int16_t deg[kDegBuckets];
+  const int b = threadIdx.x;
+  int32_t pos = off[b];
+  const int32_t end = b > 0 ? off[b - 1] : (int32_t)n_atoms;  // buckets laid out decreasing
+  const bool busy = __any(pos < end);
+  for (int64_t base = 0; base < n_atoms; base += kDegBuckets) {
+    const int64_t j = base + b;
+    int d = -1;
+    if (j < n_atoms) d = (int)min(tgt_ptr[j + 1] - tgt_ptr[j], (int64_t)kDegBuckets - 1);
+    deg[b] = (int16_t)d;
+    __syncthreads();
+    if (busy) {
+      const int n = (int)min((int64_t)kDegBuckets, n_atoms - base);
+      const int4* d8 = reinterpret_cast<const int4*>(deg);
+      for (int i8 = 0; i8 < (n + 7) / 8; ++i8) {
+        const int4 v = d8[i8];  // eight degrees (entries past n hold -1)
+        const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int dq = (int16_t)(w[q >> 1] >> (16 * (q & 1)));
+          if (dq == b) order[pos++] = (int32_t)(base + 8 * i8 + q);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -191,8 +219,8 @@ void pair_transpose(const int64_t* pair_ptr, const int32_t* pair_j, int64_t n_at
     hipLaunchKernelGGL(k_degree_hist, dim3(grid_for(n_atoms)), dim3(256), 0, st, tgt_ptr, n_atoms,
                        hist);
     hipLaunchKernelGGL(k_degree_offsets, dim3(1), dim3(kDegBuckets), 0, st, hist);
-    hipLaunchKernelGGL(k_degree_place, dim3(grid_for(n_atoms)), dim3(256), 0, st, tgt_ptr, n_atoms,
-                       hist, order);
+    hipLaunchKernelGGL(k_degree_place, dim3(1), dim3(kDegBuckets), 0, st, tgt_ptr, n_atoms, hist,
+                       order);
   }
 }
 
