@@ -278,7 +278,9 @@ class LargeFit:
         self.sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
         max_pairs = max(int(b.pair_ptr[b.cfg_ptr[c1]] - b.pair_ptr[b.cfg_ptr[c0]])
                         for c0, c1 in zip(cuts[:-1], cuts[1:]))
-        self.J = torch.empty(max_pairs, 3, w.D, dtype=torch.float32, device="cuda")
+        # rows padded to 128-byte lines (zero padding, never read)
+        self.J = torch.zeros(max_pairs, 3, self.synth.jacobian_ld(w.D), dtype=torch.float32,
+                             device="cuda")
         self.batches = []
         for c0, c1 in zip(cuts[:-1], cuts[1:]):
             a0, a1 = int(b.cfg_ptr[c0]), int(b.cfg_ptr[c1])

@@ -368,15 +368,21 @@ def device_normal_rows(out, seed: int, tag: int, e0: int, D: int, scale: float):
     return out
 
 
+def jacobian_ld(D: int) -> int:
+    """Row length of the device-drawn Jacobians: D rounded up to 32 FP32 values."""
+    return (D + 31) // 32 * 32
+
+
 def device_jacobians(w: Workload, cfg0: int, cfg1: int, out=None, device="cuda"):
     """Jacobian slots of configurations [cfg0, cfg1) drawn on the device, FP32
-    [n_pairs, 3, ld] (ld = D rounded up to 4; padding zero when ``out`` is new).
+    [n_pairs, 3, ld] (ld = D rounded up to 32, so that every row starts on a
+    128-byte line; padding zero when ``out`` is new).
     Pair p of the whole workload (global numbering) holds elements
     (p * 3 + alpha) * D + d of stream (seed, JAC_TAG), times 0.1."""
     import torch
     gptr = global_atom_offsets(w)
     p0, p1 = int(gptr[cfg0]) * w.nb, int(gptr[cfg1]) * w.nb
-    ld = (w.D + 3) // 4 * 4
+    ld = jacobian_ld(w.D)
     if out is None:
         out = torch.zeros(p1 - p0, 3, ld, dtype=torch.float32, device=device)
     elif out.shape[0] < p1 - p0 or out.shape[1] != 3 or out.shape[2] < w.D or \
