@@ -38,23 +38,33 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0
 
-# HBM traffic of the force-row kernel on the 116k-atom fit, from two rocprofv3
-# --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the same counters read
-# for a device copy of known size; see profiles/force_rows_fp64_fit_fp64_traffic.md.
-# Reported only while the kernel source is the one that was measured.
-FORCE_TRAFFIC = {
-    "workload": "fit_fp64",
-    "sources": ["paper_2310_03921_amd/csrc/force_f64.hip", "paper_2310_03921_amd/csrc/common.h"],
-    "sha256": "c4ca57d49ccc1e5b60388b78087865477b7e9d8639a158de8471a7d77c5b8d7c",
-    "fetch_kib": 51599202, "fetch_scale": 2.000,
-    "write_kib": 18350936, "write_scale": 1.000,
+# HBM traffic of the dominant kernel of each workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) scaled by what the same
+# counters read for a device-to-device copy of known size (FETCH_SIZE x 2.000,
+# WRITE_SIZE x 1.000); see profiles/force_rows_fp64_fit_fp64_traffic.md and
+# profiles/force_rows_b3w_large_mixed_576k_counters.md.  Reported only while
+# the sources that shape the kernel's accesses are the ones that were measured.
+TRAFFIC = {
+    "fit_fp64": {
+        "sources": ['paper_2310_03921_amd/csrc/force_f64.hip', 'paper_2310_03921_amd/csrc/common.h', 'paper_2310_03921_amd/csrc/pairs.hip'],
+        "sha256": "445e006a1883154a42414d7a8b5f84c9b7b6aff105ed5a00a18b893e1906b6ec",
+        "fetch_kib": 38401973, "fetch_scale": 2.000,
+        "write_kib": 17887717, "write_scale": 1.000,
+    },
+    "fit_large_mixed": {
+        "sources": ['paper_2310_03921_amd/csrc/mixed.hip', 'paper_2310_03921_amd/csrc/mma_bf16.h', 'paper_2310_03921_amd/csrc/common.h', 'paper_2310_03921_amd/csrc/pairs.hip'],
+        "sha256": "45a6c7eb912e5e3cf28557b679e8718b5d43912444ded22e7af4669006ae577e",
+        "fetch_kib": 519317379, "fetch_scale": 2.000,
+        "write_kib": 55178355, "write_scale": 1.000,
+    },
 }
 
 
 def force_traffic_bytes(w):
+    """HBM bytes per launch of the workload's force-row kernel, or None."""
     import hashlib
-    t = FORCE_TRAFFIC
-    if w.name != t["workload"]:
+    t = TRAFFIC.get(w.name)
+    if t is None:
         return None
     h = hashlib.sha256()
     try:
@@ -381,6 +391,14 @@ def large_knm_bench(args, torch, synth, gapx):
     (the assembly half of a fit, without folds or refinement)."""
     L = LargeFit(args, torch, synth, gapx)
     gap, M = L.gap, L.w.M
+    # a device-to-device copy of known size (every byte read once and written
+    # once): a counter run of this mode reads the counters' scale off it
+    cal = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    cal_out = torch.empty_like(cal)
+    cal_out.copy_(cal)
+    torch.cuda.synchronize()
+    log(f"calibration copy of {cal.numel() * 8} bytes")
+    del cal, cal_out
 
     def step():
         for bt in L.batches:
@@ -495,7 +513,7 @@ def large_fit_bench(args, torch, synth, gapx):
                      "peak": PEAK_BF16_TFLOPS / 3.0, "unit": "TFLOP/s",
                      "peak_dtype": "bf16x3 (2500 TFLOP/s BF16 dense / 3 products)",
                      "frac": force_flops / (force_ms * 1e-3) / 1e12 / (PEAK_BF16_TFLOPS / 3.0),
-                     "traffic": None, "traffic_unit": "bytes per launch",
+                     "traffic": force_traffic_bytes(w), "traffic_unit": "bytes per launch",
                      "flops_per_launch": force_flops / len(L.batches),
                      "launches_per_fit": len(L.batches),
                      "avg_launch_ms": force_ms / len(L.batches),
