@@ -231,9 +231,11 @@ def test_fit_not_pd_reported(gapx, gap):
     assert e.value.status == gapx.GAP_E_NOT_PD
 
 
+# (600, 320) and (3000, 700) have several 128-wide outer blocks and a partial
+# last one
 @pytest.mark.parametrize("m,n,cond", [(300, 70, 1e2), (1000, 129, 1e2), (777, 200, 1e10),
                                       (64, 64, 1e3), (5000, 17, 10.0), (1500, 333, 1e6),
-                                      (2100, 450, 1e3)])
+                                      (2100, 450, 1e3), (600, 320, 1e3), (3000, 700, 1e8)])
 def test_lstsq_vs_lapack(gapx, gap, m, n, cond):
     rng = np.random.default_rng(m + n)
     U, _ = np.linalg.qr(rng.standard_normal((m, n)))
