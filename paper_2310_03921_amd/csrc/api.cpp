@@ -263,10 +263,10 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
       gapk::gemm_wx_f64(W, ldw, N, M, sp->X, sp->ld_x, D, out, ldo, h->stream);
   };
   if (bf16) {
-    if (need_g) run_split(h, sp, w.split, true);
-    gapk::pstage_b3t(0, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
-                     sp->delta, c, nullptr, W32, ldw, nullptr, 0, at<double>(h, w.epart), nullptr,
-                     h->stream);
+    run_split(h, sp, w.split, need_g);
+    gapk::pstage_b3t(0, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, w.split.xh),
+                     at<__bf16>(h, w.split.xl), M, D, sp->zeta, sp->delta, c, nullptr, W32, ldw,
+                     nullptr, 0, at<double>(h, w.epart), nullptr, h->stream);
     if (ea)
       gapk::sum_parts_f64(at<double>(h, w.epart), gapk::gemm_b3_col_blocks(M), N, ea, 1, N, N,
                           h->stream);
@@ -1350,10 +1350,10 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
     s = ensure_ws(h, L.off);
     if (s != GAP_OK) return s;
     h->timer.begin(gapk::TM_BACKWARD);
-    if (d_desc) run_split(h, sp, sw, true);
-    gapk::pstage_b3t(1, a->desc, f32(a->desc_dt), a->ld_desc, N, sp->X, sp->ld_x, M, D, sp->zeta,
-                     sp->delta, c, g_e, at<float>(h, W32), ldw, at<float>(h, WT32), ldwt, nullptr,
-                     at<double>(h, dcp), h->stream);
+    run_split(h, sp, sw, d_desc != nullptr);
+    gapk::pstage_b3t(1, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, sw.xh),
+                     at<__bf16>(h, sw.xl), M, D, sp->zeta, sp->delta, c, g_e, at<float>(h, W32),
+                     ldw, at<float>(h, WT32), ldwt, nullptr, at<double>(h, dcp), h->stream);
     if (d_c)
       gapk::sum_parts_f64(at<double>(h, dcp), gapk::gemm_b3_row_blocks(N), M, d_c, 1, M, M,
                           h->stream);

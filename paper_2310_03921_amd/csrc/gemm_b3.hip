@@ -4,12 +4,14 @@
 // staged into LDS, products hi*hi + hi*lo + lo*hi on the BF16 matrix cores with
 // FP32 accumulation (see mma_bf16.h).
 //
-// A block computes a 128 x 128 tile of C with four waves (64 x 64 each: four
-// A and four B fragments, sixteen accumulators), over 32-deep k blocks whose
-// split A and B halves are double-buffered in LDS in matrix-core operand
-// order; the next k block is loaded into registers while the current one
-// feeds the matrix cores.  Each fragment read from LDS feeds twelve products,
-// so the LDS traffic stays below its bandwidth.
+// A block computes a 256 x 256 tile of C with eight waves (64 x 128 each: four
+// A and eight B fragments, thirty-two accumulators), over 32-deep k blocks
+// whose split A and B halves are double-buffered in LDS in matrix-core operand
+// order (128 KB); the next k block is loaded into registers while the current
+// one feeds the matrix cores.  A 256-wide tile moves 64 bytes of operands per
+// 768 BF16 flop (12,288 per k block and thread pair), so at the matrix cores'
+// rate the operand stream from L2 stays near 15 TB/s for the whole chip; a
+// 128-wide tile would need twice that.
 //
 // Epilogues:
 //   kPlain   C (FP64, row-major), or a split-K partial C + z * zstride;
@@ -29,10 +31,12 @@ namespace gapk {
 
 namespace {
 
-constexpr int kGT = 128;            // tile rows and columns
+constexpr int kGT = 256;            // tile rows and columns
+constexpr int kGThreads = 512;      // eight waves: 4 (64-row quarters) x 2 (128-column halves)
 constexpr int kGStage = kGT * 32;   // elements of one operand per k block
 constexpr int kGStageV = kGStage / 8 * 2;   // 16-byte LDS entries of one split block
-constexpr int kGLds = 4 * kGStageV * 16;   // dynamic LDS bytes of a block
+constexpr int kGLds = 4 * kGStageV * 16;   // dynamic LDS bytes of a block (128 KB)
+constexpr int kGRowStep = kGThreads / 4;   // rows between a thread's two staged rows
 constexpr int kPlain = 0, kPEnergy = 1, kPBack = 2;
 
 inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -44,8 +48,8 @@ struct SplitRows {
   const __bf16* lo;
 };
 
-// Thread t stages rows (t >> 2) and (t >> 2) + 64, k group 8 (t & 3) .. + 7, of
-// a 128 x 32 operand block: eight values each, split into 16-byte hi / lo
+// Thread t stages rows (t >> 2) and (t >> 2) + 128, k group 8 (t & 3) .. + 7, of
+// a 256 x 32 operand block: eight values each, split into 16-byte hi / lo
 // halves stored at [tile][hi | lo][lane] (lane = row % 16 + 16 group).
 template <typename T>
 GAP_DEV void stage_load(const T* __restrict__ p, int64_t ld, int64_t rows, int64_t K,
@@ -53,7 +57,7 @@ GAP_DEV void stage_load(const T* __restrict__ p, int64_t ld, int64_t rows, int64
   const int t = threadIdx.x, grp = t & 3;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int64_t r = r0 + (t >> 2) + 64 * h;
+    const int64_t r = r0 + (t >> 2) + kGRowStep * h;
     const int64_t k = k0 + 8 * grp;
     const T* row = p + min(r, rows - 1) * ld;
     const float ok = r < rows ? 1.f : 0.f;
@@ -71,7 +75,7 @@ GAP_DEV void stage_store(const float (&v)[2][8], bf8v* __restrict__ dst) {
   const int t = threadIdx.x, grp = t & 3;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int r = (t >> 2) + 64 * h;
+    const int r = (t >> 2) + kGRowStep * h;
     bf8v hi, lo;
     split8(v[h], hi, lo);
     bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
@@ -89,7 +93,7 @@ GAP_DEV void stage_load_split(const SplitRows& s, int64_t ld, int64_t rows, int6
   const int t = threadIdx.x, grp = t & 3;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int64_t r = r0 + (t >> 2) + 64 * h;
+    const int64_t r = r0 + (t >> 2) + kGRowStep * h;
     const int64_t off = min(r, rows - 1) * ld + k0 + 8 * grp;
     v.hi[h] = *reinterpret_cast<const bf8v*>(s.hi + off);
     v.lo[h] = *reinterpret_cast<const bf8v*>(s.lo + off);
@@ -100,7 +104,7 @@ GAP_DEV void stage_store_split(const PreSplit& v, bf8v* __restrict__ dst) {
   const int t = threadIdx.x, grp = t & 3;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int r = (t >> 2) + 64 * h;
+    const int r = (t >> 2) + kGRowStep * h;
     bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
     d[0] = v.hi[h];
     d[64] = v.lo[h];
@@ -133,26 +137,26 @@ struct EpiArgs {
 };
 
 template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__ A, int64_t lda,
                                                     int64_t n_a, TB B, int64_t ldb, int64_t n_b,
                                                     int64_t K, int64_t k_per_z, EpiArgs ep) {
   // split operand blocks, double-buffered: [A | B][buf][8 tiles x (hi | lo) x 64 lanes]
   extern __shared__ bf8v smem[];
   auto sA = [&](int buf) { return smem + buf * kGStageV; };
   auto sB = [&](int buf) { return smem + (2 + buf) * kGStageV; };
-  __shared__ double red[4][64];
+  __shared__ double red[4][kGT];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int wr = wave & 1, wc = wave >> 1;   // 64-row and 64-column half of the tile
+  const int wr = wave & 3, wc = wave >> 2;   // 64-row quarter and 128-column half of the tile
   const int64_t i0 = (int64_t)blockIdx.x * kGT, j0 = (int64_t)blockIdx.y * kGT;
   const int64_t kz0 = (int64_t)blockIdx.z * k_per_z;
   const int64_t kz1 = min(K, kz0 + k_per_z);
   const int nkb = (int)((kz1 - kz0 + 31) / 32);
 
-  f4v acc[4][4];
+  f4v acc[4][8];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = zero4f();
+    for (int b = 0; b < 8; ++b) acc[a][b] = zero4f();
 
   float va[2][8];
   BStage<TB> vb;
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
       load_b(kz0 + (int64_t)(kb + 1) * 32);
     }
     const bf8v* xa = sA(buf) + lane + wr * 4 * 128;
-    const bf8v* xb = sB(buf) + lane + wc * 4 * 128;
+    const bf8v* xb = sB(buf) + lane + wc * 8 * 128;
     bf8v ah[4], al[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
       al[a] = xa[a * 128 + 64];
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 8; ++b) {
       const bf8v bh = xb[b * 128], bl = xb[b * 128 + 64];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
   }
 
   // C[4 g + r][idx] of fragment (a, b): row i0 + 64 wr + 16 a + 4 g + r,
-  // column j0 + 64 wc + 16 b + idx
+  // column j0 + 128 wc + 16 b + idx
   if constexpr (EPI == kPlain) {
     double* C = ep.C + blockIdx.z * ep.zstride;
 #pragma unroll
@@ -218,23 +222,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
         const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
         if (i >= n_a) continue;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int64_t j = j0 + 64 * wc + 16 * b + idx;
+        for (int b = 0; b < 8; ++b) {
+          const int64_t j = j0 + 128 * wc + 16 * b + idx;
           if (j < n_b) C[i * ep.ldc + j] = (double)acc[a][b][r];
         }
       }
   } else {
     const double d2 = ep.delta * ep.delta, d2z = d2 * ep.zeta;
-    double cm[4];
+    double cm[8];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t j = j0 + 64 * wc + 16 * b + idx;
+    for (int b = 0; b < 8; ++b) {
+      const int64_t j = j0 + 128 * wc + 16 * b + idx;
       cm[b] = j < n_b ? ep.c[j] : 0.0;
     }
     double rowsum[4][4];   // kPEnergy: [a][r] partial row sums over this lane's columns
-    double colsum[4];      // kPBack: [b] partial column sums over this lane's rows
+    double colsum[8];      // kPBack: [b] partial column sums over this lane's rows
 #pragma unroll
-    for (int b = 0; b < 4; ++b) colsum[b] = 0.0;
+    for (int b = 0; b < 8; ++b) colsum[b] = 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -244,8 +248,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
         const bool iv = i < n_a;
         const double ge = (EPI == kPBack && iv) ? ep.g_e[i] : 1.0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int64_t j = j0 + 64 * wc + 16 * b + idx;
+        for (int b = 0; b < 8; ++b) {
+          const int64_t j = j0 + 128 * wc + 16 * b + idx;
           const bool jv = j < n_b;
           const double p = acc[a][b][r];
           const double pz1 = ipow(p, ep.zeta - 1);
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) red[wr * 2 + 0][16 * a + 4 * g + r] = rowsum[a][r];
+          for (int r = 0; r < 4; ++r) red[wr][16 * a + 4 * g + r] = rowsum[a][r];
       }
       __syncthreads();
       if (wc == 0 && idx == 0) {
@@ -284,27 +288,29 @@ __global__ __launch_bounds__(256, 2) void k_gemm_b3(const TA* __restrict__ A, in
           for (int r = 0; r < 4; ++r) {
             const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
             if (i < n_a)
-              ep.e_part[blockIdx.y * n_a + i] = rowsum[a][r] + red[wr * 2][16 * a + 4 * g + r];
+              ep.e_part[blockIdx.y * n_a + i] = rowsum[a][r] + red[wr][16 * a + 4 * g + r];
           }
       }
     } else {
       // column sums over the 16 rows of each fragment (lanes g, r), then the
-      // two row halves
+      // four row quarters in a fixed order
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < 8; ++b) {
         colsum[b] += __shfl_xor(colsum[b], 16);
         colsum[b] += __shfl_xor(colsum[b], 32);
       }
-      if (wr == 1 && g == 0) {
+      if (g == 0) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) red[wc][16 * b + idx] = colsum[b];
+        for (int b = 0; b < 8; ++b) red[wr][128 * wc + 16 * b + idx] = colsum[b];
       }
       __syncthreads();
       if (wr == 0 && g == 0) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int64_t j = j0 + 64 * wc + 16 * b + idx;
-          if (j < n_b) ep.dc_part[blockIdx.x * n_b + j] = colsum[b] + red[wc][16 * b + idx];
+        for (int b = 0; b < 8; ++b) {
+          const int sl = 128 * wc + 16 * b + idx;
+          const int64_t j = j0 + sl;
+          if (j < n_b)
+            ep.dc_part[blockIdx.x * n_b + j] = ((red[0][sl] + red[1][sl]) + red[2][sl]) + red[3][sl];
         }
       }
     }
@@ -355,8 +361,8 @@ void launch_gemm(const TA* A, int64_t lda, int64_t n_a, TB B, int64_t ldb, int64
                               hipFuncAttributeMaxDynamicSharedMemorySize, kGLds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_gemm_b3<TA, TB, EPI>), grid, dim3(256), kGLds, st, A, lda, n_a, B, ldb,
-                     n_b, K, kpz, ep);
+  hipLaunchKernelGGL((k_gemm_b3<TA, TB, EPI>), grid, dim3(kGThreads), kGLds, st, A, lda, n_a, B,
+                     ldb, n_b, K, kpz, ep);
 }
 
 }  // namespace
@@ -365,9 +371,9 @@ int64_t gemm_b3_col_blocks(int64_t n_b) { return (n_b + kGT - 1) / kGT; }
 int64_t gemm_b3_row_blocks(int64_t n_a) { return (n_a + kGT - 1) / kGT; }
 
 void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
-                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
-                const double* c, const double* g_e, float* W, int64_t ldw, float* WT,
-                int64_t ldwt, double* e_part, double* dc_part, hipStream_t st) {
+                const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
+                double delta, const double* c, const double* g_e, float* W, int64_t ldw,
+                float* WT, int64_t ldwt, double* e_part, double* dc_part, hipStream_t st) {
   if (n <= 0 || M <= 0) return;
   EpiArgs ep{};
   ep.zeta = zeta;
@@ -380,20 +386,23 @@ void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
   ep.ldwt = ldwt;
   ep.e_part = e_part;
   ep.dc_part = dc_part;
+  // X is taken pre-split (rows [M][split_ld(D)], hi and lo halves)
+  const SplitRows xs{Xh, Xl};
+  const int64_t ldp = split_ld(D);
   if (mode == 0) {
     if (desc_f32)
-      launch_gemm<float, const double*, kPEnergy>(static_cast<const float*>(desc), ldd, n, X, ldx,
-                                                  M, D, 1, ep, st);
+      launch_gemm<float, SplitRows, kPEnergy>(static_cast<const float*>(desc), ldd, n, xs, ldp, M,
+                                              D, 1, ep, st);
     else
-      launch_gemm<double, const double*, kPEnergy>(static_cast<const double*>(desc), ldd, n, X,
-                                                   ldx, M, D, 1, ep, st);
+      launch_gemm<double, SplitRows, kPEnergy>(static_cast<const double*>(desc), ldd, n, xs, ldp,
+                                               M, D, 1, ep, st);
   } else {
     if (desc_f32)
-      launch_gemm<float, const double*, kPBack>(static_cast<const float*>(desc), ldd, n, X, ldx,
-                                                M, D, 1, ep, st);
+      launch_gemm<float, SplitRows, kPBack>(static_cast<const float*>(desc), ldd, n, xs, ldp, M,
+                                            D, 1, ep, st);
     else
-      launch_gemm<double, const double*, kPBack>(static_cast<const double*>(desc), ldd, n, X,
-                                                 ldx, M, D, 1, ep, st);
+      launch_gemm<double, SplitRows, kPBack>(static_cast<const double*>(desc), ldd, n, xs, ldp,
+                                             M, D, 1, ep, st);
   }
 }
 

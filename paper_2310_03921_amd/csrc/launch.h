@@ -217,10 +217,11 @@ int64_t gemm_b3_col_blocks(int64_t n_b);
 int64_t gemm_b3_row_blocks(int64_t n_a);
 // P-stage: mode 0 e_part[cb][i] (cb < gemm_b3_col_blocks(M)) and W (FP32 [n][ldw]);
 // mode 1 dc_part[rb][m] (rb < gemm_b3_row_blocks(n)), W and WT (FP32 [M][ldwt]).
+// X comes split (split_x_bf16's row halves, [M][split_ld(D)]).
 void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
-                const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
-                const double* c, const double* g_e, float* W, int64_t ldw, float* WT,
-                int64_t ldwt, double* e_part, double* dc_part, hipStream_t st);
+                const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
+                double delta, const double* c, const double* g_e, float* W, int64_t ldw,
+                float* WT, int64_t ldwt, double* e_part, double* dc_part, hipStream_t st);
 // out[i][d] = sum_m W[i][m] X[m][d] from FP32 W and the split transposed X halves.
 void gemm_b3_wx(const float* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
                 const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st);
