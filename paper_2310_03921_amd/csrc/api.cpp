@@ -266,7 +266,7 @@ void run_predict(gap_handle* h, const gap_atoms* a, const gap_sparse* sp, const 
     run_split(h, sp, w.split, need_g);
     gapk::pstage_b3t(0, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, w.split.xh),
                      at<__bf16>(h, w.split.xl), M, D, sp->zeta, sp->delta, c, nullptr, W32, ldw,
-                     nullptr, 0, at<double>(h, w.epart), nullptr, h->stream);
+                     at<double>(h, w.epart), nullptr, h->stream);
     if (ea)
       gapk::sum_parts_f64(at<double>(h, w.epart), gapk::gemm_b3_col_blocks(M), N, ea, 1, N, N,
                           h->stream);
@@ -1335,12 +1335,10 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
   const bool needW = d_desc || d_X;
   const int64_t ldw = ld4(M);
   if (bf) {
-    // tiled BF16X3 path: FP32 W and W^T from the P-stage, then W X and W^T D
-    const int64_t ldwt = ld4(N);
+    // tiled BF16X3 path: FP32 W from the P-stage, then W X and W^T D (W and the
+    // descriptors read as column views)
     const size_t W32 = L.take(sizeof(float) * std::max<int64_t>(N * ldw, 1));
-    const size_t WT32 = L.take(sizeof(float) * std::max<int64_t>(M * ldwt, 1));
     const size_t dcp = L.take(sizeof(double) * (gapk::gemm_b3_row_blocks(N) * M + 8));
-    const size_t DT = d_X ? L.take(sizeof(float) * std::max<int64_t>(D * ldwt, 1)) : 0;
     const int64_t base = gapk::gemm_b3_col_blocks(M) * gapk::gemm_b3_col_blocks(D);
     const int nz = (int)std::max<int64_t>(
         1, std::min<int64_t>({32, (2048 + base - 1) / base, std::max<int64_t>(N / 512, 1)}));
@@ -1353,19 +1351,16 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
     run_split(h, sp, sw, d_desc != nullptr);
     gapk::pstage_b3t(1, a->desc, f32(a->desc_dt), a->ld_desc, N, at<__bf16>(h, sw.xh),
                      at<__bf16>(h, sw.xl), M, D, sp->zeta, sp->delta, c, g_e, at<float>(h, W32),
-                     ldw, at<float>(h, WT32), ldwt, nullptr, at<double>(h, dcp), h->stream);
+                     ldw, nullptr, at<double>(h, dcp), h->stream);
     if (d_c)
       gapk::sum_parts_f64(at<double>(h, dcp), gapk::gemm_b3_row_blocks(N), M, d_c, 1, M, M,
                           h->stream);
     if (d_desc)
       gapk::gemm_b3_wx(at<float>(h, W32), ldw, N, M, at<__bf16>(h, sw.xth),
                        at<__bf16>(h, sw.xtl), D, d_desc, D, h->stream);
-    if (d_X) {
-      gapk::transpose_f32(a->desc, f32(a->desc_dt), a->ld_desc, N, D, at<float>(h, DT), ldwt,
-                          h->stream);
-      gapk::gemm_b3_wtd(at<float>(h, WT32), ldwt, M, N, at<float>(h, DT), ldwt, D,
+    if (d_X)
+      gapk::gemm_b3_wtd(at<float>(h, W32), ldw, M, N, a->desc, f32(a->desc_dt), a->ld_desc, D,
                         at<double>(h, part), nz, d_X, D, h->stream);
-    }
     h->timer.end(gapk::TM_BACKWARD);
     HIP_TRY(h, hipGetLastError());
     return GAP_OK;

@@ -19,8 +19,10 @@
 //            block's columns of c_m k(p_im), W[i][m] = delta^2 zeta c_m p^(zeta-1)
 //            (FP32, the forward W, whose product with X is the descriptor gradient);
 //   kPBack   P-stage of the backward: dc_part[x][m] = sum over the block's rows of
-//            g_e[i] k(p_im), W[i][m] = g_e[i] delta^2 zeta c_m p^(zeta-1) and its
-//            transpose WT[m][i] (FP32).
+//            g_e[i] k(p_im), W[i][m] = g_e[i] delta^2 zeta c_m p^(zeta-1) (FP32).
+// An operand may also be a column view (ColOp: element (r, k) at p[k ld + r]),
+// which the backward's d_X = W^T D uses for both W and the descriptors, so that
+// neither is transposed in memory.
 #include <algorithm>
 #include <type_traits>
 
@@ -111,6 +113,55 @@ GAP_DEV void stage_store_split(const PreSplit& v, bf8v* __restrict__ dst) {
   }
 }
 
+// Column view of a row-major matrix: element (r, k) at p[k * ld + r].  Thread t
+// stages rows (t & 127) + 128 h and k group 8 (t >> 7) .. + 7, one load per k,
+// so that for a given k a wave's lanes read 64 consecutive r (whole 256-byte
+// runs for FP32); stage_store_col writes them to the same LDS places as
+// stage_store.  Out-of-range r and k read a clamped valid element and are
+// zeroed.
+template <typename T>
+struct ColOp {
+  const T* p;
+};
+template <typename T>
+GAP_DEV void stage_load_col(const ColOp<T>& op, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                            int64_t k0, float (&v)[2][8]) {
+  const int t = threadIdx.x, grp = t >> 7;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = r0 + (t & 127) + kGRowStep * h;
+    const int64_t rc = min(r, rows - 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + 8 * grp + e;
+      const float ok = (r < rows && k < K) ? 1.f : 0.f;
+      v[h][e] = (float)op.p[min(k, K - 1) * ld + rc] * ok;
+    }
+  }
+}
+
+GAP_DEV void stage_store_col(const float (&v)[2][8], bf8v* __restrict__ dst) {
+  const int t = threadIdx.x, grp = t >> 7;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = (t & 127) + kGRowStep * h;
+    bf8v hi, lo;
+    split8(v[h], hi, lo);
+    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+    d[0] = hi;
+    d[64] = lo;
+  }
+}
+
+template <typename T>
+struct IsCol {
+  static constexpr bool value = false;
+};
+template <typename T>
+struct IsCol<ColOp<T>> {
+  static constexpr bool value = true;
+};
+
 template <typename TB>
 struct BStage {
   float v[2][8];
@@ -119,6 +170,16 @@ template <>
 struct BStage<SplitRows> {
   PreSplit v;
 };
+template <typename T>
+GAP_DEV void stage_load_any(const T* p, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                            int64_t k0, float (&v)[2][8]) {
+  stage_load(p, ld, rows, K, r0, k0, v);
+}
+template <typename T>
+GAP_DEV void stage_load_any(const ColOp<T>& op, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                            int64_t k0, float (&v)[2][8]) {
+  stage_load_col(op, ld, rows, K, r0, k0, v);
+}
 
 struct EpiArgs {
   int zeta;
@@ -127,8 +188,6 @@ struct EpiArgs {
   const double* g_e;    // [n_a] upstream gradient (backward P-stage)
   float* W;             // [n_a][ldw]
   int64_t ldw;
-  float* WT;            // [n_b][ldwt] (backward)
-  int64_t ldwt;
   double* e_part;       // [gridDim.y][n_a]
   double* dc_part;      // [gridDim.x][n_b]
   double* C;            // plain: [n_a][ldc] (+ z * zstride)
@@ -137,9 +196,9 @@ struct EpiArgs {
 };
 
 template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__ A, int64_t lda,
-                                                    int64_t n_a, TB B, int64_t ldb, int64_t n_b,
-                                                    int64_t K, int64_t k_per_z, EpiArgs ep) {
+__global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int64_t n_a, TB B,
+                                                          int64_t ldb, int64_t n_b, int64_t K,
+                                                          int64_t k_per_z, EpiArgs ep) {
   // split operand blocks, double-buffered: [A | B][buf][8 tiles x (hi | lo) x 64 lanes]
   extern __shared__ bf8v smem[];
   auto sA = [&](int buf) { return smem + buf * kGStageV; };
@@ -164,18 +223,26 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__
     if constexpr (std::is_same<TB, SplitRows>::value)
       stage_load_split(B, ldb, n_b, j0, k0, vb.v);
     else
-      stage_load(B, ldb, n_b, kz1, j0, k0, vb.v);
+      stage_load_any(B, ldb, n_b, kz1, j0, k0, vb.v);
   };
   auto store_b = [&](int buf) {
     if constexpr (std::is_same<TB, SplitRows>::value)
       stage_store_split(vb.v, sB(buf));
+    else if constexpr (IsCol<TB>::value)
+      stage_store_col(vb.v, sB(buf));
     else
       stage_store(vb.v, sB(buf));
   };
+  auto store_a = [&](int buf) {
+    if constexpr (IsCol<TA>::value)
+      stage_store_col(va, sA(buf));
+    else
+      stage_store(va, sA(buf));
+  };
   if (nkb > 0) {
-    stage_load(A, lda, n_a, kz1, i0, kz0, va);
+    stage_load_any(A, lda, n_a, kz1, i0, kz0, va);
     load_b(kz0);
-    stage_store(va, sA(0));
+    store_a(0);
     store_b(0);
   }
   __syncthreads();
@@ -183,7 +250,7 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__
     const int buf = kb & 1;
     const bool more = kb + 1 < nkb;
     if (more) {
-      stage_load(A, lda, n_a, kz1, i0, kz0 + (int64_t)(kb + 1) * 32, va);
+      stage_load_any(A, lda, n_a, kz1, i0, kz0 + (int64_t)(kb + 1) * 32, va);
       load_b(kz0 + (int64_t)(kb + 1) * 32);
     }
     const bf8v* xa = sA(buf) + lane + wr * 4 * 128;
@@ -205,7 +272,7 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__
       }
     }
     if (more) {
-      stage_store(va, sA(buf ^ 1));
+      store_a(buf ^ 1);
       store_b(buf ^ 1);
     }
     __syncthreads();
@@ -259,7 +326,6 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__
             if (EPI == kPEnergy) rowsum[a][r] += cm[b] * kv;
             if (EPI == kPBack) colsum[b] += ge * kv;
             ep.W[i * ep.ldw + j] = (float)w;
-            if (EPI == kPBack) ep.WT[j * ep.ldwt + i] = (float)w;
           }
         }
       }
@@ -317,26 +383,6 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(const TA* __restrict__
   }
 }
 
-// dst[k][i] = src[i][k] as FP32 (K-contiguous rows of the transpose), 32 x 32
-// tiles through LDS; columns i >= n of the padded rows are written zero.
-template <typename T>
-__global__ __launch_bounds__(256) void k_transpose_f32(const T* __restrict__ src, int64_t lds,
-                                                       int64_t n, int64_t K,
-                                                       float* __restrict__ dst, int64_t ldd) {
-  __shared__ float t[32][33];
-  const int64_t i0 = (int64_t)blockIdx.x * 32, k0 = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows per pass
-  for (int y = ty; y < 32; y += 8) {
-    const int64_t i = i0 + y, k = k0 + tx;
-    t[y][tx] = (i < n && k < K) ? (float)src[i * lds + k] : 0.f;
-  }
-  __syncthreads();
-  for (int y = ty; y < 32; y += 8) {
-    const int64_t k = k0 + y, i = i0 + tx;
-    if (k < K && i < ldd) dst[k * ldd + i] = t[tx][y];
-  }
-}
-
 // out[j] = sum over z of part[z][j] (fixed order)
 __global__ void k_sum_parts(const double* __restrict__ part, int64_t nz, int64_t n,
                             int64_t stride, double* __restrict__ out, int64_t rows,
@@ -351,7 +397,7 @@ __global__ void k_sum_parts(const double* __restrict__ part, int64_t nz, int64_t
 }
 
 template <typename TA, typename TB, int EPI>
-void launch_gemm(const TA* A, int64_t lda, int64_t n_a, TB B, int64_t ldb, int64_t n_b, int64_t K,
+void launch_gemm(TA A, int64_t lda, int64_t n_a, TB B, int64_t ldb, int64_t n_b, int64_t K,
                  int nz, const EpiArgs& ep, hipStream_t st) {
   const int64_t kpz = ((K + nz - 1) / nz + 31) / 32 * 32;
   const dim3 grid(cdiv_u(n_a, kGT), cdiv_u(n_b, kGT), (unsigned)cdiv_u(K, kpz));
@@ -373,7 +419,7 @@ int64_t gemm_b3_row_blocks(int64_t n_a) { return (n_a + kGT - 1) / kGT; }
 void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
                 double delta, const double* c, const double* g_e, float* W, int64_t ldw,
-                float* WT, int64_t ldwt, double* e_part, double* dc_part, hipStream_t st) {
+                double* e_part, double* dc_part, hipStream_t st) {
   if (n <= 0 || M <= 0) return;
   EpiArgs ep{};
   ep.zeta = zeta;
@@ -382,8 +428,6 @@ void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
   ep.g_e = g_e;
   ep.W = W;
   ep.ldw = ldw;
-  ep.WT = WT;
-  ep.ldwt = ldwt;
   ep.e_part = e_part;
   ep.dc_part = dc_part;
   // X is taken pre-split (rows [M][split_ld(D)], hi and lo halves)
@@ -391,18 +435,18 @@ void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
   const int64_t ldp = split_ld(D);
   if (mode == 0) {
     if (desc_f32)
-      launch_gemm<float, SplitRows, kPEnergy>(static_cast<const float*>(desc), ldd, n, xs, ldp, M,
-                                              D, 1, ep, st);
+      launch_gemm<const float*, SplitRows, kPEnergy>(static_cast<const float*>(desc), ldd, n, xs,
+                                                     ldp, M, D, 1, ep, st);
     else
-      launch_gemm<double, SplitRows, kPEnergy>(static_cast<const double*>(desc), ldd, n, xs, ldp,
-                                               M, D, 1, ep, st);
+      launch_gemm<const double*, SplitRows, kPEnergy>(static_cast<const double*>(desc), ldd, n,
+                                                      xs, ldp, M, D, 1, ep, st);
   } else {
     if (desc_f32)
-      launch_gemm<float, SplitRows, kPBack>(static_cast<const float*>(desc), ldd, n, xs, ldp, M,
-                                            D, 1, ep, st);
+      launch_gemm<const float*, SplitRows, kPBack>(static_cast<const float*>(desc), ldd, n, xs,
+                                                   ldp, M, D, 1, ep, st);
     else
-      launch_gemm<double, SplitRows, kPBack>(static_cast<const double*>(desc), ldd, n, xs, ldp,
-                                             M, D, 1, ep, st);
+      launch_gemm<const double*, SplitRows, kPBack>(static_cast<const double*>(desc), ldd, n, xs,
+                                                    ldp, M, D, 1, ep, st);
   }
 }
 
@@ -412,19 +456,27 @@ void gemm_b3_wx(const float* W, int64_t ldw, int64_t n, int64_t M, const __bf16*
   EpiArgs ep{};
   ep.C = out;
   ep.ldc = ldo;
-  launch_gemm<float, SplitRows, kPlain>(W, ldw, n, SplitRows{Xth, Xtl}, split_ld(M), D, M, 1, ep,
-                                        st);
+  launch_gemm<const float*, SplitRows, kPlain>(W, ldw, n, SplitRows{Xth, Xtl}, split_ld(M), D, M,
+                                               1, ep, st);
 }
 
-void gemm_b3_wtd(const float* WT, int64_t ldwt, int64_t M, int64_t n, const float* DT,
-                 int64_t lddt, int64_t D, double* part, int nz, double* out, int64_t ldo,
-                 hipStream_t st) {
+void gemm_b3_wtd(const float* W, int64_t ldw, int64_t M, int64_t n, const void* desc,
+                 bool desc_f32, int64_t ldd, int64_t D, double* part, int nz, double* out,
+                 int64_t ldo, hipStream_t st) {
   if (M <= 0 || D <= 0) return;
   EpiArgs ep{};
   ep.C = part;
   ep.ldc = D;
   ep.zstride = M * D;
-  launch_gemm<float, const float*, kPlain>(WT, ldwt, M, DT, lddt, D, n, nz, ep, st);
+  // out[m][d] = sum_i W[i][m] desc[i][d]: both operands are column views (k = i)
+  if (desc_f32)
+    launch_gemm<ColOp<float>, ColOp<float>, kPlain>(ColOp<float>{W}, ldw, M,
+                                                    ColOp<float>{static_cast<const float*>(desc)},
+                                                    ldd, D, n, nz, ep, st);
+  else
+    launch_gemm<ColOp<float>, ColOp<double>, kPlain>(
+        ColOp<float>{W}, ldw, M, ColOp<double>{static_cast<const double*>(desc)}, ldd, D, n, nz, ep,
+        st);
   const unsigned g = std::max(1u, std::min(cdiv_u(M * D, 256), 65536u));
   hipLaunchKernelGGL(k_sum_parts, dim3(g), dim3(256), 0, st, part, (int64_t)nz, M * D, M * D, out,
                      M, ldo, D);
@@ -436,18 +488,6 @@ void sum_parts_f64(const double* part, int64_t nz, int64_t stride, double* out, 
   const unsigned g = std::max(1u, std::min(cdiv_u(rows * cols, 256), 65536u));
   hipLaunchKernelGGL(k_sum_parts, dim3(g), dim3(256), 0, st, part, nz, rows * cols, stride, out,
                      rows, ldo, cols);
-}
-
-void transpose_f32(const void* src, bool src_f32, int64_t lds, int64_t n, int64_t K, float* dst,
-                   int64_t ldd, hipStream_t st) {
-  if (n <= 0 || K <= 0) return;
-  const dim3 grid(cdiv_u(std::max(n, ldd), 32), cdiv_u(K, 32));
-  if (src_f32)
-    hipLaunchKernelGGL(k_transpose_f32<float>, grid, dim3(256), 0, st,
-                       static_cast<const float*>(src), lds, n, K, dst, ldd);
-  else
-    hipLaunchKernelGGL(k_transpose_f32<double>, grid, dim3(256), 0, st,
-                       static_cast<const double*>(src), lds, n, K, dst, ldd);
 }
 
 }  // namespace gapk

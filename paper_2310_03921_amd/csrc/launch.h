@@ -216,25 +216,23 @@ bool force_rows_bf16x3_split(const __bf16* Jh, const __bf16* Jl, int64_t D, cons
 int64_t gemm_b3_col_blocks(int64_t n_b);
 int64_t gemm_b3_row_blocks(int64_t n_a);
 // P-stage: mode 0 e_part[cb][i] (cb < gemm_b3_col_blocks(M)) and W (FP32 [n][ldw]);
-// mode 1 dc_part[rb][m] (rb < gemm_b3_row_blocks(n)), W and WT (FP32 [M][ldwt]).
+// mode 1 dc_part[rb][m] (rb < gemm_b3_row_blocks(n)) and W.
 // X comes split (split_x_bf16's row halves, [M][split_ld(D)]).
 void pstage_b3t(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const __bf16* Xh, const __bf16* Xl, int64_t M, int64_t D, int zeta,
                 double delta, const double* c, const double* g_e, float* W, int64_t ldw,
-                float* WT, int64_t ldwt, double* e_part, double* dc_part, hipStream_t st);
+                double* e_part, double* dc_part, hipStream_t st);
 // out[i][d] = sum_m W[i][m] X[m][d] from FP32 W and the split transposed X halves.
 void gemm_b3_wx(const float* W, int64_t ldw, int64_t n, int64_t M, const __bf16* Xth,
                 const __bf16* Xtl, int64_t D, double* out, int64_t ldo, hipStream_t st);
-// out[m][d] = sum_i WT[m][i] DT[d][i] with nz split-K partials in part [nz][M][D].
-void gemm_b3_wtd(const float* WT, int64_t ldwt, int64_t M, int64_t n, const float* DT,
-                 int64_t lddt, int64_t D, double* part, int nz, double* out, int64_t ldo,
-                 hipStream_t st);
+// out[m][d] = sum_i W[i][m] desc[i][d] (W FP32 [n][ldw]) with nz split-K partials
+// in part [nz][M][D].
+void gemm_b3_wtd(const float* W, int64_t ldw, int64_t M, int64_t n, const void* desc,
+                 bool desc_f32, int64_t ldd, int64_t D, double* part, int nz, double* out,
+                 int64_t ldo, hipStream_t st);
 // out[i][j] = sum_z part[z * stride + i * cols + j].
 void sum_parts_f64(const double* part, int64_t nz, int64_t stride, double* out, int64_t rows,
                    int64_t ldo, int64_t cols, hipStream_t st);
-// dst[k][i] = src[i][k] (FP32), K rows of length ldd (columns n .. ldd - 1 zero).
-void transpose_f32(const void* src, bool src_f32, int64_t lds, int64_t n, int64_t K, float* dst,
-                   int64_t ldd, hipStream_t st);
 // ---- linalg.hip -----------------------------------------------------------
 // A[r][0:M] *= 1/sigma_r, A[r][M] = y_r/sigma_r for r < n_rows.
 void scale_rows(double* A, int64_t ld, int64_t n_rows, int64_t M, const double* y,
