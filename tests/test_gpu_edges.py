@@ -105,3 +105,31 @@ def test_host_checks_refuse_bad_calls(gapx, gap):
     ref = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
     got = K[:w.M, :b.n_rows].T.cpu().numpy()
     assert np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+
+
+def test_fp32_rows_at_an_odd_offset(gapx, gap):
+    # FP32 descriptors and Jacobians with D = 252 (rows of 1008 bytes, 16 mod
+    # 32): a configuration range starting at an odd atom, and a row slice
+    # through the differentiable energy, must reach the ABI as aligned copies
+    # and give the oracle's values
+    w = synth.Workload("odd32", 61, n_cfg=6, atoms_lo=3, atoms_hi=9, D=252, nb=3, M=17,
+                       jac_dtype="f32", desc_dtype="f32")
+    b = synth.generate(w)
+    X = synth.sparse_points(w, b)
+    atoms = gapx.Atoms.from_host(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac)
+    c0 = next(k for k in range(1, b.n_cfg) if b.cfg_ptr[k] % 2 == 1)
+    sub = atoms.configs(c0, b.n_cfg)
+    sp = gapx.Sparse.from_host(X, w.zeta, w.delta)
+    K = gap.build_knm(sub, sp)[:w.M, :sub.n_rows].T.cpu().numpy()
+    a0, a1 = int(b.cfg_ptr[c0]), int(b.cfg_ptr[-1])
+    p0, p1 = int(b.pair_ptr[a0]), int(b.pair_ptr[a1])
+    ref = oracle.build_knm(b.cfg_ptr[c0:] - a0, b.desc[a0:a1], b.pair_ptr[a0:a1 + 1] - p0,
+                           b.pair_j[p0:p1] - a0, b.jac[p0:p1], X, w.zeta, w.delta)
+    assert np.abs(K - ref).max() <= TOL * np.abs(ref).max()
+    desc = torch.tensor(b.desc, dtype=torch.float32, device="cuda")[1:]
+    Xd = torch.tensor(X, device="cuda")
+    c = torch.tensor(np.random.default_rng(3).standard_normal(w.M), device="cuda")
+    e = gapx.gap_energy(desc, Xd, c, w.zeta, w.delta).cpu().numpy()
+    e_ref = oracle.predict([0, b.n_atoms - 1], b.desc[1:], np.zeros(b.n_atoms, np.int64),
+                           np.zeros(0, np.int32), None, X, c.cpu().numpy(), w.zeta, w.delta)[0]
+    assert np.abs(e - e_ref).max() <= TOL * np.abs(e_ref).max()
