@@ -264,8 +264,11 @@ class LargeFit:
       K_MM -> fold state [U 0; 0 0] -> per batch: Jacobians, BF16X3 rows (pair
       transpose, split, energy rows + S, force rows) into the state's block
       area, fold (Householder QR of [T; block]) -> back substitution ->
-      ``refine`` steps, each a pass of exact FP64 residual rows (Jacobians drawn
-      again) and a seminormal correction.
+      up to ``refine`` steps, each a pass of exact FP64 residual rows
+      (Jacobians drawn again) and a seminormal correction.  The steps stop
+      once the error they leave is predicted below ``refine_tol`` (relative to
+      c): each step contracts the error by about the same factor, estimated as
+      |dc_k| / |dc_k-1|, so the error after step k is about |dc_k|^2 / |dc_k-1|.
     Descriptors, pair lists and targets stay resident between fits."""
 
     def __init__(self, args, torch, synth, gapx):
@@ -274,6 +277,8 @@ class LargeFit:
         self.w = w
         n_cfg = min(w.n_cfg, args.large_cfgs) if args.large_cfgs > 0 else w.n_cfg
         self.refine = args.refine_steps
+        self.refine_tol = args.refine_tol
+        self.steps_taken = []
         t0 = time.perf_counter()
         log(f"large fit: generating descriptors and neighbour lists of {n_cfg} configurations "
             f"on the host")
@@ -364,9 +369,20 @@ class LargeFit:
         if self.refine > 0:
             for bt in self.batches:
                 gap.refine_weights(bt["atoms"], sp, out=bt["S"])
+        prev, taken = None, 0
+        self.step_norms = []
         for _ in range(self.refine):
             g = self.residual_pass(c)
-            gap.refine_solve(T, M, self.Kmm, w.jitter, g, c)
+            gap.refine_solve(T, M, self.Kmm, w.jitter, g, c)   # g holds the step dc
+            taken += 1
+            ng, nc = self.torch.stack([self.torch.linalg.vector_norm(g),
+                                       self.torch.linalg.vector_norm(c)]).tolist()
+            step = ng / max(nc, 1e-300)
+            self.step_norms.append(step)
+            if step == 0.0 or (prev is not None and step * step / prev <= self.refine_tol):
+                break
+            prev = step
+        self.steps_taken.append(taken)
         return (c, lsq, rd, fro2) if norms else c
 
     def residual_pass(self, c, rr=None):
@@ -388,8 +404,9 @@ class LargeFit:
                 f"({self.n_atoms} atoms, {self.n_pairs} pairs, {self.n_rows} observation rows), "
                 f"D={w.D}, {w.nb} neighbours/atom, M={w.M}, zeta={w.zeta}, FP32 descriptors and "
                 f"Jacobians (Jacobians drawn on the device each pass), BF16X3 rows folded in "
-                f"{len(self.batches)} batches into an FP64 Householder QR, {self.refine} FP64 "
-                f"refinement steps")
+                f"{len(self.batches)} batches into an FP64 Householder QR, up to {self.refine} "
+                f"FP64 refinement steps (stopping once the predicted error of c is below "
+                f"{self.refine_tol:g})")
 
 
 def large_knm_bench(args, torch, synth, gapx):
@@ -455,6 +472,7 @@ def large_fit_bench(args, torch, synth, gapx):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     times = []
+    n_warm = len(L.steps_taken)
     e0.record()
     for i in range(args.steps):
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -475,6 +493,7 @@ def large_fit_bench(args, torch, synth, gapx):
     assert torch.isfinite(c).all().item(), "non-finite coefficients"
     # accuracy report outside the timed region: one more fit with the block norms,
     # and a final pass for r and A^T r of the exact FP64 system
+    timed_steps = L.steps_taken[n_warm:n_warm + args.steps]
     c, lsq, rd, fro2_obs = L.fit(norms=True)
     if L.refine == 0:
         for bt in L.batches:
@@ -511,6 +530,9 @@ def large_fit_bench(args, torch, synth, gapx):
         "knm_gflops_algorithmic": knm_flops / (knm_ms * 1e-3) / 1e9 if knm_ms > 0 else None,
         "qr_ms": qr_ms, "qr_tflops": qr_flops / (qr_ms * 1e-3) / 1e12 if qr_ms > 0 else None,
         "refinement_ms": per.get("refinement", 0.0),
+        "refinement_steps_per_fit": timed_steps,
+        "refinement_step_norms": L.step_norms,    # |dc| / |c| of each step (report fit)
+        "refinement_tol": L.refine_tol,
         "stage_ms": {k: round(v, 1) for k, v in per.items()},
         # algorithmic flops (6 M D per pair) against the peak of the BF16X3 form:
         # three BF16 matrix-core products per multiply-add, so a third of the
@@ -558,7 +580,11 @@ def main():
                          "memory, minutes of CPU time) instead of a sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--refine-steps", type=int, default=3)
+    ap.add_argument("--refine-steps", type=int, default=3,
+                    help="most FP64 refinement steps of a mixed fit")
+    ap.add_argument("--refine-tol", type=float, default=1e-14,
+                    help="the 576k-atom fit stops refining once the error left in c is "
+                         "predicted below this (relative)")
     ap.add_argument("--no-virial", action="store_true",
                     help="skip timing the virial, two-body, variance and CUR legs")
     ap.add_argument("--no-predict", action="store_true",
