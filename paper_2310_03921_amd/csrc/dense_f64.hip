@@ -441,19 +441,7 @@ __global__ __launch_bounds__(256) void k_gemm_wx_cs(const double* __restrict__ W
   }
 }
 
-// out = (W diag(cs)) X (CS false: no scaling, cs unused).  A block of eight
-// waves covers 64 rows and a group of 256 columns (blockIdx.y): wave w takes
-// rows 16 (w / 2) .. + 15 and the 8 column tiles of half w % 2.  The
-// contraction runs over 32-wide chunks of k; the block stages chunk c of
-// diag(cs) X in LDS (double-buffered, one barrier per chunk), already in the
-// order the matrix core consumes it, while each wave reads its W rows straight
-// from memory.  The next chunk's loads are issued before
-// the current chunk's matrix work.  Loads in the loop are unconditional: rows
-// past n and k past ldw - 4 are clamped to valid addresses, and the staged X
-// is zero for k >= M, so W's row padding (columns M .. ldw - 1) only needs to
-// be finite; every producer in this library writes it as zero.  Each output
-// element is one sum in a fixed order.
-typedef unsigned wx_u32x2 __attribute__((ext_vector_type(2)));
+// Raw buffer resources for the staged loads of the W X and P-stage kernels.
 GAP_DEV __amdgpu_buffer_rsrc_t wx_rsrc(const double* p, uint32_t bytes) {
   const uint64_t x = reinterpret_cast<uint64_t>(p);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
@@ -466,66 +454,69 @@ GAP_DEV __amdgpu_buffer_rsrc_t wx_rsrc(const double* p, uint32_t bytes) {
 GAP_DEV double wx_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-constexpr int kSxW = 8;    // waves per block
-constexpr int kSxKC = 32;  // k per chunk
-constexpr int kSxSub = 16 * 256;  // doubles per 16-k sub-chunk: 16 tiles x [2 halves][64 lanes][2]
-constexpr int kSxPer = kSxKC * 256 / (64 * kSxW);  // staged elements per thread
+
+// out = (W diag(cs)) X (CS false: cs unused) with four-wave blocks, three of
+// them per compute unit: a block covers 64 rows and 128 columns (wave w: rows
+// 16 w .. + 15, eight column tiles), the contraction runs over 16-wide chunks
+// of k staged in LDS (16 KB per buffer, double-buffered), and the three
+// blocks on a compute unit are not held in step by one barrier, so each
+// block's staging and barrier wait are covered by the others' products.
+// Within a chunk, lane group g holds W[row][kc + 4 g + q] (one 32-byte load)
+// and product q takes k = kc + 4 g + q, so the staged X follows the same
+// order: element (k = kc + 4 g + q, column 16 u + idx) sits at
+// [(q / 2) * 8 + u][16 g + idx][q % 2].  The column groups of a row block run
+// on one XCD (xcd_group_tile), where they share the W rows in L2.  Loads in
+// the loop are unconditional: rows past n and k past ldw - 4 read clamped
+// valid addresses, the staged X is zero for k >= M and for columns >= D.
+constexpr int kQxK = 16;                  // k per chunk
+constexpr int kQxBuf = kQxK * 128;        // doubles per staged chunk
+constexpr int kQxPer = kQxBuf / 256;      // staged elements per thread
+constexpr size_t kQxLds = 2 * kQxBuf * sizeof(double);
 template <bool CS>
-__global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
+__global__ __launch_bounds__(256, 3) void k_gemm_wx_q(
     const double* __restrict__ W, int64_t ldw, int64_t n, int64_t M,
     const double* __restrict__ cs, const double* __restrict__ X, int64_t ldx, int64_t D,
-    double* __restrict__ out, int64_t ldo) {
-  extern __shared__ __attribute__((aligned(16))) double xs[];  // [2][kSxKC / 16][kSxSub]
+    double* __restrict__ out, int64_t ldo, int64_t n_ct) {
+  __shared__ __attribute__((aligned(16))) double xs[2 * kQxBuf];
+  int64_t rb, ct;
+  if (!xcd_group_tile((n + 63) / 64, n_ct, rb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int ch = wave & 1;
-  const int64_t rowbase = (int64_t)blockIdx.x * 64 + (wave >> 1) * 16;
+  const int64_t rowbase = rb * 64 + wave * 16;
   const double* wrow = W + min(rowbase + idx, n - 1) * ldw;
-  const int64_t nch = (M + kSxKC - 1) / kSxKC;
+  const int64_t nch = (M + kQxK - 1) / kQxK;
+  const int64_t cg = ct * 128;
 
-  // staging: thread t moves elements e = t + 512 it of the chunk, e = 256 kl + d
-  //   -> sub-chunk kl / 16, tile d / 16, half (kl & 3) / 2, lane 16 ((kl & 15) / 4) + d % 16, kl & 1
-  // kl = (t >> 8) + 2 it, the same in a whole wave.  X is read through a buffer
-  // resource of M rows, so rows k >= M read zero; columns d >= D take an offset
-  // past any row (zero too).  cs[k] is a wave-uniform load, applied when the
-  // element is written to LDS.
-  const int kl0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8), d = threadIdx.x & 255;
-  const int64_t cg = (int64_t)blockIdx.y * 256;  // first column of the group
+  // staging: thread t moves elements e = t + 256 it: k offset kl = t / 128 + 2 it
+  // (the same in a wave), column d = t % 128
+  const int kl0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7), d = threadIdx.x & 127;
   const auto xr = wx_rsrc(X, (uint32_t)(M * ldx * 8));
   const uint32_t xoff0 = cg + d < D ? (uint32_t)((kl0 * ldx + cg + d) * 8) : 0x80000000u;
   const uint32_t xstep = (uint32_t)(2 * ldx * 8);
   auto soff = [&](int it) {
-    const int kl = kl0 + 2 * it;
-    return (kl >> 4) * kSxSub + (d >> 4) * 256 + ((kl & 3) >> 1) * 128 +
-           (((kl & 15) >> 2) * 16 + (d & 15)) * 2 + (kl & 1);
+    const int kl = kl0 + 2 * it, gq = kl >> 2, q = kl & 3;
+    return ((q >> 1) * 8 + (d >> 4)) * 128 + (gq * 16 + (d & 15)) * 2 + (q & 1);
   };
-  auto fetch = [&](int64_t c, double v[kSxPer], double sc[kSxPer]) {
-    const uint32_t base = (uint32_t)(c * kSxKC * ldx * 8);
+  auto fetch = [&](int64_t c, double v[kQxPer], double sc[kQxPer]) {
+    const uint32_t base = (uint32_t)(c * kQxK * ldx * 8);
 #pragma unroll
-    for (int it = 0; it < kSxPer; ++it) {
+    for (int it = 0; it < kQxPer; ++it) {
       v[it] = wx_ld(xr, xoff0 + base + it * xstep, 0);
-      sc[it] = CS ? cs[min(c * kSxKC + kl0 + 2 * it, M - 1)] : 1.0;
+      sc[it] = CS ? cs[min(c * kQxK + kl0 + 2 * it, M - 1)] : 1.0;
     }
   };
-  auto stage = [&](double* dst, const double v[kSxPer], const double sc[kSxPer]) {
+  auto stage = [&](double* dst, const double v[kQxPer], const double sc[kQxPer]) {
 #pragma unroll
-    for (int it = 0; it < kSxPer; ++it) dst[soff(it)] = CS ? v[it] * sc[it] : v[it];
+    for (int it = 0; it < kQxPer; ++it) dst[soff(it)] = CS ? v[it] * sc[it] : v[it];
   };
-  // W fragment of sub-chunk h: k = 32 c + 16 h + 4 g + s (any k >= M meets a
-  // zero row of the staged X)
-  auto afrag = [&](int64_t c, double a[8]) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t k = c * kSxKC + 16 * h + 4 * g;
-      load4u(wrow + min(k, ldw - 4), a + 4 * h);
-    }
+  auto afrag = [&](int64_t c, double a[4]) {
+    load4u(wrow + min(c * kQxK + 4 * g, ldw - 4), a);
   };
 
-  double sv[kSxPer], cv[kSxPer], a_cur[8], a_nxt[8];
+  double sv[kQxPer], cv[kQxPer], a_cur[4], a_nxt[4];
   fetch(0, sv, cv);
   afrag(0, a_cur);
   stage(xs, sv, cv);
   __syncthreads();
-
   d4v acc[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) acc[u] = zero4();
@@ -533,35 +524,27 @@ __global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
     const int64_t cn = min(c + 1, nch - 1);
     fetch(cn, sv, cv);
     afrag(cn, a_nxt);
-    // keep the next chunk's loads ahead of this chunk's matrix work (the
-    // scheduler would otherwise sink them next to their use)
     __builtin_amdgcn_sched_barrier(0);
-    const double* buf = xs + (c & 1) * (kSxKC / 16) * kSxSub;
+    const d2v* xb = reinterpret_cast<const d2v*>(xs + (c & 1) * kQxBuf) + lane;
 #pragma unroll
-    for (int sc = 0; sc < kSxKC / 16; ++sc) {
-      // step (h, j) of sub-chunk sc consumes k = 32 c + 16 sc + 4 g + 2 h + j
-      const d2v* xb = reinterpret_cast<const d2v*>(buf + sc * kSxSub) + ch * 8 * 128 + lane;
+    for (int h = 0; h < 2; ++h) {
+      d2v b[8];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        d2v b[8];
+      for (int u = 0; u < 8; ++u) b[u] = xb[(h * 8 + u) * 64];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = xb[u * 128 + h * 64];
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[4 * sc + 2 * h + j], b[u][j], acc[u]);
-      }
+        for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[2 * h + j], b[u][j], acc[u]);
     }
-    // and their use (scaling, LDS writes) after it
     __builtin_amdgcn_sched_barrier(0);
-    stage(xs + ((c + 1) & 1) * (kSxKC / 16) * kSxSub, sv, cv);
-    __syncthreads();
+    stage(xs + ((c + 1) & 1) * kQxBuf, sv, cv);
+    lds_barrier();
 #pragma unroll
-    for (int s4 = 0; s4 < 8; ++s4) a_cur[s4] = a_nxt[s4];
+    for (int q = 0; q < 4; ++q) a_cur[q] = a_nxt[q];
   }
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int64_t col = cg + (int64_t)(ch * 8 + u) * 16 + idx;
+    const int64_t col = cg + (int64_t)u * 16 + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t rr = rowbase + g + 4 * r;
@@ -569,79 +552,79 @@ __global__ __launch_bounds__(64 * kSxW) void k_gemm_wx_lds(
     }
   }
 }
-constexpr size_t kSxLds = 2 * (kSxKC / 16) * kSxSub * sizeof(double);
 
-// P-stage of predict (MODE 0) and backward (MODE 1) for D % 4 == 0 in the
-// layout of k_gemm_wx_lds: a block of eight waves covers 64 rows and a group of
-// 256 sparse-point columns (blockIdx.y), the contraction over D runs in 32-wide
+// P-stage of predict (MODE 0) and backward (MODE 1) for D % 4 == 0, in the
+// layout of k_gemm_wx_q: four-wave blocks, three per compute unit, each
+// covering 64 rows and a group of 128 sparse-point columns (wave w: rows
+// 16 w .. + 15, eight column tiles); the contraction over D runs in 16-wide
 // chunks whose X rows are staged in LDS (double-buffered, in the matrix core's
-// operand order, shared by the eight waves), and each wave reads its 16
-// descriptor rows straight from memory.  Loads in the loop are unconditional:
-// rows past n, columns past M and k past D read clamped valid addresses and are
-// cancelled by zero factors when staged (X) or by the zero X rows (descriptors).
-// The epilogue is the one of k_pstage: p = d_i . x_m, W[i][m] (MODE 0: delta^2
-// zeta c_m p^(zeta-1); MODE 1: the same times g_e[i], zero row padding), and
+// operand order), each wave reads its 16 descriptor rows straight from memory,
+// and the column groups of a row block run on one XCD.  Loads in the loop are
+// unconditional: rows past n, columns past M and k past D read clamped valid
+// addresses and are cancelled by zero factors when staged (X) or by the zero X
+// rows (descriptors).  The epilogue is the one of k_pstage: p = d_i . x_m,
+// W[i][m] (MODE 0: delta^2 zeta c_m p^(zeta-1); MODE 1: the same times g_e[i],
+// zero row padding), and
 // MODE 0: per-row energy partials of the column group in e_part[group][i];
-// MODE 1: dc_part[row block][m] = sum over the block's rows of g_e[i] delta^2 p^zeta;
+// MODE 1: dc_part[row block][m] = sum over the block's 64 rows of
+//   g_e[i] delta^2 p^zeta;
 // MODE 3 (rows d_i = h_i, the refinement's column sums of the force rows, which
 // carry a minus sign): dc_part[row block][m] = - sum over the block's rows of
 // Sx[i][m] p_im, with no kernel and no W.
+// Column sums are taken per wave (16 rows), then over the four waves in order.
 template <typename TD, int MODE>
-__global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
+__global__ __launch_bounds__(256, 3) void k_pstage_q(
     const TD* __restrict__ desc, int64_t ldd, int64_t n, const double* __restrict__ X,
     int64_t ldx, int64_t M, int64_t D, int zeta, double delta, const double* __restrict__ cc,
     const double* __restrict__ g_e, double* __restrict__ W, int64_t ldw,
     double* __restrict__ e_part, double* __restrict__ dc_part, const double* __restrict__ Sx,
-    int64_t ldsx) {
-  extern __shared__ __attribute__((aligned(16))) double xs[];  // [2][kSxKC / 16][kSxSub]
-  __shared__ double red[4][2][128];  // [row-group wave][column half][row or column]
+    int64_t ldsx, int64_t n_ct) {
+  __shared__ __attribute__((aligned(16))) double xs[2 * kQxBuf];
+  __shared__ double red[4][128];
+  int64_t rb, ct;
+  if (!xcd_group_tile((n + 63) / 64, n_ct, rb, ct)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
-  const int ch = wave & 1, rgw = wave >> 1;
-  const int64_t rowbase = (int64_t)blockIdx.x * 64 + rgw * 16;
-  const int64_t cg = (int64_t)blockIdx.y * 256;
+  const int64_t rowbase = rb * 64 + wave * 16;
+  const int64_t cg = ct * 128;
   const TD* drow = desc + min(rowbase + idx, n - 1) * ldd;
-  const int64_t nch = (D + kSxKC - 1) / kSxKC;
+  const int64_t nch = (D + kQxK - 1) / kQxK;
 
-  // staging: thread t moves the 4-element groups gi = t + 512 it (it < 4) of the
-  // chunk: sparse point m = cg + gi / 8, k = 32 c + 4 (gi % 8) .. + 3
-  const double* xrow[4];
-  double xok[4];
-  int soff[4];
+  // staging: thread t moves the 4-entry groups gi = t + 256 it (it < 2) of the
+  // chunk: sparse point m = cg + gi / 4, entries k = 16 c + 4 (gi % 4) .. + 3,
+  // which land as (k = 16 c + 4 g + q, column 16 u + idx) at
+  // [(q / 2) * 8 + u][16 g + idx][q % 2]
+  const double* xrow[2];
+  double xok[2];
+  int soff[2], dqv[2];
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int gi = threadIdx.x + 64 * kSxW * it, ml = gi >> 3, dq = gi & 7;
+  for (int it = 0; it < 2; ++it) {
+    const int gi = threadIdx.x + 256 * it, ml = gi >> 2, dq = gi & 3;
     const int64_t m = cg + ml;
     xrow[it] = X + min(m, M - 1) * ldx;
     xok[it] = m < M ? 1.0 : 0.0;
-    soff[it] = (dq >> 2) * kSxSub + (ml >> 4) * 256 + ((dq & 3) * 16 + (ml & 15)) * 2;
+    dqv[it] = dq;
+    soff[it] = (ml >> 4) * 128 + (dq * 16 + (ml & 15)) * 2;
   }
-  auto fetch = [&](int64_t c, d4v v[4]) {
+  auto fetch = [&](int64_t c, d4v v[2]) {
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int dq = (threadIdx.x + 64 * kSxW * it) & 7;
-      v[it] = *reinterpret_cast<const d4v*>(xrow[it] + min(c * kSxKC + 4 * dq, D - 4));
-    }
+    for (int it = 0; it < 2; ++it)
+      v[it] = *reinterpret_cast<const d4v*>(xrow[it] + min(c * kQxK + 4 * dqv[it], D - 4));
   };
-  auto stage = [&](int64_t c, double* dst, const d4v v[4]) {
+  auto stage = [&](int64_t c, double* dst, const d4v v[2]) {
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int dq = (threadIdx.x + 64 * kSxW * it) & 7;
-      const double f = (c * kSxKC + 4 * dq < D) ? xok[it] : 0.0;
+    for (int it = 0; it < 2; ++it) {
+      const double f = (c * kQxK + 4 * dqv[it] < D) ? xok[it] : 0.0;
       const d2v lo = {f * v[it][0], f * v[it][1]}, hi = {f * v[it][2], f * v[it][3]};
       *reinterpret_cast<d2v*>(dst + soff[it]) = lo;
-      *reinterpret_cast<d2v*>(dst + soff[it] + 128) = hi;
+      *reinterpret_cast<d2v*>(dst + soff[it] + 8 * 128) = hi;
     }
   };
-  auto afrag = [&](int64_t c, double a[8]) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t k = min(c * kSxKC + 16 * h + 4 * g, D - 4);
-      load4u(drow + k, a + 4 * h);
-    }
+  auto afrag = [&](int64_t c, double a[4]) {
+    load4u(drow + min(c * kQxK + 4 * g, D - 4), a);
   };
 
-  d4v sv[4];
-  double a_cur[8], a_nxt[8];
+  d4v sv[2];
+  double a_cur[4], a_nxt[4];
   fetch(0, sv);
   afrag(0, a_cur);
   stage(0, xs, sv);
@@ -654,26 +637,22 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
     fetch(cn, sv);
     afrag(cn, a_nxt);
     __builtin_amdgcn_sched_barrier(0);
-    const double* buf = xs + (c & 1) * (kSxKC / 16) * kSxSub;
+    const d2v* xb = reinterpret_cast<const d2v*>(xs + (c & 1) * kQxBuf) + lane;
 #pragma unroll
-    for (int sc = 0; sc < kSxKC / 16; ++sc) {
-      const d2v* xb = reinterpret_cast<const d2v*>(buf + sc * kSxSub) + ch * 8 * 128 + lane;
+    for (int h = 0; h < 2; ++h) {
+      d2v b[8];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        d2v b[8];
+      for (int u = 0; u < 8; ++u) b[u] = xb[(h * 8 + u) * 64];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = xb[u * 128 + h * 64];
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[4 * sc + 2 * h + j], b[u][j], acc[u]);
-      }
+        for (int u = 0; u < 8; ++u) acc[u] = mfma_f64(a_cur[2 * h + j], b[u][j], acc[u]);
     }
     __builtin_amdgcn_sched_barrier(0);
-    stage(cn, xs + ((c + 1) & 1) * (kSxKC / 16) * kSxSub, sv);
-    __syncthreads();
+    stage(cn, xs + ((c + 1) & 1) * kQxBuf, sv);
+    lds_barrier();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a_cur[q] = a_nxt[q];
+    for (int q = 0; q < 4; ++q) a_cur[q] = a_nxt[q];
   }
 
   const double d2 = delta * delta, d2z = d2 * zeta;
@@ -687,7 +666,7 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
   }
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int64_t col = cg + ch * 128 + u * 16 + idx;
+    const int64_t col = cg + u * 16 + idx;
     const bool cvalid = col < M;
     const double cm = (MODE != 3 && cvalid) ? cc[col] : 0.0;
     double csum = 0.0;
@@ -717,31 +696,26 @@ __global__ __launch_bounds__(64 * kSxW) void k_pstage_lds(
     if (MODE != 0) {
       csum += __shfl_xor(csum, 16);
       csum += __shfl_xor(csum, 32);
-      if (g == 0) red[rgw][ch][u * 16 + idx] = csum;
+      if (g == 0) red[wave][u * 16 + idx] = csum;
     }
   }
   if (MODE == 0) {
-    // row sums over the wave's 128 columns, then the two column halves
+    // row sums over the wave's 128 columns
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) esum[r] += __shfl_xor(esum[r], o);
-      if (idx == 0) red[rgw][ch][g + 4 * r] = esum[r];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int rgi = threadIdx.x >> 4, rl = threadIdx.x & 15;
-      const int64_t rr = (int64_t)blockIdx.x * 64 + threadIdx.x;
-      if (e_part && rr < n) e_part[blockIdx.y * n + rr] = red[rgi][0][rl] + red[rgi][1][rl];
+      const int64_t rr = rowbase + g + 4 * r;
+      if (idx == 0 && e_part && rr < n) e_part[ct * n + rr] = esum[r];
     }
   } else {
     __syncthreads();
-    if (threadIdx.x < 256) {
-      const int chh = threadIdx.x >> 7, cl = threadIdx.x & 127;
+    if (threadIdx.x < 128) {
       const int64_t col = cg + threadIdx.x;
       if (col < M)
-        dc_part[(int64_t)blockIdx.x * M + col] =
-            ((red[0][chh][cl] + red[1][chh][cl]) + red[2][chh][cl]) + red[3][chh][cl];
+        dc_part[rb * M + col] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+            red[3][threadIdx.x];
     }
   }
 }
@@ -950,7 +924,7 @@ void local_rows_f64(const void* desc, bool desc_f32, int64_t ldd, int64_t n_atom
 
 int64_t pstage_row_blocks(int64_t n) { return (n + 63) / 64; }
 
-int64_t pstage_groups(int64_t M) { return (M + 255) / 256; }
+int64_t pstage_groups(int64_t M) { return (M + 127) / 128; }
 
 void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t n,
                 const double* X, int64_t ldx, int64_t M, int64_t D, int zeta, double delta,
@@ -968,43 +942,33 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
                       ((mode == 0 && c && (!e_atom || e_part)) || (mode == 1 && c && g_e) ||
                        (mode == 3 && Sx));
   if (lds_ok) {
-    static bool attr = false;
-    if (!attr) {
-      const void* ks[5] = {reinterpret_cast<const void*>(&k_pstage_lds<float, 0>),
-                           reinterpret_cast<const void*>(&k_pstage_lds<float, 1>),
-                           reinterpret_cast<const void*>(&k_pstage_lds<double, 0>),
-                           reinterpret_cast<const void*>(&k_pstage_lds<double, 1>),
-                           reinterpret_cast<const void*>(&k_pstage_lds<double, 3>)};
-      for (const void* k : ks)
-        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
-      attr = true;
-    }
     const int64_t ng = pstage_groups(M);
-    const dim3 grid((unsigned)pstage_row_blocks(n), (unsigned)ng), blk(64 * kSxW);
+    const dim3 grid(xcd_group_tile_blocks(pstage_row_blocks(n), ng)), blk(256);
     double* ep = e_atom ? e_part : nullptr;
     if (mode == 3) {
-      hipLaunchKernelGGL((k_pstage_lds<double, 3>), grid, blk, kSxLds, st, H, ldh, n, X, ldx, M,
-                         D, zeta, delta, nullptr, nullptr, nullptr, 0, nullptr, dc_part, Sx, ldsx);
+      hipLaunchKernelGGL((k_pstage_q<double, 3>), grid, blk, 0, st, H, ldh, n, X, ldx, M, D,
+                         zeta, delta, nullptr, nullptr, nullptr, 0, nullptr, dc_part, Sx, ldsx,
+                         ng);
       return;
     }
     if (desc_f32) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_pstage_lds<float, 0>), grid, blk, kSxLds, st, tptr<float>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
-                           nullptr, 0);
+        hipLaunchKernelGGL((k_pstage_q<float, 0>), grid, blk, 0, st, tptr<float>(desc), ldd, n,
+                           X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part, nullptr, 0,
+                           ng);
       else
-        hipLaunchKernelGGL((k_pstage_lds<float, 1>), grid, blk, kSxLds, st, tptr<float>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
-                           nullptr, 0);
+        hipLaunchKernelGGL((k_pstage_q<float, 1>), grid, blk, 0, st, tptr<float>(desc), ldd, n,
+                           X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part, nullptr, 0,
+                           ng);
     } else {
       if (mode == 0)
-        hipLaunchKernelGGL((k_pstage_lds<double, 0>), grid, blk, kSxLds, st, tptr<double>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
-                           nullptr, 0);
+        hipLaunchKernelGGL((k_pstage_q<double, 0>), grid, blk, 0, st, tptr<double>(desc), ldd,
+                           n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part, nullptr, 0,
+                           ng);
       else
-        hipLaunchKernelGGL((k_pstage_lds<double, 1>), grid, blk, kSxLds, st, tptr<double>(desc),
-                           ldd, n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part,
-                           nullptr, 0);
+        hipLaunchKernelGGL((k_pstage_q<double, 1>), grid, blk, 0, st, tptr<double>(desc), ldd,
+                           n, X, ldx, M, D, zeta, delta, c, g_e, W, ldw, ep, dc_part, nullptr, 0,
+                           ng);
     }
     if (mode == 0 && e_atom)
       hipLaunchKernelGGL(k_sum_groups, dim3(std::max(1u, std::min(cdiv(n, 256), 65536u))),
@@ -1026,26 +990,18 @@ void pstage_f64(int mode, const void* desc, bool desc_f32, int64_t ldd, int64_t 
 // 32-byte aligned) and X under 2 GB; the general form takes any layout.
 inline bool wx_lds_ok(const double* W, int64_t ldw, int64_t M, int64_t ldx,
                       int64_t D) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_wx_lds<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_wx_lds<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSxLds);
-    attr = true;
-  }
-  // offsets into X, including a dropped column's, stay below 2^32
-  return D > 0 && M > 0 && ldw >= 4 && ldw % 4 == 0 && D <= (int64_t)256 * 65535 &&
-         (reinterpret_cast<uintptr_t>(W) & 31) == 0 && (M + 2 * kSxKC) * ldx * 8 < (1ll << 31);
+  // offsets into X, including a dropped column's, stay below 2^31
+  return D > 0 && M > 0 && ldw >= 4 && ldw % 4 == 0 && D <= (int64_t)128 * 65535 &&
+         (reinterpret_cast<uintptr_t>(W) & 31) == 0 && (M + 2 * kQxK) * ldx * 8 < (1ll << 31);
 }
 
 void gemm_wx_f64(const double* W, int64_t ldw, int64_t n, int64_t M, const double* X,
                  int64_t ldx, int64_t D, double* out, int64_t ldo, hipStream_t st) {
   if (n <= 0 || D <= 0) return;
   if (wx_lds_ok(W, ldw, M, ldx, D)) {
-    hipLaunchKernelGGL(k_gemm_wx_lds<false>, dim3(cdiv(n, 64), cdiv(D, 256)), dim3(64 * kSxW),
-                       kSxLds, st, W, ldw, n, M,
-                       nullptr, X, ldx, D, out, ldo);
+    const int64_t n_ct = cdiv(D, 128);
+    hipLaunchKernelGGL(k_gemm_wx_q<false>, dim3(xcd_group_tile_blocks(cdiv(n, 64), n_ct)),
+                       dim3(256), 0, st, W, ldw, n, M, nullptr, X, ldx, D, out, ldo, n_ct);
     return;
   }
   hipLaunchKernelGGL(k_gemm_wx, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
@@ -1088,9 +1044,9 @@ void gemm_wx_scaled_f64(const double* W, int64_t ldw, int64_t n, int64_t M, cons
                         hipStream_t st) {
   if (n <= 0 || D <= 0) return;
   if (wx_lds_ok(W, ldw, M, ldx, D)) {
-    hipLaunchKernelGGL(k_gemm_wx_lds<true>, dim3(cdiv(n, 64), cdiv(D, 256)), dim3(64 * kSxW),
-                       kSxLds, st, W, ldw, n, M,
-                       cs, X, ldx, D, out, ldo);
+    const int64_t n_ct = cdiv(D, 128);
+    hipLaunchKernelGGL(k_gemm_wx_q<true>, dim3(xcd_group_tile_blocks(cdiv(n, 64), n_ct)),
+                       dim3(256), 0, st, W, ldw, n, M, cs, X, ldx, D, out, ldo, n_ct);
     return;
   }
   hipLaunchKernelGGL(k_gemm_wx_cs, dim3(cdiv(n, 64), cdiv(D, 64)), dim3(256), 0, st, W, ldw, n, M,
