@@ -748,6 +748,7 @@ def fit_fp64_legs(args, torch, synth, gapx, headline):
         mixed = {
             "fit_s": float(np.mean(tm)),
             "refine_steps": args.refine_steps,
+            "refine_done": minfo["refine_done"],
             "stage_ms": {k: round(v, 3) for k, v in mper.items()},
             "knm_ms": mknm,
             "knm_gflops_algorithmic": knm_flops / (mknm * 1e-3) / 1e9 if mknm > 0 else None,

@@ -256,11 +256,16 @@ gap_status gap_lstsq(gap_handle *h, double *A, int64_t ld, int64_t m, int64_t n,
  *    rows [0, n_rows) of columns [0, M) hold L-hat K_NM (as written by
  *    gap_build_knm with the same ld); the whole buffer is overwritten.
  * Kmm [M x M] col-major (ld = M), y [n_rows], sigma [n_rows] > 0, jitter >= 0.
- * refine_steps > 0 (requires `train`): after the solve, that many steps of
+ * refine_steps > 0 (requires `train`): after the solve, up to that many steps of
  *    r = b - A_exact c,  R^T R dc = A_exact^T r,  c += dc
  *    with A_exact applied matrix-free in FP64 from `train` and `sp`
  *    (iterative refinement of the mixed-precision form; the residual is exact
- *    FP64 so it removes the assembly error of a BF16X3 K_NM).
+ *    FP64 so it removes the assembly error of a BF16X3 K_NM).  Each step
+ *    contracts the error of c by about the same factor, so after step k >= 2
+ *    the error left is about |dc_k|^2 / |dc_k-1| (relative to |c|); the steps
+ *    stop once that is below 1e-14.  info->refine_done counts the steps taken,
+ *    info->resid_norm[0 .. refine_done] the |A_exact^T r| before each and after
+ *    the last.
  * c: [M] output.  info: host, may be NULL.  Synchronous.
  * Returns GAP_E_NOT_PD if the Cholesky of K_MM + jitter I fails. */
 gap_status gap_fit(gap_handle *h, double *A, int64_t ld, int64_t n_rows, const double *Kmm,

@@ -1126,25 +1126,45 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
     double* Sref = at<double>(h, rw.pw.W);
     refine_weights(h, train, sp, rw, Sref, ld4(M));
     run_pairs(h, train, rw.pw.pairs, false);
+    // Each step contracts the error of c by about the same factor, estimated
+    // from consecutive corrections, so the error left after step k is about
+    // |dc_k|^2 / |dc_k-1| (relative to |c|); the steps stop once that is below
+    // kRefineTol, and one more residual gives the reported |A^T r|.
+    constexpr double kRefineTol = 1e-14;
+    int done = 0;
+    bool stop = false;
+    double prev = -1.0;
     for (int step = 0; step <= refine_steps; ++step) {
       // A^T r = K^T Sigma^-1/2 r_top + U^T r_bot with r = b - A_exact c
       refine_residual_rows(h, train, sp, rw, Sref, ld4(M), c, y, sigma);
       gapk::residual_bot(Lm, M, M, c, at<double>(h, rbot), h->stream);
       gapk::add_ut_r(Lm, M, M, at<double>(h, rbot), gv, h->stream);
       gapk::norm2_f64(gv, M, h->dev_small + 8 + step, h->stream);
-      if (step == refine_steps) break;
+      if (step == refine_steps || stop) break;
       // R^T R dc = A^T r ; c += dc
       gapk::seminormal_solve(A, ld, M, gv, h->stream, qw.flags, at<double>(h, rbot), h->dev_err);
       gapk::axpy_f64(M, 1.0, gv, c, h->stream);
+      done = step + 1;
+      if (step + 1 < refine_steps) {
+        gapk::norm2_f64(gv, M, h->dev_small + 20, h->stream);
+        gapk::norm2_f64(c, M, h->dev_small + 21, h->stream);
+        double nn[2];
+        HIP_TRY(h, hipMemcpyAsync(nn, h->dev_small + 20, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        const double rel = nn[1] > 0.0 ? nn[0] / nn[1] : 0.0;
+        stop = rel == 0.0 || (prev > 0.0 && rel * rel / prev <= kRefineTol);
+        prev = rel;
+      }
     }
     h->timer.end(gapk::TM_REFINE);
     HIP_TRY(h, hipGetLastError());
     double rn[8];
-    HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, (refine_steps + 1) * sizeof(double),
+    HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, (done + 1) * sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
     s = drain_dev_err(h);
-    for (int i = 0; i <= refine_steps && i < 8; ++i) inf.resid_norm[i] = rn[i];
-    inf.refine_done = refine_steps;
+    for (int i = 0; i <= done && i < 8; ++i) inf.resid_norm[i] = rn[i];
+    inf.refine_done = done;
   }
   if (info) *info = inf;
   return s;

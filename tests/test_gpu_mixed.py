@@ -135,3 +135,26 @@ def test_backward_bf16x3(gapx, gap):
         r = relmax(got.cpu().numpy(), ref)
         print(f"\nbackward bf16x3 {name}: rel {r:.2e}")
         assert r <= MIXED_TOL, name
+
+
+def test_refinement_stops_once_converged(gapx, gap):
+    # with room for seven steps, the refinement stops once the error it leaves
+    # is predicted below 1e-14 (two or three steps for this system), and the
+    # report holds one |A^T r| per step taken plus the final one
+    w = synth.WORKLOADS["fit_small_mixed"]
+    b, X, atoms, sp = setup(gapx, w)
+    K = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    Kmm = oracle.build_kmm(X, w.zeta, w.delta)
+    y = K @ synth.hidden_coefficients(w) + synth.noise(w, b.cfg_ids, b.counts)
+    sig = synth.sigma_rows(w, b.counts)
+    c_ref = oracle.fit(K, Kmm, y, sig, w.jitter)
+    A = gap.build_knm(atoms, sp, precision="bf16x3")
+    c, info = gap.fit(A, b.n_rows, gap.build_kmm(sp), torch.tensor(y, device="cuda"),
+                      torch.tensor(sig, device="cuda"), w.jitter, sp, train=atoms,
+                      refine_steps=7)
+    rel = np.linalg.norm(c.cpu().numpy() - c_ref) / np.linalg.norm(c_ref)
+    print(f"\nrefinement stopped after {info['refine_done']} steps: c rel {rel:.2e}, "
+          f"|A^T r| {info['resid_norm']}")
+    assert 2 <= info["refine_done"] < 7
+    assert len(info["resid_norm"]) == info["refine_done"] + 1
+    assert rel <= 1e-10
