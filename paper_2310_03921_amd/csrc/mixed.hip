@@ -47,6 +47,17 @@ __global__ void k_zero_bf16(__bf16* __restrict__ p, int64_t n) {
 }
 
 // --------------------------------------------------------- energy rows ----
+// K_E[c][m] = sum over the atoms i of configuration c of delta^2 (d_i . x_m)^zeta
+// and the kernel-gradient scale S[i][m] = delta^2 zeta (d_i . x_m)^(zeta-1)
+// (FP32), from split-BF16 products.  A block covers one configuration and 256
+// columns (wave w: columns 64 w .. + 63, four tiles); a wave takes the
+// configuration's atoms 32 at a time (two 16-row fragments that share every X
+// fragment), and the next 32-entry block's descriptor entries and X halves
+// are loaded while the current block's products run.  Loads in the loop are
+// unconditional: rows past the configuration re-read its last atom and
+// columns past M re-read column M - 1 (neither is stored); entries past D
+// meet the zero padding of the X halves, and the last, partial block of a
+// descriptor row takes a guarded load.
 template <typename TD>
 __global__ __launch_bounds__(256) void k_energy_rows_b3(
     const TD* __restrict__ desc, int64_t ldd, const int64_t* __restrict__ cfg_ptr,
@@ -60,42 +71,93 @@ __global__ __launch_bounds__(256) void k_energy_rows_b3(
   if (colbase >= M) return;
   const int64_t a0 = max((int64_t)0, min(cfg_ptr[c], n_atoms));
   const int64_t a1 = max(a0, min(cfg_ptr[c + 1], n_atoms));
-  Frag32Split fb[kNCb];
+  const __bf16* xh[kNCb];
+  const __bf16* xl[kNCb];
 #pragma unroll
   for (int u = 0; u < kNCb; ++u) {
-    const int64_t col = colbase + u * 16 + idx;
-    const int64_t cc = col < M ? col : 0;
-    fb[u] = Frag32Split{Xh + cc * ldp, Xl + cc * ldp, col < M};
+    const int64_t col = min(colbase + u * 16 + idx, M - 1);
+    xh[u] = Xh + col * ldp + 8 * g;
+    xl[u] = Xl + col * ldp + 8 * g;
   }
+  const int64_t nkb = (D + 31) / 32, nfull = D / 32;
   const double d2 = delta * delta, d2z = d2 * zeta;
   double e[kNCb];
 #pragma unroll
   for (int u = 0; u < kNCb; ++u) e[u] = 0.0;
-  for (int64_t a = a0; a < a1; a += 16) {
-    const int64_t row = a + idx;
-    Frag32Row<TD> fa{desc + (row < a1 ? row : a0) * ldd, D, row < a1};
-    // species mask of a per-species block (see the FP64 kernel)
-    const double on_lane =
-        (species == nullptr || species[row < a1 ? row : a0] == zsel) ? 1.0 : 0.0;
-    f4v acc[kNCb];
+  for (int64_t a = a0; a < a1; a += 32) {
+    const TD* rowp[2];
+    double on_lane[2];
 #pragma unroll
-    for (int u = 0; u < kNCb; ++u) acc[u] = zero4f();
-    wave_mma_bf16x3<kNCb>(fa, fb, D, g, acc);
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = min(a + 16 * h + idx, a1 - 1);
+      rowp[h] = desc + row * ldd + 8 * g;
+      // species mask of a per-species block (see the FP64 kernel)
+      on_lane[h] = (species == nullptr || species[row] == zsel) ? 1.0 : 0.0;
+    }
+    auto load_a = [&](int64_t kb, float (&dst)[2][8]) {
 #pragma unroll
-    for (int u = 0; u < kNCb; ++u) {
-      const int64_t col = colbase + u * 16 + idx;
+      for (int h = 0; h < 2; ++h) {
+        if (kb < nfull)
+          load8f_full(rowp[h], kb * 32, dst[h]);
+        else
+          load8f(rowp[h] - 8 * g, kb * 32 + 8 * g, D, dst[h]);
+      }
+    };
+    auto load_b = [&](int64_t kb, bf8v (&h_)[kNCb], bf8v (&l_)[kNCb]) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t rr = a + 4 * g + r;
-        const double on = __shfl(on_lane, 4 * g + r);
-        if (rr < a1) {
-          const double p = acc[u][r];
-          const double pz1 = on * ipow(p, zeta - 1);
-          e[u] += d2 * pz1 * p;
-          if (col < ldS) S[rr * ldS + col] = (col < M) ? (float)(d2z * pz1) : 0.f;
+      for (int u = 0; u < kNCb; ++u) {
+        h_[u] = *reinterpret_cast<const bf8v*>(xh[u] + kb * 32);
+        l_[u] = *reinterpret_cast<const bf8v*>(xl[u] + kb * 32);
+      }
+    };
+    f4v acc[2][kNCb];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) acc[h][u] = zero4f();
+    float ra[2][8];
+    bf8v bh[kNCb], bl[kNCb];
+    load_a(0, ra);
+    load_b(0, bh, bl);
+    for (int64_t kb = 0; kb < nkb; ++kb) {
+      bf8v ah[2], al[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) split8(ra[h], ah[h], al[h]);
+      bf8v ch[kNCb], cl[kNCb];
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) {
+        ch[u] = bh[u];
+        cl[u] = bl[u];
+      }
+      const int64_t kn = min(kb + 1, nkb - 1);
+      load_a(kn, ra);
+      load_b(kn, bh, bl);
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[h][u] = mfma_bf16(ah[h], ch[u], acc[h][u]);
+          acc[h][u] = mfma_bf16(ah[h], cl[u], acc[h][u]);
+          acc[h][u] = mfma_bf16(al[h], ch[u], acc[h][u]);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < kNCb; ++u) {
+        const int64_t col = colbase + u * 16 + idx;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t rr = a + 16 * h + 4 * g + r;
+          const double on = __shfl(on_lane[h], 4 * g + r);
+          if (rr < a1) {
+            const double p = acc[h][u][r];
+            const double pz1 = on * ipow(p, zeta - 1);
+            e[u] += d2 * pz1 * p;
+            if (col < ldS) S[rr * ldS + col] = (col < M) ? (float)(d2z * pz1) : 0.f;
+          }
         }
       }
-    }
   }
 #pragma unroll
   for (int u = 0; u < kNCb; ++u) {
