@@ -260,7 +260,9 @@ class LargeFit:
     memory, so the configurations are taken in batches of about ``rows``
     observation rows and every pass over the training set draws each batch's
     Jacobians again on the device (counter-based generator, a stand-in for
-    the descriptor code that would produce them).  One fit:
+    the descriptor code that would produce them); a pass starts with the batch
+    whose Jacobians the buffer still holds from the pass before, and does not
+    draw those again.  One fit:
       K_MM -> fold state [U 0; 0 0] -> per batch: Jacobians, BF16X3 rows (pair
       transpose, split, energy rows + S, force rows) into the state's block
       area, fold (Householder QR of [T; block]) -> back substitution ->
@@ -325,6 +327,7 @@ class LargeFit:
         self.Kmm = gapx.colmajor(w.M, w.M, w.M)
         self.t_host = time.perf_counter() - t0
         self.gen_events = []
+        self.resident = None
         log(f"large fit: {self.n_atoms} atoms, {self.n_pairs} pairs, {self.n_rows} rows in "
             f"{len(self.batches)} batches of <= {self.max_rows} rows; state "
             f"{self.T.numel() * 8 / 1e9:.1f} GB, Jacobian buffer "
@@ -344,11 +347,23 @@ class LargeFit:
         self.gen_events = []
 
     def jacobians(self, bt):
+        """Draw the batch's Jacobians into the buffer, unless they are the ones
+        it already holds."""
+        if self.resident is bt:
+            return
         ev = (self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True))
         ev[0].record()
         self.synth.device_jacobians(self.w, bt["c0"], bt["c1"], out=self.J)
         ev[1].record()
         self.gen_events.append(ev)
+        self.resident = bt
+
+    def pass_order(self):
+        """The batches of one pass, the one whose Jacobians are resident first
+        (a pass sums over batches, so any order gives the same result up to the
+        rounding of that sum)."""
+        r = [bt for bt in self.batches if bt is self.resident]
+        return r + [bt for bt in self.batches if bt is not self.resident]
 
     def fit(self, norms=False):
         """One whole fit; returns c (and, with norms, the block norms for the report)."""
@@ -356,7 +371,7 @@ class LargeFit:
         gap.build_kmm(sp, out=self.Kmm)
         gap.fold_init(T, M, self.Kmm, w.jitter)
         fro2 = 0.0
-        for bt in self.batches:
+        for bt in self.pass_order():
             self.jacobians(bt)
             gap.build_knm_block(bt["atoms"], sp, T, precision="bf16x3")
             if norms:
@@ -387,7 +402,7 @@ class LargeFit:
 
     def residual_pass(self, c, rr=None):
         g = self.torch.zeros(self.w.M, dtype=self.torch.float64, device="cuda")
-        for bt in self.batches:
+        for bt in self.pass_order():
             self.jacobians(bt)
             self.gap.refine_rows_s(bt["atoms"], self.sp, bt["S"], c, bt["y"], bt["sigma"], g, rr)
         return g
@@ -403,7 +418,8 @@ class LargeFit:
         return (f"fit_large_mixed: {self.n_cfg} configurations x U[{w.atoms_lo},{w.atoms_hi}] atoms "
                 f"({self.n_atoms} atoms, {self.n_pairs} pairs, {self.n_rows} observation rows), "
                 f"D={w.D}, {w.nb} neighbours/atom, M={w.M}, zeta={w.zeta}, FP32 descriptors and "
-                f"Jacobians (Jacobians drawn on the device each pass), BF16X3 rows folded in "
+                f"Jacobians (drawn on the device in every pass but for the batch still "
+                f"resident from the previous one), BF16X3 rows folded in "
                 f"{len(self.batches)} batches into an FP64 Householder QR, up to {self.refine} "
                 f"FP64 refinement steps (stopping once the predicted error of c is below "
                 f"{self.refine_tol:g})")
