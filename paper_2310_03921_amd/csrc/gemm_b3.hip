@@ -15,10 +15,10 @@
 //
 // Epilogues:
 //   kPlain   C (FP64, row-major), or a split-K partial C + z * zstride;
-//   kPEnergy P-stage of predict: P = D X^T, e_part[y][i] = sum over the
-//            block's columns of c_m k(p_im), W[i][m] = delta^2 zeta c_m p^(zeta-1)
+//   kPEnergy P-stage of predict: P = D X^T, e_part[ct][i] = sum over the
+//            columns of column tile ct of c_m k(p_im), W[i][m] = delta^2 zeta c_m p^(zeta-1)
 //            (FP32, the forward W, whose product with X is the descriptor gradient);
-//   kPBack   P-stage of the backward: dc_part[x][m] = sum over the block's rows of
+//   kPBack   P-stage of the backward: dc_part[rt][m] = sum over the rows of row tile rt of
 //            g_e[i] k(p_im), W[i][m] = g_e[i] delta^2 zeta c_m p^(zeta-1) (FP32).
 // An operand may also be a column view (ColOp: element (r, k) at p[k ld + r]),
 // which the backward's d_X = W^T D uses for both W and the descriptors, so that
@@ -188,8 +188,8 @@ struct EpiArgs {
   const double* g_e;    // [n_a] upstream gradient (backward P-stage)
   float* W;             // [n_a][ldw]
   int64_t ldw;
-  double* e_part;       // [gridDim.y][n_a]
-  double* dc_part;      // [gridDim.x][n_b]
+  double* e_part;       // [column tiles][n_a]
+  double* dc_part;      // [row tiles][n_b]
   double* C;            // plain: [n_a][ldc] (+ z * zstride)
   int64_t ldc;
   int64_t zstride;
@@ -206,8 +206,12 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
   __shared__ double red[4][kGT];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, idx = lane & 15;
   const int wr = wave & 3, wc = wave >> 2;   // 64-row quarter and 128-column half of the tile
-  const int64_t i0 = (int64_t)blockIdx.x * kGT, j0 = (int64_t)blockIdx.y * kGT;
-  const int64_t kz0 = (int64_t)blockIdx.z * k_per_z;
+  // tiles dealt by row tile: all column tiles of a row tile run on one XCD,
+  // where they share the row tile's A rows in L2
+  int64_t rt, ct;
+  if (!xcd_group_tile((n_a + kGT - 1) / kGT, (n_b + kGT - 1) / kGT, rt, ct)) return;
+  const int64_t i0 = rt * kGT, j0 = ct * kGT;
+  const int64_t kz0 = (int64_t)blockIdx.y * k_per_z;
   const int64_t kz1 = min(K, kz0 + k_per_z);
   const int nkb = (int)((kz1 - kz0 + 31) / 32);
 
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
   // C[4 g + r][idx] of fragment (a, b): row i0 + 64 wr + 16 a + 4 g + r,
   // column j0 + 128 wc + 16 b + idx
   if constexpr (EPI == kPlain) {
-    double* C = ep.C + blockIdx.z * ep.zstride;
+    double* C = ep.C + blockIdx.y * ep.zstride;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
           for (int r = 0; r < 4; ++r) {
             const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
             if (i < n_a)
-              ep.e_part[blockIdx.y * n_a + i] = rowsum[a][r] + red[wr][16 * a + 4 * g + r];
+              ep.e_part[ct * n_a + i] = rowsum[a][r] + red[wr][16 * a + 4 * g + r];
           }
       }
     } else {
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
           const int sl = 128 * wc + 16 * b + idx;
           const int64_t j = j0 + sl;
           if (j < n_b)
-            ep.dc_part[blockIdx.x * n_b + j] = ((red[0][sl] + red[1][sl]) + red[2][sl]) + red[3][sl];
+            ep.dc_part[rt * n_b + j] = ((red[0][sl] + red[1][sl]) + red[2][sl]) + red[3][sl];
         }
       }
     }
@@ -400,7 +404,8 @@ template <typename TA, typename TB, int EPI>
 void launch_gemm(TA A, int64_t lda, int64_t n_a, TB B, int64_t ldb, int64_t n_b, int64_t K,
                  int nz, const EpiArgs& ep, hipStream_t st) {
   const int64_t kpz = ((K + nz - 1) / nz + 31) / 32 * 32;
-  const dim3 grid(cdiv_u(n_a, kGT), cdiv_u(n_b, kGT), (unsigned)cdiv_u(K, kpz));
+  const dim3 grid(xcd_group_tile_blocks(cdiv_u(n_a, kGT), cdiv_u(n_b, kGT)),
+                  (unsigned)cdiv_u(K, kpz));
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_b3<TA, TB, EPI>),
