@@ -1359,9 +1359,12 @@ gap_status gap_predict_backward(gap_handle* h, const gap_atoms* a, const gap_spa
     // descriptors read as column views)
     const size_t W32 = L.take(sizeof(float) * std::max<int64_t>(N * ldw, 1));
     const size_t dcp = L.take(sizeof(double) * (gapk::gemm_b3_row_blocks(N) * M + 8));
+    // W^T D splits its k = atom range into nz slices so that the grid holds about
+    // one 128 KB-LDS block per compute unit (256); more slices only add FP64
+    // partials (nz M D values written, then summed) to the HBM stream
     const int64_t base = gapk::gemm_b3_col_blocks(M) * gapk::gemm_b3_col_blocks(D);
     const int nz = (int)std::max<int64_t>(
-        1, std::min<int64_t>({32, (2048 + base - 1) / base, std::max<int64_t>(N / 512, 1)}));
+        1, std::min<int64_t>({32, (256 + base - 1) / base, std::max<int64_t>(N / 512, 1)}));
     const size_t part = d_X ? L.take(sizeof(double) * std::max<int64_t>(nz * M * D, 1)) : 0;
     SplitWs sw;
     layout_split(L, M, D, true, sw);
