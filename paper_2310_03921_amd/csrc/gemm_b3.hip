@@ -299,39 +299,75 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
         }
       }
   } else {
-    const double d2 = ep.delta * ep.delta, d2z = d2 * ep.zeta;
-    double cm[8];
+    // The element-wise arithmetic runs in FP32: p is an FP32 accumulation of the
+    // split products and W is stored in FP32, so FP64 here would only cost
+    // VALU time while the matrix cores idle; each lane's partial sums over
+    // its own entries are FP32, and everything past them (lanes, halves,
+    // tiles) is summed in FP64.
+    const float d2 = (float)(ep.delta * ep.delta);
+    const int zm1 = ep.zeta - 1;
+    float cf[8], cw[8];   // c_m and delta^2 zeta c_m of this lane's columns
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int64_t j = j0 + 128 * wc + 16 * b + idx;
-      cm[b] = j < n_b ? ep.c[j] : 0.0;
+      const double cj = j < n_b ? ep.c[j] : 0.0;
+      cf[b] = (float)cj;
+      cw[b] = (float)(ep.delta * ep.delta * ep.zeta * cj);
     }
+    // g_e of the wave's 64 rows, one per lane, loaded ahead of every W store
+    // (the stores could alias g_e as far as the compiler knows, and a load
+    // issued behind them would wait for all of them to complete); row
+    // 16 a + 4 g + r of the quarter is read from its lane by a shuffle
+    float ge_lane = 1.f;
+    if (EPI == kPBack && i0 + 64 * wr + lane < n_a) ge_lane = (float)ep.g_e[i0 + 64 * wr + lane];
     double rowsum[4][4];   // kPEnergy: [a][r] partial row sums over this lane's columns
-    double colsum[8];      // kPBack: [b] partial column sums over this lane's rows
+    float colsum[8];       // kPBack: [b] partial column sums over this lane's rows
 #pragma unroll
-    for (int b = 0; b < 8; ++b) colsum[b] = 0.0;
+    for (int b = 0; b < 8; ++b) colsum[b] = 0.f;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
+      // p^(zeta-1) of the 32 entries of fragment row a: one walk over the
+      // exponent's bits serves all of them
+      float pw[8][4], x[8][4];
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pw[b][r] = 1.f;
+          x[b][r] = acc[a][b][r];
+        }
+      for (int e = zm1; e > 0; e >>= 1) {
+        if (e & 1) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pw[b][r] *= x[b][r];
+        }
+        if (e > 1) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[b][r] *= x[b][r];
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        rowsum[a][r] = 0.0;
         const int64_t i = i0 + 64 * wr + 16 * a + 4 * g + r;
         const bool iv = i < n_a;
-        const double ge = (EPI == kPBack && iv) ? ep.g_e[i] : 1.0;
+        float* wrow = ep.W + (iv ? i : 0) * ep.ldw + j0 + 128 * wc + idx;
+        const float ge = EPI == kPBack ? __shfl(ge_lane, 16 * a + 4 * g + r) : 1.f;
+        float rs = 0.f;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-          const int64_t j = j0 + 128 * wc + 16 * b + idx;
-          const bool jv = j < n_b;
-          const double p = acc[a][b][r];
-          const double pz1 = ipow(p, ep.zeta - 1);
-          const double kv = d2 * pz1 * p;
-          const double w = (EPI == kPBack ? ge : 1.0) * d2z * cm[b] * pz1;
-          if (iv && jv) {
-            if (EPI == kPEnergy) rowsum[a][r] += cm[b] * kv;
+          const float pz1 = pw[b][r];
+          const float kv = d2 * pz1 * acc[a][b][r];
+          if (iv && j0 + 128 * wc + 16 * b + idx < n_b) {
+            if (EPI == kPEnergy) rs += cf[b] * kv;
             if (EPI == kPBack) colsum[b] += ge * kv;
-            ep.W[i * ep.ldw + j] = (float)w;
+            wrow[16 * b] = ge * cw[b] * pz1;
           }
         }
+        rowsum[a][r] = rs;
       }
     }
     if constexpr (EPI == kPEnergy) {
@@ -364,14 +400,16 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
     } else {
       // column sums over the 16 rows of each fragment (lanes g, r), then the
       // four row quarters in a fixed order
+      double cs[8];
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
-        colsum[b] += __shfl_xor(colsum[b], 16);
-        colsum[b] += __shfl_xor(colsum[b], 32);
+        cs[b] = colsum[b];
+        cs[b] += __shfl_xor(cs[b], 16);
+        cs[b] += __shfl_xor(cs[b], 32);
       }
       if (g == 0) {
 #pragma unroll
-        for (int b = 0; b < 8; ++b) red[wr][128 * wc + 16 * b + idx] = colsum[b];
+        for (int b = 0; b < 8; ++b) red[wr][128 * wc + 16 * b + idx] = cs[b];
       }
       __syncthreads();
       if (wr == 0 && g == 0) {
