@@ -265,12 +265,19 @@ gap_status gap_lstsq(gap_handle *h, double *A, int64_t ld, int64_t m, int64_t n,
  *    the error left is about |dc_k|^2 / |dc_k-1| (relative to |c|); the steps
  *    stop once that is below 1e-14.  info->refine_done counts the steps taken,
  *    info->resid_norm[0 .. refine_done] the |A_exact^T r| before each and after
- *    the last.
+ *    the last (that last one costs a whole residual pass and only reports;
+ *    gap_set_fit_report(h, 0) skips it, leaving resid_norm[refine_done] NaN).
  * c: [M] output.  info: host, may be NULL.  Synchronous.
  * Returns GAP_E_NOT_PD if the Cholesky of K_MM + jitter I fails. */
 gap_status gap_fit(gap_handle *h, double *A, int64_t ld, int64_t n_rows, const double *Kmm,
                    const double *y, const double *sigma, double jitter, const gap_atoms *train,
                    const gap_sparse *sp, int refine_steps, double *c, gap_fit_info *info);
+
+/* Whether gap_fit computes the residual after its last refinement step
+ * (default 1).  That residual only fills info->resid_norm[refine_done]; it
+ * changes neither c nor the number of steps, so a caller that does not read
+ * it can skip one FP64 residual pass per fit with 0. */
+gap_status gap_set_fit_report(gap_handle *h, int final_residual);
 
 /* Predictive variance of the local energies (Sec. "Regression": gp_predict
  * also returns the variances the GPR predicts).  The paper gives no formula;

@@ -99,6 +99,7 @@ def lib():
             "gap_forces_noalloc": ([P, P, P, P], S),
             "gap_split_bf16x3": ([P, P, I32, I64, I64, I64, P, P, P, P], S),
             "gap_set_workspace_limit": ([P, ctypes.c_size_t], S),
+            "gap_set_fit_report": ([P, I32], S),
             "gap_timing": ([P, I32], S),
             "gap_timing_read": ([P, P, P, I32], S),
             "gap_timing_name": ([I32], ctypes.c_char_p),
@@ -309,6 +310,7 @@ class Gap:
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._h = ctypes.c_void_p()
+        self._fit_report = True
         st = L.gap_create(ctypes.byref(self._h), self.device, ctypes.c_void_p(self.stream.cuda_stream))
         if st != GAP_OK:
             raise GapError(st, f"gap_create failed on device {self.device}")
@@ -336,6 +338,11 @@ class Gap:
     def set_workspace_limit(self, nbytes: int):
         """Cap the optional workspace (pre-split Jacobians); 0 removes the cap."""
         self._check(lib().gap_set_workspace_limit(self._h, int(nbytes)))
+
+    def set_fit_report(self, final_residual: bool):
+        """Whether fit() computes the residual after its last refinement step (default True)."""
+        self._check(lib().gap_set_fit_report(self._h, 1 if final_residual else 0))
+        self._fit_report = bool(final_residual)
 
     def timing(self, enable: bool = True):
         """Record HIP events around each library stage on this handle's stream."""
@@ -469,7 +476,8 @@ class Gap:
                                   _ptr(y), _ptr(sigma), float(jitter),
                                   tr, ctypes.byref(s), int(refine_steps), _ptr(c),
                                   ctypes.byref(info)))
-        return c, {"resid_norm": list(info.resid_norm)[:info.refine_done + 1],
+        n_rn = info.refine_done + (1 if self._fit_report else 0)
+        return c, {"resid_norm": list(info.resid_norm)[:n_rn],
                    "min_abs_rdiag": info.min_abs_rdiag, "max_abs_rdiag": info.max_abs_rdiag,
                    "refine_done": info.refine_done}
 

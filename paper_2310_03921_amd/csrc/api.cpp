@@ -44,6 +44,7 @@ struct gap_handle {
   int64_t tm_n[gapk::TM_COUNT] = {};
   void* noalloc_scratch = nullptr;  // this device's address of `scratch`
   size_t ws_limit = 0;               // cap on optional workspace (0: none)
+  bool fit_final_resid = true;       // gap_fit: residual after the last refinement step
 };
 
 namespace {
@@ -397,6 +398,12 @@ static const char* kTimerNames[gapk::TM_COUNT] = {
 gap_status gap_set_workspace_limit(gap_handle* h, size_t bytes) {
   if (!h) return GAP_E_INVALID;
   h->ws_limit = bytes;
+  return GAP_OK;
+}
+
+gap_status gap_set_fit_report(gap_handle* h, int final_residual) {
+  if (!h) return GAP_E_INVALID;
+  h->fit_final_resid = final_residual != 0;
   return GAP_OK;
 }
 
@@ -1129,12 +1136,14 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
     // Each step contracts the error of c by about the same factor, estimated
     // from consecutive corrections, so the error left after step k is about
     // |dc_k|^2 / |dc_k-1| (relative to |c|); the steps stop once that is below
-    // kRefineTol, and one more residual gives the reported |A^T r|.
+    // kRefineTol, and one more residual gives the reported |A^T r| (unless the
+    // handle was told to skip it).
     constexpr double kRefineTol = 1e-14;
     int done = 0;
     bool stop = false;
     double prev = -1.0;
     for (int step = 0; step <= refine_steps; ++step) {
+      if ((step == refine_steps || stop) && !h->fit_final_resid) break;
       // A^T r = K^T Sigma^-1/2 r_top + U^T r_bot with r = b - A_exact c
       refine_residual_rows(h, train, sp, rw, Sref, ld4(M), c, y, sigma);
       gapk::residual_bot(Lm, M, M, c, at<double>(h, rbot), h->stream);
@@ -1160,10 +1169,11 @@ gap_status gap_fit(gap_handle* h, double* A, int64_t ld, int64_t n_rows, const d
     h->timer.end(gapk::TM_REFINE);
     HIP_TRY(h, hipGetLastError());
     double rn[8];
-    HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, (done + 1) * sizeof(double),
+    const int n_rn = h->fit_final_resid ? done + 1 : done;
+    HIP_TRY(h, hipMemcpyAsync(rn, h->dev_small + 8, n_rn * sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
     s = drain_dev_err(h);
-    for (int i = 0; i <= done && i < 8; ++i) inf.resid_norm[i] = rn[i];
+    for (int i = 0; i < n_rn && i < 8; ++i) inf.resid_norm[i] = rn[i];
     inf.refine_done = done;
   }
   if (info) *info = inf;

@@ -158,3 +158,29 @@ def test_refinement_stops_once_converged(gapx, gap):
     assert 2 <= info["refine_done"] < 7
     assert len(info["resid_norm"]) == info["refine_done"] + 1
     assert rel <= 1e-10
+
+
+def test_fit_without_the_final_residual(gapx, gap):
+    # skipping the residual after the last step changes neither c nor the
+    # steps taken; the report then holds the residuals before each step only
+    w = synth.WORKLOADS["fit_small_mixed"]
+    b, X, atoms, sp = setup(gapx, w)
+    K = oracle.build_knm(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, w.zeta, w.delta)
+    y = torch.tensor(K @ synth.hidden_coefficients(w) + synth.noise(w, b.cfg_ids, b.counts),
+                     device="cuda")
+    sig = torch.tensor(synth.sigma_rows(w, b.counts), device="cuda")
+    Kmm = gap.build_kmm(sp)
+    out = {}
+    try:
+        for report in (True, False):
+            gap.set_fit_report(report)
+            A = gap.build_knm(atoms, sp, precision="bf16x3")
+            out[report] = gap.fit(A, b.n_rows, Kmm, y, sig, w.jitter, sp, train=atoms,
+                                  refine_steps=7)
+    finally:
+        gap.set_fit_report(True)
+    (c1, i1), (c0, i0) = out[True], out[False]
+    assert i0["refine_done"] == i1["refine_done"] >= 2
+    assert torch.equal(c0, c1)
+    assert len(i0["resid_norm"]) == i0["refine_done"]
+    assert i0["resid_norm"] == i1["resid_norm"][:-1]
