@@ -43,143 +43,137 @@ constexpr int kPlain = 0, kPEnergy = 1, kPBack = 2;
 
 inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+// Staging of a 256 x 32 operand block.  The next block's loads are issued
+// before the current block's products and their registers are read only when
+// the block is written to LDS after them, so the products never wait for
+// memory: a load fetches raw values from a clamped, valid address, and what
+// lies outside the operand (rows past its end, k past the slice end) is
+// replaced by zeros, by selection, only when the block is staged, where the
+// values are also converted to FP32 and split into 16-byte hi / lo halves at
+// [tile][hi | lo][lane] (lane = row % 16 + 16 group).
+template <typename TOp>
+struct Stage;
+
+// Rows (element (r, k) at p[r ld + k], ld a multiple of 4): thread t holds rows
+// (t >> 2) + 128 h, entries k0 + 8 (t & 3) .. + 7, as two 4-wide loads whose
+// start is clamped to the last 4-group that holds entries below K.
+template <typename T>
+struct Stage<const T*> {
+  T v[2][8];
+  GAP_DEV void load(const T* __restrict__ p, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                    int64_t k0) {
+    const int t = threadIdx.x, grp = t & 3;
+    const int64_t k4 = (K - 1) & ~(int64_t)3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const T* row = p + min(r0 + (t >> 2) + kGRowStep * h, rows - 1) * ld;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int64_t kk = min(k0 + 8 * grp + 4 * q, k4);
+        if constexpr (sizeof(T) == 4) {
+          const f4v x = *reinterpret_cast<const f4v*>(row + kk);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[h][4 * q + e] = x[e];
+        } else {
+          const d4v x = *reinterpret_cast<const d4v*>(row + kk);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[h][4 * q + e] = x[e];
+        }
+      }
+    }
+  }
+  GAP_DEV void store(int64_t rows, int64_t K, int64_t r0, int64_t k0,
+                     bf8v* __restrict__ dst) const {
+    const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = (t >> 2) + kGRowStep * h;
+      const bool rok = r0 + r < rows;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (rok && k0 + 8 * grp + e < K) ? (float)v[h][e] : 0.f;
+      bf8v hi, lo;
+      split8(x, hi, lo);
+      bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+      d[0] = hi;
+      d[64] = lo;
+    }
+  }
+};
+
 // Pre-split operand rows: hi and lo halves [rows][ld], ld a multiple of 32,
-// zero padded along k.
+// zero padded along k; 16-byte loads of both halves, no split.
 struct SplitRows {
   const __bf16* hi;
   const __bf16* lo;
 };
-
-// Thread t stages rows (t >> 2) and (t >> 2) + 128, k group 8 (t & 3) .. + 7, of
-// a 256 x 32 operand block: eight values each, split into 16-byte hi / lo
-// halves stored at [tile][hi | lo][lane] (lane = row % 16 + 16 group).
-template <typename T>
-GAP_DEV void stage_load(const T* __restrict__ p, int64_t ld, int64_t rows, int64_t K,
-                        int64_t r0, int64_t k0, float (&v)[2][8]) {
-  const int t = threadIdx.x, grp = t & 3;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t r = r0 + (t >> 2) + kGRowStep * h;
-    const int64_t k = k0 + 8 * grp;
-    const T* row = p + min(r, rows - 1) * ld;
-    const float ok = r < rows ? 1.f : 0.f;
-    if (k + 8 <= K) {
-      load8f_full(row, k, v[h]);
-    } else {
-      load8f(row, k, K, v[h]);
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[h][e] *= ok;
-  }
-}
-
-GAP_DEV void stage_store(const float (&v)[2][8], bf8v* __restrict__ dst) {
-  const int t = threadIdx.x, grp = t & 3;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = (t >> 2) + kGRowStep * h;
-    bf8v hi, lo;
-    split8(v[h], hi, lo);
-    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
-    d[0] = hi;
-    d[64] = lo;
-  }
-}
-
-// Pre-split rows: 16-byte loads of both halves, no split.
-struct PreSplit {
+template <>
+struct Stage<SplitRows> {
   bf8v hi[2], lo[2];
+  GAP_DEV void load(const SplitRows& s, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                    int64_t k0) {
+    const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t off = min(r0 + (t >> 2) + kGRowStep * h, rows - 1) * ld + k0 + 8 * grp;
+      hi[h] = *reinterpret_cast<const bf8v*>(s.hi + off);
+      lo[h] = *reinterpret_cast<const bf8v*>(s.lo + off);
+    }
+  }
+  GAP_DEV void store(int64_t rows, int64_t K, int64_t r0, int64_t k0,
+                     bf8v* __restrict__ dst) const {
+    const int t = threadIdx.x, grp = t & 3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = (t >> 2) + kGRowStep * h;
+      bf8v a = hi[h], b = lo[h];
+      if (r0 + r >= rows) zero_split(a, b);
+      bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+      d[0] = a;
+      d[64] = b;
+    }
+  }
 };
-GAP_DEV void stage_load_split(const SplitRows& s, int64_t ld, int64_t rows, int64_t r0,
-                              int64_t k0, PreSplit& v) {
-  const int t = threadIdx.x, grp = t & 3;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t r = r0 + (t >> 2) + kGRowStep * h;
-    const int64_t off = min(r, rows - 1) * ld + k0 + 8 * grp;
-    v.hi[h] = *reinterpret_cast<const bf8v*>(s.hi + off);
-    v.lo[h] = *reinterpret_cast<const bf8v*>(s.lo + off);
-    if (r >= rows) zero_split(v.hi[h], v.lo[h]);
-  }
-}
-GAP_DEV void stage_store_split(const PreSplit& v, bf8v* __restrict__ dst) {
-  const int t = threadIdx.x, grp = t & 3;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = (t >> 2) + kGRowStep * h;
-    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
-    d[0] = v.hi[h];
-    d[64] = v.lo[h];
-  }
-}
 
 // Column view of a row-major matrix: element (r, k) at p[k * ld + r].  Thread t
-// stages rows (t & 127) + 128 h and k group 8 (t >> 7) .. + 7, one load per k,
+// holds rows (t & 127) + 128 h and k group 8 (t >> 7) .. + 7, one load per k,
 // so that for a given k a wave's lanes read 64 consecutive r (whole 256-byte
-// runs for FP32); stage_store_col writes them to the same LDS places as
-// stage_store.  Out-of-range r and k read a clamped valid element and are
-// zeroed.
+// runs for FP32); the block lands in the same LDS places as a row operand's.
 template <typename T>
 struct ColOp {
   const T* p;
 };
 template <typename T>
-GAP_DEV void stage_load_col(const ColOp<T>& op, int64_t ld, int64_t rows, int64_t K, int64_t r0,
-                            int64_t k0, float (&v)[2][8]) {
-  const int t = threadIdx.x, grp = t >> 7;
+struct Stage<ColOp<T>> {
+  T v[2][8];
+  GAP_DEV void load(const ColOp<T>& op, int64_t ld, int64_t rows, int64_t K, int64_t r0,
+                    int64_t k0) {
+    const int t = threadIdx.x, grp = t >> 7;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t r = r0 + (t & 127) + kGRowStep * h;
-    const int64_t rc = min(r, rows - 1);
+    for (int h = 0; h < 2; ++h) {
+      const int64_t rc = min(r0 + (t & 127) + kGRowStep * h, rows - 1);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = k0 + 8 * grp + e;
-      const float ok = (r < rows && k < K) ? 1.f : 0.f;
-      v[h][e] = (float)op.p[min(k, K - 1) * ld + rc] * ok;
+      for (int e = 0; e < 8; ++e) v[h][e] = op.p[min(k0 + 8 * grp + e, K - 1) * ld + rc];
     }
   }
-}
-
-GAP_DEV void stage_store_col(const float (&v)[2][8], bf8v* __restrict__ dst) {
-  const int t = threadIdx.x, grp = t >> 7;
+  GAP_DEV void store(int64_t rows, int64_t K, int64_t r0, int64_t k0,
+                     bf8v* __restrict__ dst) const {
+    const int t = threadIdx.x, grp = t >> 7;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = (t & 127) + kGRowStep * h;
-    bf8v hi, lo;
-    split8(v[h], hi, lo);
-    bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
-    d[0] = hi;
-    d[64] = lo;
+    for (int h = 0; h < 2; ++h) {
+      const int r = (t & 127) + kGRowStep * h;
+      const bool rok = r0 + r < rows;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (rok && k0 + 8 * grp + e < K) ? (float)v[h][e] : 0.f;
+      bf8v hi, lo;
+      split8(x, hi, lo);
+      bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
+      d[0] = hi;
+      d[64] = lo;
+    }
   }
-}
-
-template <typename T>
-struct IsCol {
-  static constexpr bool value = false;
 };
-template <typename T>
-struct IsCol<ColOp<T>> {
-  static constexpr bool value = true;
-};
-
-template <typename TB>
-struct BStage {
-  float v[2][8];
-};
-template <>
-struct BStage<SplitRows> {
-  PreSplit v;
-};
-template <typename T>
-GAP_DEV void stage_load_any(const T* p, int64_t ld, int64_t rows, int64_t K, int64_t r0,
-                            int64_t k0, float (&v)[2][8]) {
-  stage_load(p, ld, rows, K, r0, k0, v);
-}
-template <typename T>
-GAP_DEV void stage_load_any(const ColOp<T>& op, int64_t ld, int64_t rows, int64_t K, int64_t r0,
-                            int64_t k0, float (&v)[2][8]) {
-  stage_load_col(op, ld, rows, K, r0, k0, v);
-}
 
 struct EpiArgs {
   int zeta;
@@ -221,42 +215,24 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc[a][b] = zero4f();
 
-  float va[2][8];
-  BStage<TB> vb;
-  auto load_b = [&](int64_t k0) {
-    if constexpr (std::is_same<TB, SplitRows>::value)
-      stage_load_split(B, ldb, n_b, j0, k0, vb.v);
-    else
-      stage_load_any(B, ldb, n_b, kz1, j0, k0, vb.v);
-  };
-  auto store_b = [&](int buf) {
-    if constexpr (std::is_same<TB, SplitRows>::value)
-      stage_store_split(vb.v, sB(buf));
-    else if constexpr (IsCol<TB>::value)
-      stage_store_col(vb.v, sB(buf));
-    else
-      stage_store(vb.v, sB(buf));
-  };
-  auto store_a = [&](int buf) {
-    if constexpr (IsCol<TA>::value)
-      stage_store_col(va, sA(buf));
-    else
-      stage_store(va, sA(buf));
-  };
+  Stage<TA> sa;
+  Stage<TB> sb;
   if (nkb > 0) {
-    stage_load_any(A, lda, n_a, kz1, i0, kz0, va);
-    load_b(kz0);
-    store_a(0);
-    store_b(0);
+    sa.load(A, lda, n_a, kz1, i0, kz0);
+    sb.load(B, ldb, n_b, kz1, j0, kz0);
+    sa.store(n_a, kz1, i0, kz0, sA(0));
+    sb.store(n_b, kz1, j0, kz0, sB(0));
   }
   __syncthreads();
   for (int kb = 0; kb < nkb; ++kb) {
     const int buf = kb & 1;
     const bool more = kb + 1 < nkb;
+    const int64_t kn = kz0 + (int64_t)(kb + 1) * 32;
     if (more) {
-      stage_load_any(A, lda, n_a, kz1, i0, kz0 + (int64_t)(kb + 1) * 32, va);
-      load_b(kz0 + (int64_t)(kb + 1) * 32);
+      sa.load(A, lda, n_a, kz1, i0, kn);
+      sb.load(B, ldb, n_b, kz1, j0, kn);
     }
+    __builtin_amdgcn_sched_barrier(0);
     const bf8v* xa = sA(buf) + lane + wr * 4 * 128;
     const bf8v* xb = sB(buf) + lane + wc * 8 * 128;
     bf8v ah[4], al[4];
@@ -275,9 +251,10 @@ __global__ __launch_bounds__(kGThreads, 1) void k_gemm_b3(TA A, int64_t lda, int
         acc[a][b] = mfma_bf16(al[a], bh, acc[a][b]);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
     if (more) {
-      store_a(buf ^ 1);
-      store_b(buf ^ 1);
+      sa.store(n_a, kz1, i0, kn, sA(buf ^ 1));
+      sb.store(n_b, kz1, j0, kn, sB(buf ^ 1));
     }
     __syncthreads();
   }
