@@ -399,11 +399,18 @@ struct FragRowKScaled {
 #pragma unroll
     for (int s = 0; s < 4; ++s) out[s] *= (k + s < kmax) ? cs[k + s] : 0.0;
   }
-  GAP_DEV void fast(int64_t k0, int g, double out[4]) const {
+  struct Raw {
+    double w[4], c[4];
+  };
+  GAP_DEV void fast(int64_t k0, int g, Raw& r) const {
     const int64_t k = k0 + 4 * g;
-    load4u(row + k, out);
+    load4u(row + k, r.w);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) out[s] *= cs[k + s];
+    for (int s = 0; s < 4; ++s) r.c[s] = cs[k + s];
+  }
+  GAP_DEV void cook(const Raw& r, double out[4]) const {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[s] = r.w[s] * r.c[s];
   }
 };
 
