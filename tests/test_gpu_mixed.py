@@ -137,6 +137,39 @@ def test_backward_bf16x3(gapx, gap):
         assert r <= MIXED_TOL, name
 
 
+@pytest.mark.parametrize("shape,ddt", [("ragged", "f64"), ("ragged", "f32"), ("tiles", "f32"),
+                                       ("tiles", "f64")])
+def test_predict_and_backward_bf16x3_ragged(gapx, gap, shape, ddt):
+    # shapes that end inside every tile of the BF16X3 GEMM: D not a multiple
+    # of 4 (a 4-entry group straddles D) nor of 32, M and N not multiples of
+    # 32 or 256 (two row and two column tiles for "tiles"), FP32 and FP64
+    # descriptors
+    if shape == "ragged":
+        w = synth.Workload("ragged_p", 41, n_cfg=9, atoms_lo=1, atoms_hi=23, D=37, nb=3, M=23,
+                           zeta=3, delta=1.7, desc_dtype=ddt, jac_dtype=ddt)
+    else:
+        w = synth.Workload("tiles_p", 43, n_cfg=7, atoms_lo=40, atoms_hi=90, D=291, nb=4, M=301,
+                           zeta=4, delta=0.9, desc_dtype=ddt, jac_dtype=ddt)
+    b, X, atoms, sp = setup(gapx, w)
+    rng = np.random.default_rng(5)
+    c = rng.standard_normal(w.M)
+    ge = rng.standard_normal(b.n_atoms)
+    out = gap.predict(atoms, sp, torch.tensor(c, device="cuda"), precision="bf16x3", dEdd=True,
+                      forces=True)
+    e, ec, g, F = oracle.predict(b.cfg_ptr, b.desc, b.pair_ptr, b.pair_j, b.jac, X, c, w.zeta,
+                                 w.delta)
+    dd, dc, dX = gap.predict_backward(atoms, sp, torch.tensor(c, device="cuda"),
+                                      torch.tensor(ge, device="cuda"), precision="bf16x3")
+    r_dd, r_dc, r_dX = oracle.predict_backward(b.desc, X, c, ge, w.zeta, w.delta)
+    print(f"\n{shape} {ddt}: {b.n_atoms} atoms, D={w.D}, M={w.M}")
+    for name, got, ref in (("e_atom", out["e_atom"], e), ("e_cfg", out["e_cfg"], ec),
+                           ("dEdd", out["dEdd"], g), ("forces", out["forces"], F),
+                           ("d_desc", dd, r_dd), ("d_c", dc, r_dc), ("d_X", dX, r_dX)):
+        r = relmax(got.cpu().numpy(), ref)
+        print(f"  {name}: rel {r:.2e}")
+        assert r <= MIXED_TOL, name
+
+
 def test_refinement_stops_once_converged(gapx, gap):
     # with room for seven steps, the refinement stops once the error it leaves
     # is predicted below 1e-14 (two or three steps for this system), and the
