@@ -54,19 +54,26 @@ inline unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b
 template <typename TOp>
 struct Stage;
 
+// Thread t of a row operand stages row 16 (t / 64) + t % 16 (+ 128 h) and k
+// group (t / 16) % 4: the 64 lanes of a wave then write 64 consecutive
+// 16-byte LDS entries, where four lanes of one row with consecutive k groups
+// would meet in the same banks four at a time.
+GAP_DEV int stage_row(int t) { return 16 * (t >> 6) + (t & 15); }
+GAP_DEV int stage_grp(int t) { return (t >> 4) & 3; }
+
 // Rows (element (r, k) at p[r ld + k], ld a multiple of 4): thread t holds rows
-// (t >> 2) + 128 h, entries k0 + 8 (t & 3) .. + 7, as two 4-wide loads whose
+// stage_row(t) + 128 h, entries k0 + 8 stage_grp(t) .. + 7, as two 4-wide loads whose
 // start is clamped to the last 4-group that holds entries below K.
 template <typename T>
 struct Stage<const T*> {
   T v[2][8];
   GAP_DEV void load(const T* __restrict__ p, int64_t ld, int64_t rows, int64_t K, int64_t r0,
                     int64_t k0) {
-    const int t = threadIdx.x, grp = t & 3;
+    const int t = threadIdx.x, grp = stage_grp(t);
     const int64_t k4 = (K - 1) & ~(int64_t)3;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const T* row = p + min(r0 + (t >> 2) + kGRowStep * h, rows - 1) * ld;
+      const T* row = p + min(r0 + stage_row(t) + kGRowStep * h, rows - 1) * ld;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int64_t kk = min(k0 + 8 * grp + 4 * q, k4);
@@ -84,10 +91,10 @@ struct Stage<const T*> {
   }
   GAP_DEV void store(int64_t rows, int64_t K, int64_t r0, int64_t k0,
                      bf8v* __restrict__ dst) const {
-    const int t = threadIdx.x, grp = t & 3;
+    const int t = threadIdx.x, grp = stage_grp(t);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int r = (t >> 2) + kGRowStep * h;
+      const int r = stage_row(t) + kGRowStep * h;
       const bool rok = r0 + r < rows;
       float x[8];
 #pragma unroll
@@ -112,20 +119,20 @@ struct Stage<SplitRows> {
   bf8v hi[2], lo[2];
   GAP_DEV void load(const SplitRows& s, int64_t ld, int64_t rows, int64_t K, int64_t r0,
                     int64_t k0) {
-    const int t = threadIdx.x, grp = t & 3;
+    const int t = threadIdx.x, grp = stage_grp(t);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t off = min(r0 + (t >> 2) + kGRowStep * h, rows - 1) * ld + k0 + 8 * grp;
+      const int64_t off = min(r0 + stage_row(t) + kGRowStep * h, rows - 1) * ld + k0 + 8 * grp;
       hi[h] = *reinterpret_cast<const bf8v*>(s.hi + off);
       lo[h] = *reinterpret_cast<const bf8v*>(s.lo + off);
     }
   }
   GAP_DEV void store(int64_t rows, int64_t K, int64_t r0, int64_t k0,
                      bf8v* __restrict__ dst) const {
-    const int t = threadIdx.x, grp = t & 3;
+    const int t = threadIdx.x, grp = stage_grp(t);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int r = (t >> 2) + kGRowStep * h;
+      const int r = stage_row(t) + kGRowStep * h;
       bf8v a = hi[h], b = lo[h];
       if (r0 + r >= rows) zero_split(a, b);
       bf8v* d = dst + (r >> 4) * 128 + (r & 15) + 16 * grp;
