@@ -615,6 +615,9 @@ def main():
     ap.add_argument("--knm-only", action="store_true",
                     help="576k-atom workload: time only the K_NM assembly of every batch "
                          "(Jacobians drawn, BF16X3 rows built), no fold, solve or refinement")
+    ap.add_argument("--predict-only", action="store_true",
+                    help="time only the predict / backward leg on the 65,536-atom predict "
+                         "workload and print its figures")
     ap.add_argument("--large-cfgs", type=int, default=0,
                     help="576k-atom fit: fit only its first N configurations (0: all 4000)")
     args = ap.parse_args()
@@ -645,6 +648,13 @@ def main():
     if args.knm_only:
         print(json.dumps(large_knm_bench(args, torch, synth, gapx)), flush=True)
         return
+    if args.predict_only:
+        gap = gapx.Gap(0)
+        out = {"leg": "predict_workload", "steps": args.steps,
+               **predict_leg(args, torch, synth, gapx, gap)}
+        gap.close()
+        print(json.dumps(out), flush=True)
+        return
     peaks = measured_peaks(torch)
     line = large_fit_bench(args, torch, synth, gapx)
     line["measured_peaks"] = peaks
@@ -661,6 +671,62 @@ def main():
     if not args.no_fp64_legs:
         line["fit_fp64_116k"] = fit_fp64_legs(args, torch, synth, gapx, headline=False)
     print(json.dumps(line), flush=True)
+
+
+def predict_leg(args, torch, synth, gapx, gap):
+    """Predict and backward on the predict workload (65,536 atoms, D = 1000,
+    M = 4000, FP32 descriptors and Jacobians): energies + descriptor gradients
+    (two GEMM-shaped contractions), the force contraction over the Jacobians
+    (an HBM stream), and the backward (three contractions), FP64 and BF16X3."""
+    wp = synth.WORKLOADS["predict"]
+    log(f"generating {wp.name} on the host")
+    bp = synth.generate(wp)
+    Xp = synth.sparse_points(wp, bp)
+    atp = gapx.Atoms.from_host(bp.cfg_ptr, bp.desc, bp.pair_ptr, bp.pair_j, bp.jac,
+                               desc_dtype=torch.float32, jac_dtype=torch.float32)
+    bp.jac = None
+    spp = gapx.Sparse.from_host(Xp, wp.zeta, wp.delta)
+    cp = torch.tensor(synth.predict_coefficients(wp), device="cuda")
+    ge = torch.ones(atp.n_atoms, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            out_ = fn()
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - ts)
+        return float(np.mean(tt)), out_
+    Np, Mp, Dp = atp.n_atoms, wp.M, wp.D
+    fwd_flops = 2.0 * 2.0 * Np * Mp * Dp
+    bwd_flops = 3.0 * 2.0 * Np * Mp * Dp
+    jbytes = float(atp.n_pairs) * 3 * Dp * 4
+    pred = {"workload": describe(wp, bp), "energy_and_gradient_s": {}, "backward_s": {},
+            "energy_and_gradient_tflops": {}, "backward_tflops": {}}
+    dEdd = None
+    for prec in ("fp64", "bf16x3"):
+        t_f, o = timed(lambda: gap.predict(atp, spp, cp, prec, e_atom=True, e_cfg=True,
+                                           dEdd=True, forces=False))
+        t_b, _ = timed(lambda: gap.predict_backward(atp, spp, cp, ge, prec))
+        pred["energy_and_gradient_s"][prec] = t_f
+        pred["backward_s"][prec] = t_b
+        pred["energy_and_gradient_tflops"][prec] = fwd_flops / t_f / 1e12
+        pred["backward_tflops"][prec] = bwd_flops / t_b / 1e12
+        if prec == "fp64":
+            dEdd = o["dEdd"]
+    t_j, _ = timed(lambda: gap.forces(atp, dEdd))
+    pred["forces_from_gradients_s"] = t_j
+    pred["forces_jacobian_bytes"] = jbytes
+    pred["forces_hbm_tbs"] = jbytes / t_j / 1e12
+    log(f"predict workload: energies + gradients {pred['energy_and_gradient_s']['fp64'] * 1e3:.1f} ms "
+        f"FP64 / {pred['energy_and_gradient_s']['bf16x3'] * 1e3:.1f} ms BF16X3, forces "
+        f"{t_j * 1e3:.1f} ms ({pred['forces_hbm_tbs']:.2f} TB/s of Jacobians), backward "
+        f"{pred['backward_s']['fp64'] * 1e3:.1f} / {pred['backward_s']['bf16x3'] * 1e3:.1f} ms")
+    del atp, dEdd
+    return pred
 
 
 def fit_fp64_legs(args, torch, synth, gapx, headline):
@@ -912,60 +978,9 @@ def fit_fp64_legs(args, torch, synth, gapx, headline):
 
     pred = None
     if not args.no_predict:
-        # predict and backward on the predict workload (65,536 atoms, D = 1000,
-        # M = 4000, FP32 descriptors and Jacobians): energies + descriptor
-        # gradients (two GEMM-shaped contractions), the force contraction over the
-        # Jacobians (an HBM stream), and the backward (three contractions)
         del A
         torch.cuda.empty_cache()
-        wp = synth.WORKLOADS["predict"]
-        log(f"generating {wp.name} on the host")
-        bp = synth.generate(wp)
-        Xp = synth.sparse_points(wp, bp)
-        atp = gapx.Atoms.from_host(bp.cfg_ptr, bp.desc, bp.pair_ptr, bp.pair_j, bp.jac,
-                                   desc_dtype=torch.float32, jac_dtype=torch.float32)
-        bp.jac = None
-        spp = gapx.Sparse.from_host(Xp, wp.zeta, wp.delta)
-        cp = torch.tensor(synth.predict_coefficients(wp), device="cuda")
-        ge = torch.ones(atp.n_atoms, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-
-        def timed(fn):
-            fn()
-            torch.cuda.synchronize()
-            tt = []
-            for _ in range(args.steps):
-                ts = time.perf_counter()
-                out_ = fn()
-                torch.cuda.synchronize()
-                tt.append(time.perf_counter() - ts)
-            return float(np.mean(tt)), out_
-        Np, Mp, Dp = atp.n_atoms, wp.M, wp.D
-        fwd_flops = 2.0 * 2.0 * Np * Mp * Dp
-        bwd_flops = 3.0 * 2.0 * Np * Mp * Dp
-        jbytes = float(atp.n_pairs) * 3 * Dp * 4
-        pred = {"workload": describe(wp, bp), "energy_and_gradient_s": {}, "backward_s": {},
-                "energy_and_gradient_tflops": {}, "backward_tflops": {}}
-        dEdd = None
-        for prec in ("fp64", "bf16x3"):
-            t_f, o = timed(lambda: gap.predict(atp, spp, cp, prec, e_atom=True, e_cfg=True,
-                                               dEdd=True, forces=False))
-            t_b, _ = timed(lambda: gap.predict_backward(atp, spp, cp, ge, prec))
-            pred["energy_and_gradient_s"][prec] = t_f
-            pred["backward_s"][prec] = t_b
-            pred["energy_and_gradient_tflops"][prec] = fwd_flops / t_f / 1e12
-            pred["backward_tflops"][prec] = bwd_flops / t_b / 1e12
-            if prec == "fp64":
-                dEdd = o["dEdd"]
-        t_j, _ = timed(lambda: gap.forces(atp, dEdd))
-        pred["forces_from_gradients_s"] = t_j
-        pred["forces_jacobian_bytes"] = jbytes
-        pred["forces_hbm_tbs"] = jbytes / t_j / 1e12
-        log(f"predict workload: energies + gradients {pred['energy_and_gradient_s']['fp64'] * 1e3:.1f} ms "
-            f"FP64 / {pred['energy_and_gradient_s']['bf16x3'] * 1e3:.1f} ms BF16X3, forces "
-            f"{t_j * 1e3:.1f} ms ({pred['forces_hbm_tbs']:.2f} TB/s of Jacobians), backward "
-            f"{pred['backward_s']['fp64'] * 1e3:.1f} / {pred['backward_s']['bf16x3'] * 1e3:.1f} ms")
-        del atp, dEdd
+        pred = predict_leg(args, torch, synth, gapx, gap)
 
     cpu = None
     if headline and not args.no_cpu_baseline:
