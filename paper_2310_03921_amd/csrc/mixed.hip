@@ -432,18 +432,9 @@ __global__ __launch_bounds__(256, 1) void k_force_rows_b3w(
 #pragma unroll
     for (int a = 0; a < 3; ++a) js.load(jr, a, kb0, nx[a]);
     for (int t = 0; t < maxdeg; ++t) {
-      const int pair_nn = tgt_pair[pair_slot(t + 2)];
-      const int src_n = pair_src[pair_n];
       const int64_t jn = js.row(pair_n);
-      // S of this step's sources (rows 4 g + r of the output tile)
+      int pair_nn = 0, src_n = 0;
       f4v s_lo[4], s_hi[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int src_r = __shfl(src, 4 * g + r);
-        const float* sp = S + (int64_t)max(src_r, 0) * ldS + scol;
-        s_lo[r] = *reinterpret_cast<const f4v*>(sp);
-        s_hi[r] = *reinterpret_cast<const f4v*>(sp + 4);
-      }
       f4v G[3][kNCW];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -459,6 +450,23 @@ __global__ __launch_bounds__(256, 1) void k_force_rows_b3w(
         const int64_t kn = more ? kb0 + (int64_t)(kb + 1) * 32 : kb0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) js.load(rn, a, kn, nx[a]);
+        if (kb == 0) {
+          // S of this step's sources (rows 4 g + r of the output tile), used
+          // after the last block, and the pair metadata of the steps ahead:
+          // issued behind the first block's Jacobian prefetch, so that the wait
+          // for that prefetch (every load before it completes first) does not
+          // wait for them as well
+          pair_nn = tgt_pair[pair_slot(t + 2)];
+          src_n = pair_src[pair_n];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int src_r = __shfl(src, 4 * g + r);
+            const float* sp = S + (int64_t)max(src_r, 0) * ldS + scol;
+            s_lo[r] = *reinterpret_cast<const f4v*>(sp);
+            s_hi[r] = *reinterpret_cast<const f4v*>(sp + 4);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // issue these loads before the products
         // X halves one tile ahead of their products, so that each tile's LDS
         // reads are in flight under the previous tile's nine products
         const bf8v* xk = xb + (size_t)kb * kNCW * 128;
