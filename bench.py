@@ -53,9 +53,9 @@ TRAFFIC = {
     },
     "fit_large_mixed": {
         "sources": ['paper_2310_03921_amd/csrc/mixed.hip', 'paper_2310_03921_amd/csrc/mma_bf16.h', 'paper_2310_03921_amd/csrc/common.h', 'paper_2310_03921_amd/csrc/pairs.hip'],
-        "sha256": "ade21d8baef518e0377cef1fdaa6794f9538d93a31f4c75f488ec68f18a10af7",
-        "fetch_kib": 516602590, "fetch_scale": 2.000,
-        "write_kib": 55181603, "write_scale": 1.000,
+        "sha256": "1ec31a79bfc19696a707564d9646bde085707dbfe732a64a0b0062cc3607935a",
+        "fetch_kib": 513259633, "fetch_scale": 2.000,
+        "write_kib": 55306258, "write_scale": 1.000,
     },
 }
 
